@@ -1,0 +1,309 @@
+// Plain, slow, FP64 CPU oracle for the iQCC hot path.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
+// this file; only the test-suite, the smoke check and the CPU-baseline leg of
+// the benchmark do.  It shares no code, header or table with the HIP library.
+//
+// Conventions (one reading of the paper, stated once here):
+//  * Pauli word of n qubits: words x[0..W-1], z[0..W-1]; qubit j is bit j%64 of
+//    word j/64.  Local operator: I (x=0,z=0), X (1,0), Z (0,1), Y (1,1), Y the
+//    Hermitian Pauli-Y; coefficients real (Eq. 2, H = sum_k C_k P_k).
+//  * Products are formed qubit by qubit from the single-qubit multiplication
+//    table (XY = iZ, YZ = iX, ZX = iY, reverses with -i, squares = I).
+//  * Dressing (Eq. 5): H_d = e^{i tau P/2} H e^{-i tau P/2}.  A term A that
+//    commutes with P is unchanged; an anticommuting A becomes
+//    cos(tau) A + i sin(tau) P A, and with P A = i^e Q (e odd) the new term is
+//    -sin(tau) a Q for e = 1 and +sin(tau) a Q for e = 3.
+//  * Merge (sortless-dressing appendix, D = H + I): equal words are combined by
+//    adding coefficients, in input order after a stable sort on the canonical
+//    key (x[W-1..0], z[W-1..0] compared as unsigned words).
+//  * Compression (iterative-procedure step "compress small terms"): drop a term
+//    when |c| < eps (strict).
+//  * QMF energy (Eq. 3 and the energy functional of App. A):
+//    E = sum_k C_k prod_j <sigma_kj>_j with <X> = sin t cos f, <Y> = sin t sin f,
+//    <Z> = cos t, product taken in ascending qubit order, Neumaier summation.
+//  * DIS gradient (Eq. 7): g_a = Im <Omega| H P_a |Omega> = sum_k C_k Im(i^e) <Q_k>
+//    with P_k P_a = i^e Q_k.
+//  * Angle gradients: analytic derivative of each single-qubit factor, product of
+//    the other factors by explicit prefix/suffix loops (no division).
+//  * tau tangents (iterated dressing, Eq. 6): forward-mode derivative of the chain
+//    with every step's truncation decision frozen at the forward pass.
+//
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared (no -ffast-math).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+namespace {
+
+// single-qubit operator codes: 0 = I, 1 = X, 2 = Y, 3 = Z
+inline int op_of(const uint64_t* x, const uint64_t* z, int q) {
+  int bx = (int)((x[q / 64] >> (q % 64)) & 1u);
+  int bz = (int)((z[q / 64] >> (q % 64)) & 1u);
+  if (bx && bz) return 2;
+  if (bx) return 1;
+  if (bz) return 3;
+  return 0;
+}
+
+inline void set_op(uint64_t* x, uint64_t* z, int q, int op) {
+  uint64_t b = (uint64_t)1 << (q % 64);
+  if (op == 1 || op == 2) x[q / 64] |= b;
+  if (op == 3 || op == 2) z[q / 64] |= b;
+}
+
+// a * b = i^k * r  for single-qubit Paulis.
+struct Mul { int r; int k; };
+const Mul kMul[4][4] = {
+    /* I* */ {{0, 0}, {1, 0}, {2, 0}, {3, 0}},
+    /* X* */ {{1, 0}, {0, 0}, {3, 1}, {2, 3}},   // XY = iZ, XZ = -iY
+    /* Y* */ {{2, 0}, {3, 3}, {0, 0}, {1, 1}},   // YX = -iZ, YZ = iX
+    /* Z* */ {{3, 0}, {2, 1}, {1, 3}, {0, 0}},   // ZX = iY, ZY = -iX
+};
+
+// P1 * P2 = i^e * P3 ; returns e in 0..3
+int product(int nq, int W, const uint64_t* x1, const uint64_t* z1, const uint64_t* x2,
+            const uint64_t* z2, uint64_t* x3, uint64_t* z3) {
+  for (int w = 0; w < W; ++w) { x3[w] = 0; z3[w] = 0; }
+  int e = 0;
+  for (int q = 0; q < nq; ++q) {
+    Mul m = kMul[op_of(x1, z1, q)][op_of(x2, z2, q)];
+    e = (e + m.k) & 3;
+    set_op(x3, z3, q, m.r);
+  }
+  return e;
+}
+
+// canonical order: x[W-1] .. x[0], then z[W-1] .. z[0], unsigned
+inline bool key_less(int W, const uint64_t* xa, const uint64_t* za, const uint64_t* xb,
+                     const uint64_t* zb) {
+  for (int w = W - 1; w >= 0; --w)
+    if (xa[w] != xb[w]) return xa[w] < xb[w];
+  for (int w = W - 1; w >= 0; --w)
+    if (za[w] != zb[w]) return za[w] < zb[w];
+  return false;
+}
+
+inline bool key_eq(int W, const uint64_t* xa, const uint64_t* za, const uint64_t* xb,
+                   const uint64_t* zb) {
+  for (int w = 0; w < W; ++w)
+    if (xa[w] != xb[w] || za[w] != zb[w]) return false;
+  return true;
+}
+
+struct Neumaier {
+  double s = 0.0, comp = 0.0;
+  void add(double v) {
+    double t = s + v;
+    if (std::fabs(s) >= std::fabs(v)) comp += (s - t) + v;
+    else comp += (v - t) + s;
+    s = t;
+  }
+  double value() const { return s + comp; }
+};
+
+// <sigma>_q of the product state, sigma in {I, X, Y, Z}
+struct Bloch {
+  std::vector<double> b;  // 4 per qubit
+  explicit Bloch(int nq, const double* th, const double* ph) : b(4 * (size_t)nq) {
+    for (int q = 0; q < nq; ++q) {
+      double st = std::sin(th[q]), ct = std::cos(th[q]);
+      double sp = std::sin(ph[q]), cp = std::cos(ph[q]);
+      b[4 * q + 0] = 1.0;
+      b[4 * q + 1] = st * cp;
+      b[4 * q + 2] = st * sp;
+      b[4 * q + 3] = ct;
+    }
+  }
+  double expect(int nq, const uint64_t* x, const uint64_t* z) const {
+    double p = 1.0;
+    for (int q = 0; q < nq; ++q) p *= b[4 * q + op_of(x, z, q)];
+    return p;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int oracle_abi_version() { return 1; }
+
+// Product of two Pauli words; returns the phase exponent e (P1 P2 = i^e P3).
+int oracle_pauli_product(int nq, int W, const uint64_t* x1, const uint64_t* z1,
+                         const uint64_t* x2, const uint64_t* z2, uint64_t* x3, uint64_t* z3) {
+  return product(nq, W, x1, z1, x2, z2, x3, z3);
+}
+
+// Raw dressing (Eq. 5), no merge: emits, for every input term, itself (commuting),
+// or itself scaled by cos(tau) plus P*A scaled by +-sin(tau) (anticommuting).
+// Output rows are written in input order (commuting/rotated row first, then the
+// new row).  Arrays are row-major: x[i*W + w].  Returns the number of rows.
+int64_t oracle_dress_raw(int nq, int W, int64_t n, const uint64_t* x, const uint64_t* z,
+                         const double* c, const uint64_t* px, const uint64_t* pz, double tau,
+                         uint64_t* ox, uint64_t* oz, double* oc) {
+  const double C = std::cos(tau), S = std::sin(tau);
+  std::vector<uint64_t> qx(W), qz(W);
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t* xi = x + i * W;
+    const uint64_t* zi = z + i * W;
+    int e = product(nq, W, px, pz, xi, zi, qx.data(), qz.data());  // P * A
+    if ((e & 1) == 0) {
+      std::memcpy(ox + m * W, xi, W * 8);
+      std::memcpy(oz + m * W, zi, W * 8);
+      oc[m++] = c[i];
+    } else {
+      std::memcpy(ox + m * W, xi, W * 8);
+      std::memcpy(oz + m * W, zi, W * 8);
+      oc[m++] = C * c[i];
+      double s = (e == 3) ? 1.0 : -1.0;
+      std::memcpy(ox + m * W, qx.data(), W * 8);
+      std::memcpy(oz + m * W, qz.data(), W * 8);
+      oc[m++] = s * (S * c[i]);
+    }
+  }
+  return m;
+}
+
+// Merge of a multiset (D = H + I) and compression |c| < eps.  Stable sort on the
+// canonical key, left-to-right sums of equal keys.  Optional second channel dc
+// (nullable) is merged the same way and dropped with its row.
+int64_t oracle_merge_truncate(int W, int64_t n, const uint64_t* x, const uint64_t* z,
+                              const double* c, const double* dc, double eps, uint64_t* ox,
+                              uint64_t* oz, double* oc, double* odc) {
+  std::vector<int64_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    return key_less(W, x + a * W, z + a * W, x + b * W, z + b * W);
+  });
+  int64_t m = 0;
+  int64_t i = 0;
+  while (i < n) {
+    int64_t j = i;
+    double s = 0.0, ds = 0.0;
+    bool first = true;
+    while (j < n && key_eq(W, x + idx[i] * W, z + idx[i] * W, x + idx[j] * W, z + idx[j] * W)) {
+      if (first) {
+        s = c[idx[j]];
+        ds = dc ? dc[idx[j]] : 0.0;
+        first = false;
+      } else {
+        s = s + c[idx[j]];
+        if (dc) ds = ds + dc[idx[j]];
+      }
+      ++j;
+    }
+    if (!(std::fabs(s) < eps)) {
+      std::memcpy(ox + m * W, x + idx[i] * W, W * 8);
+      std::memcpy(oz + m * W, z + idx[i] * W, W * 8);
+      oc[m] = s;
+      if (odc) odc[m] = ds;
+      ++m;
+    }
+    i = j;
+  }
+  return m;
+}
+
+// Dressing with a tangent channel: (c, dc) -> (c', dc').  When `active` is
+// non-zero this step's amplitude is the one being differentiated, so the
+// derivatives of cos/sin enter; otherwise dc is rotated like c.
+int64_t oracle_dress_raw_tangent(int nq, int W, int64_t n, const uint64_t* x, const uint64_t* z,
+                                 const double* c, const double* dc, const uint64_t* px,
+                                 const uint64_t* pz, double tau, int active, uint64_t* ox,
+                                 uint64_t* oz, double* oc, double* odc) {
+  const double C = std::cos(tau), S = std::sin(tau);
+  const double dC = active ? -S : 0.0, dS = active ? C : 0.0;
+  std::vector<uint64_t> qx(W), qz(W);
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t* xi = x + i * W;
+    const uint64_t* zi = z + i * W;
+    int e = product(nq, W, px, pz, xi, zi, qx.data(), qz.data());
+    std::memcpy(ox + m * W, xi, W * 8);
+    std::memcpy(oz + m * W, zi, W * 8);
+    if ((e & 1) == 0) {
+      oc[m] = c[i];
+      odc[m++] = dc[i];
+    } else {
+      double s = (e == 3) ? 1.0 : -1.0;
+      oc[m] = C * c[i];
+      odc[m++] = C * dc[i] + dC * c[i];
+      std::memcpy(ox + m * W, qx.data(), W * 8);
+      std::memcpy(oz + m * W, qz.data(), W * 8);
+      oc[m] = s * (S * c[i]);
+      odc[m++] = s * (S * dc[i] + dS * c[i]);
+    }
+  }
+  return m;
+}
+
+// QMF energy.
+double oracle_qmf_energy(int nq, int W, int64_t n, const uint64_t* x, const uint64_t* z,
+                         const double* c, const double* theta, const double* phi) {
+  Bloch B(nq, theta, phi);
+  Neumaier acc;
+  for (int64_t i = 0; i < n; ++i) acc.add(c[i] * B.expect(nq, x + i * W, z + i * W));
+  return acc.value();
+}
+
+// Per-term expectation values <P_k> (for sampled checks).
+void oracle_expectations(int nq, int W, int64_t n, const uint64_t* x, const uint64_t* z,
+                         const double* theta, const double* phi, double* out) {
+  Bloch B(nq, theta, phi);
+  for (int64_t i = 0; i < n; ++i) out[i] = B.expect(nq, x + i * W, z + i * W);
+}
+
+// DIS gradients for n_cand candidate generators (row-major cx, cz).
+void oracle_dis_gradients(int nq, int W, int64_t n, const uint64_t* x, const uint64_t* z,
+                          const double* c, const double* theta, const double* phi,
+                          int64_t n_cand, const uint64_t* cx, const uint64_t* cz, double* g) {
+  Bloch B(nq, theta, phi);
+  std::vector<uint64_t> qx(W), qz(W);
+  for (int64_t a = 0; a < n_cand; ++a) {
+    Neumaier acc;
+    for (int64_t k = 0; k < n; ++k) {
+      int e = product(nq, W, x + k * W, z + k * W, cx + a * W, cz + a * W, qx.data(), qz.data());
+      if (e == 1) acc.add(c[k] * B.expect(nq, qx.data(), qz.data()));
+      else if (e == 3) acc.add(-(c[k] * B.expect(nq, qx.data(), qz.data())));
+    }
+    g[a] = acc.value();
+  }
+}
+
+// dE/dtheta_j and dE/dphi_j.
+void oracle_qmf_grad_angles(int nq, int W, int64_t n, const uint64_t* x, const uint64_t* z,
+                            const double* c, const double* theta, const double* phi,
+                            double* dtheta, double* dphi) {
+  Bloch B(nq, theta, phi);
+  std::vector<double> dbt(4 * (size_t)nq), dbp(4 * (size_t)nq);
+  for (int q = 0; q < nq; ++q) {
+    double st = std::sin(theta[q]), ct = std::cos(theta[q]);
+    double sp = std::sin(phi[q]), cp = std::cos(phi[q]);
+    dbt[4 * q + 0] = 0.0; dbt[4 * q + 1] = ct * cp; dbt[4 * q + 2] = ct * sp; dbt[4 * q + 3] = -st;
+    dbp[4 * q + 0] = 0.0; dbp[4 * q + 1] = -st * sp; dbp[4 * q + 2] = st * cp; dbp[4 * q + 3] = 0.0;
+  }
+  std::vector<Neumaier> at(nq), ap(nq);
+  std::vector<int> ops(nq);
+  std::vector<double> pre(nq + 1), suf(nq + 1);
+  for (int64_t k = 0; k < n; ++k) {
+    for (int q = 0; q < nq; ++q) ops[q] = op_of(x + k * W, z + k * W, q);
+    pre[0] = 1.0;
+    for (int q = 0; q < nq; ++q) pre[q + 1] = pre[q] * B.b[4 * q + ops[q]];
+    suf[nq] = 1.0;
+    for (int q = nq - 1; q >= 0; --q) suf[q] = suf[q + 1] * B.b[4 * q + ops[q]];
+    for (int q = 0; q < nq; ++q) {
+      if (ops[q] == 0) continue;
+      double others = pre[q] * suf[q + 1];
+      at[q].add(c[k] * dbt[4 * q + ops[q]] * others);
+      ap[q].add(c[k] * dbp[4 * q + ops[q]] * others);
+    }
+  }
+  for (int q = 0; q < nq; ++q) { dtheta[q] = at[q].value(); dphi[q] = ap[q].value(); }
+}
+
+}  // extern "C"
