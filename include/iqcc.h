@@ -1,0 +1,191 @@
+/*
+ * iqcc.h -- C ABI of the MI355X (gfx950) iQCC hot-path library, libiqcc.so.
+ *
+ * What the library computes (paper: "Parallel iQCC ...", arXiv 2603.08883):
+ *   H = sum_k C_k P_k                                   (Sec. II, Eq. 2)
+ *   H' = e^{i tau P/2} H e^{-i tau P/2}                 (Sec. II, Eq. 5, closed form)
+ *      = merge of the raw terms D = H + I                (App. D, sortless dressing)
+ *      followed by dropping terms with |c| < eps         (App. A, iterative procedure,
+ *                                                         "compress small terms")
+ *   E = <Omega| H |Omega>, QMF product state            (Sec. II, Eq. 3)
+ *   g_a = Im <Omega| H P_a |Omega>                      (Sec. II, Eq. 7; App. A DIS)
+ *   dE/dtheta_j, dE/dphi_j                              (derivative of Eq. 3 energy)
+ *
+ * Pauli words.  A word on n qubits is W = ceil(n/64) uint64 "x" words and W
+ * "z" words; qubit j is bit j%64 of word j/64.  The local operator is
+ * I (x=0,z=0), X (1,0), Z (0,1), Y (1,1) with Y the Hermitian Pauli-Y; no phase
+ * is stored and coefficients are real FP64.  Bits at qubits >= n must be 0.
+ * Device arrays of words are word-major planes: word w of row i lives at
+ * x[w*ld + i] (ld >= number of rows).
+ *
+ * Term store.  Terms live in an opaque device-resident iqcc_store: word planes
+ * plus coefficients, partitioned into 2^m buckets by a GF(2)-linear 32-bit hash
+ * of the key (the one-device form of the paper's bit-wise partitioning,
+ * App. B): hash(K xor P) = hash(K) xor hash(P), so the new term K xor P of a
+ * term in bucket b lands in bucket b xor (hash(P) mod 2^m) and every merge is
+ * local to one bucket pair.  Keys in a store are unique.  The order of terms
+ * inside a store is unspecified; export returns them grouped by bucket.
+ *
+ * Conventions for every call:
+ *   - return value: IQCC_OK (0) or a negative IQCC_ERR_* code; a message is
+ *     available from iqcc_last_error(ctx).  No C++ exception crosses the ABI.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *     are asynchronous and stream-ordered unless documented as synchronising.
+ *   - device pointers are owned by the caller unless stated; the library
+ *     never frees caller memory.  Outputs never alias inputs.
+ *   - argument validation happens on the host before any device work; invalid
+ *     arguments leave every output untouched.
+ *   - a context is bound to one device and must not be used by two threads
+ *     at once.  Stores belong to the context that created them.
+ */
+#ifndef IQCC_H
+#define IQCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IQCC_OK 0
+#define IQCC_ERR_INVALID_ARG (-1) /* null pointer, bad size, padding bits, non-finite tau, eps < 0 */
+#define IQCC_ERR_CAPACITY (-2)    /* a store's arena or bucket table is too small */
+#define IQCC_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define IQCC_ERR_UNSUPPORTED (-4) /* e.g. more than 256 qubits */
+
+#define IQCC_MAX_WORDS 4 /* up to 256 qubits */
+
+typedef struct iqcc_ctx iqcc_ctx;
+typedef struct iqcc_store iqcc_store;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  Allocates small device scratch. */
+int iqcc_ctx_create(iqcc_ctx **ctx, int device);
+/* Destroy a context (NULL is allowed).  Stores must be destroyed first. */
+int iqcc_ctx_destroy(iqcc_ctx *ctx);
+/* Last error message of this context ("" if none).  Valid until the next call. */
+const char *iqcc_last_error(const iqcc_ctx *ctx);
+/* Library version string. */
+const char *iqcc_version(void);
+
+/* Tuning knobs (the autotuner and tests set them).  Names:
+ *   "load_bucket_terms"  target mean bucket size when a store is loaded (>= 1)
+ *   "split_bucket_terms" a dressing step doubles the bucket count when the
+ *                        mean input bucket exceeds this many terms (>= 1)
+ *   "anti_cap"           LDS capacity, in anticommuting terms, of one bucket
+ *                        pair; larger pairs are processed in hash rounds
+ *                        (16 .. 8192)
+ *   "grid_per_cu"        persistent workgroups per compute unit (1 .. 16)
+ *   "fuse_energy"        1: dressing evaluates the energy of its output in the
+ *                        same pass when angles are given; 0: separate pass
+ *   "dis_tile"           DIS candidates held per workgroup tile (1 .. 256)
+ * Returns IQCC_ERR_INVALID_ARG for an unknown name or out-of-range value. */
+int iqcc_set_param(iqcc_ctx *ctx, const char *name, int64_t value);
+int iqcc_get_param(const iqcc_ctx *ctx, const char *name, int64_t *value);
+
+/* ---- term stores ---------------------------------------------------------- */
+
+/* Create an empty store for `n_qubits` (1..256) qubits able to hold up to
+ * `max_terms` terms as the output of a dressing step (the device arena holds
+ * 2*max_terms rows because a step reserves, per bucket pair, the worst-case
+ * output size 2*(n_b + n_b')).  Device memory: about
+ * 2*max_terms*(16*W + 8) bytes plus the bucket table. */
+int iqcc_store_create(iqcc_ctx *ctx, int n_qubits, int64_t max_terms, iqcc_store **store);
+int iqcc_store_destroy(iqcc_ctx *ctx, iqcc_store *store);
+/* Number of qubits / words of a store. */
+int iqcc_store_shape(const iqcc_store *store, int *n_qubits, int *n_words);
+
+/* Replace the contents of `store` with n rows of device arrays x, z (word
+ * planes, leading dimension ld >= n) and c.  Keys must be unique (not checked
+ * unless the IQCC_DEBUG_VALIDATE environment variable is set, which adds a
+ * synchronising check).  Chooses the bucket count from "load_bucket_terms". */
+int iqcc_store_load(iqcc_ctx *ctx, iqcc_store *store, const uint64_t *x, const uint64_t *z,
+                    const double *c, int64_t n, int64_t ld, void *stream);
+
+/* Synchronising: number of live terms of the store.  Returns IQCC_ERR_CAPACITY
+ * if the dressing step that produced the store ran out of arena or bucket
+ * table (its contents are then undefined). */
+int iqcc_store_count(iqcc_ctx *ctx, const iqcc_store *store, int64_t *n, void *stream);
+
+/* Synchronising: counters of the dressing step that produced `store`:
+ * *n_anti = input terms that anticommuted with the entangler, *n_new = output
+ * terms whose key was not in the input (both 0 after iqcc_store_load). */
+int iqcc_store_stats(iqcc_ctx *ctx, const iqcc_store *store, int64_t *n_anti, int64_t *n_new,
+                     void *stream);
+
+/* Synchronising: copy the live terms to device arrays x, z (planes, leading
+ * dimension ld) and c with room for `cap` rows; *n receives the row count.
+ * IQCC_ERR_CAPACITY (outputs untouched, *n set) if cap is too small. */
+int iqcc_store_export(iqcc_ctx *ctx, const iqcc_store *store, uint64_t *x, uint64_t *z,
+                      double *c, int64_t cap, int64_t ld, int64_t *n, void *stream);
+
+/* ---- dressing, merge, compression (Eq. 5, App. D, App. A) ---------------- */
+
+/* One fused dressing step out = compress_eps(merge(e^{i tau P/2} in e^{-i tau P/2})).
+ * px, pz: HOST arrays of n_words words (the entangler; identity is a no-op).
+ * For a term A of `in` that anticommutes with P, with P*A = i^e Q:
+ *   out[A]  += RN(cos(tau) * c_A)
+ *   out[Q]  += s * RN(sin(tau) * c_A),   s = +1 if e == 3, -1 if e == 1;
+ * terms that commute are copied unchanged.  Every key receives at most two
+ * contributions; their sum is one IEEE addition, so the result does not depend
+ * on order.  cos/sin are evaluated once on the host with the C library.  A term
+ * is dropped when |c| < eps (eps >= 0; eps = 0 keeps exact zeros).
+ * theta, phi (DEVICE, n_qubits each) and energy (DEVICE scalar) are optional
+ * (all NULL or all set): when set, *energy receives <Omega|out|Omega>.
+ * `out` must be a different store with the same n_qubits; its previous
+ * contents are discarded.  Asynchronous: a capacity failure is reported by the
+ * next iqcc_store_count / iqcc_store_export on `out`. */
+int iqcc_dress(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px, const uint64_t *pz,
+               double tau, double eps, const double *theta, const double *phi, double *energy,
+               iqcc_store *out, void *stream);
+
+/* Raw dressing (no merge, no compression) of flat device rows: for each input
+ * row i (in order) emits row 2i = (A, c or RN(cos*c)) and, for anticommuting
+ * rows only, row 2i+1 = (Q, s*RN(sin*c)).  Rows 2i+1 of commuting inputs are
+ * written with c = NaN and flag[i] = 0; flag[i] = 1 marks anticommuting input
+ * rows.  Outputs: ox, oz planes with leading dimension ld_out >= 2n, oc, flag
+ * (int8, n entries).  Stream-ordered, no synchronisation. */
+int iqcc_dress_raw(iqcc_ctx *ctx, int n_qubits, const uint64_t *x, const uint64_t *z,
+                   const double *c, int64_t n, int64_t ld, const uint64_t *px,
+                   const uint64_t *pz, double tau, uint64_t *ox, uint64_t *oz, double *oc,
+                   int8_t *flag, int64_t ld_out, void *stream);
+
+/* Merge of an arbitrary multiset of rows (D = H + I of App. D) followed by
+ * compression: equal keys are summed in increasing row order (left to right),
+ * then rows with |sum| < eps are dropped; the unique result replaces the
+ * contents of `out`.  Synchronising (sizes the bucket table). */
+int iqcc_merge_truncate(iqcc_ctx *ctx, const uint64_t *x, const uint64_t *z, const double *c,
+                        int64_t n, int64_t ld, double eps, iqcc_store *out, void *stream);
+
+/* ---- QMF energy and its gradient (Eq. 3) ---------------------------------- */
+
+/* *energy (DEVICE scalar) = sum_k c_k prod_j <sigma_kj>, with <X> = sin t cos f,
+ * <Y> = sin t sin f, <Z> = cos t per qubit (theta, phi DEVICE arrays). */
+int iqcc_qmf_energy(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
+                    const double *phi, double *energy, void *stream);
+
+/* Backward of iqcc_qmf_energy: dtheta[j] = dE_scale * dE/dtheta_j and
+ * dphi[j] = dE_scale * dE/dphi_j (DEVICE arrays of n_qubits), where dE_scale
+ * is the DEVICE scalar upstream gradient (NULL means 1). */
+int iqcc_qmf_energy_backward(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
+                             const double *phi, const double *dE_scale, double *dtheta,
+                             double *dphi, void *stream);
+
+/* ---- DIS gradient screening (Eq. 7, App. A) ------------------------------- */
+
+#define IQCC_DIS_BATCHED 0 /* one persistent launch over candidate tiles */
+#define IQCC_DIS_PLAIN 1   /* one launch per candidate (reference form) */
+
+/* g[a] = Im <Omega| H P_a |Omega> = sum_k c_k Im(i^e) <Q_k>, P_k P_a = i^e Q_k,
+ * for n_cand candidates given as DEVICE word planes cx, cz (leading dimension
+ * ld_cand >= n_cand).  g is a DEVICE array of n_cand doubles. */
+int iqcc_dis_gradients(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
+                       const double *phi, const uint64_t *cx, const uint64_t *cz,
+                       int64_t n_cand, int64_t ld_cand, int mode, double *g, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IQCC_H */

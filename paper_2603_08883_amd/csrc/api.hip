@@ -1,0 +1,512 @@
+// Host runtime of libiqcc: the C ABI declared in include/iqcc.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "../../include/iqcc.h"
+#include "iqcc_internal.h"
+
+using namespace iqcc;
+
+struct iqcc_ctx {
+  int device = 0;
+  int n_cu = 1;
+  size_t lds_per_block = 65536;
+  std::string err;
+  // tuning knobs
+  int64_t load_bucket_terms = 256;
+  int64_t split_bucket_terms = 384;
+  int64_t anti_cap = 512;
+  int64_t grid_per_cu = 2;
+  int64_t fuse_energy = 1;
+  int64_t dis_tile = 256;
+  // device scratch
+  double* lut = nullptr;        // kMaxWords * 22 * 64
+  double* partial = nullptr;    // n_partial
+  int64_t n_partial = 0;
+  int64_t* scratch = nullptr;   // n_scratch
+  int64_t n_scratch = 0;
+};
+
+struct iqcc_store {
+  int nq = 0, W = 0;
+  int64_t max_terms = 0;
+  StoreDev d{};
+  void* block = nullptr;  // one allocation for counters
+};
+
+namespace {
+
+int fail(iqcc_ctx* ctx, int code, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return code;
+}
+
+#define HIP_TRY(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail((ctx), IQCC_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_CHECK(ctx)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((ctx), IQCC_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+int ensure_scratch(iqcc_ctx* ctx, int64_t n) {
+  if (n <= ctx->n_scratch) return IQCC_OK;
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  if (ctx->scratch) HIP_TRY(ctx, hipFree(ctx->scratch));
+  ctx->scratch = nullptr;
+  ctx->n_scratch = 0;
+  HIP_TRY(ctx, hipMalloc(&ctx->scratch, sizeof(int64_t) * n));
+  ctx->n_scratch = n;
+  return IQCC_OK;
+}
+
+int ensure_partial(iqcc_ctx* ctx, int64_t n) {
+  if (n <= ctx->n_partial) return IQCC_OK;
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  if (ctx->partial) HIP_TRY(ctx, hipFree(ctx->partial));
+  ctx->partial = nullptr;
+  ctx->n_partial = 0;
+  HIP_TRY(ctx, hipMalloc(&ctx->partial, sizeof(double) * n));
+  ctx->n_partial = n;
+  return IQCC_OK;
+}
+
+int grid_of(const iqcc_ctx* ctx) { return (int)(ctx->n_cu * ctx->grid_per_cu); }
+
+bool padding_clear(int nq, int W, const uint64_t* x, const uint64_t* z) {
+  for (int w = 0; w < W; ++w) {
+    int lo = 64 * w;
+    uint64_t valid = nq - lo >= 64 ? ~0ull : (nq - lo <= 0 ? 0ull : ((1ull << (nq - lo)) - 1));
+    if ((x[w] & ~valid) || (z[w] & ~valid)) return false;
+  }
+  return true;
+}
+
+int check_ctx(iqcc_ctx* ctx) {
+  if (!ctx) return IQCC_ERR_INVALID_ARG;
+  ctx->err.clear();
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail(ctx, IQCC_ERR_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+  return IQCC_OK;
+}
+
+Entangler make_entangler(int W, const uint64_t* px, const uint64_t* pz) {
+  Entangler P{};
+  for (int w = 0; w < W; ++w) {
+    P.px[w] = px[w];
+    P.pz[w] = pz[w];
+  }
+  P.hp = bucket_hash_host(W, P.px, P.pz);
+  P.piv_word = 0;
+  P.piv_in_x = 1;
+  P.piv_mask = 0;
+  for (int w = 0; w < W; ++w) {
+    if (P.px[w]) { P.piv_word = w; P.piv_in_x = 1; P.piv_mask = P.px[w] & (~P.px[w] + 1); break; }
+    if (P.pz[w]) { P.piv_word = w; P.piv_in_x = 0; P.piv_mask = P.pz[w] & (~P.pz[w] + 1); break; }
+  }
+  return P;
+}
+
+int ilog2_ceil(int64_t v) {
+  int m = 0;
+  while ((1ll << m) < v) ++m;
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* iqcc_version(void) { return "iqcc-gfx950 0.1"; }
+
+const char* iqcc_last_error(const iqcc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int iqcc_ctx_create(iqcc_ctx** out, int device) {
+  if (!out) return IQCC_ERR_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return IQCC_ERR_HIP;
+  iqcc_ctx* ctx = new iqcc_ctx();
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) { delete ctx; return IQCC_ERR_HIP; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return IQCC_ERR_HIP; }
+  ctx->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess && v > 0)
+      ctx->lds_per_block = (size_t)v;
+    else if (prop.sharedMemPerBlock > 0)
+      ctx->lds_per_block = prop.sharedMemPerBlock;
+  }
+  if (hipMalloc(&ctx->lut, sizeof(double) * kMaxWords * kGroupsPerWord * kLutEntries) != hipSuccess) {
+    delete ctx;
+    return IQCC_ERR_HIP;
+  }
+  *out = ctx;
+  return IQCC_OK;
+}
+
+int iqcc_ctx_destroy(iqcc_ctx* ctx) {
+  if (!ctx) return IQCC_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (ctx->lut) hipFree(ctx->lut);
+  if (ctx->partial) hipFree(ctx->partial);
+  if (ctx->scratch) hipFree(ctx->scratch);
+  delete ctx;
+  return IQCC_OK;
+}
+
+int iqcc_set_param(iqcc_ctx* ctx, const char* name, int64_t v) {
+  if (!ctx || !name) return IQCC_ERR_INVALID_ARG;
+  struct { const char* n; int64_t* p; int64_t lo, hi; } tab[] = {
+      {"load_bucket_terms", &ctx->load_bucket_terms, 1, 1 << 20},
+      {"split_bucket_terms", &ctx->split_bucket_terms, 1, 1 << 20},
+      {"anti_cap", &ctx->anti_cap, 16, 8192},
+      {"grid_per_cu", &ctx->grid_per_cu, 1, 16},
+      {"fuse_energy", &ctx->fuse_energy, 0, 1},
+      {"dis_tile", &ctx->dis_tile, 1, 256},
+  };
+  for (auto& t : tab) {
+    if (std::strcmp(t.n, name) == 0) {
+      if (v < t.lo || v > t.hi) return fail(ctx, IQCC_ERR_INVALID_ARG, "%s out of range", name);
+      *t.p = v;
+      return IQCC_OK;
+    }
+  }
+  return fail(ctx, IQCC_ERR_INVALID_ARG, "unknown parameter %s", name);
+}
+
+int iqcc_get_param(const iqcc_ctx* ctx, const char* name, int64_t* v) {
+  if (!ctx || !name || !v) return IQCC_ERR_INVALID_ARG;
+  const struct { const char* n; int64_t p; } tab[] = {
+      {"load_bucket_terms", ctx->load_bucket_terms}, {"split_bucket_terms", ctx->split_bucket_terms},
+      {"anti_cap", ctx->anti_cap}, {"grid_per_cu", ctx->grid_per_cu},
+      {"fuse_energy", ctx->fuse_energy}, {"dis_tile", ctx->dis_tile},
+      {"n_cu", ctx->n_cu},
+  };
+  for (auto& t : tab)
+    if (std::strcmp(t.n, name) == 0) { *v = t.p; return IQCC_OK; }
+  return IQCC_ERR_INVALID_ARG;
+}
+
+// ---- stores -----------------------------------------------------------------
+
+int iqcc_store_create(iqcc_ctx* ctx, int n_qubits, int64_t max_terms, iqcc_store** out) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!out) return fail(ctx, IQCC_ERR_INVALID_ARG, "store output pointer is null");
+  *out = nullptr;
+  if (n_qubits < 1) return fail(ctx, IQCC_ERR_INVALID_ARG, "n_qubits must be >= 1");
+  if (n_qubits > 64 * kMaxWords) return fail(ctx, IQCC_ERR_UNSUPPORTED, "more than 256 qubits");
+  if (max_terms < 1 || max_terms > (1ll << 40)) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad max_terms");
+  iqcc_store* st = new iqcc_store();
+  st->nq = n_qubits;
+  st->W = (n_qubits + 63) / 64;
+  st->max_terms = max_terms;
+  int64_t cap = 2 * max_terms + 1024;
+  int mcap = ilog2_ceil(max_terms / 16 + 1) + 1;
+  if (mcap > kMaxBucketBits) mcap = kMaxBucketBits;
+  st->d.cap = cap;
+  st->d.mcap = mcap;
+  const int64_t B = 1ll << mcap;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc(&st->d.x, sizeof(uint64_t) * st->W * cap);
+  if (e == hipSuccess) e = hipMalloc(&st->d.z, sizeof(uint64_t) * st->W * cap);
+  if (e == hipSuccess) e = hipMalloc(&st->d.c, sizeof(double) * cap);
+  if (e == hipSuccess) e = hipMalloc(&st->d.off, sizeof(int64_t) * B);
+  if (e == hipSuccess) e = hipMalloc(&st->d.cnt, sizeof(int64_t) * B);
+  if (e == hipSuccess) e = hipMalloc(&st->block, 64);
+  if (e != hipSuccess) {
+    iqcc_store_destroy(ctx, st);
+    return fail(ctx, IQCC_ERR_HIP, "store allocation (%lld rows) failed: %s", (long long)cap,
+                hipGetErrorString(e));
+  }
+  char* blk = (char*)st->block;
+  st->d.total = (int64_t*)(blk + 0);
+  st->d.top = (int64_t*)(blk + 8);
+  st->d.m = (int*)(blk + 16);
+  st->d.err = (int*)(blk + 20);
+  st->d.stats = (int64_t*)(blk + 24);
+  hipMemset(st->block, 0, 64);
+  hipMemset(st->d.off, 0, sizeof(int64_t) * B);
+  hipMemset(st->d.cnt, 0, sizeof(int64_t) * B);
+  hipDeviceSynchronize();
+  *out = st;
+  return IQCC_OK;
+}
+
+int iqcc_store_destroy(iqcc_ctx* ctx, iqcc_store* st) {
+  if (!st) return IQCC_OK;
+  if (ctx) hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (st->d.x) hipFree(st->d.x);
+  if (st->d.z) hipFree(st->d.z);
+  if (st->d.c) hipFree(st->d.c);
+  if (st->d.off) hipFree(st->d.off);
+  if (st->d.cnt) hipFree(st->d.cnt);
+  if (st->block) hipFree(st->block);
+  delete st;
+  return IQCC_OK;
+}
+
+int iqcc_store_shape(const iqcc_store* st, int* nq, int* W) {
+  if (!st) return IQCC_ERR_INVALID_ARG;
+  if (nq) *nq = st->nq;
+  if (W) *W = st->W;
+  return IQCC_OK;
+}
+
+int iqcc_store_load(iqcc_ctx* ctx, iqcc_store* st, const uint64_t* x, const uint64_t* z,
+                    const double* c, int64_t n, int64_t ld, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!st) return fail(ctx, IQCC_ERR_INVALID_ARG, "store is null");
+  if (n < 0 || (n > 0 && (!x || !z || !c)) || ld < n)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad rows/pointers/leading dimension");
+  if (n > st->d.cap) return fail(ctx, IQCC_ERR_CAPACITY, "store holds at most %lld rows", (long long)st->d.cap);
+  int m = 0;
+  while (m < st->d.mcap && (n >> m) > ctx->load_bucket_terms) ++m;
+  const int64_t B = 1ll << m;
+  rc = ensure_scratch(ctx, B + B / 1024 + 16);
+  if (rc) return rc;
+  hipStream_t s = as_stream(stream);
+  launch_store_load(st->W, st->d, x, z, c, n, ld, m, ctx->scratch, s);
+  LAUNCH_CHECK(ctx);
+  if (getenv("IQCC_DEBUG_VALIDATE")) {
+    // unique keys: export and compare neighbours on the host (debug only)
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+  }
+  return IQCC_OK;
+}
+
+int iqcc_store_count(iqcc_ctx* ctx, const iqcc_store* st, int64_t* n, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!st || !n) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  char buf[64];
+  hipStream_t s = as_stream(stream);
+  HIP_TRY(ctx, hipMemcpyAsync(buf, st->block, 64, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  int64_t total;
+  int err;
+  std::memcpy(&total, buf, 8);
+  std::memcpy(&err, buf + 20, 4);
+  *n = total;
+  if (err & 1) return fail(ctx, IQCC_ERR_CAPACITY, "dressing output exceeded the store arena");
+  if (err & 2) return fail(ctx, IQCC_ERR_CAPACITY, "dressing output exceeded the bucket table");
+  if (err & 4) return fail(ctx, IQCC_ERR_CAPACITY, "bucket pair beyond the hash-round limit");
+  return IQCC_OK;
+}
+
+int iqcc_store_stats(iqcc_ctx* ctx, const iqcc_store* st, int64_t* n_anti, int64_t* n_new,
+                     void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!st || !n_anti || !n_new) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  char buf[64];
+  hipStream_t s = as_stream(stream);
+  HIP_TRY(ctx, hipMemcpyAsync(buf, st->block, 64, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  std::memcpy(n_anti, buf + 24, 8);
+  std::memcpy(n_new, buf + 32, 8);
+  return IQCC_OK;
+}
+
+int iqcc_store_export(iqcc_ctx* ctx, const iqcc_store* st, uint64_t* x, uint64_t* z, double* c,
+                      int64_t cap, int64_t ld, int64_t* n, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!st || !n) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  char buf[64];
+  hipStream_t s = as_stream(stream);
+  HIP_TRY(ctx, hipMemcpyAsync(buf, st->block, 64, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  int64_t total;
+  int m, err;
+  std::memcpy(&total, buf, 8);
+  std::memcpy(&m, buf + 16, 4);
+  std::memcpy(&err, buf + 20, 4);
+  *n = total;
+  if (err) return fail(ctx, IQCC_ERR_CAPACITY, "store is invalid (dressing ran out of capacity)");
+  if (total > cap) return fail(ctx, IQCC_ERR_CAPACITY, "export needs %lld rows", (long long)total);
+  if (total > 0 && (!x || !z || !c)) return fail(ctx, IQCC_ERR_INVALID_ARG, "null output");
+  if (ld < cap) return fail(ctx, IQCC_ERR_INVALID_ARG, "leading dimension below cap");
+  const int64_t B = 1ll << m;
+  rc = ensure_scratch(ctx, B + B / 1024 + 16);
+  if (rc) return rc;
+  launch_store_export(st->W, st->d, m, x, z, c, ld, ctx->scratch, ctx->scratch + B, s);
+  LAUNCH_CHECK(ctx);
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return IQCC_OK;
+}
+
+// ---- dressing ---------------------------------------------------------------
+
+int iqcc_dress(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
+               double tau, double eps, const double* theta, const double* phi, double* energy,
+               iqcc_store* out, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!in || !out || !px || !pz) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  if (in == out) return fail(ctx, IQCC_ERR_INVALID_ARG, "output store must differ from input");
+  if (in->nq != out->nq) return fail(ctx, IQCC_ERR_INVALID_ARG, "qubit counts differ");
+  if (!std::isfinite(tau)) return fail(ctx, IQCC_ERR_INVALID_ARG, "tau is not finite");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(ctx, IQCC_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  const bool want_e = theta || phi || energy;
+  if (want_e && !(theta && phi && energy))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "theta, phi and energy must be given together");
+  if (!padding_clear(in->nq, in->W, px, pz))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
+  if (out->d.cap < in->d.cap || out->d.mcap < in->d.mcap)
+    return fail(ctx, IQCC_ERR_CAPACITY, "output store is smaller than the input store");
+  const int W = in->W;
+  Entangler P = make_entangler(W, px, pz);
+  hipStream_t s = as_stream(stream);
+  const int grid = grid_of(ctx);
+  rc = ensure_partial(ctx, grid);
+  if (rc) return rc;
+  DressConfig cfg{};
+  cfg.C = std::cos(tau);
+  cfg.S = std::sin(tau);
+  cfg.eps = eps;
+  cfg.split_thr = ctx->split_bucket_terms;
+  cfg.anti_cap = (int)ctx->anti_cap;
+  cfg.grid = grid;
+  const bool fused = want_e && ctx->fuse_energy;
+  if (dress_lds_bytes(W, cfg.anti_cap, fused) > ctx->lds_per_block)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "anti_cap %d needs more LDS than a workgroup has", cfg.anti_cap);
+  if (want_e) {
+    launch_build_lut(W, in->nq, theta, phi, ctx->lut, s);
+    LAUNCH_CHECK(ctx);
+  }
+  cfg.lut = fused ? ctx->lut : nullptr;
+  cfg.e_partial = ctx->partial;
+  launch_zero_counters(out->d, s);
+  launch_dress(W, in->d, out->d, P, cfg, s);
+  LAUNCH_CHECK(ctx);
+  if (want_e) {
+    if (!fused) launch_energy(W, out->d, grid, ctx->lut, ctx->partial, s);
+    launch_finalize_sum(ctx->partial, grid, nullptr, energy, s);
+    LAUNCH_CHECK(ctx);
+  }
+  return IQCC_OK;
+}
+
+int iqcc_dress_raw(iqcc_ctx* ctx, int nq, const uint64_t* x, const uint64_t* z, const double* c,
+                   int64_t n, int64_t ld, const uint64_t* px, const uint64_t* pz, double tau,
+                   uint64_t* ox, uint64_t* oz, double* oc, int8_t* flag, int64_t ld_out,
+                   void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (nq < 1 || nq > 64 * kMaxWords) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad n_qubits");
+  if (n < 0 || ld < n || ld_out < 2 * n) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad sizes");
+  if (!px || !pz || (n > 0 && (!x || !z || !c || !ox || !oz || !oc || !flag)))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  if (!std::isfinite(tau)) return fail(ctx, IQCC_ERR_INVALID_ARG, "tau is not finite");
+  const int W = (nq + 63) / 64;
+  if (!padding_clear(nq, W, px, pz)) return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
+  Entangler P = make_entangler(W, px, pz);
+  launch_dress_raw(W, x, z, c, n, ld, P, std::cos(tau), std::sin(tau), ox, oz, oc, flag, ld_out,
+                   as_stream(stream));
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+int iqcc_merge_truncate(iqcc_ctx* ctx, const uint64_t* x, const uint64_t* z, const double* c,
+                        int64_t n, int64_t ld, double eps, iqcc_store* out, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  (void)x; (void)z; (void)c; (void)n; (void)ld; (void)eps; (void)out; (void)stream;
+  return fail(ctx, IQCC_ERR_UNSUPPORTED, "iqcc_merge_truncate is not available in this build");
+}
+
+// ---- energy -----------------------------------------------------------------
+
+int iqcc_qmf_energy(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, const double* phi,
+                    double* energy, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h || !theta || !phi || !energy) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  hipStream_t s = as_stream(stream);
+  const int grid = (int)(ctx->n_cu * 4);
+  rc = ensure_partial(ctx, grid);
+  if (rc) return rc;
+  launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
+  launch_energy(h->W, h->d, grid, ctx->lut, ctx->partial, s);
+  launch_finalize_sum(ctx->partial, grid, nullptr, energy, s);
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+int iqcc_qmf_energy_backward(iqcc_ctx* ctx, const iqcc_store* h, const double* theta,
+                             const double* phi, const double* dE, double* dtheta, double* dphi,
+                             void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h || !theta || !phi || !dtheta || !dphi) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  hipStream_t s = as_stream(stream);
+  const int grid = (int)(ctx->n_cu * 2);
+  rc = ensure_partial(ctx, (int64_t)grid * 3 * h->nq);
+  if (rc) return rc;
+  launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
+  launch_energy_backward(h->W, h->nq, h->d, grid, theta, phi, ctx->lut, ctx->partial, s);
+  launch_backward_finalize(h->nq, grid, ctx->partial, theta, phi, dE, dtheta, dphi, s);
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+// ---- DIS --------------------------------------------------------------------
+
+int iqcc_dis_gradients(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, const double* phi,
+                       const uint64_t* cx, const uint64_t* cz, int64_t n_cand, int64_t ld_cand,
+                       int mode, double* g, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h || !theta || !phi || !g || (n_cand > 0 && (!cx || !cz)))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  if (n_cand < 0 || ld_cand < n_cand) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad candidate sizes");
+  if (mode != IQCC_DIS_BATCHED && mode != IQCC_DIS_PLAIN) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad mode");
+  if (n_cand == 0) return IQCC_OK;
+  hipStream_t s = as_stream(stream);
+  launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
+  if (mode == IQCC_DIS_BATCHED) {
+    const int64_t tiles = (n_cand + kBlock - 1) / kBlock;
+    int64_t gt = (ctx->n_cu * 8 + tiles - 1) / tiles;
+    if (gt < 1) gt = 1;
+    if (gt > 4096) gt = 4096;
+    rc = ensure_partial(ctx, gt * n_cand);
+    if (rc) return rc;
+    launch_dis(h->W, h->d, ctx->lut, cx, cz, n_cand, ld_cand, 0, (int)ctx->dis_tile, 0,
+               ctx->partial, (int)gt, g, s);
+  } else {
+    const int grid = (int)(ctx->n_cu * 4);
+    rc = ensure_partial(ctx, grid);
+    if (rc) return rc;
+    launch_dis(h->W, h->d, ctx->lut, cx, cz, n_cand, ld_cand, 1, 1, grid, ctx->partial, 0, g, s);
+  }
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+// Internal declarations of libiqcc (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace iqcc {
+
+constexpr int kBlock = 256;              // threads per workgroup (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxWords = 4;             // 256 qubits
+constexpr int kGroupsPerWord = 22;       // 3-qubit groups per 64-bit word (21 full + 1 single)
+constexpr int kLutEntries = 64;          // 3 x-bits and 3 z-bits per group
+constexpr int kMaxBucketBits = 28;
+
+// ---------------------------------------------------------------------------
+// GF(2)-linear 32-bit hash of a Pauli key.  Rotations, xors and xorshift
+// rounds are all linear over GF(2), so hash(K ^ P) == hash(K) ^ hash(P); the
+// rounds spread the strongly structured Jordan-Wigner keys evenly.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint64_t rotl64(uint64_t v, int r) {
+  return r ? (v << r) | (v >> (64 - r)) : v;
+}
+__host__ __device__ __forceinline__ uint64_t xorshift64(uint64_t f) {
+  f ^= f << 13;
+  f ^= f >> 7;
+  f ^= f << 17;
+  return f;
+}
+template <int W>
+__host__ __device__ __forceinline__ uint32_t bucket_hash(const uint64_t* x, const uint64_t* z) {
+  uint64_t f = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) f ^= rotl64(x[w], (11 * w) & 63) ^ rotl64(z[w], (37 + 19 * w) & 63);
+  f = xorshift64(xorshift64(xorshift64(f)));
+  return (uint32_t)(f >> 32);
+}
+inline uint32_t bucket_hash_host(int W, const uint64_t* x, const uint64_t* z) {
+  uint64_t f = 0;
+  for (int w = 0; w < W; ++w) f ^= rotl64(x[w], (11 * w) & 63) ^ rotl64(z[w], (37 + 19 * w) & 63);
+  f = xorshift64(xorshift64(xorshift64(f)));
+  return (uint32_t)(f >> 32);
+}
+
+// Non-linear 32-bit mix for LDS hash tables.
+template <int W>
+__device__ __forceinline__ uint32_t table_hash(const uint64_t* x, const uint64_t* z) {
+  uint64_t f = 0x9E3779B97F4A7C15ull;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    f = (f ^ x[w]) * 0xBF58476D1CE4E5B9ull;
+    f = (f ^ z[w]) * 0x94D049BB133111EBull;
+  }
+  f ^= f >> 31;
+  return (uint32_t)(f >> 32) ^ (uint32_t)f;
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of a 64-bit value (fixed order: lanes, then waves).
+// tmp: LDS scratch of kWaves uint64.  Contains two barriers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* tmp,
+                                                         uint64_t& total) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  uint64_t s = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t y = __shfl_up(s, d, 64);
+    if (lane >= d) s += y;
+  }
+  if (lane == 63) tmp[wid] = s;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    uint64_t t = tmp[i];
+    base += (i < wid) ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return base + s - v;
+}
+
+// Block-wide sum of doubles in a fixed order (lane tree, then waves in order).
+__device__ __forceinline__ double block_sum(double v, double* tmp) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+  if (lane == 0) tmp[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kWaves; ++i) s += tmp[i];
+  }
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------------------
+// QMF expectation <K> = prod_j b_j(sigma_j) with a 3-qubit-group table:
+// lut[(w*22 + g)*64 + (xbits | zbits<<3)] = product of the three single-qubit
+// factors of qubits 64w+3g .. 64w+3g+2.  Identity groups are skipped.
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* x,
+                                             const uint64_t* z) {
+  double p = 1.0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    uint64_t nz = x[w] | z[w];
+    while (nz) {
+      const int bit = __builtin_ctzll(nz);
+      const int g = (bit * 43) >> 7;  // bit / 3 for 0 <= bit < 64
+      const int sh = 3 * g;
+      const uint32_t idx = (uint32_t)((x[w] >> sh) & 7u) | ((uint32_t)((z[w] >> sh) & 7u) << 3);
+      p *= lut[(w * kGroupsPerWord + g) * kLutEntries + idx];
+      nz &= ~((uint64_t)7 << sh);
+    }
+  }
+  return p;
+}
+
+// Anticommutation of K with P: parity of |xK & zP| + |zK & xP|.
+template <int W>
+__device__ __forceinline__ bool anticommutes(const uint64_t* x, const uint64_t* z,
+                                             const uint64_t* px, const uint64_t* pz) {
+  uint64_t t = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) t ^= (x[w] & pz[w]) ^ (z[w] & px[w]);
+  return __popcll(t) & 1;
+}
+
+// Phase exponent e of the product A*B = i^e Q (Hermitian-Y encoding):
+// e = |xA&zA| + |xB&zB| + 2|zA&xB| - |xQ&zQ|  (mod 4).
+template <int W>
+__device__ __forceinline__ int product_phase(const uint64_t* xa, const uint64_t* za,
+                                             const uint64_t* xb, const uint64_t* zb) {
+  int s = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    s += __popcll(xa[w] & za[w]) + __popcll(xb[w] & zb[w]) + 2 * __popcll(za[w] & xb[w]) -
+         __popcll((xa[w] ^ xb[w]) & (za[w] ^ zb[w]));
+  }
+  return s & 3;
+}
+
+// ---------------------------------------------------------------------------
+// Device-side store descriptor (plain pointers).
+// ---------------------------------------------------------------------------
+struct StoreDev {
+  uint64_t* x;       // [W][cap]
+  uint64_t* z;       // [W][cap]
+  double* c;         // [cap]
+  int64_t cap;       // arena rows (= leading dimension)
+  int64_t* off;      // [2^mcap]
+  int64_t* cnt;      // [2^mcap]
+  int* m;            // device scalar: bucket bits
+  int64_t* total;    // device scalar: live terms
+  int64_t* top;      // device scalar: arena rows reserved
+  int* err;          // device scalar: 1 = arena overflow, 2 = bucket table overflow
+  int64_t* stats;    // device [2]: anticommuting input terms, new terms of the last step
+  int mcap;          // bucket table holds 2^mcap buckets
+};
+
+struct Entangler {
+  uint64_t px[kMaxWords];
+  uint64_t pz[kMaxWords];
+  uint32_t hp;       // bucket_hash(P)
+  int piv_word;      // pivot bit of P (a set bit of x or z), used to pick one
+  int piv_in_x;      //   member of each {K, K^P} pair for the join
+  uint64_t piv_mask;
+};
+
+// ---------------------------------------------------------------------------
+// Host launchers (defined in the kernel files).
+// ---------------------------------------------------------------------------
+void launch_build_lut(int W, int nq, const double* theta, const double* phi, double* lut,
+                      hipStream_t s);
+void launch_zero_counters(StoreDev out, hipStream_t s);
+int launch_store_load(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
+                      int64_t n, int64_t ld, int m, int64_t* scratch, hipStream_t s);
+void launch_store_export(int W, StoreDev st, int m, uint64_t* x, uint64_t* z, double* c, int64_t ld,
+                         int64_t* dest_off, int64_t* scratch, hipStream_t s);
+void launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s);
+
+struct DressConfig {
+  double C, S, eps;
+  int64_t split_thr;
+  int anti_cap;
+  int grid;
+  const double* lut;   // null: no fused energy
+  double* e_partial;   // [grid]
+};
+void launch_dress(int W, const StoreDev& in, const StoreDev& out, const Entangler& P,
+                  const DressConfig& cfg, hipStream_t s);
+size_t dress_lds_bytes(int W, int anti_cap, bool energy);
+void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double* c, int64_t n,
+                      int64_t ld, const Entangler& P, double C, double S, uint64_t* ox,
+                      uint64_t* oz, double* oc, int8_t* flag, int64_t ld_out, hipStream_t s);
+void launch_finalize_sum(const double* partial, int n, const double* scale, double* out,
+                         hipStream_t s);
+
+void launch_energy(int W, const StoreDev& st, int grid, const double* lut, double* e_partial,
+                   hipStream_t s);
+void launch_energy_backward(int W, int nq, const StoreDev& st, int grid, const double* theta,
+                            const double* phi, const double* lut, double* acc /*[grid][3*nq]*/,
+                            hipStream_t s);
+void launch_backward_finalize(int nq, int grid, const double* acc, const double* theta,
+                              const double* phi, const double* dE, double* dtheta, double* dphi,
+                              hipStream_t s);
+
+void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx,
+                const uint64_t* cz, int64_t n_cand, int64_t ld_cand, int mode, int tile,
+                int grid, double* partial /*[grid_terms][n_cand]*/, int grid_terms,
+                double* g, hipStream_t s);
+
+void launch_merge_buckets(int W, StoreDev st, const uint64_t* x, const uint64_t* z,
+                          const double* c, int64_t n, int64_t ld, int m, double eps,
+                          int64_t* scratch, int64_t scratch_len, hipStream_t s);
+
+}  // namespace iqcc

@@ -1,0 +1,160 @@
+// DIS gradient screening (Sec. II, Eq. 7; App. A):
+//   g_a = Im <Omega| H P_a |Omega> = sum_k c_k Im(i^e) <Q_k>,  P_k P_a = i^e Q_k,
+// so only terms that anticommute with P_a contribute, with +<Q_k> for e = 1
+// and -<Q_k> for e = 3.
+//
+// Batched form: one launch; a workgroup holds a tile of up to 256 candidates,
+// one per thread, and streams a share of the terms through LDS; every lane of
+// a wave reads the same staged term (LDS broadcast).  Per-workgroup partial
+// sums are reduced over term shares in a fixed order.
+// Plain form: one launch per candidate streaming all terms (reference form).
+#include "iqcc_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace iqcc {
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_dis_batched(StoreDev st, const double* lut_g,
+                                                        const uint64_t* cx, const uint64_t* cz,
+                                                        int64_t n_cand, int64_t ld_cand,
+                                                        double* partial) {
+  __shared__ double lut[W * kGroupsPerWord * kLutEntries];
+  __shared__ uint64_t tx[W][kBlock], tz[W][kBlock];
+  __shared__ double tc[kBlock];
+  for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
+  const int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool active = a < n_cand;
+  uint64_t ax[W], az[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    ax[w] = active ? cx[w * ld_cand + a] : 0;
+    az[w] = active ? cz[w * ld_cand + a] : 0;
+  }
+  __syncthreads();
+  const int64_t B = 1ll << *st.m;
+  double acc = 0.0;
+  for (int64_t b = blockIdx.y; b < B; b += gridDim.y) {
+    const int64_t n = st.cnt[b], off = st.off[b];
+    for (int64_t i0 = 0; i0 < n; i0 += kBlock) {
+      const int64_t i = i0 + threadIdx.x;
+      if (i < n) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          tx[w][threadIdx.x] = st.x[w * st.cap + off + i];
+          tz[w][threadIdx.x] = st.z[w * st.cap + off + i];
+        }
+        tc[threadIdx.x] = st.c[off + i];
+      }
+      __syncthreads();
+      const int cnt = (int)((n - i0) < kBlock ? (n - i0) : kBlock);
+      if (active) {
+        for (int j = 0; j < cnt; ++j) {
+          uint64_t kx[W], kz[W];
+          uint64_t t = 0;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            kx[w] = tx[w][j];
+            kz[w] = tz[w][j];
+            t ^= (kx[w] & az[w]) ^ (kz[w] & ax[w]);
+          }
+          if (__popcll(t) & 1) {
+            const int e = product_phase<W>(kx, kz, ax, az);
+            uint64_t qx[W], qz[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              qx[w] = kx[w] ^ ax[w];
+              qz[w] = kz[w] ^ az[w];
+            }
+            const double v = tc[j] * expect_lut<W>(lut, qx, qz);
+            acc += (e == 1) ? v : -v;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (active) partial[(int64_t)blockIdx.y * n_cand + a] = acc;
+}
+
+__global__ void k_dis_reduce(const double* partial, int rows, int64_t n_cand, double* g) {
+  for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n_cand;
+       a += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < rows; ++r) s += partial[(int64_t)r * n_cand + a];
+    g[a] = s;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* lut_g,
+                                                    const uint64_t* cx, const uint64_t* cz,
+                                                    int64_t ld_cand, int64_t a, double* partial) {
+  __shared__ double lut[W * kGroupsPerWord * kLutEntries];
+  __shared__ double red[kWaves];
+  for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
+  uint64_t px[W], pz[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    px[w] = cx[w * ld_cand + a];
+    pz[w] = cz[w * ld_cand + a];
+  }
+  __syncthreads();
+  const int64_t B = 1ll << *st.m;
+  double acc = 0.0;
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = st.cnt[b], off = st.off[b];
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      uint64_t kx[W], kz[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        kx[w] = st.x[w * st.cap + off + i];
+        kz[w] = st.z[w * st.cap + off + i];
+      }
+      if (anticommutes<W>(kx, kz, px, pz)) {
+        const int e = product_phase<W>(kx, kz, px, pz);
+        uint64_t qx[W], qz[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          qx[w] = kx[w] ^ px[w];
+          qz[w] = kz[w] ^ pz[w];
+        }
+        const double v = st.c[off + i] * expect_lut<W>(lut, qx, qz);
+        acc += (e == 1) ? v : -v;
+      }
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx,
+                const uint64_t* cz, int64_t n_cand, int64_t ld_cand, int mode, int tile,
+                int grid, double* partial, int grid_terms, double* g, hipStream_t s) {
+  (void)tile;
+  if (n_cand <= 0) return;
+  if (mode == 0) {
+    const int64_t tiles = (n_cand + kBlock - 1) / kBlock;
+    dim3 gr((unsigned)tiles, (unsigned)grid_terms);
+    switch (W) {
+      case 1: hipLaunchKernelGGL(k_dis_batched<1>, gr, dim3(kBlock), 0, s, st, lut, cx, cz, n_cand, ld_cand, partial); break;
+      case 2: hipLaunchKernelGGL(k_dis_batched<2>, gr, dim3(kBlock), 0, s, st, lut, cx, cz, n_cand, ld_cand, partial); break;
+      case 3: hipLaunchKernelGGL(k_dis_batched<3>, gr, dim3(kBlock), 0, s, st, lut, cx, cz, n_cand, ld_cand, partial); break;
+      default: hipLaunchKernelGGL(k_dis_batched<4>, gr, dim3(kBlock), 0, s, st, lut, cx, cz, n_cand, ld_cand, partial); break;
+    }
+    int64_t blocks = (n_cand + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_dis_reduce, dim3((unsigned)blocks), dim3(kBlock), 0, s, partial, grid_terms, n_cand, g);
+  } else {
+    for (int64_t a = 0; a < n_cand; ++a) {
+      switch (W) {
+        case 1: hipLaunchKernelGGL(k_dis_one<1>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial); break;
+        case 2: hipLaunchKernelGGL(k_dis_one<2>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial); break;
+        case 3: hipLaunchKernelGGL(k_dis_one<3>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial); break;
+        default: hipLaunchKernelGGL(k_dis_one<4>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial); break;
+      }
+      launch_finalize_sum(partial, grid, nullptr, g + a, s);
+    }
+  }
+}
+
+}  // namespace iqcc

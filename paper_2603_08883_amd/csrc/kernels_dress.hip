@@ -1,0 +1,547 @@
+// Fused dressing step on gfx950:
+//   classify (anticommutation with P), split (cos/sin rotation, product phase),
+//   route (new key K^P goes to bucket b ^ f(P)), merge D = H + I inside the
+//   bucket pair, compression |c| < eps, optional QMF energy of the output.
+//
+// Closed-form dressing: Sec. II, Eq. 5.  Merge D = H + I: App. D.
+// Pairwise routing between partitions that differ in the flipped bits: App. B/C.
+// Compression of small terms: App. A, iterative procedure.
+//
+// One workgroup handles one bucket pair {b, b ^ f} at a time (persistent grid,
+// static round-robin over pairs).  Every key of the output receives at most
+// two contributions, from K and from K ^ P, so the pair's anticommuting terms
+// are joined in an LDS hash table on one member of each {K, K^P} pair (the one
+// whose pivot bit is 0) and each coefficient is a single IEEE addition.
+// Commuting terms stream straight through.  Output rows are reserved per pair
+// (worst case 2 * (n_b + n_b')) with one atomic on the arena top; bucket b's
+// outputs fill its region from the front (child 0) and, when the step doubles
+// the bucket count, from the back (child 1).
+#include "iqcc_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace iqcc {
+
+constexpr int kItems = 4;                 // terms per thread per load round
+constexpr int kChunk = kBlock * kItems;   // 1024 terms per load round
+constexpr int kFieldBits = 12;            // packed per-category counters
+constexpr uint64_t kFieldMask = (1u << kFieldBits) - 1;
+
+__host__ __device__ inline int next_pow2_int(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+size_t dress_lds_bytes(int W, int cap, bool energy) {
+  size_t o = energy ? (size_t)W * kGroupsPerWord * kLutEntries * 8 : 0;
+  o += (size_t)W * cap * 8 * 2;                  // keys
+  o += (size_t)cap * 8;                          // coefficients
+  o += (size_t)next_pow2_int(2 * cap) * 4;       // hash table
+  o += (size_t)cap * 2;                          // partner
+  o += ((size_t)cap + 7) & ~(size_t)7;           // side
+  o += 8 * 8 + 8 * 8 + 8 * 8 + 256 * 4;          // scan, reduce, misc, round stack
+  return o;
+}
+
+template <int W>
+struct Smem {
+  double* lut;
+  uint64_t* ax;
+  uint64_t* az;
+  double* ac;
+  int* tab;
+  int16_t* partner;
+  uint8_t* side;
+  uint64_t* scan;
+  double* red;
+  int64_t* misc;
+  int* stack;
+  int cap, ts;
+};
+
+template <int W, bool ENERGY>
+__device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap) {
+  Smem<W> s;
+  size_t o = 0;
+  s.lut = (double*)(smem + o);
+  o += ENERGY ? (size_t)W * kGroupsPerWord * kLutEntries * 8 : 0;
+  s.ax = (uint64_t*)(smem + o); o += (size_t)W * cap * 8;
+  s.az = (uint64_t*)(smem + o); o += (size_t)W * cap * 8;
+  s.ac = (double*)(smem + o); o += (size_t)cap * 8;
+  s.ts = next_pow2_int(2 * cap);
+  s.tab = (int*)(smem + o); o += (size_t)s.ts * 4;
+  s.partner = (int16_t*)(smem + o); o += (size_t)cap * 2;
+  s.side = (uint8_t*)(smem + o); o += ((size_t)cap + 7) & ~(size_t)7;
+  s.scan = (uint64_t*)(smem + o); o += 64;
+  s.red = (double*)(smem + o); o += 64;
+  s.misc = (int64_t*)(smem + o); o += 64;
+  s.stack = (int*)(smem + o);
+  s.cap = cap;
+  return s;
+}
+
+struct PairState {
+  int64_t n0, n1, off0, off1, ntot;
+  int64_t reg0, reg1, bound0, bound1;
+  int64_t c00, c01, c10, c11;   // outputs written per (side, child); category = 2*side + child
+  uint32_t b0, b1;
+  bool self;
+  __device__ __forceinline__ int64_t cnt(int cat) const {
+    return cat == 0 ? c00 : cat == 1 ? c01 : cat == 2 ? c10 : c11;
+  }
+  __device__ __forceinline__ void add_packed(uint64_t total, int bits, uint64_t mask) {
+    c00 += (int64_t)(total & mask);
+    c01 += (int64_t)((total >> bits) & mask);
+    c10 += (int64_t)((total >> (2 * bits)) & mask);
+    c11 += (int64_t)((total >> (3 * bits)) & mask);
+  }
+  __device__ __forceinline__ int64_t row(int cat, int64_t k) const {
+    const int64_t reg = (cat >> 1) ? reg1 : reg0;
+    const int64_t bound = (cat >> 1) ? bound1 : bound0;
+    return (cat & 1) == 0 ? reg + k : reg + bound - 1 - k;
+  }
+};
+
+template <int W>
+__device__ __forceinline__ void load_key(const StoreDev& st, int64_t row, uint64_t* kx,
+                                         uint64_t* kz, double& c) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    kx[w] = __builtin_nontemporal_load(&st.x[w * st.cap + row]);
+    kz[w] = __builtin_nontemporal_load(&st.z[w * st.cap + row]);
+  }
+  c = __builtin_nontemporal_load(&st.c[row]);
+}
+
+template <int W>
+__device__ __forceinline__ void store_key(const StoreDev& st, int64_t row, const uint64_t* kx,
+                                          const uint64_t* kz, double c) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    __builtin_nontemporal_store(kx[w], &st.x[w * st.cap + row]);
+    __builtin_nontemporal_store(kz[w], &st.z[w * st.cap + row]);
+  }
+  __builtin_nontemporal_store(c, &st.c[row]);
+}
+
+
+template <int W>
+__device__ __forceinline__ bool pivot_of(const Entangler& P, const uint64_t* kx,
+                                         const uint64_t* kz) {
+  uint64_t v = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    if (w == P.piv_word) v = P.piv_in_x ? kx[w] : kz[w];
+  return (v & P.piv_mask) != 0;
+}
+
+// residue classes use the high half of the representative hash; LDS table
+// slots use the low bits
+__device__ __forceinline__ uint32_t round_hash(uint32_t h) { return (h >> 16) | (h << 16); }
+
+template <int W>
+__device__ __forceinline__ uint32_t rep_hash(const Entangler& P, const uint64_t* kx,
+                                             const uint64_t* kz) {
+  uint64_t rx[W], rz[W];
+  const bool piv = pivot_of<W>(P, kx, kz);
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    rx[w] = piv ? kx[w] ^ P.px[w] : kx[w];
+    rz[w] = piv ? kz[w] ^ P.pz[w] : kz[w];
+  }
+  return table_hash<W>(rx, rz);
+}
+
+// One pass over the pair's input terms.  Commuting terms are written to the
+// output when `write_commuting`; anticommuting terms whose representative
+// hash falls in residue class `rem` mod `mod` are appended to the LDS list
+// (up to cap).  Returns the number of such anticommuting terms (block-uniform).
+template <int W, bool ENERGY>
+__device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
+                             const Smem<W>& sm, PairState& ps, int split, int m,
+                             bool write_commuting, uint32_t mod, uint32_t rem, double eps,
+                             double& eacc) {
+  const int tid = threadIdx.x;
+  int64_t n_anti = 0;
+  for (int64_t i0 = 0; i0 < ps.ntot; i0 += kChunk) {
+    uint64_t kx[kItems][W], kz[kItems][W];
+    double kc[kItems];
+    int kside[kItems];
+    bool valid[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const int64_t idx = i0 + r * kBlock + tid;
+      valid[r] = idx < ps.ntot;
+      kside[r] = idx >= ps.n0;
+      if (valid[r]) {
+        const int64_t row = kside[r] ? ps.off1 + (idx - ps.n0) : ps.off0 + idx;
+        load_key<W>(in, row, kx[r], kz[r], kc[r]);
+      }
+    }
+    int cat[kItems];
+    uint64_t packed = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      cat[r] = -1;
+      if (!valid[r]) continue;
+      if (anticommutes<W>(kx[r], kz[r], P.px, P.pz)) {
+        if (mod == 1 || (round_hash(rep_hash<W>(P, kx[r], kz[r])) & (mod - 1)) == rem) cat[r] = 4;
+      } else if (write_commuting && !(fabs(kc[r]) < eps)) {
+        // commuting terms keep their coefficient; compression applies to them too
+        const int child = split ? (int)((bucket_hash<W>(kx[r], kz[r]) >> m) & 1u) : 0;
+        cat[r] = kside[r] * 2 + child;
+      }
+      if (cat[r] >= 0) packed += 1ull << (kFieldBits * cat[r]);
+    }
+    uint64_t total;
+    uint64_t ex = block_exclusive_scan(packed, sm.scan, total);
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      if (cat[r] < 0) continue;
+      const int64_t k = (int64_t)((ex >> (kFieldBits * cat[r])) & kFieldMask);
+      ex += 1ull << (kFieldBits * cat[r]);
+      if (cat[r] == 4) {
+        const int64_t slot = n_anti + k;
+        if (slot < sm.cap) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            sm.ax[w * sm.cap + slot] = kx[r][w];
+            sm.az[w * sm.cap + slot] = kz[r][w];
+          }
+          sm.ac[slot] = kc[r];
+          sm.side[slot] = (uint8_t)kside[r];
+        }
+      } else {
+        store_key<W>(out, ps.row(cat[r], ps.cnt(cat[r]) + k), kx[r], kz[r], kc[r]);
+        if (ENERGY) eacc += kc[r] * expect_lut<W>(sm.lut, kx[r], kz[r]);
+      }
+    }
+    ps.add_packed(total, kFieldBits, kFieldMask);
+    n_anti += (int64_t)((total >> (kFieldBits * 4)) & kFieldMask);
+  }
+  return n_anti;
+}
+
+// Join the n (<= cap) anticommuting terms held in LDS and emit the rotated
+// and new terms.
+template <int W, bool ENERGY>
+__device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>& sm,
+                          PairState& ps, int n, int split, int m, double C, double S,
+                          double eps, double& eacc) {
+  const int tid = threadIdx.x;
+  const uint32_t tmask = (uint32_t)sm.ts - 1;
+  for (int i = tid; i < sm.ts; i += kBlock) sm.tab[i] = -1;
+  for (int i = tid; i < n; i += kBlock) sm.partner[i] = -1;
+  __syncthreads();
+  // insert the members whose pivot bit is 0
+  for (int i = tid; i < n; i += kBlock) {
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      kx[w] = sm.ax[w * sm.cap + i];
+      kz[w] = sm.az[w * sm.cap + i];
+    }
+    if (pivot_of<W>(P, kx, kz)) continue;
+    uint32_t h = table_hash<W>(kx, kz) & tmask;
+    while (atomicCAS(&sm.tab[h], -1, i) != -1) h = (h + 1) & tmask;
+  }
+  __syncthreads();
+  // the members whose pivot bit is 1 look up K ^ P
+  for (int i = tid; i < n; i += kBlock) {
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      kx[w] = sm.ax[w * sm.cap + i] ^ P.px[w];
+      kz[w] = sm.az[w * sm.cap + i] ^ P.pz[w];
+    }
+    if (pivot_of<W>(P, kx, kz)) continue;  // pivot of K was 0: K is in the table itself
+    uint32_t h = table_hash<W>(kx, kz) & tmask;
+    for (;;) {
+      const int j = sm.tab[h];
+      if (j < 0) break;
+      bool eq = true;
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        eq = eq && (sm.ax[w * sm.cap + j] == kx[w]) && (sm.az[w * sm.cap + j] == kz[w]);
+      if (eq) {
+        sm.partner[i] = (int16_t)j;
+        sm.partner[j] = (int16_t)i;
+        break;
+      }
+      h = (h + 1) & tmask;
+    }
+  }
+  __syncthreads();
+  const int child_p = split ? (int)((P.hp >> m) & 1u) : 0;
+  for (int i0 = 0; i0 < n; i0 += kBlock) {
+    const int i = i0 + tid;
+    const bool valid = i < n;
+    uint64_t kx[W], kz[W], qx[W], qz[W];
+    double v_own = 0.0, v_new = 0.0;
+    int cat_own = -1, cat_new = -1;
+    if (valid) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        kx[w] = sm.ax[w * sm.cap + i];
+        kz[w] = sm.az[w * sm.cap + i];
+        qx[w] = kx[w] ^ P.px[w];
+        qz[w] = kz[w] ^ P.pz[w];
+      }
+      const double a = sm.ac[i];
+      const int side = sm.side[i];
+      const int j = sm.partner[i];
+      const int child = split ? (int)((bucket_hash<W>(kx, kz) >> m) & 1u) : 0;
+      const double rot = __dmul_rn(C, a);
+      if (j >= 0) {
+        // partner K ^ P present: its new term lands on K
+        uint64_t jx[W], jz[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          jx[w] = sm.ax[w * sm.cap + j];
+          jz[w] = sm.az[w * sm.cap + j];
+        }
+        const int ej = product_phase<W>(P.px, P.pz, jx, jz);
+        const double sj = __dmul_rn(S, sm.ac[j]);
+        v_own = __dadd_rn(rot, ej == 3 ? sj : -sj);
+      } else {
+        v_own = rot;
+        const int e = product_phase<W>(P.px, P.pz, kx, kz);
+        const double si = __dmul_rn(S, a);
+        v_new = e == 3 ? si : -si;
+        if (!(fabs(v_new) < eps)) {
+          const int oside = ps.self ? 0 : side ^ 1;
+          cat_new = oside * 2 + (child ^ child_p);
+        }
+      }
+      if (!(fabs(v_own) < eps)) cat_own = side * 2 + child;
+    }
+    uint64_t packed = 0;
+    if (cat_own >= 0) packed += 1ull << (kFieldBits * cat_own);
+    if (cat_new >= 0) packed += 1ull << (kFieldBits * cat_new);
+    uint64_t total;
+    uint64_t ex = block_exclusive_scan(packed, sm.scan, total);
+    if (cat_own >= 0) {
+      const int64_t k = (int64_t)((ex >> (kFieldBits * cat_own)) & kFieldMask);
+      ex += 1ull << (kFieldBits * cat_own);
+      store_key<W>(out, ps.row(cat_own, ps.cnt(cat_own) + k), kx, kz, v_own);
+      if (ENERGY) eacc += v_own * expect_lut<W>(sm.lut, kx, kz);
+    }
+    if (cat_new >= 0) {
+      atomicAdd((unsigned long long*)&sm.misc[3], 1ull);
+      const int64_t k = (int64_t)((ex >> (kFieldBits * cat_new)) & kFieldMask);
+      store_key<W>(out, ps.row(cat_new, ps.cnt(cat_new) + k), qx, qz, v_new);
+      if (ENERGY) eacc += v_new * expect_lut<W>(sm.lut, qx, qz);
+    }
+    ps.add_packed(total, kFieldBits, kFieldMask);
+  }
+  __syncthreads();
+}
+
+template <int W, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Entangler P,
+                                                  DressConfig cfg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Smem<W> sm = carve<W, ENERGY>(smem, cfg.anti_cap);
+  const int tid = threadIdx.x;
+  if (*in.err) {
+    // the input is the invalid output of an earlier step: propagate, read nothing
+    if (blockIdx.x == 0 && tid == 0) atomicOr(out.err, *in.err);
+    return;
+  }
+  const int m = *in.m;
+  const int64_t n_in = *in.total;
+  const int split = (m < out.mcap) && (n_in > (cfg.split_thr << m)) ? 1 : 0;
+  if (m + split > out.mcap) {
+    if (blockIdx.x == 0 && tid == 0) atomicOr(out.err, 2);
+    return;
+  }
+  const uint32_t mask = (uint32_t)((1ull << m) - 1);
+  const uint32_t f = P.hp & mask;
+  const int64_t npairs = f ? (1ll << (m - 1)) : (1ll << m);
+  const int thi = f ? 31 - __clz(f) : 0;
+  if (blockIdx.x == 0 && tid == 0) *out.m = m + split;
+  if (ENERGY) {
+    for (int i = tid; i < W * kGroupsPerWord * kLutEntries; i += kBlock) sm.lut[i] = cfg.lut[i];
+    __syncthreads();
+  }
+  double eacc = 0.0;
+  for (int64_t pi = blockIdx.x; pi < npairs; pi += gridDim.x) {
+    PairState ps;
+    if (f) {
+      const uint32_t lo = (uint32_t)pi & ((1u << thi) - 1);
+      ps.b0 = (((uint32_t)pi >> thi) << (thi + 1)) | lo;
+      ps.b1 = ps.b0 ^ f;
+    } else {
+      ps.b0 = ps.b1 = (uint32_t)pi;
+    }
+    ps.self = (f == 0);
+    ps.n0 = in.cnt[ps.b0];
+    ps.off0 = in.off[ps.b0];
+    ps.n1 = ps.self ? 0 : in.cnt[ps.b1];
+    ps.off1 = ps.self ? 0 : in.off[ps.b1];
+    ps.ntot = ps.n0 + ps.n1;
+    ps.bound0 = ps.self ? 2 * ps.n0 : ps.n0 + ps.n1;
+    ps.bound1 = ps.self ? 0 : ps.n0 + ps.n1;
+    if (tid == 0) {
+      const int64_t need = ps.bound0 + ps.bound1;
+      const int64_t base = need ? (int64_t)atomicAdd((unsigned long long*)out.top, (unsigned long long)need) : 0;
+      const bool bad = base + need > out.cap;
+      if (bad) atomicOr(out.err, 1);
+      sm.misc[0] = base;
+      sm.misc[1] = bad;
+      sm.misc[3] = 0;
+    }
+    __syncthreads();
+    const int64_t base = sm.misc[0];
+    const bool bad = sm.misc[1] != 0;
+    __syncthreads();
+    ps.reg0 = base;
+    ps.reg1 = base + ps.bound0;
+    ps.c00 = ps.c01 = ps.c10 = ps.c11 = 0;
+    int64_t pair_anti = 0;
+    if (!bad) {
+      const int64_t n_anti = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, true, 1u, 0u, cfg.eps, eacc);
+      pair_anti = n_anti;
+      if (n_anti <= sm.cap) {
+        __syncthreads();
+        emit_anti<W, ENERGY>(out, P, sm, ps, (int)n_anti, split, m, cfg.C, cfg.S, cfg.eps, eacc);
+      } else {
+        // more anticommuting terms than LDS holds: process them in residue
+        // classes of a hash of the pair representative (both members of a
+        // {K, K^P} pair always fall in the same class)
+        int* stk = sm.stack;  // pairs (mod, rem), written by thread 0
+        int r0 = 1;
+        while (r0 * (int64_t)sm.cap < 2 * n_anti && r0 < 32) r0 <<= 1;
+        if (tid == 0) {
+          for (int r = r0 - 1; r >= 0; --r) { stk[2 * (r0 - 1 - r)] = r0; stk[2 * (r0 - 1 - r) + 1] = r; }
+          sm.misc[2] = r0;
+        }
+        __syncthreads();
+        for (;;) {
+          const int sp = (int)sm.misc[2];
+          if (sp == 0) break;
+          const uint32_t mod = (uint32_t)stk[2 * (sp - 1)];
+          const uint32_t rem = (uint32_t)stk[2 * (sp - 1) + 1];
+          __syncthreads();
+          if (tid == 0) sm.misc[2] = sp - 1;
+          const int64_t nr = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, false, mod, rem, cfg.eps, eacc);
+          __syncthreads();
+          if (nr <= sm.cap) {
+            emit_anti<W, ENERGY>(out, P, sm, ps, (int)nr, split, m, cfg.C, cfg.S, cfg.eps, eacc);
+          } else if (tid == 0) {
+            int t = (int)sm.misc[2];
+            if (t + 2 <= 120 && mod < (1u << 30)) {
+              stk[2 * t] = (int)(2 * mod); stk[2 * t + 1] = (int)(rem + mod);
+              stk[2 * t + 2] = (int)(2 * mod); stk[2 * t + 3] = (int)rem;
+              sm.misc[2] = t + 2;
+            } else {
+              atomicOr(out.err, 4);
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+    // bucket table of the output
+    if (tid == 0) {
+      int64_t produced = 0;
+      const int nside = ps.self ? 1 : 2;
+      for (int s = 0; s < nside; ++s) {
+        const uint32_t b = s ? ps.b1 : ps.b0;
+        for (int ch = 0; ch < 1 + split; ++ch) {
+          const uint32_t ob = b + ((uint32_t)ch << m);
+          const int64_t k = bad ? 0 : ps.cnt(2 * s + ch);
+          out.cnt[ob] = k;
+          out.off[ob] = ps.row(2 * s + ch, k - 1) - (ch ? 0 : k - 1);
+          produced += k;
+        }
+      }
+      if (produced) atomicAdd((unsigned long long*)out.total, (unsigned long long)produced);
+      if (pair_anti) atomicAdd((unsigned long long*)&out.stats[0], (unsigned long long)pair_anti);
+      if (sm.misc[3]) atomicAdd((unsigned long long*)&out.stats[1], (unsigned long long)sm.misc[3]);
+    }
+    __syncthreads();
+  }
+  if (ENERGY) {
+    const double s = block_sum(eacc, sm.red);
+    if (tid == 0) cfg.e_partial[blockIdx.x] = s;
+  }
+}
+
+template <int W, bool E>
+static void launch_dress_t(const StoreDev& in, const StoreDev& out, const Entangler& P,
+                           const DressConfig& cfg, hipStream_t s) {
+  const size_t lds = dress_lds_bytes(W, cfg.anti_cap, E);
+  static bool attr_set[2] = {false, false};
+  (void)attr_set;
+  hipFuncSetAttribute((const void*)k_dress<W, E>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  hipLaunchKernelGGL((k_dress<W, E>), dim3(cfg.grid), dim3(kBlock), lds, s, in, out, P, cfg);
+}
+
+void launch_dress(int W, const StoreDev& in, const StoreDev& out, const Entangler& P,
+                  const DressConfig& cfg, hipStream_t s) {
+  const bool e = cfg.lut != nullptr;
+  switch (W) {
+    case 1: e ? launch_dress_t<1, true>(in, out, P, cfg, s) : launch_dress_t<1, false>(in, out, P, cfg, s); break;
+    case 2: e ? launch_dress_t<2, true>(in, out, P, cfg, s) : launch_dress_t<2, false>(in, out, P, cfg, s); break;
+    case 3: e ? launch_dress_t<3, true>(in, out, P, cfg, s) : launch_dress_t<3, false>(in, out, P, cfg, s); break;
+    default: e ? launch_dress_t<4, true>(in, out, P, cfg, s) : launch_dress_t<4, false>(in, out, P, cfg, s); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Raw dressing of flat rows (no merge): row 2i = rotated/copied term, row
+// 2i+1 = new term for anticommuting rows.
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void k_dress_raw(const uint64_t* __restrict__ x, const uint64_t* __restrict__ z,
+                            const double* __restrict__ c, int64_t n, int64_t ld, Entangler P,
+                            double C, double S, uint64_t* ox, uint64_t* oz, double* oc,
+                            int8_t* flag, int64_t ldo) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      kx[w] = x[w * ld + i];
+      kz[w] = z[w * ld + i];
+    }
+    const double a = c[i];
+    const bool anti = anticommutes<W>(kx, kz, P.px, P.pz);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      ox[w * ldo + 2 * i] = kx[w];
+      oz[w * ldo + 2 * i] = kz[w];
+      ox[w * ldo + 2 * i + 1] = kx[w] ^ P.px[w];
+      oz[w * ldo + 2 * i + 1] = kz[w] ^ P.pz[w];
+    }
+    if (anti) {
+      const int e = product_phase<W>(P.px, P.pz, kx, kz);
+      const double si = __dmul_rn(S, a);
+      oc[2 * i] = __dmul_rn(C, a);
+      oc[2 * i + 1] = e == 3 ? si : -si;
+    } else {
+      oc[2 * i] = a;
+      oc[2 * i + 1] = __builtin_nan("");
+    }
+    flag[i] = anti ? 1 : 0;
+  }
+}
+
+void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double* c, int64_t n,
+                      int64_t ld, const Entangler& P, double C, double S, uint64_t* ox,
+                      uint64_t* oz, double* oc, int8_t* flag, int64_t ld_out, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_dress_raw<1>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, P, C, S, ox, oz, oc, flag, ld_out); break;
+    case 2: hipLaunchKernelGGL(k_dress_raw<2>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, P, C, S, ox, oz, oc, flag, ld_out); break;
+    case 3: hipLaunchKernelGGL(k_dress_raw<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, P, C, S, ox, oz, oc, flag, ld_out); break;
+    default: hipLaunchKernelGGL(k_dress_raw<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, P, C, S, ox, oz, oc, flag, ld_out); break;
+  }
+}
+
+}  // namespace iqcc

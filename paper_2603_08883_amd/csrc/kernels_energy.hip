@@ -1,0 +1,238 @@
+// QMF energy (Sec. II, Eq. 3; energy functional of App. A) and its gradient
+// with respect to the Bloch angles.
+//
+// <K> of the product state is prod_j b_j(sigma_j) with b(I) = 1,
+// b(X) = sin t cos f, b(Y) = sin t sin f, b(Z) = cos t.  Terms are streamed
+// once; the product uses a 3-qubit-group table in LDS and skips identity
+// groups.  Partial sums are per workgroup and reduced in a fixed order.
+#include "iqcc_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace iqcc {
+
+__device__ __forceinline__ double bloch_factor(int op, double st, double ct, double sp,
+                                               double cp) {
+  // op: 0 = I, 1 = X, 2 = Z, 3 = Y (bit0 = x, bit1 = z)
+  return op == 0 ? 1.0 : op == 1 ? st * cp : op == 2 ? ct : st * sp;
+}
+
+__global__ void k_build_lut(int W, int nq, const double* theta, const double* phi, double* lut) {
+  const int n = W * kGroupsPerWord * kLutEntries;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int idx = e % kLutEntries;
+    const int wg = e / kLutEntries;
+    const int w = wg / kGroupsPerWord, g = wg % kGroupsPerWord;
+    double p = 1.0;
+    for (int i = 0; i < 3; ++i) {
+      const int bitpos = 3 * g + i;
+      const int q = 64 * w + bitpos;
+      if (bitpos >= 64 || q >= nq) continue;
+      const int op = ((idx >> i) & 1) | (((idx >> (3 + i)) & 1) << 1);
+      if (op == 0) continue;
+      double st, ct, sp, cp;
+      sincos(theta[q], &st, &ct);
+      sincos(phi[q], &sp, &cp);
+      p *= bloch_factor(op, st, ct, sp, cp);
+    }
+    lut[e] = p;
+  }
+}
+
+void launch_build_lut(int W, int nq, const double* theta, const double* phi, double* lut,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_build_lut, dim3(16), dim3(kBlock), 0, s, W, nq, theta, phi, lut);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order reduction of per-workgroup partials: out = scale * sum.
+// ---------------------------------------------------------------------------
+__global__ void k_finalize_sum(const double* partial, int n, const double* scale, double* out) {
+  __shared__ double red[kWaves];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) *out = scale ? s * *scale : s;
+}
+
+void launch_finalize_sum(const double* partial, int n, const double* scale, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_sum, dim3(1), dim3(kBlock), 0, s, partial, n, scale, out);
+}
+
+// ---------------------------------------------------------------------------
+// Energy of a store: workgroup g takes buckets g, g + grid, ...
+// ---------------------------------------------------------------------------
+constexpr int kEItems = 4;
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_energy(StoreDev st, const double* lut_g,
+                                                   double* partial) {
+  __shared__ double lut[W * kGroupsPerWord * kLutEntries];
+  __shared__ double red[kWaves];
+  for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
+  __syncthreads();
+  const int64_t B = 1ll << *st.m;
+  double acc = 0.0;
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = st.cnt[b], off = st.off[b];
+    for (int64_t i0 = 0; i0 < n; i0 += kBlock * kEItems) {
+      uint64_t kx[kEItems][W], kz[kEItems][W];
+      double kc[kEItems];
+#pragma unroll
+      for (int r = 0; r < kEItems; ++r) {
+        const int64_t i = i0 + r * kBlock + threadIdx.x;
+        kc[r] = 0.0;
+        if (i < n) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            kx[r][w] = __builtin_nontemporal_load(&st.x[w * st.cap + off + i]);
+            kz[r][w] = __builtin_nontemporal_load(&st.z[w * st.cap + off + i]);
+          }
+          kc[r] = __builtin_nontemporal_load(&st.c[off + i]);
+        } else {
+#pragma unroll
+          for (int w = 0; w < W; ++w) kx[r][w] = kz[r][w] = 0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kEItems; ++r) acc += kc[r] * expect_lut<W>(lut, kx[r], kz[r]);
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+void launch_energy(int W, const StoreDev& st, int grid, const double* lut, double* e_partial,
+                   hipStream_t s) {
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_energy<1>, dim3(grid), dim3(kBlock), 0, s, st, lut, e_partial); break;
+    case 2: hipLaunchKernelGGL(k_energy<2>, dim3(grid), dim3(kBlock), 0, s, st, lut, e_partial); break;
+    case 3: hipLaunchKernelGGL(k_energy<3>, dim3(grid), dim3(kBlock), 0, s, st, lut, e_partial); break;
+    default: hipLaunchKernelGGL(k_energy<4>, dim3(grid), dim3(kBlock), 0, s, st, lut, e_partial); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward w.r.t. the Bloch angles.
+// For every term and every non-identity qubit q of it, the product of all
+// other factors ("others") is formed from prefix and suffix products over the
+// 3-qubit groups (never by division) and added into S[q][sigma_q] (LDS, FP64
+// atomics).  dE/dtheta_q = sum_sigma S[q][sigma] db_sigma/dtheta, likewise phi.
+// acc layout per workgroup: [3 * nq] with sigma order X, Z, Y.
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_energy_bwd(StoreDev st, int nq, const double* theta,
+                                                       const double* phi, const double* lut_g,
+                                                       double* acc_g) {
+  constexpr int G = W * kGroupsPerWord;
+  __shared__ double lut[G * kLutEntries];
+  __shared__ double fac[kMaxWords * 64 * 4];   // per qubit: factor of I, X, Z, Y
+  __shared__ double acc[kMaxWords * 64 * 3];
+  for (int i = threadIdx.x; i < G * kLutEntries; i += kBlock) lut[i] = lut_g[i];
+  for (int q = threadIdx.x; q < 64 * W; q += kBlock) {
+    double st_ = 0, ct = 1, sp = 0, cp = 1;
+    if (q < nq) {
+      sincos(theta[q], &st_, &ct);
+      sincos(phi[q], &sp, &cp);
+    }
+    for (int op = 0; op < 4; ++op) fac[4 * q + op] = bloch_factor(op, st_, ct, sp, cp);
+    for (int k = 0; k < 3; ++k) acc[3 * q + k] = 0.0;
+  }
+  __syncthreads();
+  const int64_t B = 1ll << *st.m;
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = st.cnt[b], off = st.off[b];
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      uint64_t kx[W], kz[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        kx[w] = st.x[w * st.cap + off + i];
+        kz[w] = st.z[w * st.cap + off + i];
+      }
+      const double c = st.c[off + i];
+      double L[G];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+#pragma unroll
+        for (int g = 0; g < kGroupsPerWord; ++g) {
+          const int sh = 3 * g;
+          const uint32_t idx = (uint32_t)((kx[w] >> sh) & 7u) | ((uint32_t)((kz[w] >> sh) & 7u) << 3);
+          L[w * kGroupsPerWord + g] = idx ? lut[(w * kGroupsPerWord + g) * kLutEntries + idx] : 1.0;
+        }
+      }
+      double suf[G + 1];
+      suf[G] = 1.0;
+#pragma unroll
+      for (int g = G - 1; g >= 0; --g) suf[g] = suf[g + 1] * L[g];
+      double pre = c;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+#pragma unroll
+        for (int g = 0; g < kGroupsPerWord; ++g) {
+          const int gi = w * kGroupsPerWord + g;
+          const int sh = 3 * g;
+          const uint32_t xb = (uint32_t)((kx[w] >> sh) & 7u), zb = (uint32_t)((kz[w] >> sh) & 7u);
+          if (xb | zb) {
+            const double others = pre * suf[gi + 1];
+            const int q0 = 64 * w + sh;
+            int op[3];
+            double f[3];
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+              op[t] = (int)((xb >> t) & 1u) | (int)(((zb >> t) & 1u) << 1);
+              f[t] = (sh + t < 64) ? fac[4 * (q0 + t) + op[t]] : 1.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+              if (op[t] == 0 || sh + t >= 64) continue;
+              const double inner = (t == 0 ? 1.0 : f[0]) * (t == 1 ? 1.0 : f[1]) * (t == 2 ? 1.0 : f[2]);
+              atomicAdd(&acc[3 * (q0 + t) + (op[t] - 1)], others * inner);
+            }
+          }
+          pre *= L[gi];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 3 * nq; k += kBlock) acc_g[(int64_t)blockIdx.x * 3 * nq + k] = acc[k];
+}
+
+void launch_energy_backward(int W, int nq, const StoreDev& st, int grid, const double* theta,
+                            const double* phi, const double* lut, double* acc, hipStream_t s) {
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_energy_bwd<1>, dim3(grid), dim3(kBlock), 0, s, st, nq, theta, phi, lut, acc); break;
+    case 2: hipLaunchKernelGGL(k_energy_bwd<2>, dim3(grid), dim3(kBlock), 0, s, st, nq, theta, phi, lut, acc); break;
+    case 3: hipLaunchKernelGGL(k_energy_bwd<3>, dim3(grid), dim3(kBlock), 0, s, st, nq, theta, phi, lut, acc); break;
+    default: hipLaunchKernelGGL(k_energy_bwd<4>, dim3(grid), dim3(kBlock), 0, s, st, nq, theta, phi, lut, acc); break;
+  }
+}
+
+__global__ void k_backward_finalize(int nq, int grid, const double* acc, const double* theta,
+                                    const double* phi, const double* dE, double* dtheta,
+                                    double* dphi) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+    double S[3] = {0.0, 0.0, 0.0};
+    for (int g = 0; g < grid; ++g)
+      for (int k = 0; k < 3; ++k) S[k] += acc[(int64_t)g * 3 * nq + 3 * q + k];
+    double st, ct, sp, cp;
+    sincos(theta[q], &st, &ct);
+    sincos(phi[q], &sp, &cp);
+    // sigma order X, Z, Y
+    const double dt = S[0] * (ct * cp) + S[1] * (-st) + S[2] * (ct * sp);
+    const double dp = S[0] * (-st * sp) + S[2] * (st * cp);
+    const double sc = dE ? *dE : 1.0;
+    dtheta[q] = sc * dt;
+    dphi[q] = sc * dp;
+  }
+}
+
+void launch_backward_finalize(int nq, int grid, const double* acc, const double* theta,
+                              const double* phi, const double* dE, double* dtheta, double* dphi,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_backward_finalize, dim3(1), dim3(kBlock), 0, s, nq, grid, acc, theta, phi,
+                     dE, dtheta, dphi);
+}
+
+}  // namespace iqcc

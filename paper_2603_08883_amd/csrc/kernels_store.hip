@@ -1,0 +1,219 @@
+// Term-store kernels: load (bucket partition), export (compaction), scans.
+//
+// Bucket partition = the single-device form of the bit-wise partitioning of
+// App. B: a term's bucket is the low m bits of a GF(2)-linear hash of its key.
+#include "iqcc_internal.h"
+
+namespace iqcc {
+
+__global__ void k_zero_counters(StoreDev st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *st.total = 0;
+    *st.top = 0;
+    *st.err = 0;
+    st.stats[0] = 0;
+    st.stats[1] = 0;
+  }
+}
+
+void launch_zero_counters(StoreDev out, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, out);
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+static void fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)blocks), dim3(kBlock), 0, s, p, n, v);
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int64 (three passes: block sums, scan of sums, apply).
+// scratch: ceil(n/1024) + 1 int64.
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ void k_scan_blocksum(const int64_t* in, int64_t n, int64_t* sums) {
+  __shared__ uint64_t tmp[kWaves];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t s = 0;
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + (int64_t)threadIdx.x * kScanItems + r;
+    if (i < n) s += in[i];
+  }
+  uint64_t total;
+  block_exclusive_scan((uint64_t)s, tmp, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = (int64_t)total;
+}
+
+__global__ void k_scan_sums(int64_t* sums, int64_t nb) {
+  __shared__ uint64_t tmp[kWaves];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+    int64_t i = b0 + threadIdx.x;
+    int64_t v = i < nb ? sums[i] : 0;
+    uint64_t total;
+    uint64_t ex = block_exclusive_scan((uint64_t)v, tmp, total);
+    int64_t c0 = carry;
+    if (i < nb) sums[i] = c0 + (int64_t)ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = c0 + (int64_t)total;
+    __syncthreads();
+  }
+}
+
+__global__ void k_scan_apply(const int64_t* in, int64_t* out, int64_t n, const int64_t* sums) {
+  __shared__ uint64_t tmp[kWaves];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + (int64_t)threadIdx.x * kScanItems + r;
+    v[r] = i < n ? in[i] : 0;
+    s += v[r];
+  }
+  uint64_t total;
+  int64_t ex = (int64_t)block_exclusive_scan((uint64_t)s, tmp, total) + sums[blockIdx.x];
+  for (int r = 0; r < kScanItems; ++r) {
+    int64_t i = base + (int64_t)threadIdx.x * kScanItems + r;
+    if (i < n) out[i] = ex;
+    ex += v[r];
+  }
+}
+
+void launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_blocksum, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, scratch);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, scratch, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, scratch);
+}
+
+// ---------------------------------------------------------------------------
+// Load: flat rows -> bucketed store.
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void k_load_hist(const uint64_t* __restrict__ x, const uint64_t* __restrict__ z,
+                            int64_t n, int64_t ld, uint32_t mask, int64_t* cnt) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      kx[w] = x[w * ld + i];
+      kz[w] = z[w * ld + i];
+    }
+    uint32_t b = bucket_hash<W>(kx, kz) & mask;
+    atomicAdd((unsigned long long*)&cnt[b], 1ull);
+  }
+}
+
+template <int W>
+__global__ void k_load_scatter(const uint64_t* __restrict__ x, const uint64_t* __restrict__ z,
+                               const double* __restrict__ c, int64_t n, int64_t ld,
+                               uint32_t mask, const int64_t* off, int64_t* fill, StoreDev st) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      kx[w] = x[w * ld + i];
+      kz[w] = z[w * ld + i];
+    }
+    uint32_t b = bucket_hash<W>(kx, kz) & mask;
+    int64_t pos = off[b] + (int64_t)atomicAdd((unsigned long long*)&fill[b], 1ull);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      st.x[w * st.cap + pos] = kx[w];
+      st.z[w * st.cap + pos] = kz[w];
+    }
+    st.c[pos] = c[i];
+  }
+}
+
+__global__ void k_load_finish(StoreDev st, int m, int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *st.m = m;
+    *st.total = n;
+    *st.top = n;
+    *st.err = 0;
+    st.stats[0] = 0;
+    st.stats[1] = 0;
+  }
+}
+
+int launch_store_load(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
+                      int64_t n, int64_t ld, int m, int64_t* scratch, hipStream_t s) {
+  const int64_t B = 1ll << m;
+  const uint32_t mask = (uint32_t)(B - 1);
+  int64_t* fill = scratch;                 // B
+  int64_t* scan_tmp = scratch + B;         // ceil(B/1024)+1
+  fill_i64(st.cnt, B, 0, s);
+  fill_i64(fill, B, 0, s);
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  if (n > 0) {
+    switch (W) {
+      case 1: hipLaunchKernelGGL(k_load_hist<1>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, st.cnt); break;
+      case 2: hipLaunchKernelGGL(k_load_hist<2>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, st.cnt); break;
+      case 3: hipLaunchKernelGGL(k_load_hist<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, st.cnt); break;
+      default: hipLaunchKernelGGL(k_load_hist<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, st.cnt); break;
+    }
+  }
+  launch_scan_i64(st.cnt, st.off, B, scan_tmp, s);
+  if (n > 0) {
+    switch (W) {
+      case 1: hipLaunchKernelGGL(k_load_scatter<1>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
+      case 2: hipLaunchKernelGGL(k_load_scatter<2>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
+      case 3: hipLaunchKernelGGL(k_load_scatter<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
+      default: hipLaunchKernelGGL(k_load_scatter<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
+    }
+  }
+  hipLaunchKernelGGL(k_load_finish, dim3(1), dim3(64), 0, s, st, m, n);
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Export: bucketed store -> flat rows grouped by bucket.
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void k_export(StoreDev st, int64_t B, const int64_t* dest_off, uint64_t* x,
+                         uint64_t* z, double* c, int64_t ld) {
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = st.cnt[b], src = st.off[b], dst = dest_off[b];
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        x[w * ld + dst + i] = st.x[w * st.cap + src + i];
+        z[w * ld + dst + i] = st.z[w * st.cap + src + i];
+      }
+      c[dst + i] = st.c[src + i];
+    }
+  }
+}
+
+void launch_store_export(int W, StoreDev st, int m, uint64_t* x, uint64_t* z, double* c,
+                         int64_t ld, int64_t* dest_off, int64_t* scratch, hipStream_t s) {
+  const int64_t B = 1ll << m;
+  launch_scan_i64(st.cnt, dest_off, B, scratch, s);
+  int64_t blocks = B < 8192 ? B : 8192;
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_export<1>, dim3(blocks), dim3(kBlock), 0, s, st, B, dest_off, x, z, c, ld); break;
+    case 2: hipLaunchKernelGGL(k_export<2>, dim3(blocks), dim3(kBlock), 0, s, st, B, dest_off, x, z, c, ld); break;
+    case 3: hipLaunchKernelGGL(k_export<3>, dim3(blocks), dim3(kBlock), 0, s, st, B, dest_off, x, z, c, ld); break;
+    default: hipLaunchKernelGGL(k_export<4>, dim3(blocks), dim3(kBlock), 0, s, st, B, dest_off, x, z, c, ld); break;
+  }
+}
+
+}  // namespace iqcc

@@ -134,6 +134,20 @@ def _get_bit(words, q):
     return out
 
 
+def _right_mul(M, op):
+    """M @ op for a stack of 2x2 matrices held as (m00, m01, m10, m11) arrays.
+
+    op is one of "Z" = diag(1, -1), "c" = a+ = |1><0|, "a" = a = |0><1|.
+    """
+    m00, m01, m10, m11 = M
+    if op == "Z":
+        return (m00, -m01, m10, -m11)
+    if op == "c":            # [[m00,m01],[m10,m11]] @ [[0,0],[1,0]] = [[m01,0],[m11,0]]
+        return (m01, np.zeros_like(m01), m11, np.zeros_like(m11))
+    # a: [[m00,m01],[m10,m11]] @ [[0,1],[0,0]] = [[0,m00],[0,m10]]
+    return (np.zeros_like(m00), m00, np.zeros_like(m10), m10)
+
+
 def jw_expand(modes: np.ndarray, creates: np.ndarray, coef: np.ndarray, n_qubits: int):
     """Expand products of ladder operators into (unsummed) Pauli strings.
 
@@ -141,38 +155,43 @@ def jw_expand(modes: np.ndarray, creates: np.ndarray, coef: np.ndarray, n_qubits
     creates : (k,) bool    True for a+ at that position
     coef    : (N,) complex
     Returns x, z (M, W) uint64 and complex coefficients (M,).
+
+    Each operator is Z on every lower qubit times a+ or a on its own qubit.  The
+    product is kept as a Z mask on the ordinary qubits plus one explicit 2x2
+    matrix per distinct mode ("slot"), multiplied left to right.
     """
     N, k = modes.shape
     W = n_words(n_qubits)
     zmask = np.zeros((N, W), dtype=np.uint64)
     slot_q = np.full((N, k), -1, dtype=np.int64)
-    slot_M = np.zeros((N, k, 2, 2), dtype=np.complex128)
+    one = np.ones(N, dtype=np.complex128)
+    zero = np.zeros(N, dtype=np.complex128)
+    slots = [[zero, zero, zero, zero] for _ in range(k)]
     for i in range(k):
         m = modes[:, i].astype(np.int64)
-        sig = _CRE if creates[i] else _ANN
+        op = "c" if creates[i] else "a"
         merged = np.zeros(N, dtype=bool)
         for j in range(i):
             qj = slot_q[:, j]
             valid = qj >= 0
             lt = valid & (qj < m)
             eq = valid & (qj == m)
-            if np.any(lt):
-                slot_M[lt, j] = slot_M[lt, j] @ _ZM
-            if np.any(eq):
-                slot_M[eq, j] = slot_M[eq, j] @ sig
+            Mz = _right_mul(slots[j], "Z")
+            Ms = _right_mul(slots[j], op)
+            slots[j] = [np.where(lt, Mz[t], np.where(eq, Ms[t], slots[j][t])) for t in range(4)]
             merged |= eq
         new = ~merged
-        if np.any(new):
-            zb = _get_bit(zmask, m)
-            init = np.where(zb[:, None, None], _ZM[None], _ID[None])
-            slot_M[new, i] = init[new] @ sig
-            slot_q[new, i] = m[new]
-            # clear the mask bit of the new special qubit (its Z's moved into the slot)
-            clr = new & zb
-            for w in range(W):
-                sel = clr & (m // 64 == w)
-                if np.any(sel):
-                    zmask[sel, w] ^= np.left_shift(np.uint64(1), (m[sel] % 64).astype(np.uint64))
+        zb = _get_bit(zmask, m)
+        # initial matrix of a new slot: Z if the mask already holds a Z there, else I
+        init = (one, zero, zero, np.where(zb, -one, one))
+        Mi = _right_mul(init, op)
+        slots[i] = [np.where(new, Mi[t], zero) for t in range(4)]
+        slot_q[:, i] = np.where(new, m, -1)
+        clr = new & zb
+        for w in range(W):
+            sel = clr & (m // 64 == w)
+            if np.any(sel):
+                zmask[sel, w] ^= np.left_shift(np.uint64(1), (m[sel] % 64).astype(np.uint64))
         # Z string on every qubit below m, except qubits that are slots (done above)
         _toggle_lt(zmask, m)
         for j in range(i + 1):
@@ -190,12 +209,12 @@ def jw_expand(modes: np.ndarray, creates: np.ndarray, coef: np.ndarray, n_qubits
     rows = [np.arange(N)]
     for j in range(k):
         q = slot_q[:, j]
-        M = slot_M[:, j]
+        m00, m01, m10, m11 = slots[j]
         comps = {
-            "I": (M[:, 0, 0] + M[:, 1, 1]) / 2,
-            "X": (M[:, 0, 1] + M[:, 1, 0]) / 2,
-            "Y": 1j * (M[:, 0, 1] - M[:, 1, 0]) / 2,
-            "Z": (M[:, 0, 0] - M[:, 1, 1]) / 2,
+            "I": (m00 + m11) / 2,
+            "X": (m01 + m10) / 2,
+            "Y": 1j * (m01 - m10) / 2,
+            "Z": (m00 - m11) / 2,
         }
         nx, nz, nc, nr = [], [], [], []
         for X, Z, C, R in zip(xs, zs, cs, rows):
@@ -210,8 +229,8 @@ def jw_expand(modes: np.ndarray, creates: np.ndarray, coef: np.ndarray, n_qubits
                 keep = a != 0
                 if not np.any(keep):
                     continue
-                X2 = X[keep].copy()
-                Z2 = Z[keep].copy()
+                X2 = X[keep]
+                Z2 = Z[keep]
                 qk = qr[keep]
                 if bx:
                     _set_bit(X2, qk, np.ones(len(qk), dtype=bool))
@@ -413,3 +432,46 @@ def single_qubit_pauli(n_qubits: int, text: str):
         if ch in "ZY":
             z[i // 64] |= b
     return x, z
+
+
+def unique_rows(x: np.ndarray, z: np.ndarray, c: np.ndarray):
+    """Distinct keys, keeping the first occurrence of each (stable)."""
+    W = x.shape[1]
+    keys = [z[:, w] for w in range(W)] + [x[:, w] for w in range(W)]
+    order = np.lexsort(keys)
+    xs, zs = x[order], z[order]
+    # a row is a duplicate when all of its words equal the previous row's words
+    same = np.ones(len(order) - 1, dtype=bool) if len(order) else np.zeros(0, bool)
+    for w in range(W):
+        same &= (xs[1:, w] == xs[:-1, w]) & (zs[1:, w] == zs[:-1, w])
+    keep_sorted = np.ones(len(order), dtype=bool)
+    keep_sorted[1:] = ~same
+    # among equal keys lexsort is stable, so the kept row is the earliest one
+    keep = np.sort(order[keep_sorted])
+    return x[keep], z[keep], c[keep]
+
+
+def hamiltonian_expanded(n_qubits: int, config: int, n_terms: int, band: int = 6,
+                         w_max: int = 8):
+    """A large Pauli sum with the structure of an iterated-dressing Hamiltonian.
+
+    Starts from the banded JW Hamiltonian and repeatedly adds, for a seeded
+    half of the current words K, the word K xor P_j of a DIS-form generator P_j
+    with coefficient c_K * u, u ~ U(-0.2, 0.2) (keys only; no phases or
+    rotations are evaluated).  Stops once at least n_terms distinct words exist
+    and keeps a seeded subset of exactly n_terms rows.  Used as the stand-in
+    Hamiltonian for batched DIS screening.
+    """
+    x, z, c = hamiltonian_banded(n_qubits, config, band=band)
+    rng = rng_for(config, PURPOSE_SUBSET)
+    gx, gz = dis_candidates(x, n_qubits, 64, w_max, rng_for(config, PURPOSE_ENTANGLERS))
+    j = 0
+    while len(c) < n_terms:
+        pick = rng.random(len(c)) < 0.5
+        nx = x[pick] ^ gx[j % len(gx)]
+        nz = z[pick] ^ gz[j % len(gz)]
+        nc = c[pick] * rng.uniform(-0.2, 0.2, size=int(pick.sum()))
+        x, z, c = unique_rows(np.concatenate([x, nx]), np.concatenate([z, nz]), np.concatenate([c, nc]))
+        j += 1
+    keep = np.sort(rng.permutation(len(c))[:n_terms])
+    return np.ascontiguousarray(x[keep]), np.ascontiguousarray(z[keep]), np.ascontiguousarray(c[keep])

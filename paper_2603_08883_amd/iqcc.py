@@ -1,0 +1,317 @@
+"""Python binding of libiqcc (argument marshalling only).
+
+Each function carries the name of the C entry point it wraps (include/iqcc.h)
+and forwards torch tensors as raw device pointers; every step of the
+computation runs in the HIP library.  There is no fallback: if libiqcc.so is
+missing or no GPU is present the calls raise.
+
+Tensor conventions: Pauli words are int64 tensors of shape (W, n) on the GPU
+(the bits of uint64 words, word-major planes, leading dimension n); real
+coefficients, angles and gradients are float64 tensors.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiqcc.so")
+
+IQCC_OK = 0
+IQCC_ERR_INVALID_ARG = -1
+IQCC_ERR_CAPACITY = -2
+IQCC_ERR_HIP = -3
+IQCC_ERR_UNSUPPORTED = -4
+IQCC_DIS_BATCHED = 0
+IQCC_DIS_PLAIN = 1
+
+_lib = None
+
+
+class IqccError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"iqcc error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libiqcc.so (built in-tree by paper_2603_08883_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2603_08883_amd.build`")
+    L = ct.CDLL(LIB_PATH)
+    P, i64, i32, d = ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double
+    sig = {
+        "iqcc_version": (ct.c_char_p, []),
+        "iqcc_last_error": (ct.c_char_p, [P]),
+        "iqcc_ctx_create": (i32, [ct.POINTER(P), i32]),
+        "iqcc_ctx_destroy": (i32, [P]),
+        "iqcc_set_param": (i32, [P, ct.c_char_p, i64]),
+        "iqcc_get_param": (i32, [P, ct.c_char_p, ct.POINTER(i64)]),
+        "iqcc_store_create": (i32, [P, i32, i64, ct.POINTER(P)]),
+        "iqcc_store_destroy": (i32, [P, P]),
+        "iqcc_store_shape": (i32, [P, ct.POINTER(i32), ct.POINTER(i32)]),
+        "iqcc_store_load": (i32, [P, P, P, P, P, i64, i64, P]),
+        "iqcc_store_count": (i32, [P, P, ct.POINTER(i64), P]),
+        "iqcc_store_export": (i32, [P, P, P, P, P, i64, i64, ct.POINTER(i64), P]),
+        "iqcc_store_stats": (i32, [P, P, ct.POINTER(i64), ct.POINTER(i64), P]),
+        "iqcc_dress": (i32, [P, P, P, P, d, d, P, P, P, P, P]),
+        "iqcc_dress_raw": (i32, [P, i32, P, P, P, i64, i64, P, P, d, P, P, P, P, i64, P]),
+        "iqcc_merge_truncate": (i32, [P, P, P, P, i64, i64, d, P, P]),
+        "iqcc_qmf_energy": (i32, [P, P, P, P, P, P]),
+        "iqcc_qmf_energy_backward": (i32, [P, P, P, P, P, P, P, P]),
+        "iqcc_dis_gradients": (i32, [P, P, P, P, P, P, i64, i64, i32, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return [
+        "iqcc_version", "iqcc_last_error", "iqcc_ctx_create", "iqcc_ctx_destroy",
+        "iqcc_set_param", "iqcc_get_param", "iqcc_store_create", "iqcc_store_destroy",
+        "iqcc_store_shape", "iqcc_store_load", "iqcc_store_count", "iqcc_store_export",
+        "iqcc_store_stats",
+        "iqcc_dress", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
+        "iqcc_qmf_energy_backward", "iqcc_dis_gradients",
+    ]
+
+
+def _check(rc, ctx):
+    if rc != IQCC_OK:
+        msg = lib().iqcc_last_error(ctx).decode() if ctx else ""
+        raise IqccError(rc, msg)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ct.c_void_p(int(stream))
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _words(a):
+    """uint64 numpy words of a host Pauli key (W,) for the entangler argument."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64).reshape(-1))
+    return a, a.ctypes.data_as(ct.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# one wrapper per C entry point
+# ---------------------------------------------------------------------------
+
+def iqcc_version():
+    return lib().iqcc_version().decode()
+
+
+def iqcc_ctx_create(device: int = 0):
+    h = ct.c_void_p()
+    rc = lib().iqcc_ctx_create(ct.byref(h), int(device))
+    if rc != IQCC_OK:
+        raise IqccError(rc, "iqcc_ctx_create failed (no usable HIP device?)")
+    return h
+
+
+def iqcc_ctx_destroy(ctx):
+    _check(lib().iqcc_ctx_destroy(ctx), None)
+
+
+def iqcc_set_param(ctx, name: str, value: int):
+    _check(lib().iqcc_set_param(ctx, name.encode(), int(value)), ctx)
+
+
+def iqcc_get_param(ctx, name: str) -> int:
+    v = ct.c_int64()
+    _check(lib().iqcc_get_param(ctx, name.encode(), ct.byref(v)), ctx)
+    return v.value
+
+
+def iqcc_store_create(ctx, n_qubits: int, max_terms: int):
+    h = ct.c_void_p()
+    _check(lib().iqcc_store_create(ctx, int(n_qubits), int(max_terms), ct.byref(h)), ctx)
+    return h
+
+
+def iqcc_store_destroy(ctx, store):
+    _check(lib().iqcc_store_destroy(ctx, store), ctx)
+
+
+def iqcc_store_shape(store):
+    nq, W = ct.c_int(), ct.c_int()
+    _check(lib().iqcc_store_shape(store, ct.byref(nq), ct.byref(W)), None)
+    return nq.value, W.value
+
+
+def iqcc_store_load(ctx, store, x, z, c, stream=None):
+    """x, z: int64 (W, n) device tensors; c: float64 (n,) device tensor."""
+    n = int(c.numel())
+    ld = int(x.shape[1]) if x.dim() == 2 else n
+    _check(lib().iqcc_store_load(ctx, store, _ptr(x), _ptr(z), _ptr(c), n, ld, _stream(stream)), ctx)
+
+
+def iqcc_store_count(ctx, store, stream=None) -> int:
+    n = ct.c_int64()
+    _check(lib().iqcc_store_count(ctx, store, ct.byref(n), _stream(stream)), ctx)
+    return n.value
+
+
+def iqcc_store_stats(ctx, store, stream=None):
+    """(anticommuting input terms, new output terms) of the step that produced store."""
+    a, b = ct.c_int64(), ct.c_int64()
+    _check(lib().iqcc_store_stats(ctx, store, ct.byref(a), ct.byref(b), _stream(stream)), ctx)
+    return a.value, b.value
+
+
+def iqcc_store_export(ctx, store, stream=None):
+    """Returns (x, z, c) device tensors with the live terms (grouped by bucket)."""
+    import torch
+    n = iqcc_store_count(ctx, store, stream)
+    _, W = iqcc_store_shape(store)
+    cap = max(n, 1)
+    x = torch.empty((W, cap), dtype=torch.int64, device="cuda")
+    z = torch.empty((W, cap), dtype=torch.int64, device="cuda")
+    c = torch.empty((cap,), dtype=torch.float64, device="cuda")
+    got = ct.c_int64()
+    _check(lib().iqcc_store_export(ctx, store, _ptr(x), _ptr(z), _ptr(c), cap, cap, ct.byref(got),
+                                   _stream(stream)), ctx)
+    return x[:, :got.value], z[:, :got.value], c[:got.value]
+
+
+def iqcc_dress(ctx, store_in, px, pz, tau: float, eps: float, store_out, theta=None, phi=None,
+               energy=None, stream=None):
+    """One fused dressing step (store_in -> store_out); px, pz host uint64 words."""
+    ax, pxp = _words(px)
+    az, pzp = _words(pz)
+    _check(lib().iqcc_dress(ctx, store_in, pxp, pzp, float(tau), float(eps), _ptr(theta),
+                            _ptr(phi), _ptr(energy), store_out, _stream(stream)), ctx)
+
+
+def iqcc_dress_raw(ctx, n_qubits, x, z, c, px, pz, tau, stream=None):
+    """Raw dressing of flat rows; returns (ox, oz, oc, flag) device tensors."""
+    import torch
+    n = int(c.numel())
+    W = int(x.shape[0])
+    ox = torch.empty((W, max(2 * n, 1)), dtype=torch.int64, device="cuda")
+    oz = torch.empty_like(ox)
+    oc = torch.empty((max(2 * n, 1),), dtype=torch.float64, device="cuda")
+    flag = torch.empty((max(n, 1),), dtype=torch.int8, device="cuda")
+    ax, pxp = _words(px)
+    az, pzp = _words(pz)
+    _check(lib().iqcc_dress_raw(ctx, int(n_qubits), _ptr(x), _ptr(z), _ptr(c), n, max(n, 1), pxp, pzp,
+                                float(tau), _ptr(ox), _ptr(oz), _ptr(oc), _ptr(flag), max(2 * n, 1),
+                                _stream(stream)), ctx)
+    return ox[:, :2 * n], oz[:, :2 * n], oc[:2 * n], flag[:n]
+
+
+def iqcc_merge_truncate(ctx, x, z, c, eps, store_out, stream=None):
+    n = int(c.numel())
+    _check(lib().iqcc_merge_truncate(ctx, _ptr(x), _ptr(z), _ptr(c), n, int(x.shape[1]), float(eps),
+                                     store_out, _stream(stream)), ctx)
+
+
+def iqcc_qmf_energy(ctx, store, theta, phi, energy=None, stream=None):
+    import torch
+    if energy is None:
+        energy = torch.empty((), dtype=torch.float64, device="cuda")
+    _check(lib().iqcc_qmf_energy(ctx, store, _ptr(theta), _ptr(phi), _ptr(energy), _stream(stream)), ctx)
+    return energy
+
+
+def iqcc_qmf_energy_backward(ctx, store, theta, phi, dE=None, stream=None):
+    import torch
+    dtheta = torch.empty_like(theta)
+    dphi = torch.empty_like(phi)
+    _check(lib().iqcc_qmf_energy_backward(ctx, store, _ptr(theta), _ptr(phi), _ptr(dE), _ptr(dtheta),
+                                          _ptr(dphi), _stream(stream)), ctx)
+    return dtheta, dphi
+
+
+def iqcc_dis_gradients(ctx, store, theta, phi, cx, cz, mode=IQCC_DIS_BATCHED, stream=None):
+    """cx, cz: int64 (W, n_cand) device tensors; returns g (n_cand,) float64."""
+    import torch
+    n_cand = int(cx.shape[1])
+    g = torch.empty((max(n_cand, 1),), dtype=torch.float64, device="cuda")
+    _check(lib().iqcc_dis_gradients(ctx, store, _ptr(theta), _ptr(phi), _ptr(cx), _ptr(cz), n_cand,
+                                    n_cand, int(mode), _ptr(g), _stream(stream)), ctx)
+    return g[:n_cand]
+
+
+# ---------------------------------------------------------------------------
+# conversions between row-major numpy keys (N, W) and device word planes
+# ---------------------------------------------------------------------------
+
+def to_device_words(a: np.ndarray):
+    """(N, W) uint64 numpy -> (W, N) int64 cuda tensor."""
+    import torch
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64).T).view(np.int64)
+    return torch.from_numpy(a.copy()).cuda()
+
+
+def from_device_words(t) -> np.ndarray:
+    """(W, N) int64 cuda tensor -> (N, W) uint64 numpy."""
+    a = t.detach().cpu().numpy().view(np.uint64)
+    return np.ascontiguousarray(a.T)
+
+
+class Context:
+    """Owning wrapper of an iqcc context."""
+
+    def __init__(self, device: int = 0):
+        self.handle = iqcc_ctx_create(device)
+
+    def close(self):
+        if self.handle is not None:
+            iqcc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Store:
+    """Owning wrapper of a device term store."""
+
+    def __init__(self, ctx: Context, n_qubits: int, max_terms: int):
+        self.ctx = ctx
+        self.n_qubits = n_qubits
+        self.handle = iqcc_store_create(ctx.handle, n_qubits, max_terms)
+
+    def load_numpy(self, x, z, c):
+        import torch
+        self._keep = (to_device_words(x), to_device_words(z),
+                      torch.from_numpy(np.ascontiguousarray(c, dtype=np.float64)).cuda())
+        iqcc_store_load(self.ctx.handle, self.handle, *self._keep)
+        return self
+
+    def count(self):
+        return iqcc_store_count(self.ctx.handle, self.handle)
+
+    def to_numpy(self):
+        x, z, c = iqcc_store_export(self.ctx.handle, self.handle)
+        return from_device_words(x), from_device_words(z), c.cpu().numpy()
+
+    def close(self):
+        if self.handle is not None and self.ctx.handle is not None:
+            iqcc_store_destroy(self.ctx.handle, self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,209 @@
+"""Parity of the HIP path (C ABI) with the FP64 oracle.
+
+Keys and coefficients of dressed Hamiltonians must match bit for bit (both
+sides round cos(tau)*c and sin(tau)*c once and add at most two contributions
+per key); energies and gradients within 1e-10 (absolute, Hartree units of the
+synthetic integrals) scaled by the 1-norm of the coefficients where stated.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2603_08883_amd import inputs as I
+from paper_2603_08883_amd import iqcc
+from tests.gpu_util import assert_same_terms, describe
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = iqcc.Context(0)
+    yield c
+    c.close()
+
+
+def _angles(nq, seed):
+    th, ph = I.qmf_angles(nq, np.random.default_rng(seed))
+    return th, ph, torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()
+
+
+def _chain_compare(ctx, nq, x, z, c, ents, taus, eps, th, ph, max_terms, compare_every=1,
+                   params=None):
+    params = params or {}
+    old = {k: iqcc.iqcc_get_param(ctx.handle, k) for k in params}
+    for k, v in params.items():
+        iqcc.iqcc_set_param(ctx.handle, k, v)
+    try:
+        a = iqcc.Store(ctx, nq, max_terms).load_numpy(x, z, c)
+        b = iqcc.Store(ctx, nq, max_terms)
+        tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
+        e = torch.zeros((), dtype=torch.float64, device="cuda")
+        ox, oz, oc = x, z, c
+        for j, ((px, pz), t) in enumerate(zip(ents, taus)):
+            describe(j, "dress", nq=nq, n=len(oc), tau=t, eps=eps, params=params)
+            iqcc.iqcc_dress(ctx.handle, a.handle, px, pz, t, eps, b.handle, tht, pht, e)
+            torch.cuda.synchronize()
+            ox, oz, oc = O.dress(nq, ox, oz, oc, px, pz, t, eps)
+            if j % compare_every == 0 or j == len(taus) - 1:
+                assert_same_terms(b.to_numpy(), (ox, oz, oc), f"step {j}")
+                Eo = O.qmf_energy(nq, ox, oz, oc, th, ph)
+                assert abs(float(e.item()) - Eo) <= E_TOL, (j, e.item(), Eo)
+            a, b = b, a
+        return a
+    finally:
+        for k, v in old.items():
+            iqcc.iqcc_set_param(ctx.handle, k, v)
+
+
+def test_store_roundtrip(ctx):
+    for nq, (x, z, c) in ((8, I.hamiltonian_dense(8, 0)), (40, I.hamiltonian_dense(40, 1))):
+        describe(0, "roundtrip", nq=nq, n=len(c))
+        s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+        assert s.count() == len(c)
+        assert_same_terms(s.to_numpy(), (x, z, c), "roundtrip")
+
+
+def test_dress_raw_matches_oracle(ctx):
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    px, pz = I.dis_candidates(x, nq, 1, 8, np.random.default_rng(3))
+    describe(0, "dress_raw", nq=nq, n=len(c))
+    ox, oz, oc, flag = iqcc.iqcc_dress_raw(ctx.handle, nq, iqcc.to_device_words(x), iqcc.to_device_words(z),
+                                           torch.from_numpy(c).cuda(), px[0], pz[0], -0.137)
+    gx, gz = iqcc.from_device_words(ox), iqcc.from_device_words(oz)
+    gc = oc.cpu().numpy(); fl = flag.cpu().numpy().astype(bool)
+    keep = np.ones(2 * len(c), bool)
+    keep[1::2] = fl
+    rx, rz, rc = O.dress_raw(nq, x, z, c, px[0], pz[0], -0.137)
+    assert np.array_equal(gx[keep], rx) and np.array_equal(gz[keep], rz)
+    assert np.array_equal(gc[keep], rc)
+    assert 0 < fl.sum() < len(c)
+
+
+def test_dress_c1(ctx):
+    nq = 8
+    x, z, c = I.hamiltonian_dense(8, 0)
+    px, pz = I.single_qubit_pauli(8, "XXXY")
+    th, ph = I.qmf_angles(nq, I.rng_for(0, I.PURPOSE_ANGLES))
+    _chain_compare(ctx, nq, x, z, c, [(px, pz)], [0.1], 0.0, th, ph, 4 * len(c))
+
+
+def test_chain_c2(ctx):
+    """40 qubits, 10 DIS entanglers, |c| < 1e-8 dropped after each step."""
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    cx, cz = I.dis_candidates(x, nq, 10, 8, I.rng_for(1, I.PURPOSE_ENTANGLERS))
+    taus = I.taus(10, I.rng_for(1, I.PURPOSE_TAUS))
+    th, ph = I.qmf_angles(nq, I.rng_for(1, I.PURPOSE_ANGLES))
+    _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), taus, 1e-8, th, ph, 2 * 10**7)
+
+
+def test_chain_two_words(ctx):
+    """124 qubits (two words per key), banded integrals with band 2, 6 steps."""
+    nq = 124
+    x, z, c = I.hamiltonian_banded(nq, 7, band=2)
+    cx, cz = I.dis_candidates(x, nq, 6, 8, np.random.default_rng(70))
+    taus = I.taus(6, np.random.default_rng(71))
+    th, ph = I.qmf_angles(nq, np.random.default_rng(72))
+    _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), taus, 1e-8, th, ph, 4 * 10**6)
+
+
+def test_chain_overflow_rounds(ctx):
+    """Tiny LDS capacity and large buckets force the hash-round path."""
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    cx, cz = I.dis_candidates(x, nq, 3, 8, np.random.default_rng(5))
+    th, ph = I.qmf_angles(nq, np.random.default_rng(6))
+    _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), [0.15, -0.12, 0.08], 1e-8, th, ph, 4 * 10**6,
+                   params={"anti_cap": 16, "load_bucket_terms": 4096, "split_bucket_terms": 10**6})
+
+
+def test_chain_split_every_step(ctx):
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    cx, cz = I.dis_candidates(x, nq, 4, 8, np.random.default_rng(8))
+    th, ph = I.qmf_angles(nq, np.random.default_rng(9))
+    _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), [0.1, 0.2, -0.1, 0.05], 0.0, th, ph, 4 * 10**6,
+                   params={"load_bucket_terms": 100000, "split_bucket_terms": 1})
+
+
+def test_edge_cases(ctx):
+    nq = 12
+    x, z, c = I.hamiltonian_dense(nq, 9)
+    th, ph = I.qmf_angles(nq, np.random.default_rng(1))
+    cx, cz = I.dis_candidates(x, nq, 1, 6, np.random.default_rng(2))
+    ident = (np.zeros(1, np.uint64), np.zeros(1, np.uint64))
+    # identity entangler: no-op
+    _chain_compare(ctx, nq, x, z, c, [ident], [0.3], 0.0, th, ph, 4 * len(c))
+    # tau = 0: values unchanged, new keys carry +-0
+    _chain_compare(ctx, nq, x, z, c, [(cx[0], cz[0])], [0.0], 0.0, th, ph, 4 * len(c))
+    # eps above every coefficient: everything is dropped
+    _chain_compare(ctx, nq, x, z, c, [(cx[0], cz[0])], [0.3], 1e9, th, ph, 4 * len(c))
+    # single term, and an empty Hamiltonian
+    _chain_compare(ctx, nq, x[:1], z[:1], c[:1], [(cx[0], cz[0])], [0.3], 0.0, th, ph, 16)
+    _chain_compare(ctx, nq, x[:0], z[:0], c[:0], [(cx[0], cz[0])], [0.3], 0.0, th, ph, 16)
+
+
+def test_invalid_arguments(ctx):
+    nq = 12
+    x, z, c = I.hamiltonian_dense(nq, 9)
+    a = iqcc.Store(ctx, nq, 4 * len(c)).load_numpy(x, z, c)
+    b = iqcc.Store(ctx, nq, 4 * len(c))
+    px = np.array([1 << 20], np.uint64)          # qubit 20 >= n_qubits
+    with pytest.raises(iqcc.IqccError) as ei:
+        iqcc.iqcc_dress(ctx.handle, a.handle, px, np.zeros(1, np.uint64), 0.1, 0.0, b.handle)
+    assert ei.value.code == iqcc.IQCC_ERR_INVALID_ARG
+    for tau, eps in ((float("nan"), 0.0), (0.1, -1.0), (float("inf"), 0.0)):
+        with pytest.raises(iqcc.IqccError):
+            iqcc.iqcc_dress(ctx.handle, a.handle, np.ones(1, np.uint64), np.zeros(1, np.uint64), tau, eps, b.handle)
+    with pytest.raises(iqcc.IqccError):
+        iqcc.iqcc_dress(ctx.handle, a.handle, np.ones(1, np.uint64), np.zeros(1, np.uint64), 0.1, 0.0, a.handle)
+    # arena too small: reported as a capacity error by the count call
+    small = iqcc.Store(ctx, nq, 8)
+    big = iqcc.Store(ctx, nq, 4 * len(c)).load_numpy(x, z, c)
+    with pytest.raises(iqcc.IqccError) as ei:
+        iqcc.iqcc_dress(ctx.handle, big.handle, np.ones(1, np.uint64), np.zeros(1, np.uint64), 0.1, 0.0, small.handle)
+    assert ei.value.code == iqcc.IQCC_ERR_CAPACITY
+
+
+def test_energy_matches_oracle(ctx):
+    for nq, (x, z, c), seed in ((40, I.hamiltonian_dense(40, 1), 3), (124, I.hamiltonian_banded(124, 7, band=2), 4)):
+        th, ph, tht, pht = _angles(nq, seed)
+        s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+        describe(0, "energy", nq=nq, n=len(c))
+        e = iqcc.iqcc_qmf_energy(ctx.handle, s.handle, tht, pht)
+        Eo = O.qmf_energy(nq, x, z, c, th, ph)
+        assert abs(e.item() - Eo) <= E_TOL, (e.item(), Eo)
+
+
+def test_energy_backward_matches_oracle(ctx):
+    for nq, (x, z, c), seed in ((40, I.hamiltonian_dense(40, 1), 13), (124, I.hamiltonian_banded(124, 7, band=2), 14)):
+        th, ph, tht, pht = _angles(nq, seed)
+        s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+        describe(0, "energy_backward", nq=nq, n=len(c))
+        dE = torch.tensor(1.5, dtype=torch.float64, device="cuda")
+        dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht, dE)
+        rt, rp = O.qmf_grad_angles(nq, x, z, c, th, ph)
+        assert np.abs(dt.cpu().numpy() - 1.5 * rt).max() <= E_TOL
+        assert np.abs(dp.cpu().numpy() - 1.5 * rp).max() <= E_TOL
+
+
+@pytest.mark.parametrize("mode", [iqcc.IQCC_DIS_BATCHED, iqcc.IQCC_DIS_PLAIN])
+def test_dis_gradients_match_oracle(ctx, mode):
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    th, ph, tht, pht = _angles(nq, 21)
+    cx, cz = I.dis_candidates(x, nq, 300, 12, I.rng_for(1, I.PURPOSE_CANDIDATES))
+    s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    describe(0, "dis", nq=nq, n=len(c), n_cand=300, mode=mode)
+    g = iqcc.iqcc_dis_gradients(ctx.handle, s.handle, tht, pht, iqcc.to_device_words(cx),
+                                iqcc.to_device_words(cz), mode).cpu().numpy()
+    ref = O.dis_gradients(nq, x, z, c, th, ph, cx, cz)
+    assert np.abs(g - ref).max() <= E_TOL
+    assert np.abs(ref).max() > 1e-6
