@@ -154,9 +154,45 @@ int iqcc_dress_raw(iqcc_ctx *ctx, int n_qubits, const uint64_t *x, const uint64_
 /* Merge of an arbitrary multiset of rows (D = H + I of App. D) followed by
  * compression: equal keys are summed in increasing row order (left to right),
  * then rows with |sum| < eps are dropped; the unique result replaces the
- * contents of `out`.  Synchronising (sizes the bucket table). */
+ * contents of `out` (which needs room for n rows).  x, z are device word planes
+ * with leading dimension ld >= n, c device coefficients.  Asynchronous; uses
+ * about (16*W + 24) * n bytes of context scratch. */
 int iqcc_merge_truncate(iqcc_ctx *ctx, const uint64_t *x, const uint64_t *z, const double *c,
                         int64_t n, int64_t ld, double eps, iqcc_store *out, void *stream);
+
+/* ---- reverse mode through the dressing chain (Eqs. 4 and 6) -------------- */
+
+/* Host value: rows of the store's arena (the length of per-row arrays such as
+ * tapes and cotangents indexed by arena row). */
+int iqcc_store_rows(const iqcc_store *store, int64_t *rows);
+
+/* iqcc_dress without energy that also records a tape for the backward pass:
+ * for every live row r of `in`, tape_self[r] = output row of its key (-1 if
+ * compression dropped it) and tape_partner[r] = output row of key ^ P for
+ * anticommuting rows (-1 if absent or dropped), -2 for commuting rows.  Both
+ * are DEVICE int64 arrays of iqcc_store_rows(in) entries (caller-owned); the
+ * tape stays valid while `in` and `out` are unchanged. */
+int iqcc_dress_taped(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px, const uint64_t *pz,
+                     double tau, double eps, iqcc_store *out, int64_t *tape_self,
+                     int64_t *tape_partner, void *stream);
+
+/* Backward of one taped dressing step with the compression decisions of the
+ * forward pass held fixed.  lambda_out: DEVICE cotangent dE/dc per row of
+ * `out` (iqcc_store_rows(out) entries, read at live rows only); lambda_in:
+ * DEVICE output per row of `in`; *dtau (DEVICE scalar) = dE/dtau of this step:
+ *   lambda_in[A] = cos(t) lambda_out[A] + s_A sin(t) lambda_out[A^P]  (anticommuting A)
+ *   lambda_in[A] = lambda_out[A]                                      (commuting A)
+ *   dtau = sum_A -sin(t) c_A lambda_out[A] + s_A cos(t) c_A lambda_out[A^P]. */
+int iqcc_dress_backward(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px,
+                        const uint64_t *pz, double tau, const int64_t *tape_self,
+                        const int64_t *tape_partner, const double *lambda_out,
+                        double *lambda_in, double *dtau, void *stream);
+
+/* out[r] = scale * <Omega| P_r |Omega> for every live row r of the store
+ * (DEVICE array of iqcc_store_rows entries; scale a DEVICE scalar or NULL = 1):
+ * the cotangent of the energy with respect to each coefficient. */
+int iqcc_expectations(iqcc_ctx *ctx, const iqcc_store *h, const double *theta, const double *phi,
+                      const double *scale, double *out, void *stream);
 
 /* ---- QMF energy and its gradient (Eq. 3) ---------------------------------- */
 

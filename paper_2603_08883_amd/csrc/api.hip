@@ -363,9 +363,10 @@ int iqcc_store_export(iqcc_ctx* ctx, const iqcc_store* st, uint64_t* x, uint64_t
 
 // ---- dressing ---------------------------------------------------------------
 
-int iqcc_dress(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
-               double tau, double eps, const double* theta, const double* phi, double* energy,
-               iqcc_store* out, void* stream) {
+static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
+                      double tau, double eps, const double* theta, const double* phi,
+                      double* energy, iqcc_store* out, int64_t* tape_self, int64_t* tape_partner,
+                      void* stream) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
   if (!in || !out || !px || !pz) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
@@ -402,6 +403,8 @@ int iqcc_dress(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const ui
   }
   cfg.lut = fused ? ctx->lut : nullptr;
   cfg.e_partial = ctx->partial;
+  cfg.tape_self = tape_self;
+  cfg.tape_partner = tape_partner;
   launch_zero_counters(out->d, s);
   launch_dress(W, in->d, out->d, P, cfg, s);
   LAUNCH_CHECK(ctx);
@@ -410,6 +413,61 @@ int iqcc_dress(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const ui
     launch_finalize_sum(ctx->partial, grid, nullptr, energy, s);
     LAUNCH_CHECK(ctx);
   }
+  return IQCC_OK;
+}
+
+int iqcc_dress(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
+               double tau, double eps, const double* theta, const double* phi, double* energy,
+               iqcc_store* out, void* stream) {
+  return dress_impl(ctx, in, px, pz, tau, eps, theta, phi, energy, out, nullptr, nullptr, stream);
+}
+
+int iqcc_store_rows(const iqcc_store* st, int64_t* rows) {
+  if (!st || !rows) return IQCC_ERR_INVALID_ARG;
+  *rows = st->d.cap;
+  return IQCC_OK;
+}
+
+int iqcc_dress_taped(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
+                     double tau, double eps, iqcc_store* out, int64_t* tape_self,
+                     int64_t* tape_partner, void* stream) {
+  if (ctx && (!tape_self || !tape_partner)) return fail(ctx, IQCC_ERR_INVALID_ARG, "tape arrays are null");
+  return dress_impl(ctx, in, px, pz, tau, eps, nullptr, nullptr, nullptr, out, tape_self,
+                    tape_partner, stream);
+}
+
+int iqcc_dress_backward(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px,
+                        const uint64_t* pz, double tau, const int64_t* tape_self,
+                        const int64_t* tape_partner, const double* lambda_out,
+                        double* lambda_in, double* dtau, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!in || !px || !pz || !tape_self || !tape_partner || !lambda_out || !lambda_in || !dtau)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  if (!std::isfinite(tau)) return fail(ctx, IQCC_ERR_INVALID_ARG, "tau is not finite");
+  if (!padding_clear(in->nq, in->W, px, pz))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
+  Entangler P = make_entangler(in->W, px, pz);
+  hipStream_t s = as_stream(stream);
+  const int grid = (int)(ctx->n_cu * 4);
+  rc = ensure_partial(ctx, grid);
+  if (rc) return rc;
+  launch_dress_backward(in->W, in->d, P, std::cos(tau), std::sin(tau), tape_self, tape_partner,
+                        lambda_out, lambda_in, ctx->partial, grid, s);
+  launch_finalize_sum(ctx->partial, grid, nullptr, dtau, s);
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+int iqcc_expectations(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, const double* phi,
+                      const double* scale, double* out, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h || !theta || !phi || !out) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  hipStream_t s = as_stream(stream);
+  launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
+  launch_expectations(h->W, h->d, ctx->lut, scale, out, (int)(ctx->n_cu * 4), s);
+  LAUNCH_CHECK(ctx);
   return IQCC_OK;
 }
 
@@ -437,8 +495,19 @@ int iqcc_merge_truncate(iqcc_ctx* ctx, const uint64_t* x, const uint64_t* z, con
                         int64_t n, int64_t ld, double eps, iqcc_store* out, void* stream) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
-  (void)x; (void)z; (void)c; (void)n; (void)ld; (void)eps; (void)out; (void)stream;
-  return fail(ctx, IQCC_ERR_UNSUPPORTED, "iqcc_merge_truncate is not available in this build");
+  if (!out) return fail(ctx, IQCC_ERR_INVALID_ARG, "output store is null");
+  if (n < 0 || ld < n || (n > 0 && (!x || !z || !c)))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad rows/pointers/leading dimension");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(ctx, IQCC_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  if (n > out->d.cap) return fail(ctx, IQCC_ERR_CAPACITY, "store holds at most %lld rows", (long long)out->d.cap);
+  int m = 0;
+  while (m < out->d.mcap && (n >> m) > 512) ++m;
+  rc = ensure_scratch(ctx, merge_scratch_len(out->W, n, m));
+  if (rc) return rc;
+  launch_merge_buckets(out->W, out->d, x, z, c, n, ld, m, eps, ctx->scratch, ctx->n_scratch,
+                       as_stream(stream));
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
 }
 
 // ---- energy -----------------------------------------------------------------

@@ -193,6 +193,8 @@ struct DressConfig {
   int grid;
   const double* lut;   // null: no fused energy
   double* e_partial;   // [grid]
+  int64_t* tape_self;     // null, or per input arena row: output row of K (-1 dropped)
+  int64_t* tape_partner;  //   and output row of K^P (-1 absent/dropped, -2 commuting)
 };
 void launch_dress(int W, const StoreDev& in, const StoreDev& out, const Entangler& P,
                   const DressConfig& cfg, hipStream_t s);
@@ -217,6 +219,13 @@ void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx
                 int grid, double* partial /*[grid_terms][n_cand]*/, int grid_terms,
                 double* g, hipStream_t s);
 
+void launch_dress_backward(int W, const StoreDev& in, const Entangler& P, double C, double S,
+                           const int64_t* tape_self, const int64_t* tape_partner,
+                           const double* lam_out, double* lam_in, double* partial, int grid,
+                           hipStream_t s);
+void launch_expectations(int W, const StoreDev& st, const double* lut, const double* scale,
+                         double* out, int grid, hipStream_t s);
+int64_t merge_scratch_len(int W, int64_t n, int m);
 void launch_merge_buckets(int W, StoreDev st, const uint64_t* x, const uint64_t* z,
                           const double* c, int64_t n, int64_t ld, int m, double eps,
                           int64_t* scratch, int64_t scratch_len, hipStream_t s);

@@ -41,6 +41,7 @@ size_t dress_lds_bytes(int W, int cap, bool energy) {
   o += (size_t)cap * 2;                          // partner
   o += ((size_t)cap + 7) & ~(size_t)7;           // side
   o += 8 * 8 + 8 * 8 + 8 * 8 + 256 * 4;          // scan, reduce, misc, round stack
+  o += (size_t)cap * 8 * 2;                      // tape: input row, own output row
   return o;
 }
 
@@ -57,6 +58,8 @@ struct Smem {
   double* red;
   int64_t* misc;
   int* stack;
+  int64_t* arow;   // tape: input row of each anticommuting entry
+  int64_t* orow;   // tape: output row of its own key (-1 if dropped)
   int cap, ts;
 };
 
@@ -76,7 +79,9 @@ __device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap) {
   s.scan = (uint64_t*)(smem + o); o += 64;
   s.red = (double*)(smem + o); o += 64;
   s.misc = (int64_t*)(smem + o); o += 64;
-  s.stack = (int*)(smem + o);
+  s.stack = (int*)(smem + o); o += 256 * 4;
+  s.arow = (int64_t*)(smem + o); o += (size_t)cap * 8;
+  s.orow = (int64_t*)(smem + o);
   s.cap = cap;
   return s;
 }
@@ -161,12 +166,13 @@ template <int W, bool ENERGY>
 __device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
                              const Smem<W>& sm, PairState& ps, int split, int m,
                              bool write_commuting, uint32_t mod, uint32_t rem, double eps,
-                             double& eacc) {
+                             int64_t* tape_self, int64_t* tape_partner, double& eacc) {
   const int tid = threadIdx.x;
   int64_t n_anti = 0;
   for (int64_t i0 = 0; i0 < ps.ntot; i0 += kChunk) {
     uint64_t kx[kItems][W], kz[kItems][W];
     double kc[kItems];
+    int64_t krow[kItems];
     int kside[kItems];
     bool valid[kItems];
 #pragma unroll
@@ -174,10 +180,8 @@ __device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Enta
       const int64_t idx = i0 + r * kBlock + tid;
       valid[r] = idx < ps.ntot;
       kside[r] = idx >= ps.n0;
-      if (valid[r]) {
-        const int64_t row = kside[r] ? ps.off1 + (idx - ps.n0) : ps.off0 + idx;
-        load_key<W>(in, row, kx[r], kz[r], kc[r]);
-      }
+      krow[r] = kside[r] ? ps.off1 + (idx - ps.n0) : ps.off0 + idx;
+      if (valid[r]) load_key<W>(in, krow[r], kx[r], kz[r], kc[r]);
     }
     int cat[kItems];
     uint64_t packed = 0;
@@ -187,10 +191,15 @@ __device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Enta
       if (!valid[r]) continue;
       if (anticommutes<W>(kx[r], kz[r], P.px, P.pz)) {
         if (mod == 1 || (round_hash(rep_hash<W>(P, kx[r], kz[r])) & (mod - 1)) == rem) cat[r] = 4;
-      } else if (write_commuting && !(fabs(kc[r]) < eps)) {
-        // commuting terms keep their coefficient; compression applies to them too
-        const int child = split ? (int)((bucket_hash<W>(kx[r], kz[r]) >> m) & 1u) : 0;
-        cat[r] = kside[r] * 2 + child;
+      } else if (write_commuting) {
+        if (!(fabs(kc[r]) < eps)) {
+          // commuting terms keep their coefficient; compression applies to them too
+          const int child = split ? (int)((bucket_hash<W>(kx[r], kz[r]) >> m) & 1u) : 0;
+          cat[r] = kside[r] * 2 + child;
+        } else if (tape_self) {
+          tape_self[krow[r]] = -1;
+          tape_partner[krow[r]] = -2;
+        }
       }
       if (cat[r] >= 0) packed += 1ull << (kFieldBits * cat[r]);
     }
@@ -211,9 +220,15 @@ __device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Enta
           }
           sm.ac[slot] = kc[r];
           sm.side[slot] = (uint8_t)kside[r];
+          sm.arow[slot] = krow[r];
         }
       } else {
-        store_key<W>(out, ps.row(cat[r], ps.cnt(cat[r]) + k), kx[r], kz[r], kc[r]);
+        const int64_t orow = ps.row(cat[r], ps.cnt(cat[r]) + k);
+        store_key<W>(out, orow, kx[r], kz[r], kc[r]);
+        if (tape_self) {
+          tape_self[krow[r]] = orow;
+          tape_partner[krow[r]] = -2;
+        }
         if (ENERGY) eacc += kc[r] * expect_lut<W>(sm.lut, kx[r], kz[r]);
       }
     }
@@ -228,7 +243,8 @@ __device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Enta
 template <int W, bool ENERGY>
 __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>& sm,
                           PairState& ps, int n, int split, int m, double C, double S,
-                          double eps, double& eacc) {
+                          double eps, int64_t* tape_self, int64_t* tape_partner,
+                          double& eacc) {
   const int tid = threadIdx.x;
   const uint32_t tmask = (uint32_t)sm.ts - 1;
   for (int i = tid; i < sm.ts; i += kBlock) sm.tab[i] = -1;
@@ -321,21 +337,37 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
     if (cat_new >= 0) packed += 1ull << (kFieldBits * cat_new);
     uint64_t total;
     uint64_t ex = block_exclusive_scan(packed, sm.scan, total);
+    int64_t own_row = -1, new_row = -1;
     if (cat_own >= 0) {
       const int64_t k = (int64_t)((ex >> (kFieldBits * cat_own)) & kFieldMask);
       ex += 1ull << (kFieldBits * cat_own);
-      store_key<W>(out, ps.row(cat_own, ps.cnt(cat_own) + k), kx, kz, v_own);
+      own_row = ps.row(cat_own, ps.cnt(cat_own) + k);
+      store_key<W>(out, own_row, kx, kz, v_own);
       if (ENERGY) eacc += v_own * expect_lut<W>(sm.lut, kx, kz);
     }
     if (cat_new >= 0) {
       atomicAdd((unsigned long long*)&sm.misc[3], 1ull);
       const int64_t k = (int64_t)((ex >> (kFieldBits * cat_new)) & kFieldMask);
-      store_key<W>(out, ps.row(cat_new, ps.cnt(cat_new) + k), qx, qz, v_new);
+      new_row = ps.row(cat_new, ps.cnt(cat_new) + k);
+      store_key<W>(out, new_row, qx, qz, v_new);
       if (ENERGY) eacc += v_new * expect_lut<W>(sm.lut, qx, qz);
+    }
+    if (tape_self && valid) {
+      sm.orow[i] = own_row;
+      tape_self[sm.arow[i]] = own_row;
+      if (sm.partner[i] < 0) tape_partner[sm.arow[i]] = new_row;
     }
     ps.add_packed(total, kFieldBits, kFieldMask);
   }
   __syncthreads();
+  if (tape_self) {
+    // the partner K^P of a paired entry is the other member's own output row
+    for (int i = tid; i < n; i += kBlock) {
+      const int j = sm.partner[i];
+      if (j >= 0) tape_partner[sm.arow[i]] = sm.orow[j];
+    }
+    __syncthreads();
+  }
 }
 
 template <int W, bool ENERGY>
@@ -401,11 +433,13 @@ __global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Ent
     ps.c00 = ps.c01 = ps.c10 = ps.c11 = 0;
     int64_t pair_anti = 0;
     if (!bad) {
-      const int64_t n_anti = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, true, 1u, 0u, cfg.eps, eacc);
+      const int64_t n_anti = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, true, 1u, 0u, cfg.eps,
+                                                    cfg.tape_self, cfg.tape_partner, eacc);
       pair_anti = n_anti;
       if (n_anti <= sm.cap) {
         __syncthreads();
-        emit_anti<W, ENERGY>(out, P, sm, ps, (int)n_anti, split, m, cfg.C, cfg.S, cfg.eps, eacc);
+        emit_anti<W, ENERGY>(out, P, sm, ps, (int)n_anti, split, m, cfg.C, cfg.S, cfg.eps,
+                             cfg.tape_self, cfg.tape_partner, eacc);
       } else {
         // more anticommuting terms than LDS holds: process them in residue
         // classes of a hash of the pair representative (both members of a
@@ -425,10 +459,12 @@ __global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Ent
           const uint32_t rem = (uint32_t)stk[2 * (sp - 1) + 1];
           __syncthreads();
           if (tid == 0) sm.misc[2] = sp - 1;
-          const int64_t nr = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, false, mod, rem, cfg.eps, eacc);
+          const int64_t nr = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, false, mod, rem, cfg.eps,
+                                                      cfg.tape_self, cfg.tape_partner, eacc);
           __syncthreads();
           if (nr <= sm.cap) {
-            emit_anti<W, ENERGY>(out, P, sm, ps, (int)nr, split, m, cfg.C, cfg.S, cfg.eps, eacc);
+            emit_anti<W, ENERGY>(out, P, sm, ps, (int)nr, split, m, cfg.C, cfg.S, cfg.eps,
+                               cfg.tape_self, cfg.tape_partner, eacc);
           } else if (tid == 0) {
             int t = (int)sm.misc[2];
             if (t + 2 <= 120 && mod < (1u << 30)) {

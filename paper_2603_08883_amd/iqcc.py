@@ -65,6 +65,10 @@ def lib():
         "iqcc_qmf_energy": (i32, [P, P, P, P, P, P]),
         "iqcc_qmf_energy_backward": (i32, [P, P, P, P, P, P, P, P]),
         "iqcc_dis_gradients": (i32, [P, P, P, P, P, P, i64, i64, i32, P, P]),
+        "iqcc_store_rows": (i32, [P, ct.POINTER(i64)]),
+        "iqcc_dress_taped": (i32, [P, P, P, P, d, d, P, P, P, P]),
+        "iqcc_dress_backward": (i32, [P, P, P, P, d, P, P, P, P, P, P]),
+        "iqcc_expectations": (i32, [P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -81,7 +85,8 @@ def exported_symbols():
         "iqcc_store_shape", "iqcc_store_load", "iqcc_store_count", "iqcc_store_export",
         "iqcc_store_stats",
         "iqcc_dress", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
-        "iqcc_qmf_energy_backward", "iqcc_dis_gradients",
+        "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
+        "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
     ]
 
 
@@ -246,6 +251,35 @@ def iqcc_dis_gradients(ctx, store, theta, phi, cx, cz, mode=IQCC_DIS_BATCHED, st
     _check(lib().iqcc_dis_gradients(ctx, store, _ptr(theta), _ptr(phi), _ptr(cx), _ptr(cz), n_cand,
                                     n_cand, int(mode), _ptr(g), _stream(stream)), ctx)
     return g[:n_cand]
+
+
+def iqcc_store_rows(store) -> int:
+    r = ct.c_int64()
+    _check(lib().iqcc_store_rows(store, ct.byref(r)), None)
+    return r.value
+
+
+def iqcc_dress_taped(ctx, store_in, px, pz, tau, eps, store_out, tape_self, tape_partner,
+                     stream=None):
+    ax, pxp = _words(px)
+    az, pzp = _words(pz)
+    _check(lib().iqcc_dress_taped(ctx, store_in, pxp, pzp, float(tau), float(eps), store_out,
+                                  _ptr(tape_self), _ptr(tape_partner), _stream(stream)), ctx)
+
+
+def iqcc_dress_backward(ctx, store_in, px, pz, tau, tape_self, tape_partner, lambda_out,
+                        lambda_in, dtau, stream=None):
+    ax, pxp = _words(px)
+    az, pzp = _words(pz)
+    _check(lib().iqcc_dress_backward(ctx, store_in, pxp, pzp, float(tau), _ptr(tape_self),
+                                     _ptr(tape_partner), _ptr(lambda_out), _ptr(lambda_in),
+                                     _ptr(dtau), _stream(stream)), ctx)
+
+
+def iqcc_expectations(ctx, store, theta, phi, out, scale=None, stream=None):
+    _check(lib().iqcc_expectations(ctx, store, _ptr(theta), _ptr(phi), _ptr(scale), _ptr(out),
+                                   _stream(stream)), ctx)
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -207,3 +207,31 @@ def test_dis_gradients_match_oracle(ctx, mode):
     ref = O.dis_gradients(nq, x, z, c, th, ph, cx, cz)
     assert np.abs(g - ref).max() <= E_TOL
     assert np.abs(ref).max() > 1e-6
+
+
+def test_merge_truncate_matches_oracle(ctx):
+    """General multiset merge: raw dressing rows, shuffled, plus heavy duplicates."""
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    px, pz = I.dis_candidates(x, nq, 1, 8, np.random.default_rng(31))
+    rx, rz, rc = O.dress_raw(nq, x, z, c, px[0], pz[0], 0.21)
+    rng = np.random.default_rng(32)
+    perm = rng.permutation(len(rc))
+    # 3000 copies of one key (a bucket far beyond the LDS tile) and a few triples
+    dup = np.concatenate([np.full(3000, 17), rng.integers(0, len(rc), 500)])
+    mx = np.concatenate([rx[perm], rx[dup]])
+    mz = np.concatenate([rz[perm], rz[dup]])
+    mc = np.concatenate([rc[perm], rng.normal(size=len(dup)) * 1e-3])
+    for eps in (0.0, 1e-8, 1e-3):
+        describe(0, "merge_truncate", nq=nq, n=len(mc), eps=eps)
+        s = iqcc.Store(ctx, nq, len(mc))
+        iqcc.iqcc_merge_truncate(ctx.handle, iqcc.to_device_words(mx), iqcc.to_device_words(mz),
+                                 torch.from_numpy(mc).cuda(), eps, s.handle)
+        assert_same_terms(s.to_numpy(), O.merge_truncate(mx, mz, mc, eps=eps), f"merge eps={eps}")
+    # the merged store is a valid dressing input
+    s2 = iqcc.Store(ctx, nq, 4 * len(mc))
+    th, ph, tht, pht = _angles(nq, 33)
+    e = torch.zeros((), dtype=torch.float64, device="cuda")
+    iqcc.iqcc_dress(ctx.handle, s.handle, px[0], pz[0], -0.3, 0.0, s2.handle, tht, pht, e)
+    ref = O.dress(nq, *O.merge_truncate(mx, mz, mc, eps=1e-3), px[0], pz[0], -0.3, 0.0)
+    assert_same_terms(s2.to_numpy(), ref, "dress after merge")
