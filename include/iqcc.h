@@ -57,6 +57,7 @@ extern "C" {
 
 typedef struct iqcc_ctx iqcc_ctx;
 typedef struct iqcc_store iqcc_store;
+typedef struct iqcc_batch iqcc_batch;
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -159,6 +160,29 @@ int iqcc_dress_raw(iqcc_ctx *ctx, int n_qubits, const uint64_t *x, const uint64_
  * about (16*W + 24) * n bytes of context scratch. */
 int iqcc_merge_truncate(iqcc_ctx *ctx, const uint64_t *x, const uint64_t *z, const double *c,
                         int64_t n, int64_t ld, double eps, iqcc_store *out, void *stream);
+
+/* ---- many Hamiltonians at once (one entangler each) --------------------- */
+
+/* Dress n_ham independent Hamiltonians, item i: outs[i] = compress_eps(dress(
+ * ins[i], P_i, taus[i])) with the same rules as iqcc_dress (no energy).  All
+ * stores share n_words; px, pz are HOST arrays [n_ham][n_words], taus HOST
+ * [n_ham].  One persistent launch takes (Hamiltonian, bucket pair) items from
+ * a device queue, the single-device analogue of over-partitioning with dynamic
+ * reassignment (App. C).  Outputs must be distinct from each other and from
+ * every input.  Synchronises the stream before returning. */
+int iqcc_dress_batched(iqcc_ctx *ctx, int n_ham, const iqcc_store *const *ins,
+                       iqcc_store *const *outs, const uint64_t *px, const uint64_t *pz,
+                       const double *taus, double eps, void *stream);
+
+/* The same batch captured once into a HIP graph (plan kernel + persistent
+ * kernel; every size is computed on the device, no memset nodes).
+ * iqcc_batch_launch replays it asynchronously on `stream`; the stores are
+ * referenced, not copied, so replays see their current contents. */
+int iqcc_batch_create(iqcc_ctx *ctx, int n_ham, const iqcc_store *const *ins,
+                      iqcc_store *const *outs, const uint64_t *px, const uint64_t *pz,
+                      const double *taus, double eps, iqcc_batch **batch);
+int iqcc_batch_launch(iqcc_ctx *ctx, iqcc_batch *batch, void *stream);
+int iqcc_batch_destroy(iqcc_ctx *ctx, iqcc_batch *batch);
 
 /* ---- reverse mode through the dressing chain (Eqs. 4 and 6) -------------- */
 

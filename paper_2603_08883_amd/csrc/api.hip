@@ -31,6 +31,17 @@ struct iqcc_ctx {
   int64_t n_scratch = 0;
 };
 
+struct iqcc_batch {
+  int n = 0, W = 0;
+  BatchItem* d_items = nullptr;
+  BatchPlan* d_plan = nullptr;
+  int64_t* d_queue = nullptr;
+  DressConfig cfg{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+};
+
 struct iqcc_store {
   int nq = 0, W = 0;
   int64_t max_terms = 0;
@@ -468,6 +479,123 @@ int iqcc_expectations(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, c
   launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
   launch_expectations(h->W, h->d, ctx->lut, scale, out, (int)(ctx->n_cu * 4), s);
   LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+static int batch_build(iqcc_ctx* ctx, int n_ham, const iqcc_store* const* ins,
+                       iqcc_store* const* outs, const uint64_t* px, const uint64_t* pz,
+                       const double* taus, double eps, iqcc_batch* b) {
+  if (n_ham < 1 || n_ham > (1 << 20) || !ins || !outs || !px || !pz || !taus)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad batch arguments");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(ctx, IQCC_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  const int W = ins[0] ? ins[0]->W : 0;
+  if (!W) return fail(ctx, IQCC_ERR_INVALID_ARG, "null store in batch");
+  BatchItem* h = new BatchItem[n_ham];
+  for (int i = 0; i < n_ham; ++i) {
+    const iqcc_store* a = ins[i];
+    const iqcc_store* o = outs[i];
+    if (!a || !o || a == o || a->nq != o->nq || a->W != W || !std::isfinite(taus[i]) ||
+        o->d.cap < a->d.cap || o->d.mcap < a->d.mcap ||
+        !padding_clear(a->nq, W, px + (size_t)i * W, pz + (size_t)i * W)) {
+      delete[] h;
+      return fail(ctx, IQCC_ERR_INVALID_ARG, "batch item %d is invalid", i);
+    }
+    h[i].in = a->d;
+    h[i].out = o->d;
+    h[i].P = make_entangler(W, px + (size_t)i * W, pz + (size_t)i * W);
+    h[i].C = std::cos(taus[i]);
+    h[i].S = std::sin(taus[i]);
+  }
+  for (int i = 0; i < n_ham; ++i)
+    for (int j = 0; j < n_ham; ++j)
+      if (i != j && (outs[i] == outs[j] || outs[i] == ins[j])) {
+        delete[] h;
+        return fail(ctx, IQCC_ERR_INVALID_ARG, "batch outputs alias (items %d, %d)", i, j);
+      }
+  b->n = n_ham;
+  b->W = W;
+  hipError_t e = hipMalloc(&b->d_items, sizeof(BatchItem) * n_ham);
+  if (e == hipSuccess) e = hipMalloc(&b->d_plan, sizeof(BatchPlan) * (n_ham + 1));
+  if (e == hipSuccess) e = hipMalloc(&b->d_queue, 64);
+  if (e == hipSuccess) e = hipMemcpy(b->d_items, h, sizeof(BatchItem) * n_ham, hipMemcpyHostToDevice);
+  delete[] h;
+  if (e != hipSuccess) return fail(ctx, IQCC_ERR_HIP, "batch allocation: %s", hipGetErrorString(e));
+  b->cfg = DressConfig{};
+  b->cfg.eps = eps;
+  b->cfg.split_thr = ctx->split_bucket_terms;
+  b->cfg.anti_cap = (int)ctx->anti_cap;
+  b->cfg.grid = grid_of(ctx);
+  if (dress_lds_bytes(W, b->cfg.anti_cap, false) > ctx->lds_per_block)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "anti_cap needs more LDS than a workgroup has");
+  set_dress_batch_attributes(W, b->cfg.anti_cap);
+  return IQCC_OK;
+}
+
+static void batch_free(iqcc_batch* b) {
+  if (!b) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  if (b->d_items) hipFree(b->d_items);
+  if (b->d_plan) hipFree(b->d_plan);
+  if (b->d_queue) hipFree(b->d_queue);
+  delete b;
+}
+
+int iqcc_dress_batched(iqcc_ctx* ctx, int n_ham, const iqcc_store* const* ins,
+                       iqcc_store* const* outs, const uint64_t* px, const uint64_t* pz,
+                       const double* taus, double eps, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  iqcc_batch* b = new iqcc_batch();
+  rc = batch_build(ctx, n_ham, ins, outs, px, pz, taus, eps, b);
+  if (rc) { batch_free(b); return rc; }
+  hipStream_t s = as_stream(stream);
+  launch_dress_batch(b->W, b->n, b->d_items, b->d_plan, b->cfg, b->d_queue, s);
+  hipError_t e = hipGetLastError();
+  hipStreamSynchronize(s);
+  batch_free(b);
+  if (e != hipSuccess) return fail(ctx, IQCC_ERR_HIP, "batched launch: %s", hipGetErrorString(e));
+  return IQCC_OK;
+}
+
+int iqcc_batch_create(iqcc_ctx* ctx, int n_ham, const iqcc_store* const* ins,
+                      iqcc_store* const* outs, const uint64_t* px, const uint64_t* pz,
+                      const double* taus, double eps, iqcc_batch** out) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!out) return fail(ctx, IQCC_ERR_INVALID_ARG, "null output");
+  *out = nullptr;
+  iqcc_batch* b = new iqcc_batch();
+  rc = batch_build(ctx, n_ham, ins, outs, px, pz, taus, eps, b);
+  if (rc) { batch_free(b); return rc; }
+  hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    launch_dress_batch(b->W, b->n, b->d_items, b->d_plan, b->cfg, b->d_queue, b->cap_stream);
+    e = hipStreamEndCapture(b->cap_stream, &b->graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return fail(ctx, IQCC_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return IQCC_OK;
+}
+
+int iqcc_batch_launch(iqcc_ctx* ctx, iqcc_batch* b, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!b || !b->exec) return fail(ctx, IQCC_ERR_INVALID_ARG, "null batch");
+  HIP_TRY(ctx, hipGraphLaunch(b->exec, as_stream(stream)));
+  return IQCC_OK;
+}
+
+int iqcc_batch_destroy(iqcc_ctx* ctx, iqcc_batch* b) {
+  if (ctx) hipSetDevice(ctx->device);
+  if (b) hipDeviceSynchronize();
+  batch_free(b);
   return IQCC_OK;
 }
 

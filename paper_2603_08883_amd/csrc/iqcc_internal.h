@@ -198,6 +198,23 @@ struct DressConfig {
 };
 void launch_dress(int W, const StoreDev& in, const StoreDev& out, const Entangler& P,
                   const DressConfig& cfg, hipStream_t s);
+
+// One Hamiltonian of a batched dressing launch.
+struct BatchItem {
+  StoreDev in, out;
+  Entangler P;
+  double C, S;
+};
+// Device-side sizing of one Hamiltonian's step (written by the plan kernel).
+struct BatchPlan {
+  int64_t item_start;   // first work item (bucket pair) of this Hamiltonian
+  int64_t npairs;
+  uint32_t f;
+  int m, split, thi;
+};
+void set_dress_batch_attributes(int W, int anti_cap);
+void launch_dress_batch(int W, int n_ham, const BatchItem* items, BatchPlan* plan,
+                        const DressConfig& cfg, int64_t* queue, hipStream_t s);
 size_t dress_lds_bytes(int W, int anti_cap, bool energy);
 void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double* c, int64_t n,
                       int64_t ld, const Entangler& P, double C, double S, uint64_t* ox,

@@ -370,6 +370,113 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
   }
 }
 
+// Everything one workgroup does for bucket pair `pi` of one dressing step.
+template <int W, bool ENERGY>
+__device__ void process_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
+                             const DressConfig& cfg, const Smem<W>& sm, int64_t pi, int m,
+                             int split, uint32_t f, int thi, double& eacc) {
+  const int tid = threadIdx.x;
+  PairState ps;
+  if (f) {
+    const uint32_t lo = (uint32_t)pi & ((1u << thi) - 1);
+    ps.b0 = (((uint32_t)pi >> thi) << (thi + 1)) | lo;
+    ps.b1 = ps.b0 ^ f;
+  } else {
+    ps.b0 = ps.b1 = (uint32_t)pi;
+  }
+  ps.self = (f == 0);
+  ps.n0 = in.cnt[ps.b0];
+  ps.off0 = in.off[ps.b0];
+  ps.n1 = ps.self ? 0 : in.cnt[ps.b1];
+  ps.off1 = ps.self ? 0 : in.off[ps.b1];
+  ps.ntot = ps.n0 + ps.n1;
+  ps.bound0 = ps.self ? 2 * ps.n0 : ps.n0 + ps.n1;
+  ps.bound1 = ps.self ? 0 : ps.n0 + ps.n1;
+  if (tid == 0) {
+    const int64_t need = ps.bound0 + ps.bound1;
+    const int64_t base = need ? (int64_t)atomicAdd((unsigned long long*)out.top, (unsigned long long)need) : 0;
+    const bool bad = base + need > out.cap;
+    if (bad) atomicOr(out.err, 1);
+    sm.misc[0] = base;
+    sm.misc[1] = bad;
+    sm.misc[3] = 0;
+  }
+  __syncthreads();
+  const int64_t base = sm.misc[0];
+  const bool bad = sm.misc[1] != 0;
+  __syncthreads();
+  ps.reg0 = base;
+  ps.reg1 = base + ps.bound0;
+  ps.c00 = ps.c01 = ps.c10 = ps.c11 = 0;
+  int64_t pair_anti = 0;
+  if (!bad) {
+    const int64_t n_anti = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, true, 1u, 0u, cfg.eps,
+                                                cfg.tape_self, cfg.tape_partner, eacc);
+    pair_anti = n_anti;
+    if (n_anti <= sm.cap) {
+      __syncthreads();
+      emit_anti<W, ENERGY>(out, P, sm, ps, (int)n_anti, split, m, cfg.C, cfg.S, cfg.eps,
+                           cfg.tape_self, cfg.tape_partner, eacc);
+    } else {
+      // more anticommuting terms than LDS holds: process them in residue
+      // classes of a hash of the pair representative (both members of a
+      // {K, K^P} pair always fall in the same class)
+      int* stk = sm.stack;  // pairs (mod, rem), written by thread 0
+      int r0 = 1;
+      while (r0 * (int64_t)sm.cap < 2 * n_anti && r0 < 32) r0 <<= 1;
+      if (tid == 0) {
+        for (int r = r0 - 1; r >= 0; --r) { stk[2 * (r0 - 1 - r)] = r0; stk[2 * (r0 - 1 - r) + 1] = r; }
+        sm.misc[2] = r0;
+      }
+      __syncthreads();
+      for (;;) {
+        const int sp = (int)sm.misc[2];
+        if (sp == 0) break;
+        const uint32_t mod = (uint32_t)stk[2 * (sp - 1)];
+        const uint32_t rem = (uint32_t)stk[2 * (sp - 1) + 1];
+        __syncthreads();
+        if (tid == 0) sm.misc[2] = sp - 1;
+        const int64_t nr = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, false, mod, rem, cfg.eps,
+                                                cfg.tape_self, cfg.tape_partner, eacc);
+        __syncthreads();
+        if (nr <= sm.cap) {
+          emit_anti<W, ENERGY>(out, P, sm, ps, (int)nr, split, m, cfg.C, cfg.S, cfg.eps,
+                               cfg.tape_self, cfg.tape_partner, eacc);
+        } else if (tid == 0) {
+          int t = (int)sm.misc[2];
+          if (t + 2 <= 120 && mod < (1u << 30)) {
+            stk[2 * t] = (int)(2 * mod); stk[2 * t + 1] = (int)(rem + mod);
+            stk[2 * t + 2] = (int)(2 * mod); stk[2 * t + 3] = (int)rem;
+            sm.misc[2] = t + 2;
+          } else {
+            atomicOr(out.err, 4);
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // bucket table of the output
+  if (tid == 0) {
+    int64_t produced = 0;
+    const int nside = ps.self ? 1 : 2;
+    for (int s = 0; s < nside; ++s) {
+      const uint32_t b = s ? ps.b1 : ps.b0;
+      for (int ch = 0; ch < 1 + split; ++ch) {
+        const uint32_t ob = b + ((uint32_t)ch << m);
+        const int64_t k = bad ? 0 : ps.cnt(2 * s + ch);
+        out.cnt[ob] = k;
+        out.off[ob] = ps.row(2 * s + ch, k - 1) - (ch ? 0 : k - 1);
+        produced += k;
+      }
+    }
+    if (produced) atomicAdd((unsigned long long*)out.total, (unsigned long long)produced);
+    if (pair_anti) atomicAdd((unsigned long long*)&out.stats[0], (unsigned long long)pair_anti);
+    if (sm.misc[3]) atomicAdd((unsigned long long*)&out.stats[1], (unsigned long long)sm.misc[3]);
+  }
+  __syncthreads();
+}
+
 template <int W, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Entangler P,
                                                   DressConfig cfg) {
@@ -398,110 +505,106 @@ __global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Ent
     __syncthreads();
   }
   double eacc = 0.0;
-  for (int64_t pi = blockIdx.x; pi < npairs; pi += gridDim.x) {
-    PairState ps;
-    if (f) {
-      const uint32_t lo = (uint32_t)pi & ((1u << thi) - 1);
-      ps.b0 = (((uint32_t)pi >> thi) << (thi + 1)) | lo;
-      ps.b1 = ps.b0 ^ f;
-    } else {
-      ps.b0 = ps.b1 = (uint32_t)pi;
-    }
-    ps.self = (f == 0);
-    ps.n0 = in.cnt[ps.b0];
-    ps.off0 = in.off[ps.b0];
-    ps.n1 = ps.self ? 0 : in.cnt[ps.b1];
-    ps.off1 = ps.self ? 0 : in.off[ps.b1];
-    ps.ntot = ps.n0 + ps.n1;
-    ps.bound0 = ps.self ? 2 * ps.n0 : ps.n0 + ps.n1;
-    ps.bound1 = ps.self ? 0 : ps.n0 + ps.n1;
-    if (tid == 0) {
-      const int64_t need = ps.bound0 + ps.bound1;
-      const int64_t base = need ? (int64_t)atomicAdd((unsigned long long*)out.top, (unsigned long long)need) : 0;
-      const bool bad = base + need > out.cap;
-      if (bad) atomicOr(out.err, 1);
-      sm.misc[0] = base;
-      sm.misc[1] = bad;
-      sm.misc[3] = 0;
-    }
-    __syncthreads();
-    const int64_t base = sm.misc[0];
-    const bool bad = sm.misc[1] != 0;
-    __syncthreads();
-    ps.reg0 = base;
-    ps.reg1 = base + ps.bound0;
-    ps.c00 = ps.c01 = ps.c10 = ps.c11 = 0;
-    int64_t pair_anti = 0;
-    if (!bad) {
-      const int64_t n_anti = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, true, 1u, 0u, cfg.eps,
-                                                    cfg.tape_self, cfg.tape_partner, eacc);
-      pair_anti = n_anti;
-      if (n_anti <= sm.cap) {
-        __syncthreads();
-        emit_anti<W, ENERGY>(out, P, sm, ps, (int)n_anti, split, m, cfg.C, cfg.S, cfg.eps,
-                             cfg.tape_self, cfg.tape_partner, eacc);
-      } else {
-        // more anticommuting terms than LDS holds: process them in residue
-        // classes of a hash of the pair representative (both members of a
-        // {K, K^P} pair always fall in the same class)
-        int* stk = sm.stack;  // pairs (mod, rem), written by thread 0
-        int r0 = 1;
-        while (r0 * (int64_t)sm.cap < 2 * n_anti && r0 < 32) r0 <<= 1;
-        if (tid == 0) {
-          for (int r = r0 - 1; r >= 0; --r) { stk[2 * (r0 - 1 - r)] = r0; stk[2 * (r0 - 1 - r) + 1] = r; }
-          sm.misc[2] = r0;
-        }
-        __syncthreads();
-        for (;;) {
-          const int sp = (int)sm.misc[2];
-          if (sp == 0) break;
-          const uint32_t mod = (uint32_t)stk[2 * (sp - 1)];
-          const uint32_t rem = (uint32_t)stk[2 * (sp - 1) + 1];
-          __syncthreads();
-          if (tid == 0) sm.misc[2] = sp - 1;
-          const int64_t nr = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, false, mod, rem, cfg.eps,
-                                                      cfg.tape_self, cfg.tape_partner, eacc);
-          __syncthreads();
-          if (nr <= sm.cap) {
-            emit_anti<W, ENERGY>(out, P, sm, ps, (int)nr, split, m, cfg.C, cfg.S, cfg.eps,
-                               cfg.tape_self, cfg.tape_partner, eacc);
-          } else if (tid == 0) {
-            int t = (int)sm.misc[2];
-            if (t + 2 <= 120 && mod < (1u << 30)) {
-              stk[2 * t] = (int)(2 * mod); stk[2 * t + 1] = (int)(rem + mod);
-              stk[2 * t + 2] = (int)(2 * mod); stk[2 * t + 3] = (int)rem;
-              sm.misc[2] = t + 2;
-            } else {
-              atomicOr(out.err, 4);
-            }
-          }
-          __syncthreads();
-        }
-      }
-    }
-    // bucket table of the output
-    if (tid == 0) {
-      int64_t produced = 0;
-      const int nside = ps.self ? 1 : 2;
-      for (int s = 0; s < nside; ++s) {
-        const uint32_t b = s ? ps.b1 : ps.b0;
-        for (int ch = 0; ch < 1 + split; ++ch) {
-          const uint32_t ob = b + ((uint32_t)ch << m);
-          const int64_t k = bad ? 0 : ps.cnt(2 * s + ch);
-          out.cnt[ob] = k;
-          out.off[ob] = ps.row(2 * s + ch, k - 1) - (ch ? 0 : k - 1);
-          produced += k;
-        }
-      }
-      if (produced) atomicAdd((unsigned long long*)out.total, (unsigned long long)produced);
-      if (pair_anti) atomicAdd((unsigned long long*)&out.stats[0], (unsigned long long)pair_anti);
-      if (sm.misc[3]) atomicAdd((unsigned long long*)&out.stats[1], (unsigned long long)sm.misc[3]);
-    }
-    __syncthreads();
-  }
+  for (int64_t pi = blockIdx.x; pi < npairs; pi += gridDim.x)
+    process_pair<W, ENERGY>(in, out, P, cfg, sm, pi, m, split, f, thi, eacc);
   if (ENERGY) {
     const double s = block_sum(eacc, sm.red);
     if (tid == 0) cfg.e_partial[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched dressing of many independent Hamiltonians (one entangler each) in
+// one persistent launch.  A plan kernel sizes every Hamiltonian's step on the
+// device (no host synchronisation, so the pair of launches can be captured in
+// a HIP graph); workgroups then take (Hamiltonian, bucket pair) items from an
+// atomic queue, so uneven sizes balance across the chip.
+// ---------------------------------------------------------------------------
+__global__ void k_batch_plan(int n_ham, const BatchItem* items, BatchPlan* plan,
+                             int64_t split_thr, int64_t* queue) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t start = 0;
+  for (int i = 0; i < n_ham; ++i) {
+    const BatchItem& it = items[i];
+    BatchPlan p{};
+    p.item_start = start;
+    *it.out.total = 0;
+    *it.out.top = 0;
+    *it.out.err = 0;
+    it.out.stats[0] = 0;
+    it.out.stats[1] = 0;
+    const int ierr = *it.in.err;
+    const int m = *it.in.m;
+    const int64_t n_in = *it.in.total;
+    const int split = (m < it.out.mcap) && (n_in > (split_thr << m)) ? 1 : 0;
+    if (ierr || m + split > it.out.mcap) {
+      *it.out.err = ierr ? ierr : 2;
+      p.npairs = 0;
+    } else {
+      const uint32_t f = it.P.hp & (uint32_t)((1ull << m) - 1);
+      p.m = m;
+      p.split = split;
+      p.f = f;
+      p.thi = f ? 31 - __clz(f) : 0;
+      p.npairs = f ? (1ll << (m - 1)) : (1ll << m);
+      *it.out.m = m + split;
+    }
+    start += p.npairs;
+    plan[i] = p;
+  }
+  plan[n_ham].item_start = start;
+  *queue = 0;
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_dress_batch(int n_ham, const BatchItem* items,
+                                                        const BatchPlan* plan, DressConfig cfg,
+                                                        int64_t* queue) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Smem<W> sm = carve<W, false>(smem, cfg.anti_cap);
+  const int64_t total = plan[n_ham].item_start;
+  double eacc = 0.0;
+  for (;;) {
+    if (threadIdx.x == 0) sm.misc[4] = (int64_t)atomicAdd((unsigned long long*)queue, 1ull);
+    __syncthreads();
+    const int64_t item = sm.misc[4];
+    __syncthreads();
+    if (item >= total) break;
+    int lo = 0, hi = n_ham - 1;   // last i with item_start <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (plan[mid].item_start <= item) lo = mid; else hi = mid - 1;
+    }
+    const BatchItem& it = items[lo];
+    const BatchPlan p = plan[lo];
+    DressConfig c = cfg;
+    c.C = it.C;
+    c.S = it.S;
+    process_pair<W, false>(it.in, it.out, it.P, c, sm, item - p.item_start, p.m, p.split, p.f, p.thi, eacc);
+  }
+}
+
+void set_dress_batch_attributes(int W, int anti_cap) {
+  const int lds = (int)dress_lds_bytes(W, anti_cap, false);
+  switch (W) {
+    case 1: hipFuncSetAttribute((const void*)k_dress_batch<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds); break;
+    case 2: hipFuncSetAttribute((const void*)k_dress_batch<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds); break;
+    case 3: hipFuncSetAttribute((const void*)k_dress_batch<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds); break;
+    default: hipFuncSetAttribute((const void*)k_dress_batch<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds); break;
+  }
+}
+
+// Launches only (no attribute calls), so the pair can be captured in a graph.
+void launch_dress_batch(int W, int n_ham, const BatchItem* items, BatchPlan* plan,
+                        const DressConfig& cfg, int64_t* queue, hipStream_t s) {
+  const size_t lds = dress_lds_bytes(W, cfg.anti_cap, false);
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(64), 0, s, n_ham, items, plan, cfg.split_thr, queue);
+  const BatchPlan* cp = plan;
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_dress_batch<1>, dim3(cfg.grid), dim3(kBlock), lds, s, n_ham, items, cp, cfg, queue); break;
+    case 2: hipLaunchKernelGGL(k_dress_batch<2>, dim3(cfg.grid), dim3(kBlock), lds, s, n_ham, items, cp, cfg, queue); break;
+    case 3: hipLaunchKernelGGL(k_dress_batch<3>, dim3(cfg.grid), dim3(kBlock), lds, s, n_ham, items, cp, cfg, queue); break;
+    default: hipLaunchKernelGGL(k_dress_batch<4>, dim3(cfg.grid), dim3(kBlock), lds, s, n_ham, items, cp, cfg, queue); break;
   }
 }
 

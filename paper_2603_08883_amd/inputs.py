@@ -451,6 +451,26 @@ def unique_rows(x: np.ndarray, z: np.ndarray, c: np.ndarray):
     return x[keep], z[keep], c[keep]
 
 
+def expand_to(x, z, c, n_terms, gx, gz, rng):
+    """Grow a Pauli sum to >= n_terms distinct words by XOR with generators.
+
+    For a seeded half of the current words K, adds K xor P_j with coefficient
+    c_K * u, u ~ U(-0.2, 0.2) (keys only; no phases or rotations), cycling
+    through the generators; then keeps a seeded subset of exactly n_terms rows
+    (also when the input is already larger).
+    """
+    j = 0
+    while len(c) < n_terms:
+        pick = rng.random(len(c)) < 0.5
+        nx = x[pick] ^ gx[j % len(gx)]
+        nz = z[pick] ^ gz[j % len(gz)]
+        nc = c[pick] * rng.uniform(-0.2, 0.2, size=int(pick.sum()))
+        x, z, c = unique_rows(np.concatenate([x, nx]), np.concatenate([z, nz]), np.concatenate([c, nc]))
+        j += 1
+    keep = np.sort(rng.permutation(len(c))[:n_terms])
+    return np.ascontiguousarray(x[keep]), np.ascontiguousarray(z[keep]), np.ascontiguousarray(c[keep])
+
+
 def hamiltonian_expanded(n_qubits: int, config: int, n_terms: int, band: int = 6,
                          w_max: int = 8):
     """A large Pauli sum with the structure of an iterated-dressing Hamiltonian.
@@ -465,13 +485,33 @@ def hamiltonian_expanded(n_qubits: int, config: int, n_terms: int, band: int = 6
     x, z, c = hamiltonian_banded(n_qubits, config, band=band)
     rng = rng_for(config, PURPOSE_SUBSET)
     gx, gz = dis_candidates(x, n_qubits, 64, w_max, rng_for(config, PURPOSE_ENTANGLERS))
-    j = 0
-    while len(c) < n_terms:
-        pick = rng.random(len(c)) < 0.5
-        nx = x[pick] ^ gx[j % len(gx)]
-        nz = z[pick] ^ gz[j % len(gz)]
-        nc = c[pick] * rng.uniform(-0.2, 0.2, size=int(pick.sum()))
-        x, z, c = unique_rows(np.concatenate([x, nx]), np.concatenate([z, nz]), np.concatenate([c, nc]))
-        j += 1
-    keep = np.sort(rng.permutation(len(c))[:n_terms])
-    return np.ascontiguousarray(x[keep]), np.ascontiguousarray(z[keep]), np.ascontiguousarray(c[keep])
+    return expand_to(x, z, c, n_terms, gx, gz, rng)
+
+
+def batch_hamiltonians(config: int, n_ham: int = 64, q_lo: int = 16, q_hi: int = 64,
+                       size_lo: float = 1e3, size_hi: float = 1e6, band: int = 2):
+    """Many independent Hamiltonians of uneven size for batched dressing.
+
+    n_i ~ U{q_lo, q_lo+2, ..., q_hi} qubits, target sizes s_i log-uniform in
+    [size_lo, size_hi]; each starts from the banded JW Hamiltonian on n_i/2
+    orbitals (one per distinct n_i) and is grown or subset to exactly s_i
+    distinct words by expand_to.  One DIS-form entangler (weight 2-8) and
+    tau ~ U(-0.2, 0.2) per Hamiltonian.  Returns a list of dicts.
+    """
+    rng = rng_for(config, PURPOSE_SUBSET)
+    qs = rng.integers(q_lo // 2, q_hi // 2 + 1, size=n_ham) * 2
+    sizes = np.exp(rng.uniform(np.log(size_lo), np.log(size_hi), size=n_ham)).astype(np.int64)
+    base = {}
+    out = []
+    for i in range(n_ham):
+        nq = int(qs[i])
+        if nq not in base:
+            bx, bz, bc = hamiltonian_banded(nq, config + nq, band=band)
+            gx, gz = dis_candidates(bx, nq, 16, 8, rng_for(config + nq, PURPOSE_ENTANGLERS))
+            base[nq] = (bx, bz, bc, gx, gz)
+        bx, bz, bc, gx, gz = base[nq]
+        x, z, c = expand_to(bx, bz, bc, int(sizes[i]), gx, gz, rng)
+        px, pz = dis_candidates(x, nq, 1, 8, rng)
+        out.append({"n_qubits": nq, "x": x, "z": z, "c": c, "px": px[0], "pz": pz[0],
+                    "tau": float(rng.uniform(-0.2, 0.2))})
+    return out

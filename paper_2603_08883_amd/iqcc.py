@@ -69,6 +69,10 @@ def lib():
         "iqcc_dress_taped": (i32, [P, P, P, P, d, d, P, P, P, P]),
         "iqcc_dress_backward": (i32, [P, P, P, P, d, P, P, P, P, P, P]),
         "iqcc_expectations": (i32, [P, P, P, P, P, P, P]),
+        "iqcc_dress_batched": (i32, [P, i32, P, P, P, P, P, d, P]),
+        "iqcc_batch_create": (i32, [P, i32, P, P, P, P, P, d, ct.POINTER(P)]),
+        "iqcc_batch_launch": (i32, [P, P, P]),
+        "iqcc_batch_destroy": (i32, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -87,6 +91,7 @@ def exported_symbols():
         "iqcc_dress", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
         "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
         "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
+        "iqcc_dress_batched", "iqcc_batch_create", "iqcc_batch_launch", "iqcc_batch_destroy",
     ]
 
 
@@ -280,6 +285,41 @@ def iqcc_expectations(ctx, store, theta, phi, out, scale=None, stream=None):
     _check(lib().iqcc_expectations(ctx, store, _ptr(theta), _ptr(phi), _ptr(scale), _ptr(out),
                                    _stream(stream)), ctx)
     return out
+
+
+def _batch_args(ins, outs, pxs, pzs, taus):
+    n = len(ins)
+    a_in = (ct.c_void_p * n)(*[s.value if hasattr(s, "value") else s for s in ins])
+    a_out = (ct.c_void_p * n)(*[s.value if hasattr(s, "value") else s for s in outs])
+    px = np.ascontiguousarray(np.asarray(pxs, dtype=np.uint64).reshape(n, -1))
+    pz = np.ascontiguousarray(np.asarray(pzs, dtype=np.uint64).reshape(n, -1))
+    tt = np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
+    return n, a_in, a_out, px, pz, tt
+
+
+def iqcc_dress_batched(ctx, ins, outs, pxs, pzs, taus, eps, stream=None):
+    """ins/outs: lists of store handles; pxs, pzs: (n, W) uint64; taus: (n,)."""
+    n, a_in, a_out, px, pz, tt = _batch_args(ins, outs, pxs, pzs, taus)
+    _check(lib().iqcc_dress_batched(ctx, n, a_in, a_out, px.ctypes.data_as(ct.c_void_p),
+                                    pz.ctypes.data_as(ct.c_void_p), tt.ctypes.data_as(ct.c_void_p),
+                                    float(eps), _stream(stream)), ctx)
+
+
+def iqcc_batch_create(ctx, ins, outs, pxs, pzs, taus, eps):
+    n, a_in, a_out, px, pz, tt = _batch_args(ins, outs, pxs, pzs, taus)
+    h = ct.c_void_p()
+    _check(lib().iqcc_batch_create(ctx, n, a_in, a_out, px.ctypes.data_as(ct.c_void_p),
+                                   pz.ctypes.data_as(ct.c_void_p), tt.ctypes.data_as(ct.c_void_p),
+                                   float(eps), ct.byref(h)), ctx)
+    return h
+
+
+def iqcc_batch_launch(ctx, batch, stream=None):
+    _check(lib().iqcc_batch_launch(ctx, batch, _stream(stream)), ctx)
+
+
+def iqcc_batch_destroy(ctx, batch):
+    _check(lib().iqcc_batch_destroy(ctx, batch), ctx)
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,90 @@
+"""Batched dressing of many uneven Hamiltonians: one persistent launch, and
+the same launch captured in a HIP graph and replayed."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2603_08883_amd import inputs as I
+from paper_2603_08883_amd import iqcc
+from tests.gpu_util import assert_same_terms, describe
+
+pytestmark = pytest.mark.gpu
+EPS = 1e-8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = iqcc.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def hams():
+    hs = I.batch_hamiltonians(41, n_ham=12, q_lo=16, q_hi=40, size_lo=1e3, size_hi=1e5)
+    # degenerate members: a single term and an empty Hamiltonian
+    one = dict(hs[0]); one.update(x=hs[0]["x"][:1], z=hs[0]["z"][:1], c=hs[0]["c"][:1])
+    empty = dict(hs[1]); empty.update(x=hs[1]["x"][:0], z=hs[1]["z"][:0], c=hs[1]["c"][:0])
+    return hs + [one, empty]
+
+
+def _stores(ctx, hs):
+    ins, outs = [], []
+    for h in hs:
+        cap = max(4 * len(h["c"]), 64)
+        ins.append(iqcc.Store(ctx, h["n_qubits"], cap).load_numpy(h["x"], h["z"], h["c"]))
+        outs.append(iqcc.Store(ctx, h["n_qubits"], cap))
+    return ins, outs
+
+
+def _refs(hs):
+    return [O.dress(h["n_qubits"], h["x"], h["z"], h["c"], h["px"], h["pz"], h["tau"], EPS) for h in hs]
+
+
+def _args(hs):
+    W = 1
+    pxs = np.array([np.asarray(h["px"], np.uint64).reshape(W) for h in hs])
+    pzs = np.array([np.asarray(h["pz"], np.uint64).reshape(W) for h in hs])
+    return pxs, pzs, [h["tau"] for h in hs]
+
+
+def test_batched_matches_oracle(ctx, hams):
+    ins, outs = _stores(ctx, hams)
+    pxs, pzs, taus = _args(hams)
+    describe(0, "dress_batched", n_ham=len(hams), terms=sum(len(h["c"]) for h in hams))
+    iqcc.iqcc_dress_batched(ctx.handle, [s.handle for s in ins], [s.handle for s in outs], pxs, pzs, taus, EPS)
+    for i, (o, r) in enumerate(zip(outs, _refs(hams))):
+        assert_same_terms(o.to_numpy(), r, f"item {i}")
+
+
+def test_batched_graph_replays(ctx, hams):
+    ins, outs = _stores(ctx, hams)
+    pxs, pzs, taus = _args(hams)
+    refs = _refs(hams)
+    describe(0, "batch graph", n_ham=len(hams))
+    b = iqcc.iqcc_batch_create(ctx.handle, [s.handle for s in ins], [s.handle for s in outs], pxs, pzs, taus, EPS)
+    try:
+        for rep in range(3):
+            describe(rep, "batch graph replay")
+            iqcc.iqcc_batch_launch(ctx.handle, b)
+            torch.cuda.synchronize()
+            for i, (o, r) in enumerate(zip(outs, refs)):
+                assert_same_terms(o.to_numpy(), r, f"replay {rep} item {i}")
+            # unrelated eager work between replays
+            t = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+            assert torch.isfinite(t.sum()).item()
+            torch.cuda.synchronize()
+    finally:
+        iqcc.iqcc_batch_destroy(ctx.handle, b)
+
+
+def test_batch_rejects_aliasing(ctx, hams):
+    ins, outs = _stores(ctx, hams[:2])
+    pxs, pzs, taus = _args(hams[:2])
+    with pytest.raises(iqcc.IqccError):
+        iqcc.iqcc_dress_batched(ctx.handle, [ins[0].handle, ins[1].handle], [outs[0].handle, outs[0].handle],
+                                pxs, pzs, taus, EPS)
+    with pytest.raises(iqcc.IqccError):
+        iqcc.iqcc_dress_batched(ctx.handle, [ins[0].handle, ins[1].handle], [outs[0].handle, ins[0].handle],
+                                pxs, pzs, taus, EPS)
