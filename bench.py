@@ -28,6 +28,7 @@ N_STEPS_CHAIN = 20
 EPS = 1e-8
 CONFIG = 2          # seed family of the 124-qubit workload
 DIS_CONFIG = 3      # seed family of the DIS workload
+BATCH_CONFIG = 4    # seed family of the 64-Hamiltonian batch
 
 
 def log(*a):
@@ -72,6 +73,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dis", action="store_true")
     ap.add_argument("--no-chain", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--dis-plain-sample", type=int, default=256)
     ap.add_argument("--max-terms", type=float, default=6e8)
     args = ap.parse_args()
@@ -233,6 +236,55 @@ def main():
         if "value" not in result:
             result.update({"value": cx.shape[0] / tb, "unit": "DIS grads/s", "ms_per_step": tb * 1e3,
                            "config": {"workload": result["dis"]["workload"]}})
+
+    if not args.no_batch:
+        t = time.perf_counter()
+        hs = I.batch_hamiltonians(BATCH_CONFIG)
+        log(f"batch workload: {len(hs)} Hamiltonians, {sum(len(h['c']) for h in hs)} terms, "
+            f"{time.perf_counter() - t:.1f}s")
+        ins = [iqcc.Store(ctx, h["n_qubits"], max(2 * len(h["c"]), 64)).load_numpy(h["x"], h["z"], h["c"])
+               for h in hs]
+        outs = [iqcc.Store(ctx, h["n_qubits"], max(2 * len(h["c"]), 64)) for h in hs]
+        pxs = np.array([np.asarray(h["px"], np.uint64).reshape(1) for h in hs])
+        pzs = np.array([np.asarray(h["pz"], np.uint64).reshape(1) for h in hs])
+        btaus = [h["tau"] for h in hs]
+        hin = [s.handle for s in ins]
+        hout = [s.handle for s in outs]
+        n_terms = sum(len(h["c"]) for h in hs)
+        tuned = None
+        if args.autotune:
+            from paper_2603_08883_amd import autotune
+            tuned = autotune.tune_batch(ctx, hin, hout, pxs, pzs, btaus, EPS, 1, n_terms)[0]
+
+        def plain():
+            for i in range(len(hs)):
+                iqcc.iqcc_dress(ctx.handle, hin[i], pxs[i], pzs[i], btaus[i], EPS, hout[i])
+
+        b = iqcc.iqcc_batch_create(ctx.handle, hin, hout, pxs, pzs, btaus, EPS)
+
+        def timed(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) * 1e-3 / reps
+
+        tp = timed(plain)
+        tg = timed(lambda: iqcc.iqcc_batch_launch(ctx.handle, b))
+        n_out = sum(o.count() for o in outs)
+        iqcc.iqcc_batch_destroy(ctx.handle, b)
+        result["batch"] = {
+            "workload": f"{len(hs)} Hamiltonians, 16-64 qubits, {n_terms} terms (log-uniform "
+                        "1e3-1e6 each), one entangler each, eps=1e-8",
+            "graph_ms": tg * 1e3, "plain_calls_ms": tp * 1e3, "speedup_graph_vs_plain": tp / tg,
+            "terms_per_s_graph": n_out / tg, "autotuned": tuned}
+        log(f"batch: graph {tg*1e3:.3f} ms vs {len(hs)} plain calls {tp*1e3:.3f} ms")
+        for s_ in ins + outs:
+            s_.close()
 
     ctx.close()
     print(json.dumps(result), flush=True)

@@ -406,7 +406,7 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
   cfg.anti_cap = (int)ctx->anti_cap;
   cfg.grid = grid;
   const bool fused = want_e && ctx->fuse_energy;
-  if (dress_lds_bytes(W, cfg.anti_cap, fused) > ctx->lds_per_block)
+  if (dress_lds_bytes(W, cfg.anti_cap, fused, tape_self != nullptr) > ctx->lds_per_block)
     return fail(ctx, IQCC_ERR_INVALID_ARG, "anti_cap %d needs more LDS than a workgroup has", cfg.anti_cap);
   if (want_e) {
     launch_build_lut(W, in->nq, theta, phi, ctx->lut, s);
@@ -525,7 +525,7 @@ static int batch_build(iqcc_ctx* ctx, int n_ham, const iqcc_store* const* ins,
   b->cfg.split_thr = ctx->split_bucket_terms;
   b->cfg.anti_cap = (int)ctx->anti_cap;
   b->cfg.grid = grid_of(ctx);
-  if (dress_lds_bytes(W, b->cfg.anti_cap, false) > ctx->lds_per_block)
+  if (dress_lds_bytes(W, b->cfg.anti_cap, false, false) > ctx->lds_per_block)
     return fail(ctx, IQCC_ERR_INVALID_ARG, "anti_cap needs more LDS than a workgroup has");
   set_dress_batch_attributes(W, b->cfg.anti_cap);
   return IQCC_OK;

@@ -215,7 +215,7 @@ struct BatchPlan {
 void set_dress_batch_attributes(int W, int anti_cap);
 void launch_dress_batch(int W, int n_ham, const BatchItem* items, BatchPlan* plan,
                         const DressConfig& cfg, int64_t* queue, hipStream_t s);
-size_t dress_lds_bytes(int W, int anti_cap, bool energy);
+size_t dress_lds_bytes(int W, int anti_cap, bool energy, bool tape);
 void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double* c, int64_t n,
                       int64_t ld, const Entangler& P, double C, double S, uint64_t* ox,
                       uint64_t* oz, double* oc, int8_t* flag, int64_t ld_out, hipStream_t s);

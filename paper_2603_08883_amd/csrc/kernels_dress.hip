@@ -33,7 +33,7 @@ __host__ __device__ inline int next_pow2_int(int v) {
   return p;
 }
 
-size_t dress_lds_bytes(int W, int cap, bool energy) {
+size_t dress_lds_bytes(int W, int cap, bool energy, bool tape) {
   size_t o = energy ? (size_t)W * kGroupsPerWord * kLutEntries * 8 : 0;
   o += (size_t)W * cap * 8 * 2;                  // keys
   o += (size_t)cap * 8;                          // coefficients
@@ -41,7 +41,7 @@ size_t dress_lds_bytes(int W, int cap, bool energy) {
   o += (size_t)cap * 2;                          // partner
   o += ((size_t)cap + 7) & ~(size_t)7;           // side
   o += 8 * 8 + 8 * 8 + 8 * 8 + 256 * 4;          // scan, reduce, misc, round stack
-  o += (size_t)cap * 8 * 2;                      // tape: input row, own output row
+  if (tape) o += (size_t)cap * 8 * 2;            // tape: input row, own output row
   return o;
 }
 
@@ -80,6 +80,7 @@ __device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap) {
   s.red = (double*)(smem + o); o += 64;
   s.misc = (int64_t*)(smem + o); o += 64;
   s.stack = (int*)(smem + o); o += 256 * 4;
+  // tape rows (only carved, and only touched, when the step records a tape)
   s.arow = (int64_t*)(smem + o); o += (size_t)cap * 8;
   s.orow = (int64_t*)(smem + o);
   s.cap = cap;
@@ -220,7 +221,7 @@ __device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Enta
           }
           sm.ac[slot] = kc[r];
           sm.side[slot] = (uint8_t)kside[r];
-          sm.arow[slot] = krow[r];
+          if (tape_self) sm.arow[slot] = krow[r];
         }
       } else {
         const int64_t orow = ps.row(cat[r], ps.cnt(cat[r]) + k);
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_dress_batch(int n_ham, const BatchIt
 }
 
 void set_dress_batch_attributes(int W, int anti_cap) {
-  const int lds = (int)dress_lds_bytes(W, anti_cap, false);
+  const int lds = (int)dress_lds_bytes(W, anti_cap, false, false);
   switch (W) {
     case 1: hipFuncSetAttribute((const void*)k_dress_batch<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds); break;
     case 2: hipFuncSetAttribute((const void*)k_dress_batch<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds); break;
@@ -597,7 +598,7 @@ void set_dress_batch_attributes(int W, int anti_cap) {
 // Launches only (no attribute calls), so the pair can be captured in a graph.
 void launch_dress_batch(int W, int n_ham, const BatchItem* items, BatchPlan* plan,
                         const DressConfig& cfg, int64_t* queue, hipStream_t s) {
-  const size_t lds = dress_lds_bytes(W, cfg.anti_cap, false);
+  const size_t lds = dress_lds_bytes(W, cfg.anti_cap, false, false);
   hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(64), 0, s, n_ham, items, plan, cfg.split_thr, queue);
   const BatchPlan* cp = plan;
   switch (W) {
@@ -611,7 +612,7 @@ void launch_dress_batch(int W, int n_ham, const BatchItem* items, BatchPlan* pla
 template <int W, bool E>
 static void launch_dress_t(const StoreDev& in, const StoreDev& out, const Entangler& P,
                            const DressConfig& cfg, hipStream_t s) {
-  const size_t lds = dress_lds_bytes(W, cfg.anti_cap, E);
+  const size_t lds = dress_lds_bytes(W, cfg.anti_cap, E, cfg.tape_self != nullptr);
   static bool attr_set[2] = {false, false};
   (void)attr_set;
   hipFuncSetAttribute((const void*)k_dress<W, E>, hipFuncAttributeMaxDynamicSharedMemorySize,
