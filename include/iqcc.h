@@ -115,6 +115,13 @@ int iqcc_store_count(iqcc_ctx *ctx, const iqcc_store *store, int64_t *n, void *s
 int iqcc_store_stats(iqcc_ctx *ctx, const iqcc_store *store, int64_t *n_anti, int64_t *n_new,
                      void *stream);
 
+/* Point lookup of n keys (DEVICE word planes qx, qz, leading dimension ld):
+ * found[i] = 1 and val[i] = coefficient if key i is in the store, else 0 and
+ * 0.0 (DEVICE int8 / double arrays).  One wave scans the key's bucket. */
+int iqcc_store_lookup(iqcc_ctx *ctx, const iqcc_store *store, const uint64_t *qx,
+                      const uint64_t *qz, int64_t n, int64_t ld, int8_t *found, double *val,
+                      void *stream);
+
 /* Synchronising: copy the live terms to device arrays x, z (planes, leading
  * dimension ld) and c with room for `cap` rows; *n receives the row count.
  * IQCC_ERR_CAPACITY (outputs untouched, *n set) if cap is too small. */

@@ -32,6 +32,8 @@
 // Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared (no -ffast-math).
 
 #include <algorithm>
+#include <map>
+#include <string>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -304,6 +306,107 @@ void oracle_qmf_grad_angles(int nq, int W, int64_t n, const uint64_t* x, const u
     }
   }
   for (int q = 0; q < nq; ++q) { dtheta[q] = at[q].value(); dphi[q] = ap[q].value(); }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Point query of the iterated dressing (Eq. 6 applied to one key at a time).
+//
+// The coefficient of key K after step j depends only on the coefficients of K
+// and K^P_j after step j-1 (Eq. 5: a commuting K keeps its value; an
+// anticommuting K receives cos(t) c[K] from itself and s sin(t) c[K^P] from its
+// partner), followed by the compression rule |c| < eps.  Evaluated
+// recursively with memoisation; H0 is given sorted in the canonical order.
+// Returns 1 and the value if K is present after the last step, else 0.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PointChain {
+  int nq, W, K;
+  int64_t n0;
+  const uint64_t *x0, *z0;
+  const double* c0;
+  const uint64_t *px, *pz;   // [K][W]
+  const double* taus;
+  double eps;
+  std::map<std::string, std::pair<int, double>> memo;
+
+  std::string key(int j, const uint64_t* x, const uint64_t* z) const {
+    std::string k((const char*)&j, sizeof j);
+    k.append((const char*)x, 8 * W);
+    k.append((const char*)z, 8 * W);
+    return k;
+  }
+
+  int lookup0(const uint64_t* x, const uint64_t* z, double* v) const {
+    int64_t lo = 0, hi = n0;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) / 2;
+      if (key_less(W, x0 + mid * W, z0 + mid * W, x, z)) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < n0 && key_eq(W, x0 + lo * W, z0 + lo * W, x, z)) {
+      *v = c0[lo];
+      return 1;
+    }
+    return 0;
+  }
+
+  // present after step j (j = 0: H0)?
+  int value(int j, const uint64_t* x, const uint64_t* z, double* v) {
+    if (j == 0) return lookup0(x, z, v);
+    std::string k = key(j, x, z);
+    auto it = memo.find(k);
+    if (it != memo.end()) {
+      *v = it->second.second;
+      return it->second.first;
+    }
+    const uint64_t* ex = px + (size_t)(j - 1) * W;
+    const uint64_t* ez = pz + (size_t)(j - 1) * W;
+    std::vector<uint64_t> qx(W), qz(W);
+    int e = product(nq, W, ex, ez, x, z, qx.data(), qz.data());   // P * K
+    double a = 0.0;
+    int have = value(j - 1, x, z, &a);
+    double out = 0.0;
+    int present = 0;
+    if ((e & 1) == 0) {
+      present = have;
+      out = a;
+    } else {
+      const double C = std::cos(taus[j - 1]), S = std::sin(taus[j - 1]);
+      double b = 0.0;
+      int have_p = value(j - 1, qx.data(), qz.data(), &b);
+      std::vector<uint64_t> rx(W), rz(W);
+      int ep = product(nq, W, ex, ez, qx.data(), qz.data(), rx.data(), rz.data());  // P * (K^P)
+      double from_p = (ep == 3 ? 1.0 : -1.0) * (S * b);
+      if (have && have_p) { out = C * a + from_p; present = 1; }
+      else if (have) { out = C * a; present = 1; }
+      else if (have_p) { out = from_p; present = 1; }
+    }
+    if (present && std::fabs(out) < eps) present = 0;
+    memo[k] = {present, out};
+    *v = out;
+    return present;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+// H0 sorted canonically (row-major x0/z0 [n0][W]); entanglers px/pz [K][W].
+// For each of n_q query keys: found[i] = present after all K steps, val[i].
+void oracle_chain_point(int nq, int W, int64_t n0, const uint64_t* x0, const uint64_t* z0,
+                        const double* c0, int K, const uint64_t* px, const uint64_t* pz,
+                        const double* taus, double eps, int64_t n_q, const uint64_t* qx,
+                        const uint64_t* qz, int8_t* found, double* val) {
+  PointChain pc{nq, W, K, n0, x0, z0, c0, px, pz, taus, eps, {}};
+  for (int64_t i = 0; i < n_q; ++i) {
+    double v = 0.0;
+    found[i] = (int8_t)pc.value(K, qx + i * W, qz + i * W, &v);
+    val[i] = v;
+  }
 }
 
 }  // extern "C"

@@ -57,6 +57,9 @@ def lib():
         L.oracle_expectations.argtypes = [ct.c_int, ct.c_int, i64, P, P, P, P, P]
         L.oracle_dis_gradients.restype = None
         L.oracle_dis_gradients.argtypes = [ct.c_int, ct.c_int, i64, P, P, P, P, P, i64, P, P, P]
+        L.oracle_chain_point.restype = None
+        L.oracle_chain_point.argtypes = [ct.c_int, ct.c_int, i64, P, P, P, ct.c_int, P, P, P,
+                                         ct.c_double, i64, P, P, P, P]
         L.oracle_qmf_grad_angles.restype = None
         L.oracle_qmf_grad_angles.argtypes = [ct.c_int, ct.c_int, i64, P, P, P, P, P, P, P]
         _lib = L
@@ -197,3 +200,23 @@ def canonical(x, z, c):
     keys = [z[:, w] for w in range(W)] + [x[:, w] for w in range(W)]
     o = np.lexsort(keys)
     return x[o], z[o], c[o]
+
+
+def chain_point(nq, x0, z0, c0, ents, taus, eps, qx, qz):
+    """Coefficient of each query key after the whole chain, one key at a time.
+
+    Returns (found: bool array, value: float array).  H0 need not be sorted.
+    """
+    x0, z0, c0 = canonical(x0, z0, c0)
+    W = x0.shape[1]
+    K = len(ents)
+    px = np.ascontiguousarray(np.array([np.asarray(p, np.uint64).reshape(W) for p, _ in ents]), np.uint64)
+    pz = np.ascontiguousarray(np.array([np.asarray(q, np.uint64).reshape(W) for _, q in ents]), np.uint64)
+    tt = np.ascontiguousarray(taus, np.float64)
+    qx = np.ascontiguousarray(qx, np.uint64).reshape(-1, W)
+    qz = np.ascontiguousarray(qz, np.uint64).reshape(-1, W)
+    found = np.zeros(qx.shape[0], np.int8)
+    val = np.zeros(qx.shape[0], np.float64)
+    lib().oracle_chain_point(nq, W, x0.shape[0], _p(x0), _p(z0), _p(c0), K, _p(px), _p(pz), _p(tt),
+                             float(eps), qx.shape[0], _p(qx), _p(qz), _p(found), _p(val))
+    return found.astype(bool), val

@@ -344,6 +344,17 @@ int iqcc_store_stats(iqcc_ctx* ctx, const iqcc_store* st, int64_t* n_anti, int64
   return IQCC_OK;
 }
 
+int iqcc_store_lookup(iqcc_ctx* ctx, const iqcc_store* st, const uint64_t* qx, const uint64_t* qz,
+                      int64_t n, int64_t ld, int8_t* found, double* val, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!st || n < 0 || ld < n || (n > 0 && (!qx || !qz || !found || !val)))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad lookup arguments");
+  launch_lookup(st->W, st->d, qx, qz, n, ld, found, val, as_stream(stream));
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
 int iqcc_store_export(iqcc_ctx* ctx, const iqcc_store* st, uint64_t* x, uint64_t* z, double* c,
                       int64_t cap, int64_t ld, int64_t* n, void* stream) {
   int rc = check_ctx(ctx);

@@ -216,4 +216,55 @@ void launch_store_export(int W, StoreDev st, int m, uint64_t* x, uint64_t* z, do
   }
 }
 
+// ---------------------------------------------------------------------------
+// Lookup: for each query key, scan its bucket (one wave per query).
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void k_lookup(StoreDev st, const uint64_t* qx, const uint64_t* qz, int64_t nq_,
+                         int64_t ld, int8_t* found, double* val) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const uint32_t mask = (uint32_t)((1ull << *st.m) - 1);
+  for (int64_t q = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); q < nq_; q += waves) {
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      kx[w] = qx[w * ld + q];
+      kz[w] = qz[w * ld + q];
+    }
+    const uint32_t b = bucket_hash<W>(kx, kz) & mask;
+    const int64_t n = st.cnt[b], off = st.off[b];
+    int64_t hit = -1;
+    for (int64_t i0 = 0; i0 < n; i0 += 64) {
+      const int64_t i = i0 + lane;
+      bool eq = i < n;
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        eq = eq && st.x[w * st.cap + off + i] == kx[w] && st.z[w * st.cap + off + i] == kz[w];
+      const uint64_t ball = __ballot(eq);
+      if (ball) {
+        hit = off + i0 + __ffsll((unsigned long long)ball) - 1;
+        break;
+      }
+    }
+    if (lane == 0) {
+      found[q] = hit >= 0 ? 1 : 0;
+      val[q] = hit >= 0 ? st.c[hit] : 0.0;
+    }
+  }
+}
+
+void launch_lookup(int W, const StoreDev& st, const uint64_t* qx, const uint64_t* qz, int64_t n,
+                   int64_t ld, int8_t* found, double* val, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + kWaves - 1) / kWaves;
+  if (blocks > 8192) blocks = 8192;
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_lookup<1>, dim3(blocks), dim3(kBlock), 0, s, st, qx, qz, n, ld, found, val); break;
+    case 2: hipLaunchKernelGGL(k_lookup<2>, dim3(blocks), dim3(kBlock), 0, s, st, qx, qz, n, ld, found, val); break;
+    case 3: hipLaunchKernelGGL(k_lookup<3>, dim3(blocks), dim3(kBlock), 0, s, st, qx, qz, n, ld, found, val); break;
+    default: hipLaunchKernelGGL(k_lookup<4>, dim3(blocks), dim3(kBlock), 0, s, st, qx, qz, n, ld, found, val); break;
+  }
+}
+
 }  // namespace iqcc

@@ -59,6 +59,7 @@ def lib():
         "iqcc_store_count": (i32, [P, P, ct.POINTER(i64), P]),
         "iqcc_store_export": (i32, [P, P, P, P, P, i64, i64, ct.POINTER(i64), P]),
         "iqcc_store_stats": (i32, [P, P, ct.POINTER(i64), ct.POINTER(i64), P]),
+        "iqcc_store_lookup": (i32, [P, P, P, P, i64, i64, P, P, P]),
         "iqcc_dress": (i32, [P, P, P, P, d, d, P, P, P, P, P]),
         "iqcc_dress_raw": (i32, [P, i32, P, P, P, i64, i64, P, P, d, P, P, P, P, i64, P]),
         "iqcc_merge_truncate": (i32, [P, P, P, P, i64, i64, d, P, P]),
@@ -87,7 +88,7 @@ def exported_symbols():
         "iqcc_version", "iqcc_last_error", "iqcc_ctx_create", "iqcc_ctx_destroy",
         "iqcc_set_param", "iqcc_get_param", "iqcc_store_create", "iqcc_store_destroy",
         "iqcc_store_shape", "iqcc_store_load", "iqcc_store_count", "iqcc_store_export",
-        "iqcc_store_stats",
+        "iqcc_store_stats", "iqcc_store_lookup",
         "iqcc_dress", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
         "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
         "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
@@ -182,6 +183,17 @@ def iqcc_store_stats(ctx, store, stream=None):
     a, b = ct.c_int64(), ct.c_int64()
     _check(lib().iqcc_store_stats(ctx, store, ct.byref(a), ct.byref(b), _stream(stream)), ctx)
     return a.value, b.value
+
+
+def iqcc_store_lookup(ctx, store, qx, qz, stream=None):
+    """qx, qz: int64 (W, n) device tensors -> (found bool, value float64) device tensors."""
+    import torch
+    n = int(qx.shape[1])
+    found = torch.empty((max(n, 1),), dtype=torch.int8, device="cuda")
+    val = torch.empty((max(n, 1),), dtype=torch.float64, device="cuda")
+    _check(lib().iqcc_store_lookup(ctx, store, _ptr(qx), _ptr(qz), n, max(n, 1), _ptr(found), _ptr(val),
+                                   _stream(stream)), ctx)
+    return found[:n].bool(), val[:n]
 
 
 def iqcc_store_export(ctx, store, stream=None):

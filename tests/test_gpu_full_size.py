@@ -1,0 +1,85 @@
+"""Parity at the full 124-qubit workload, in the launch configuration bench.py
+times (default knobs, fused energy, ping-pong stores).
+
+* The first 6 steps are compared with the oracle's full chain term by term
+  (bit-exact) and energy by energy (1e-10).
+* After all 20 steps (~1.5e8 terms) 4000 sampled output terms are recomputed
+  one by one by the oracle's point query of the chain (bit-exact), and keys
+  K ^ P_j around them are checked both ways (present/absent and value) through
+  the device lookup.
+* The energy fused into every dressing step equals the stand-alone energy
+  kernel on that step's output (property that holds at any size).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2603_08883_amd import inputs as I
+from paper_2603_08883_amd import iqcc
+from tests.gpu_util import assert_same_terms, describe
+
+pytestmark = pytest.mark.gpu
+
+NQ, STEPS, EPS, CONFIG = 124, 20, 1e-8, 2
+PREFIX = 6
+
+
+@pytest.fixture(scope="module")
+def workload():
+    x, z, c = I.hamiltonian_banded(NQ, CONFIG, band=6, decay=3.0)
+    cx, cz = I.dis_candidates(x, NQ, STEPS, 8, I.rng_for(CONFIG, I.PURPOSE_ENTANGLERS))
+    taus = I.taus(STEPS, I.rng_for(CONFIG, I.PURPOSE_TAUS))
+    th, ph = I.qmf_angles(NQ, I.rng_for(CONFIG, I.PURPOSE_ANGLES))
+    return x, z, c, list(zip(cx, cz)), taus, th, ph
+
+
+def test_full_size_chain(workload):
+    x, z, c, ents, taus, th, ph = workload
+    ctx = iqcc.Context(0)
+    h0 = iqcc.Store(ctx, NQ, 2 * len(c)).load_numpy(x, z, c)
+    s1 = iqcc.Store(ctx, NQ, int(6e8))
+    s2 = iqcc.Store(ctx, NQ, int(6e8))
+    tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
+    e = torch.zeros(STEPS, dtype=torch.float64, device="cuda")
+    src, outs = h0, (s1, s2)
+    ox, oz, oc = x, z, c
+    for j, ((px, pz), t) in enumerate(zip(ents, taus)):
+        dst = outs[j % 2]
+        describe(j, "full-size dress", n=src.count())
+        iqcc.iqcc_dress(ctx.handle, src.handle, px, pz, t, EPS, dst.handle, tht, pht, e[j:j + 1])
+        n = dst.count()
+        # fused energy == stand-alone energy kernel on the same output
+        e2 = iqcc.iqcc_qmf_energy(ctx.handle, dst.handle, tht, pht)
+        assert abs(e[j].item() - e2.item()) <= 1e-10, (j, e[j].item(), e2.item())
+        if j < PREFIX:
+            ox, oz, oc = O.dress(NQ, ox, oz, oc, px, pz, t, EPS)
+            assert_same_terms(dst.to_numpy(), (ox, oz, oc), f"step {j}")
+            assert abs(e[j].item() - O.qmf_energy(NQ, ox, oz, oc, th, ph)) <= 1e-10
+        src = dst
+    final = src
+    n_final = final.count()
+    assert n_final > 5e7
+    # sampled output rows, recomputed one by one by the oracle
+    fx, fz, fc = iqcc.iqcc_store_export(ctx.handle, final.handle)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    idx = torch.randint(0, n_final, (4000,), device="cuda", generator=g)
+    sx = iqcc.from_device_words(fx[:, idx]); sz = iqcc.from_device_words(fz[:, idx])
+    sc = fc[idx].cpu().numpy()
+    del fx, fz, fc
+    torch.cuda.empty_cache()
+    describe(STEPS, "point queries", n=len(sc))
+    found, val = O.chain_point(NQ, x, z, c, ents, taus, EPS, sx, sz)
+    assert found.all()
+    assert np.array_equal(val, sc)
+    # neighbours K ^ P_j: presence and value must agree both ways
+    for j in (STEPS - 1, STEPS - 2, 3):
+        qx = sx[:1000] ^ np.asarray(ents[j][0], np.uint64)
+        qz = sz[:1000] ^ np.asarray(ents[j][1], np.uint64)
+        f_o, v_o = O.chain_point(NQ, x, z, c, ents, taus, EPS, qx, qz)
+        f_g, v_g = iqcc.iqcc_store_lookup(ctx.handle, final.handle, iqcc.to_device_words(qx),
+                                          iqcc.to_device_words(qz))
+        f_g = f_g.cpu().numpy(); v_g = v_g.cpu().numpy()
+        assert np.array_equal(f_o, f_g), (j, f_o.sum(), f_g.sum())
+        assert np.array_equal(v_o[f_o], v_g[f_g])
+    h0.close(); s1.close(); s2.close(); ctx.close()

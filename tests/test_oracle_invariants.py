@@ -217,3 +217,27 @@ def test_tau_gradient_last_step_at_zero_is_dis_gradient(oracle):
     hx, hz, hc = oracle.chain(nq, x, z, c, ents[:2], taus[:2])
     gd = oracle.dis_gradients(nq, hx, hz, hc, th, ph, cx[2:3], cz[2:3])[0]
     assert abs(g - gd) <= 1e-12 * np.abs(c).sum()
+
+
+def test_chain_point_query_matches_full_chain(oracle):
+    """The one-key-at-a-time evaluation of the chain reproduces the full chain."""
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    cx, cz = I.dis_candidates(x, nq, 5, 8, np.random.default_rng(61))
+    taus = I.taus(5, np.random.default_rng(62))
+    ents = list(zip(cx, cz))
+    fx, fz, fc = oracle.chain(nq, x, z, c, ents, taus, 1e-8)
+    rng = np.random.default_rng(63)
+    idx = rng.integers(0, len(fc), 2000)
+    found, val = oracle.chain_point(nq, x, z, c, ents, taus, 1e-8, fx[idx], fz[idx])
+    assert found.all() and np.array_equal(val, fc[idx])
+    table = {tuple(a) + tuple(b): v for a, b, v in zip(fx.tolist(), fz.tolist(), fc.tolist())}
+    for j in (4, 2):
+        qx = fx[idx] ^ cx[j]
+        qz = fz[idx] ^ cz[j]
+        f2, v2 = oracle.chain_point(nq, x, z, c, ents, taus, 1e-8, qx, qz)
+        for a, b, f, v in zip(qx.tolist(), qz.tolist(), f2, v2):
+            k = tuple(a) + tuple(b)
+            assert f == (k in table)
+            if f:
+                assert v == table[k]
