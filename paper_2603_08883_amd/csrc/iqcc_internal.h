@@ -107,20 +107,35 @@ __device__ __forceinline__ double block_sum(double v, double* tmp) {
 template <int W>
 __device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* x,
                                              const uint64_t* z) {
-  double p = 1.0;
+  // four independent lookups per iteration keep several LDS reads in flight
+  double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     uint64_t nz = x[w] | z[w];
+    const double* lw = lut + w * kGroupsPerWord * kLutEntries;
     while (nz) {
-      const int bit = __builtin_ctzll(nz);
-      const int g = (bit * 43) >> 7;  // bit / 3 for 0 <= bit < 64
-      const int sh = 3 * g;
-      const uint32_t idx = (uint32_t)((x[w] >> sh) & 7u) | ((uint32_t)((z[w] >> sh) & 7u) << 3);
-      p *= lut[(w * kGroupsPerWord + g) * kLutEntries + idx];
-      nz &= ~((uint64_t)7 << sh);
+      uint32_t e[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        // entry 0 of group 0 is 1.0 and serves as the identity once nz is empty
+        uint32_t off = 0;
+        if (nz) {
+          const int bit = __builtin_ctzll(nz);
+          const int g = (bit * 43) >> 7;  // bit / 3 for 0 <= bit < 64
+          const int sh = 3 * g;
+          off = (uint32_t)(g * kLutEntries) + ((uint32_t)((x[w] >> sh) & 7u) |
+                                               ((uint32_t)((z[w] >> sh) & 7u) << 3));
+          nz &= ~((uint64_t)7 << sh);
+        }
+        e[k] = off;
+      }
+      p0 *= lw[e[0]];
+      p1 *= lw[e[1]];
+      p2 *= lw[e[2]];
+      p3 *= lw[e[3]];
     }
   }
-  return p;
+  return (p0 * p1) * (p2 * p3);
 }
 
 // Anticommutation of K with P: parity of |xK & zP| + |zK & xP|.

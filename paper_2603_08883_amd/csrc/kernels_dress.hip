@@ -372,19 +372,59 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
 }
 
 // Everything one workgroup does for bucket pair `pi` of one dressing step.
+__device__ __forceinline__ void pair_buckets(int64_t pi, uint32_t f, int thi, uint32_t& b0,
+                                             uint32_t& b1) {
+  if (f) {
+    const uint32_t lo = (uint32_t)pi & ((1u << thi) - 1);
+    b0 = (((uint32_t)pi >> thi) << (thi + 1)) | lo;
+    b1 = b0 ^ f;
+  } else {
+    b0 = b1 = (uint32_t)pi;
+  }
+}
+
+// Rows a pair reserves in the output arena: the worst case 2 (n_b + n_b').
+__device__ __forceinline__ int64_t pair_need(const StoreDev& in, int64_t pi, uint32_t f, int thi) {
+  uint32_t b0, b1;
+  pair_buckets(pi, f, thi, b0, b1);
+  const int64_t n0 = in.cnt[b0];
+  return f ? 2 * (n0 + in.cnt[b1]) : 2 * n0;
+}
+
+// Rows for every pair this workgroup owns (pi = first, first + stride, ...),
+// reserved with one atomic; returns the base (block-uniform) or -1 when the
+// arena is too small.
+__device__ int64_t reserve_rows(const StoreDev& in, const StoreDev& out, int64_t first,
+                                int64_t stride, int64_t npairs, uint32_t f, int thi,
+                                uint64_t* scan_tmp, int64_t* misc) {
+  int64_t mine = 0;
+  const int64_t count = first < npairs ? (npairs - first + stride - 1) / stride : 0;
+  for (int64_t k = threadIdx.x; k < count; k += kBlock) mine += pair_need(in, first + k * stride, f, thi);
+  uint64_t total;
+  block_exclusive_scan((uint64_t)mine, scan_tmp, total);
+  if (threadIdx.x == 0) {
+    int64_t base = total ? (int64_t)atomicAdd((unsigned long long*)out.top, (unsigned long long)total) : 0;
+    if (base + (int64_t)total > out.cap) {
+      atomicOr(out.err, 1);
+      base = -1;
+    }
+    misc[5] = base;
+  }
+  __syncthreads();
+  const int64_t base = misc[5];
+  __syncthreads();
+  return base;
+}
+
+// Everything one workgroup does for bucket pair `pi` of one dressing step;
+// `base` is the first arena row reserved for it (-1: no room, write nothing).
 template <int W, bool ENERGY>
 __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
                              const DressConfig& cfg, const Smem<W>& sm, int64_t pi, int m,
-                             int split, uint32_t f, int thi, double& eacc) {
+                             int split, uint32_t f, int thi, int64_t base, double& eacc) {
   const int tid = threadIdx.x;
   PairState ps;
-  if (f) {
-    const uint32_t lo = (uint32_t)pi & ((1u << thi) - 1);
-    ps.b0 = (((uint32_t)pi >> thi) << (thi + 1)) | lo;
-    ps.b1 = ps.b0 ^ f;
-  } else {
-    ps.b0 = ps.b1 = (uint32_t)pi;
-  }
+  pair_buckets(pi, f, thi, ps.b0, ps.b1);
   ps.self = (f == 0);
   ps.n0 = in.cnt[ps.b0];
   ps.off0 = in.off[ps.b0];
@@ -393,18 +433,8 @@ __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Enta
   ps.ntot = ps.n0 + ps.n1;
   ps.bound0 = ps.self ? 2 * ps.n0 : ps.n0 + ps.n1;
   ps.bound1 = ps.self ? 0 : ps.n0 + ps.n1;
-  if (tid == 0) {
-    const int64_t need = ps.bound0 + ps.bound1;
-    const int64_t base = need ? (int64_t)atomicAdd((unsigned long long*)out.top, (unsigned long long)need) : 0;
-    const bool bad = base + need > out.cap;
-    if (bad) atomicOr(out.err, 1);
-    sm.misc[0] = base;
-    sm.misc[1] = bad;
-    sm.misc[3] = 0;
-  }
-  __syncthreads();
-  const int64_t base = sm.misc[0];
-  const bool bad = sm.misc[1] != 0;
+  const bool bad = base < 0;
+  if (tid == 0) sm.misc[3] = 0;
   __syncthreads();
   ps.reg0 = base;
   ps.reg1 = base + ps.bound0;
@@ -506,8 +536,11 @@ __global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Ent
     __syncthreads();
   }
   double eacc = 0.0;
-  for (int64_t pi = blockIdx.x; pi < npairs; pi += gridDim.x)
-    process_pair<W, ENERGY>(in, out, P, cfg, sm, pi, m, split, f, thi, eacc);
+  int64_t base = reserve_rows(in, out, blockIdx.x, gridDim.x, npairs, f, thi, sm.scan, sm.misc);
+  for (int64_t pi = blockIdx.x; pi < npairs; pi += gridDim.x) {
+    process_pair<W, ENERGY>(in, out, P, cfg, sm, pi, m, split, f, thi, base, eacc);
+    if (base >= 0) base += pair_need(in, pi, f, thi);
+  }
   if (ENERGY) {
     const double s = block_sum(eacc, sm.red);
     if (tid == 0) cfg.e_partial[blockIdx.x] = s;
@@ -581,7 +614,21 @@ __global__ __launch_bounds__(kBlock) void k_dress_batch(int n_ham, const BatchIt
     DressConfig c = cfg;
     c.C = it.C;
     c.S = it.S;
-    process_pair<W, false>(it.in, it.out, it.P, c, sm, item - p.item_start, p.m, p.split, p.f, p.thi, eacc);
+    // items come from a dynamic queue: reserve per pair
+    const int64_t pi = item - p.item_start;
+    const int64_t need = pair_need(it.in, pi, p.f, p.thi);
+    if (threadIdx.x == 0) {
+      int64_t b = need ? (int64_t)atomicAdd((unsigned long long*)it.out.top, (unsigned long long)need) : 0;
+      if (b + need > it.out.cap) {
+        atomicOr(it.out.err, 1);
+        b = -1;
+      }
+      sm.misc[5] = b;
+    }
+    __syncthreads();
+    const int64_t base = sm.misc[5];
+    __syncthreads();
+    process_pair<W, false>(it.in, it.out, it.P, c, sm, pi, p.m, p.split, p.f, p.thi, base, eacc);
   }
 }
 
