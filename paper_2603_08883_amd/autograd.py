@@ -33,12 +33,18 @@ class DressingChain:
         self.stores = [None] * len(self.ents)      # output store of step j
         self.caps = [0] * len(self.ents)
         self.tapes = [None] * len(self.ents)       # (tape_self, tape_partner) of step j
+        self.version = 0                           # bumped by every run()
 
     def _input(self, j):
         return self.h0 if j == 0 else self.stores[j - 1]
 
     def run(self, taus):
-        """Dress H0 through every step; returns the final store."""
+        """Dress H0 through every step; returns the final store.
+
+        The chain owns one set of device stores and tapes, so each run replaces
+        the previous one; `version` identifies the current contents.
+        """
+        self.version += 1
         prev_cap = self.h0_max
         for j, ((px, pz), t) in enumerate(zip(self.ents, taus)):
             src = self._input(j)
@@ -90,7 +96,7 @@ class QMFChainEnergy(torch.autograd.Function):
         final = chain.run(tau_list)
         E = iqcc.iqcc_qmf_energy(chain.ctx.handle, final.handle, theta, phi)
         fctx.chain = chain
-        fctx.final = final
+        fctx.version = chain.version
         fctx.tau_list = tau_list
         fctx.save_for_backward(theta, phi, taus)
         return E
@@ -98,7 +104,12 @@ class QMFChainEnergy(torch.autograd.Function):
     @staticmethod
     def backward(fctx, gE):
         theta, phi, taus = fctx.saved_tensors
-        chain, final = fctx.chain, fctx.final
+        chain = fctx.chain
+        if chain.version != fctx.version:
+            # another forward ran on this chain since: recompute this one's tape
+            final = chain.run(fctx.tau_list)
+        else:
+            final = chain.stores[-1] if chain.ents else chain.h0
         g = gE.detach().to(device="cuda", dtype=torch.float64).reshape(())
         dth, dph = iqcc.iqcc_qmf_energy_backward(chain.ctx.handle, final.handle, theta, phi, g)
         lam = torch.empty(iqcc.iqcc_store_rows(final.handle), dtype=torch.float64, device="cuda")
