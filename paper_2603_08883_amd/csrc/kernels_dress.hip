@@ -418,10 +418,17 @@ __device__ int64_t reserve_rows(const StoreDev& in, const StoreDev& out, int64_t
 
 // Everything one workgroup does for bucket pair `pi` of one dressing step;
 // `base` is the first arena row reserved for it (-1: no room, write nothing).
+// Per-workgroup totals of one step, flushed to the output store's device
+// counters once at the end (same-address global atomics serialise in L2).
+struct StepCounts {
+  int64_t produced = 0, anti = 0, fresh = 0;
+};
+
 template <int W, bool ENERGY>
 __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
                              const DressConfig& cfg, const Smem<W>& sm, int64_t pi, int m,
-                             int split, uint32_t f, int thi, int64_t base, double& eacc) {
+                             int split, uint32_t f, int thi, int64_t base, double& eacc,
+                             StepCounts& counts) {
   const int tid = threadIdx.x;
   PairState ps;
   pair_buckets(pi, f, thi, ps.b0, ps.b1);
@@ -501,11 +508,19 @@ __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Enta
         produced += k;
       }
     }
-    if (produced) atomicAdd((unsigned long long*)out.total, (unsigned long long)produced);
-    if (pair_anti) atomicAdd((unsigned long long*)&out.stats[0], (unsigned long long)pair_anti);
-    if (sm.misc[3]) atomicAdd((unsigned long long*)&out.stats[1], (unsigned long long)sm.misc[3]);
+    counts.produced += produced;
+    counts.anti += pair_anti;
+    counts.fresh += sm.misc[3];
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void flush_counts(const StoreDev& out, const StepCounts& counts) {
+  if (threadIdx.x == 0) {
+    if (counts.produced) atomicAdd((unsigned long long*)out.total, (unsigned long long)counts.produced);
+    if (counts.anti) atomicAdd((unsigned long long*)&out.stats[0], (unsigned long long)counts.anti);
+    if (counts.fresh) atomicAdd((unsigned long long*)&out.stats[1], (unsigned long long)counts.fresh);
+  }
 }
 
 template <int W, bool ENERGY>
@@ -536,11 +551,13 @@ __global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Ent
     __syncthreads();
   }
   double eacc = 0.0;
+  StepCounts counts;
   int64_t base = reserve_rows(in, out, blockIdx.x, gridDim.x, npairs, f, thi, sm.scan, sm.misc);
   for (int64_t pi = blockIdx.x; pi < npairs; pi += gridDim.x) {
-    process_pair<W, ENERGY>(in, out, P, cfg, sm, pi, m, split, f, thi, base, eacc);
+    process_pair<W, ENERGY>(in, out, P, cfg, sm, pi, m, split, f, thi, base, eacc, counts);
     if (base >= 0) base += pair_need(in, pi, f, thi);
   }
+  flush_counts(out, counts);
   if (ENERGY) {
     const double s = block_sum(eacc, sm.red);
     if (tid == 0) cfg.e_partial[blockIdx.x] = s;
@@ -598,11 +615,16 @@ __global__ __launch_bounds__(kBlock) void k_dress_batch(int n_ham, const BatchIt
   const Smem<W> sm = carve<W, false>(smem, cfg.anti_cap);
   const int64_t total = plan[n_ham].item_start;
   double eacc = 0.0;
+  constexpr int64_t kGrab = 4;   // items taken per queue atomic
+  int64_t item = 0, left = 0;
   for (;;) {
-    if (threadIdx.x == 0) sm.misc[4] = (int64_t)atomicAdd((unsigned long long*)queue, 1ull);
-    __syncthreads();
-    const int64_t item = sm.misc[4];
-    __syncthreads();
+    if (left == 0) {
+      if (threadIdx.x == 0) sm.misc[4] = (int64_t)atomicAdd((unsigned long long*)queue, (unsigned long long)kGrab);
+      __syncthreads();
+      item = sm.misc[4];
+      __syncthreads();
+      left = kGrab;
+    }
     if (item >= total) break;
     int lo = 0, hi = n_ham - 1;   // last i with item_start <= item
     while (lo < hi) {
@@ -628,7 +650,11 @@ __global__ __launch_bounds__(kBlock) void k_dress_batch(int n_ham, const BatchIt
     __syncthreads();
     const int64_t base = sm.misc[5];
     __syncthreads();
-    process_pair<W, false>(it.in, it.out, it.P, c, sm, pi, p.m, p.split, p.f, p.thi, base, eacc);
+    StepCounts counts;
+    process_pair<W, false>(it.in, it.out, it.P, c, sm, pi, p.m, p.split, p.f, p.thi, base, eacc, counts);
+    flush_counts(it.out, counts);
+    ++item;
+    --left;
   }
 }
 
