@@ -9,7 +9,8 @@ namespace iqcc {
 constexpr int kBlock = 256;              // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxWords = 4;             // 256 qubits
-constexpr int kGroupsPerWord = 22;       // 3-qubit groups per 64-bit word (21 full + 1 single)
+constexpr int kGroupsPerHalf = 11;       // 3-qubit groups per 32-bit half word (10 full + 1 of 2)
+constexpr int kGroupsPerWord = 2 * kGroupsPerHalf;
 constexpr int kLutEntries = 64;          // 3 x-bits and 3 z-bits per group
 constexpr int kMaxBucketBits = 28;
 
@@ -100,19 +101,25 @@ __device__ __forceinline__ double block_sum(double v, double* tmp) {
 }
 
 // ---------------------------------------------------------------------------
-// QMF expectation <K> = prod_j b_j(sigma_j) with a 3-qubit-group table:
-// lut[(w*22 + g)*64 + (xbits | zbits<<3)] = product of the three single-qubit
-// factors of qubits 64w+3g .. 64w+3g+2.  Identity groups are skipped.
+// QMF expectation <K> = prod_j b_j(sigma_j) with a 3-qubit-group table.
+// Qubits are grouped per 32-bit half word h (qubits 32h .. 32h+31) into 11
+// groups of 3 (the last one of 2); group index gi = 11 h + g.
+// lut[gi*64 + (xbits | zbits<<3)] = product of the group's single-qubit factors.
+// Identity groups are skipped; four independent lookups per iteration keep
+// several LDS reads in flight.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t div3_small(uint32_t b) { return (b * 11u) >> 5; }  // b < 32
+
 template <int W>
 __device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* x,
                                              const uint64_t* z) {
-  // four independent lookups per iteration keep several LDS reads in flight
   double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0;
 #pragma unroll
-  for (int w = 0; w < W; ++w) {
-    uint64_t nz = x[w] | z[w];
-    const double* lw = lut + w * kGroupsPerWord * kLutEntries;
+  for (int h = 0; h < 2 * W; ++h) {
+    const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
+    const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
+    uint32_t nz = xh | zh;
+    const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
     while (nz) {
       uint32_t e[4];
 #pragma unroll
@@ -120,19 +127,17 @@ __device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* 
         // entry 0 of group 0 is 1.0 and serves as the identity once nz is empty
         uint32_t off = 0;
         if (nz) {
-          const int bit = __builtin_ctzll(nz);
-          const int g = (bit * 43) >> 7;  // bit / 3 for 0 <= bit < 64
-          const int sh = 3 * g;
-          off = (uint32_t)(g * kLutEntries) + ((uint32_t)((x[w] >> sh) & 7u) |
-                                               ((uint32_t)((z[w] >> sh) & 7u) << 3));
-          nz &= ~((uint64_t)7 << sh);
+          const uint32_t g = div3_small((uint32_t)__builtin_ctz(nz));
+          const uint32_t sh = 3 * g;
+          off = g * kLutEntries + (__builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3));
+          nz &= ~(7u << sh);
         }
         e[k] = off;
       }
-      p0 *= lw[e[0]];
-      p1 *= lw[e[1]];
-      p2 *= lw[e[2]];
-      p3 *= lw[e[3]];
+      p0 *= lh[e[0]];
+      p1 *= lh[e[1]];
+      p2 *= lh[e[2]];
+      p3 *= lh[e[3]];
     }
   }
   return (p0 * p1) * (p2 * p3);

@@ -21,13 +21,13 @@ __global__ void k_build_lut(int W, int nq, const double* theta, const double* ph
   const int n = W * kGroupsPerWord * kLutEntries;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
     const int idx = e % kLutEntries;
-    const int wg = e / kLutEntries;
-    const int w = wg / kGroupsPerWord, g = wg % kGroupsPerWord;
+    const int gi = e / kLutEntries;
+    const int h = gi / kGroupsPerHalf, g = gi % kGroupsPerHalf;
     double p = 1.0;
     for (int i = 0; i < 3; ++i) {
-      const int bitpos = 3 * g + i;
-      const int q = 64 * w + bitpos;
-      if (bitpos >= 64 || q >= nq) continue;
+      const int bitpos = 3 * g + i;          // bit within the 32-bit half
+      const int q = 32 * h + bitpos;
+      if (bitpos >= 32 || q >= nq) continue;
       const int op = ((idx >> i) & 1) | (((idx >> (3 + i)) & 1) << 1);
       if (op == 0) continue;
       double st, ct, sp, cp;
@@ -153,13 +153,12 @@ __global__ __launch_bounds__(kBlock) void k_energy_bwd(StoreDev st, int nq, cons
       const double c = st.c[off + i];
       double L[G];
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-#pragma unroll
-        for (int g = 0; g < kGroupsPerWord; ++g) {
-          const int sh = 3 * g;
-          const uint32_t idx = (uint32_t)((kx[w] >> sh) & 7u) | ((uint32_t)((kz[w] >> sh) & 7u) << 3);
-          L[w * kGroupsPerWord + g] = idx ? lut[(w * kGroupsPerWord + g) * kLutEntries + idx] : 1.0;
-        }
+      for (int gi = 0; gi < G; ++gi) {
+        const int h = gi / kGroupsPerHalf, sh = 3 * (gi % kGroupsPerHalf);
+        const uint32_t xh = (uint32_t)(kx[h >> 1] >> (32 * (h & 1)));
+        const uint32_t zh = (uint32_t)(kz[h >> 1] >> (32 * (h & 1)));
+        const uint32_t idx = ((xh >> sh) & 7u) | (((zh >> sh) & 7u) << 3);
+        L[gi] = idx ? lut[gi * kLutEntries + idx] : 1.0;
       }
       double suf[G + 1];
       suf[G] = 1.0;
@@ -167,31 +166,29 @@ __global__ __launch_bounds__(kBlock) void k_energy_bwd(StoreDev st, int nq, cons
       for (int g = G - 1; g >= 0; --g) suf[g] = suf[g + 1] * L[g];
       double pre = c;
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
+      for (int gi = 0; gi < G; ++gi) {
+        const int h = gi / kGroupsPerHalf, sh = 3 * (gi % kGroupsPerHalf);
+        const uint32_t xh = (uint32_t)(kx[h >> 1] >> (32 * (h & 1)));
+        const uint32_t zh = (uint32_t)(kz[h >> 1] >> (32 * (h & 1)));
+        const uint32_t xb = (xh >> sh) & 7u, zb = (zh >> sh) & 7u;
+        if (xb | zb) {
+          const double others = pre * suf[gi + 1];
+          const int q0 = 32 * h + sh;
+          int op[3];
+          double f[3];
 #pragma unroll
-        for (int g = 0; g < kGroupsPerWord; ++g) {
-          const int gi = w * kGroupsPerWord + g;
-          const int sh = 3 * g;
-          const uint32_t xb = (uint32_t)((kx[w] >> sh) & 7u), zb = (uint32_t)((kz[w] >> sh) & 7u);
-          if (xb | zb) {
-            const double others = pre * suf[gi + 1];
-            const int q0 = 64 * w + sh;
-            int op[3];
-            double f[3];
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-              op[t] = (int)((xb >> t) & 1u) | (int)(((zb >> t) & 1u) << 1);
-              f[t] = (sh + t < 64) ? fac[4 * (q0 + t) + op[t]] : 1.0;
-            }
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-              if (op[t] == 0 || sh + t >= 64) continue;
-              const double inner = (t == 0 ? 1.0 : f[0]) * (t == 1 ? 1.0 : f[1]) * (t == 2 ? 1.0 : f[2]);
-              atomicAdd(&acc[3 * (q0 + t) + (op[t] - 1)], others * inner);
-            }
+          for (int t = 0; t < 3; ++t) {
+            op[t] = (int)((xb >> t) & 1u) | (int)(((zb >> t) & 1u) << 1);
+            f[t] = (sh + t < 32) ? fac[4 * (q0 + t) + op[t]] : 1.0;
           }
-          pre *= L[gi];
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            if (op[t] == 0 || sh + t >= 32) continue;
+            const double inner = (t == 0 ? 1.0 : f[0]) * (t == 1 ? 1.0 : f[1]) * (t == 2 ? 1.0 : f[2]);
+            atomicAdd(&acc[3 * (q0 + t) + (op[t] - 1)], others * inner);
+          }
         }
+        pre *= L[gi];
       }
     }
   }
