@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--no-chain", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (scale for profiler byte counters)")
     ap.add_argument("--dis-plain-sample", type=int, default=256)
     ap.add_argument("--max-terms", type=float, default=6e8)
     args = ap.parse_args()
@@ -94,6 +96,14 @@ def main():
     result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
               "data": "synthetic"}
+
+    if args.calib_copy:
+        src_t = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst_t = torch.empty_like(src_t)
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = 2 * src_t.numel() * 8
+        del src_t, dst_t
 
     if not args.no_chain:
         t = time.perf_counter()

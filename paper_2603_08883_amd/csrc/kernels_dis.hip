@@ -49,23 +49,30 @@ __global__ __launch_bounds__(kBlock) void k_dis_batched(StoreDev st, const doubl
       __syncthreads();
       const int cnt = (int)((n - i0) < kBlock ? (n - i0) : kBlock);
       if (active) {
-        for (int j = 0; j < cnt; ++j) {
-          uint64_t kx[W], kz[W];
-          uint64_t t = 0;
+        for (int j0 = 0; j0 < cnt; j0 += 64) {
+          // which of the next 64 staged terms anticommute with this lane's
+          // candidate (every lane reads the same term: LDS broadcast)
+          const int jn = (cnt - j0) < 64 ? (cnt - j0) : 64;
+          uint64_t mask = 0;
+          for (int j = 0; j < jn; ++j) {
+            uint64_t t = 0;
 #pragma unroll
-          for (int w = 0; w < W; ++w) {
-            kx[w] = tx[w][j];
-            kz[w] = tz[w][j];
-            t ^= (kx[w] & az[w]) ^ (kz[w] & ax[w]);
+            for (int w = 0; w < W; ++w) t ^= (tx[w][j0 + j] & az[w]) ^ (tz[w][j0 + j] & ax[w]);
+            mask |= (uint64_t)(__popcll(t) & 1) << j;
           }
-          if (__popcll(t) & 1) {
-            const int e = product_phase<W>(kx, kz, ax, az);
-            uint64_t qx[W], qz[W];
+          // only the anticommuting terms of this lane
+          while (mask) {
+            const int j = j0 + __builtin_ctzll(mask);
+            mask &= mask - 1;
+            uint64_t kx[W], kz[W], qx[W], qz[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) {
+              kx[w] = tx[w][j];
+              kz[w] = tz[w][j];
               qx[w] = kx[w] ^ ax[w];
               qz[w] = kz[w] ^ az[w];
             }
+            const int e = product_phase<W>(kx, kz, ax, az);
             const double v = tc[j] * expect_lut<W>(lut, qx, qz);
             acc += (e == 1) ? v : -v;
           }
@@ -90,6 +97,7 @@ template <int W>
 __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* lut_g,
                                                     const uint64_t* cx, const uint64_t* cz,
                                                     int64_t ld_cand, int64_t a, double* partial) {
+  constexpr int R = 4;   // terms per thread per load round
   __shared__ double lut[W * kGroupsPerWord * kLutEntries];
   __shared__ double red[kWaves];
   for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
@@ -104,23 +112,32 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
   double acc = 0.0;
   for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
     const int64_t n = st.cnt[b], off = st.off[b];
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
-      uint64_t kx[W], kz[W];
+    for (int64_t i0 = 0; i0 < n; i0 += kBlock * R) {
+      uint64_t kx[R][W], kz[R][W];
+      bool ok[R];
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        kx[w] = st.x[w * st.cap + off + i];
-        kz[w] = st.z[w * st.cap + off + i];
-      }
-      if (anticommutes<W>(kx, kz, px, pz)) {
-        const int e = product_phase<W>(kx, kz, px, pz);
-        uint64_t qx[W], qz[W];
+      for (int r = 0; r < R; ++r) {
+        const int64_t i = i0 + r * kBlock + threadIdx.x;
+        ok[r] = i < n;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          qx[w] = kx[w] ^ px[w];
-          qz[w] = kz[w] ^ pz[w];
+          kx[r][w] = ok[r] ? st.x[w * st.cap + off + i] : 0;
+          kz[r][w] = ok[r] ? st.z[w * st.cap + off + i] : 0;
         }
-        const double v = st.c[off + i] * expect_lut<W>(lut, qx, qz);
-        acc += (e == 1) ? v : -v;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (ok[r] && anticommutes<W>(kx[r], kz[r], px, pz)) {
+          const int e = product_phase<W>(kx[r], kz[r], px, pz);
+          uint64_t qx[W], qz[W];
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            qx[w] = kx[r][w] ^ px[w];
+            qz[w] = kz[r][w] ^ pz[w];
+          }
+          const double v = st.c[off + i0 + r * kBlock + threadIdx.x] * expect_lut<W>(lut, qx, qz);
+          acc += (e == 1) ? v : -v;
+        }
       }
     }
   }
