@@ -134,6 +134,22 @@ Entangler make_entangler(int W, const uint64_t* px, const uint64_t* pz) {
     if (P.px[w]) { P.piv_word = w; P.piv_in_x = 1; P.piv_mask = P.px[w] & (~P.px[w] + 1); break; }
     if (P.pz[w]) { P.piv_word = w; P.piv_in_x = 0; P.piv_mask = P.pz[w] & (~P.pz[w] + 1); break; }
   }
+  // 3-qubit groups (per 32-bit half word) that P touches
+  int t = 0;
+  for (int h = 0; h < 2 * W; ++h) {
+    P.gstart[h] = (uint8_t)t;
+    const uint32_t v = (uint32_t)((P.px[h >> 1] | P.pz[h >> 1]) >> (32 * (h & 1)));
+    uint32_t bits = 0;
+    for (int g = 0; g < kGroupsPerHalf; ++g) {
+      const uint32_t m = (7u << (3 * g));
+      if (v & m) {
+        P.glist[t++] = (uint8_t)g;
+        bits |= m;
+      }
+    }
+    P.gbits[h] = bits;
+  }
+  P.gstart[2 * W] = (uint8_t)t;
   return P;
 }
 

@@ -84,6 +84,47 @@ __device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* t
   return base + s - v;
 }
 
+template <int NW>
+__device__ __forceinline__ uint64_t block_exclusive_scan_n(uint64_t v, uint64_t* tmp,
+                                                           uint64_t& total) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  uint64_t s = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t y = __shfl_up(s, d, 64);
+    if (lane >= d) s += y;
+  }
+  if (lane == 63) tmp[wid] = s;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    uint64_t t = tmp[i];
+    base += (i < wid) ? t : 0;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return base + s - v;
+}
+
+template <int NW>
+__device__ __forceinline__ double block_sum_n(double v, double* tmp) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+  if (lane == 0) tmp[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NW; ++i) s += tmp[i];
+  }
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
 // Block-wide sum of doubles in a fixed order (lane tree, then waves in order).
 __device__ __forceinline__ double block_sum(double v, double* tmp) {
   const int lane = threadIdx.x & 63;
@@ -192,6 +233,11 @@ struct Entangler {
   int piv_word;      // pivot bit of P (a set bit of x or z), used to pick one
   int piv_in_x;      //   member of each {K, K^P} pair for the join
   uint64_t piv_mask;
+  // the 3-qubit groups P touches, for the split expectation product
+  // <K> = A * B and <K^P> = A * B' (A over the other groups of K)
+  uint32_t gbits[2 * kMaxWords];                        // per half word: bits of those groups
+  uint8_t gstart[2 * kMaxWords + 1];                    // glist range of each half word
+  uint8_t glist[2 * kMaxWords * kGroupsPerHalf];        // group index within its half word
 };
 
 // ---------------------------------------------------------------------------

@@ -7,24 +7,26 @@
 // Pairwise routing between partitions that differ in the flipped bits: App. B/C.
 // Compression of small terms: App. A, iterative procedure.
 //
-// One workgroup handles one bucket pair {b, b ^ f} at a time (persistent grid,
-// static round-robin over pairs).  Every key of the output receives at most
-// two contributions, from K and from K ^ P, so the pair's anticommuting terms
-// are joined in an LDS hash table on one member of each {K, K^P} pair (the one
-// whose pivot bit is 0) and each coefficient is a single IEEE addition.
-// Commuting terms stream straight through.  Output rows are reserved per pair
-// (worst case 2 * (n_b + n_b')) with one atomic on the arena top; bucket b's
-// outputs fill its region from the front (child 0) and, when the step doubles
-// the bucket count, from the back (child 1).
+// One 512-thread workgroup handles one bucket pair {b, b ^ f} at a time
+// (persistent grid, static round-robin over pairs, one arena reservation per
+// workgroup).  Every key of the output receives at most two contributions,
+// from K and from K ^ P, so the pair's anticommuting terms are joined in an
+// LDS hash table on one member of each {K, K^P} pair (the one whose pivot bit
+// is 0) and each coefficient is a single IEEE addition.  Commuting terms
+// stream straight through.  Bucket b's outputs fill its region from the front
+// (child 0) and, when the step doubles the bucket count, from the back
+// (child 1).  The energy of every output is formed while the input term is in
+// registers: <K> = A * B and <K^P> = A * B', where B, B' run over the few
+// 3-qubit groups P touches and A over the rest of K.
 #include "iqcc_internal.h"
 
 #pragma clang fp contract(off)
 
 namespace iqcc {
 
-constexpr int kItems = 4;                 // terms per thread per load round
-constexpr int kChunk = kBlock * kItems;   // 1024 terms per load round
-constexpr int kFieldBits = 12;            // packed per-category counters
+constexpr int kDB = 512;                  // threads per dressing workgroup
+constexpr int kDW = kDB / 64;             // waves per dressing workgroup
+constexpr int kFieldBits = 12;            // packed per-category counters (<= 1024 per round)
 constexpr uint64_t kFieldMask = (1u << kFieldBits) - 1;
 
 __host__ __device__ inline int next_pow2_int(int v) {
@@ -37,6 +39,7 @@ size_t dress_lds_bytes(int W, int cap, bool energy, bool tape) {
   size_t o = energy ? (size_t)W * kGroupsPerWord * kLutEntries * 8 : 0;
   o += (size_t)W * cap * 8 * 2;                  // keys
   o += (size_t)cap * 8;                          // coefficients
+  if (energy) o += (size_t)cap * 8 * 2;          // <K>, <K^P>
   o += (size_t)next_pow2_int(2 * cap) * 4;       // hash table
   o += (size_t)cap * 2;                          // partner
   o += ((size_t)cap + 7) & ~(size_t)7;           // side
@@ -51,6 +54,8 @@ struct Smem {
   uint64_t* ax;
   uint64_t* az;
   double* ac;
+  double* ek;     // <K> of each anticommuting entry
+  double* ekp;    // <K^P>
   int* tab;
   int16_t* partner;
   uint8_t* side;
@@ -64,7 +69,7 @@ struct Smem {
 };
 
 template <int W, bool ENERGY>
-__device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap) {
+__device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap, bool tape) {
   Smem<W> s;
   size_t o = 0;
   s.lut = (double*)(smem + o);
@@ -72,6 +77,8 @@ __device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap) {
   s.ax = (uint64_t*)(smem + o); o += (size_t)W * cap * 8;
   s.az = (uint64_t*)(smem + o); o += (size_t)W * cap * 8;
   s.ac = (double*)(smem + o); o += (size_t)cap * 8;
+  s.ek = (double*)(smem + o); o += ENERGY ? (size_t)cap * 8 : 0;
+  s.ekp = (double*)(smem + o); o += ENERGY ? (size_t)cap * 8 : 0;
   s.ts = next_pow2_int(2 * cap);
   s.tab = (int*)(smem + o); o += (size_t)s.ts * 4;
   s.partner = (int16_t*)(smem + o); o += (size_t)cap * 2;
@@ -81,7 +88,7 @@ __device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap) {
   s.misc = (int64_t*)(smem + o); o += 64;
   s.stack = (int*)(smem + o); o += 256 * 4;
   // tape rows (only carved, and only touched, when the step records a tape)
-  s.arow = (int64_t*)(smem + o); o += (size_t)cap * 8;
+  s.arow = (int64_t*)(smem + o); o += tape ? (size_t)cap * 8 : 0;
   s.orow = (int64_t*)(smem + o);
   s.cap = cap;
   return s;
@@ -96,11 +103,11 @@ struct PairState {
   __device__ __forceinline__ int64_t cnt(int cat) const {
     return cat == 0 ? c00 : cat == 1 ? c01 : cat == 2 ? c10 : c11;
   }
-  __device__ __forceinline__ void add_packed(uint64_t total, int bits, uint64_t mask) {
-    c00 += (int64_t)(total & mask);
-    c01 += (int64_t)((total >> bits) & mask);
-    c10 += (int64_t)((total >> (2 * bits)) & mask);
-    c11 += (int64_t)((total >> (3 * bits)) & mask);
+  __device__ __forceinline__ void add_packed(uint64_t total) {
+    c00 += (int64_t)(total & kFieldMask);
+    c01 += (int64_t)((total >> kFieldBits) & kFieldMask);
+    c10 += (int64_t)((total >> (2 * kFieldBits)) & kFieldMask);
+    c11 += (int64_t)((total >> (3 * kFieldBits)) & kFieldMask);
   }
   __device__ __forceinline__ int64_t row(int cat, int64_t k) const {
     const int64_t reg = (cat >> 1) ? reg1 : reg0;
@@ -131,7 +138,6 @@ __device__ __forceinline__ void store_key(const StoreDev& st, int64_t row, const
   __builtin_nontemporal_store(c, &st.c[row]);
 }
 
-
 template <int W>
 __device__ __forceinline__ bool pivot_of(const Entangler& P, const uint64_t* kx,
                                          const uint64_t* kz) {
@@ -159,81 +165,124 @@ __device__ __forceinline__ uint32_t rep_hash(const Entangler& P, const uint64_t*
   return table_hash<W>(rx, rz);
 }
 
-// One pass over the pair's input terms.  Commuting terms are written to the
-// output when `write_commuting`; anticommuting terms whose representative
-// hash falls in residue class `rem` mod `mod` are appended to the LDS list
-// (up to cap).  Returns the number of such anticommuting terms (block-uniform).
+// <K> and <K^P> of the product state: A over the non-identity groups of K
+// that P does not touch (four independent lookups per iteration), B and B'
+// over P's groups for K and K^P.
+template <int W>
+__device__ __forceinline__ void expect_split(const double* lut, const Entangler& P,
+                                             const uint64_t* x, const uint64_t* z, double& ek,
+                                             double& ekp) {
+  double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0, b = 1.0, b2 = 1.0;
+#pragma unroll
+  for (int h = 0; h < 2 * W; ++h) {
+    const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
+    const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
+    const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
+    uint32_t nz = (xh | zh) & ~P.gbits[h];
+    while (nz) {
+      uint32_t e[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        uint32_t off = 0;   // entry 0 of group 0 is 1.0: the identity once nz is empty
+        if (nz) {
+          const uint32_t g = div3_small((uint32_t)__builtin_ctz(nz));
+          const uint32_t sh = 3 * g;
+          off = g * kLutEntries + (__builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3));
+          nz &= ~(7u << sh);
+        }
+        e[k] = off;
+      }
+      p0 *= lh[e[0]];
+      p1 *= lh[e[1]];
+      p2 *= lh[e[2]];
+      p3 *= lh[e[3]];
+    }
+    const uint32_t pxh = (uint32_t)(P.px[h >> 1] >> (32 * (h & 1)));
+    const uint32_t pzh = (uint32_t)(P.pz[h >> 1] >> (32 * (h & 1)));
+    for (int t = P.gstart[h]; t < P.gstart[h + 1]; ++t) {
+      const uint32_t sh = 3 * (uint32_t)P.glist[t];
+      const uint32_t ix = __builtin_amdgcn_ubfe(xh, sh, 3), iz = __builtin_amdgcn_ubfe(zh, sh, 3);
+      const uint32_t base = (uint32_t)P.glist[t] * kLutEntries;
+      b *= lh[base + (ix | (iz << 3))];
+      b2 *= lh[base + ((ix ^ __builtin_amdgcn_ubfe(pxh, sh, 3)) | ((iz ^ __builtin_amdgcn_ubfe(pzh, sh, 3)) << 3))];
+    }
+  }
+  const double a = (p0 * p1) * (p2 * p3);
+  ek = a * b;
+  ekp = a * b2;
+}
+
+// One pass over the pair's input terms (one term per thread per round).
+// Commuting terms are written to the output when `full`; anticommuting terms
+// whose representative hash falls in residue class `rem` mod `mod` are
+// appended to the LDS list (up to cap).  Returns the number of such
+// anticommuting terms (block-uniform).
 template <int W, bool ENERGY>
 __device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
-                             const Smem<W>& sm, PairState& ps, int split, int m,
-                             bool write_commuting, uint32_t mod, uint32_t rem, double eps,
-                             int64_t* tape_self, int64_t* tape_partner, double& eacc) {
+                             const Smem<W>& sm, PairState& ps, int split, int m, bool full,
+                             uint32_t mod, uint32_t rem, double eps, int64_t* tape_self,
+                             int64_t* tape_partner, double& eacc) {
   const int tid = threadIdx.x;
   int64_t n_anti = 0;
-  for (int64_t i0 = 0; i0 < ps.ntot; i0 += kChunk) {
-    uint64_t kx[kItems][W], kz[kItems][W];
-    double kc[kItems];
-    int64_t krow[kItems];
-    int kside[kItems];
-    bool valid[kItems];
+  for (int64_t i0 = 0; i0 < ps.ntot; i0 += kDB) {
+    const int64_t idx = i0 + tid;
+    const bool valid = idx < ps.ntot;
+    const int kside = idx >= ps.n0;
+    const int64_t krow = kside ? ps.off1 + (idx - ps.n0) : ps.off0 + idx;
+    uint64_t kx[W], kz[W];
+    double kc = 0.0;
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const int64_t idx = i0 + r * kBlock + tid;
-      valid[r] = idx < ps.ntot;
-      kside[r] = idx >= ps.n0;
-      krow[r] = kside[r] ? ps.off1 + (idx - ps.n0) : ps.off0 + idx;
-      if (valid[r]) load_key<W>(in, krow[r], kx[r], kz[r], kc[r]);
-    }
-    int cat[kItems];
-    uint64_t packed = 0;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      cat[r] = -1;
-      if (!valid[r]) continue;
-      if (anticommutes<W>(kx[r], kz[r], P.px, P.pz)) {
-        if (mod == 1 || (round_hash(rep_hash<W>(P, kx[r], kz[r])) & (mod - 1)) == rem) cat[r] = 4;
-      } else if (write_commuting) {
-        if (!(fabs(kc[r]) < eps)) {
+    for (int w = 0; w < W; ++w) kx[w] = kz[w] = 0;
+    if (valid) load_key<W>(in, krow, kx, kz, kc);
+    int cat = -1;
+    if (valid) {
+      if (anticommutes<W>(kx, kz, P.px, P.pz)) {
+        if (mod == 1 || (round_hash(rep_hash<W>(P, kx, kz)) & (mod - 1)) == rem) cat = 4;
+      } else if (full) {
+        if (!(fabs(kc) < eps)) {
           // commuting terms keep their coefficient; compression applies to them too
-          const int child = split ? (int)((bucket_hash<W>(kx[r], kz[r]) >> m) & 1u) : 0;
-          cat[r] = kside[r] * 2 + child;
+          const int child = split ? (int)((bucket_hash<W>(kx, kz) >> m) & 1u) : 0;
+          cat = kside * 2 + child;
         } else if (tape_self) {
-          tape_self[krow[r]] = -1;
-          tape_partner[krow[r]] = -2;
+          tape_self[krow] = -1;
+          tape_partner[krow] = -2;
         }
       }
-      if (cat[r] >= 0) packed += 1ull << (kFieldBits * cat[r]);
     }
+    double ek = 0.0, ekp = 0.0;
+    if (ENERGY && cat >= 0) expect_split<W>(sm.lut, P, kx, kz, ek, ekp);
     uint64_t total;
-    uint64_t ex = block_exclusive_scan(packed, sm.scan, total);
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      if (cat[r] < 0) continue;
-      const int64_t k = (int64_t)((ex >> (kFieldBits * cat[r])) & kFieldMask);
-      ex += 1ull << (kFieldBits * cat[r]);
-      if (cat[r] == 4) {
+    const uint64_t ex = block_exclusive_scan_n<kDW>(cat >= 0 ? 1ull << (kFieldBits * cat) : 0ull,
+                                                    sm.scan, total);
+    if (cat >= 0) {
+      const int64_t k = (int64_t)((ex >> (kFieldBits * cat)) & kFieldMask);
+      if (cat == 4) {
         const int64_t slot = n_anti + k;
         if (slot < sm.cap) {
 #pragma unroll
           for (int w = 0; w < W; ++w) {
-            sm.ax[w * sm.cap + slot] = kx[r][w];
-            sm.az[w * sm.cap + slot] = kz[r][w];
+            sm.ax[w * sm.cap + slot] = kx[w];
+            sm.az[w * sm.cap + slot] = kz[w];
           }
-          sm.ac[slot] = kc[r];
-          sm.side[slot] = (uint8_t)kside[r];
-          if (tape_self) sm.arow[slot] = krow[r];
+          sm.ac[slot] = kc;
+          sm.side[slot] = (uint8_t)kside;
+          if (ENERGY) {
+            sm.ek[slot] = ek;
+            sm.ekp[slot] = ekp;
+          }
+          if (tape_self) sm.arow[slot] = krow;
         }
       } else {
-        const int64_t orow = ps.row(cat[r], ps.cnt(cat[r]) + k);
-        store_key<W>(out, orow, kx[r], kz[r], kc[r]);
+        const int64_t orow = ps.row(cat, ps.cnt(cat) + k);
+        store_key<W>(out, orow, kx, kz, kc);
+        if (ENERGY) eacc += kc * ek;
         if (tape_self) {
-          tape_self[krow[r]] = orow;
-          tape_partner[krow[r]] = -2;
+          tape_self[krow] = orow;
+          tape_partner[krow] = -2;
         }
-        if (ENERGY) eacc += kc[r] * expect_lut<W>(sm.lut, kx[r], kz[r]);
       }
     }
-    ps.add_packed(total, kFieldBits, kFieldMask);
+    ps.add_packed(total);
     n_anti += (int64_t)((total >> (kFieldBits * 4)) & kFieldMask);
   }
   return n_anti;
@@ -248,11 +297,11 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
                           double& eacc) {
   const int tid = threadIdx.x;
   const uint32_t tmask = (uint32_t)sm.ts - 1;
-  for (int i = tid; i < sm.ts; i += kBlock) sm.tab[i] = -1;
-  for (int i = tid; i < n; i += kBlock) sm.partner[i] = -1;
+  for (int i = tid; i < sm.ts; i += kDB) sm.tab[i] = -1;
+  for (int i = tid; i < n; i += kDB) sm.partner[i] = -1;
   __syncthreads();
   // insert the members whose pivot bit is 0
-  for (int i = tid; i < n; i += kBlock) {
+  for (int i = tid; i < n; i += kDB) {
     uint64_t kx[W], kz[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -265,7 +314,7 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
   }
   __syncthreads();
   // the members whose pivot bit is 1 look up K ^ P
-  for (int i = tid; i < n; i += kBlock) {
+  for (int i = tid; i < n; i += kDB) {
     uint64_t kx[W], kz[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -291,10 +340,10 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
   }
   __syncthreads();
   const int child_p = split ? (int)((P.hp >> m) & 1u) : 0;
-  for (int i0 = 0; i0 < n; i0 += kBlock) {
+  for (int i0 = 0; i0 < n; i0 += kDB) {
     const int i = i0 + tid;
     const bool valid = i < n;
-    uint64_t kx[W], kz[W], qx[W], qz[W];
+    uint64_t kx[W], kz[W];
     double v_own = 0.0, v_new = 0.0;
     int cat_own = -1, cat_new = -1;
     if (valid) {
@@ -302,8 +351,6 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
       for (int w = 0; w < W; ++w) {
         kx[w] = sm.ax[w * sm.cap + i];
         kz[w] = sm.az[w * sm.cap + i];
-        qx[w] = kx[w] ^ P.px[w];
-        qz[w] = kz[w] ^ P.pz[w];
       }
       const double a = sm.ac[i];
       const int side = sm.side[i];
@@ -337,33 +384,39 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
     if (cat_own >= 0) packed += 1ull << (kFieldBits * cat_own);
     if (cat_new >= 0) packed += 1ull << (kFieldBits * cat_new);
     uint64_t total;
-    uint64_t ex = block_exclusive_scan(packed, sm.scan, total);
+    uint64_t ex = block_exclusive_scan_n<kDW>(packed, sm.scan, total);
     int64_t own_row = -1, new_row = -1;
     if (cat_own >= 0) {
       const int64_t k = (int64_t)((ex >> (kFieldBits * cat_own)) & kFieldMask);
       ex += 1ull << (kFieldBits * cat_own);
       own_row = ps.row(cat_own, ps.cnt(cat_own) + k);
       store_key<W>(out, own_row, kx, kz, v_own);
-      if (ENERGY) eacc += v_own * expect_lut<W>(sm.lut, kx, kz);
+      if (ENERGY) eacc += v_own * sm.ek[i];
     }
     if (cat_new >= 0) {
       atomicAdd((unsigned long long*)&sm.misc[3], 1ull);
       const int64_t k = (int64_t)((ex >> (kFieldBits * cat_new)) & kFieldMask);
       new_row = ps.row(cat_new, ps.cnt(cat_new) + k);
+      uint64_t qx[W], qz[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        qx[w] = kx[w] ^ P.px[w];
+        qz[w] = kz[w] ^ P.pz[w];
+      }
       store_key<W>(out, new_row, qx, qz, v_new);
-      if (ENERGY) eacc += v_new * expect_lut<W>(sm.lut, qx, qz);
+      if (ENERGY) eacc += v_new * sm.ekp[i];
     }
     if (tape_self && valid) {
       sm.orow[i] = own_row;
       tape_self[sm.arow[i]] = own_row;
       if (sm.partner[i] < 0) tape_partner[sm.arow[i]] = new_row;
     }
-    ps.add_packed(total, kFieldBits, kFieldMask);
+    ps.add_packed(total);
   }
   __syncthreads();
   if (tape_self) {
     // the partner K^P of a paired entry is the other member's own output row
-    for (int i = tid; i < n; i += kBlock) {
+    for (int i = tid; i < n; i += kDB) {
       const int j = sm.partner[i];
       if (j >= 0) tape_partner[sm.arow[i]] = sm.orow[j];
     }
@@ -371,7 +424,6 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
   }
 }
 
-// Everything one workgroup does for bucket pair `pi` of one dressing step.
 __device__ __forceinline__ void pair_buckets(int64_t pi, uint32_t f, int thi, uint32_t& b0,
                                              uint32_t& b1) {
   if (f) {
@@ -399,9 +451,9 @@ __device__ int64_t reserve_rows(const StoreDev& in, const StoreDev& out, int64_t
                                 uint64_t* scan_tmp, int64_t* misc) {
   int64_t mine = 0;
   const int64_t count = first < npairs ? (npairs - first + stride - 1) / stride : 0;
-  for (int64_t k = threadIdx.x; k < count; k += kBlock) mine += pair_need(in, first + k * stride, f, thi);
+  for (int64_t k = threadIdx.x; k < count; k += kDB) mine += pair_need(in, first + k * stride, f, thi);
   uint64_t total;
-  block_exclusive_scan((uint64_t)mine, scan_tmp, total);
+  block_exclusive_scan_n<kDW>((uint64_t)mine, scan_tmp, total);
   if (threadIdx.x == 0) {
     int64_t base = total ? (int64_t)atomicAdd((unsigned long long*)out.top, (unsigned long long)total) : 0;
     if (base + (int64_t)total > out.cap) {
@@ -416,14 +468,14 @@ __device__ int64_t reserve_rows(const StoreDev& in, const StoreDev& out, int64_t
   return base;
 }
 
-// Everything one workgroup does for bucket pair `pi` of one dressing step;
-// `base` is the first arena row reserved for it (-1: no room, write nothing).
 // Per-workgroup totals of one step, flushed to the output store's device
 // counters once at the end (same-address global atomics serialise in L2).
 struct StepCounts {
   int64_t produced = 0, anti = 0, fresh = 0;
 };
 
+// Everything one workgroup does for bucket pair `pi` of one dressing step;
+// `base` is the first arena row reserved for it (-1: no room, write nothing).
 template <int W, bool ENERGY>
 __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
                              const DressConfig& cfg, const Smem<W>& sm, int64_t pi, int m,
@@ -441,57 +493,59 @@ __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Enta
   ps.bound0 = ps.self ? 2 * ps.n0 : ps.n0 + ps.n1;
   ps.bound1 = ps.self ? 0 : ps.n0 + ps.n1;
   const bool bad = base < 0;
-  if (tid == 0) sm.misc[3] = 0;
+  if (tid == 0) {
+    sm.misc[2] = 0;   // round stack depth
+    sm.misc[3] = 0;   // new terms of this pair
+  }
   __syncthreads();
   ps.reg0 = base;
   ps.reg1 = base + ps.bound0;
   ps.c00 = ps.c01 = ps.c10 = ps.c11 = 0;
   int64_t pair_anti = 0;
   if (!bad) {
-    const int64_t n_anti = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, true, 1u, 0u, cfg.eps,
-                                                cfg.tape_self, cfg.tape_partner, eacc);
-    pair_anti = n_anti;
-    if (n_anti <= sm.cap) {
+    // The first pass writes the commuting terms and collects all
+    // anticommuting ones.  If they do not fit in LDS they are processed in
+    // residue classes of a hash of the pair representative (both members of
+    // a {K, K^P} pair fall in the same class); oversized classes split.  One
+    // call site each for the scan and the join keeps the code small.
+    int* stk = sm.stack;   // pairs (mod, rem), written by thread 0
+    bool full = true;
+    uint32_t mod = 1, rem = 0;
+    for (;;) {
+      const int64_t na = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, full, mod, rem, cfg.eps,
+                                              cfg.tape_self, cfg.tape_partner, eacc);
       __syncthreads();
-      emit_anti<W, ENERGY>(out, P, sm, ps, (int)n_anti, split, m, cfg.C, cfg.S, cfg.eps,
-                           cfg.tape_self, cfg.tape_partner, eacc);
-    } else {
-      // more anticommuting terms than LDS holds: process them in residue
-      // classes of a hash of the pair representative (both members of a
-      // {K, K^P} pair always fall in the same class)
-      int* stk = sm.stack;  // pairs (mod, rem), written by thread 0
-      int r0 = 1;
-      while (r0 * (int64_t)sm.cap < 2 * n_anti && r0 < 32) r0 <<= 1;
-      if (tid == 0) {
-        for (int r = r0 - 1; r >= 0; --r) { stk[2 * (r0 - 1 - r)] = r0; stk[2 * (r0 - 1 - r) + 1] = r; }
-        sm.misc[2] = r0;
-      }
-      __syncthreads();
-      for (;;) {
-        const int sp = (int)sm.misc[2];
-        if (sp == 0) break;
-        const uint32_t mod = (uint32_t)stk[2 * (sp - 1)];
-        const uint32_t rem = (uint32_t)stk[2 * (sp - 1) + 1];
-        __syncthreads();
-        if (tid == 0) sm.misc[2] = sp - 1;
-        const int64_t nr = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, false, mod, rem, cfg.eps,
-                                                cfg.tape_self, cfg.tape_partner, eacc);
-        __syncthreads();
-        if (nr <= sm.cap) {
-          emit_anti<W, ENERGY>(out, P, sm, ps, (int)nr, split, m, cfg.C, cfg.S, cfg.eps,
-                               cfg.tape_self, cfg.tape_partner, eacc);
-        } else if (tid == 0) {
-          int t = (int)sm.misc[2];
-          if (t + 2 <= 120 && mod < (1u << 30)) {
-            stk[2 * t] = (int)(2 * mod); stk[2 * t + 1] = (int)(rem + mod);
-            stk[2 * t + 2] = (int)(2 * mod); stk[2 * t + 3] = (int)rem;
-            sm.misc[2] = t + 2;
-          } else {
-            atomicOr(out.err, 4);
+      if (full) pair_anti = na;
+      if (na <= sm.cap) {
+        emit_anti<W, ENERGY>(out, P, sm, ps, (int)na, split, m, cfg.C, cfg.S, cfg.eps,
+                             cfg.tape_self, cfg.tape_partner, eacc);
+      } else if (tid == 0) {
+        int t = (int)sm.misc[2];
+        if (full) {
+          int r0 = 1;
+          while (r0 * (int64_t)sm.cap < 2 * na && r0 < 32) r0 <<= 1;
+          for (int r = r0 - 1; r >= 0; --r) {
+            stk[2 * t] = r0;
+            stk[2 * t + 1] = r;
+            ++t;
           }
+        } else if (t + 2 <= 120 && mod < (1u << 30)) {
+          stk[2 * t] = (int)(2 * mod); stk[2 * t + 1] = (int)(rem + mod);
+          stk[2 * t + 2] = (int)(2 * mod); stk[2 * t + 3] = (int)rem;
+          t += 2;
+        } else {
+          atomicOr(out.err, 4);
         }
-        __syncthreads();
+        sm.misc[2] = t;
       }
+      __syncthreads();
+      const int sp = (int)sm.misc[2];
+      if (sp == 0) break;
+      mod = (uint32_t)stk[2 * (sp - 1)];
+      rem = (uint32_t)stk[2 * (sp - 1) + 1];
+      full = false;
+      __syncthreads();
+      if (tid == 0) sm.misc[2] = sp - 1;
     }
   }
   // bucket table of the output
@@ -524,10 +578,10 @@ __device__ __forceinline__ void flush_counts(const StoreDev& out, const StepCoun
 }
 
 template <int W, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Entangler P,
-                                                  DressConfig cfg) {
+__global__ __launch_bounds__(kDB) __attribute__((amdgpu_waves_per_eu(4))) void k_dress(StoreDev in, StoreDev out, Entangler P,
+                                               DressConfig cfg) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const Smem<W> sm = carve<W, ENERGY>(smem, cfg.anti_cap);
+  const Smem<W> sm = carve<W, ENERGY>(smem, cfg.anti_cap, cfg.tape_self != nullptr);
   const int tid = threadIdx.x;
   if (*in.err) {
     // the input is the invalid output of an earlier step: propagate, read nothing
@@ -547,7 +601,7 @@ __global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Ent
   const int thi = f ? 31 - __clz(f) : 0;
   if (blockIdx.x == 0 && tid == 0) *out.m = m + split;
   if (ENERGY) {
-    for (int i = tid; i < W * kGroupsPerWord * kLutEntries; i += kBlock) sm.lut[i] = cfg.lut[i];
+    for (int i = tid; i < W * kGroupsPerWord * kLutEntries; i += kDB) sm.lut[i] = cfg.lut[i];
     __syncthreads();
   }
   double eacc = 0.0;
@@ -559,7 +613,7 @@ __global__ __launch_bounds__(kBlock) void k_dress(StoreDev in, StoreDev out, Ent
   }
   flush_counts(out, counts);
   if (ENERGY) {
-    const double s = block_sum(eacc, sm.red);
+    const double s = block_sum_n<kDW>(eacc, sm.red);
     if (tid == 0) cfg.e_partial[blockIdx.x] = s;
   }
 }
@@ -608,11 +662,11 @@ __global__ void k_batch_plan(int n_ham, const BatchItem* items, BatchPlan* plan,
 }
 
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_dress_batch(int n_ham, const BatchItem* items,
-                                                        const BatchPlan* plan, DressConfig cfg,
-                                                        int64_t* queue) {
+__global__ __launch_bounds__(kDB) __attribute__((amdgpu_waves_per_eu(4))) void k_dress_batch(int n_ham, const BatchItem* items,
+                                                     const BatchPlan* plan, DressConfig cfg,
+                                                     int64_t* queue) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const Smem<W> sm = carve<W, false>(smem, cfg.anti_cap);
+  const Smem<W> sm = carve<W, false>(smem, cfg.anti_cap, false);
   const int64_t total = plan[n_ham].item_start;
   double eacc = 0.0;
   constexpr int64_t kGrab = 4;   // items taken per queue atomic
@@ -675,10 +729,10 @@ void launch_dress_batch(int W, int n_ham, const BatchItem* items, BatchPlan* pla
   hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(64), 0, s, n_ham, items, plan, cfg.split_thr, queue);
   const BatchPlan* cp = plan;
   switch (W) {
-    case 1: hipLaunchKernelGGL(k_dress_batch<1>, dim3(cfg.grid), dim3(kBlock), lds, s, n_ham, items, cp, cfg, queue); break;
-    case 2: hipLaunchKernelGGL(k_dress_batch<2>, dim3(cfg.grid), dim3(kBlock), lds, s, n_ham, items, cp, cfg, queue); break;
-    case 3: hipLaunchKernelGGL(k_dress_batch<3>, dim3(cfg.grid), dim3(kBlock), lds, s, n_ham, items, cp, cfg, queue); break;
-    default: hipLaunchKernelGGL(k_dress_batch<4>, dim3(cfg.grid), dim3(kBlock), lds, s, n_ham, items, cp, cfg, queue); break;
+    case 1: hipLaunchKernelGGL(k_dress_batch<1>, dim3(cfg.grid), dim3(kDB), lds, s, n_ham, items, cp, cfg, queue); break;
+    case 2: hipLaunchKernelGGL(k_dress_batch<2>, dim3(cfg.grid), dim3(kDB), lds, s, n_ham, items, cp, cfg, queue); break;
+    case 3: hipLaunchKernelGGL(k_dress_batch<3>, dim3(cfg.grid), dim3(kDB), lds, s, n_ham, items, cp, cfg, queue); break;
+    default: hipLaunchKernelGGL(k_dress_batch<4>, dim3(cfg.grid), dim3(kDB), lds, s, n_ham, items, cp, cfg, queue); break;
   }
 }
 
@@ -686,11 +740,9 @@ template <int W, bool E>
 static void launch_dress_t(const StoreDev& in, const StoreDev& out, const Entangler& P,
                            const DressConfig& cfg, hipStream_t s) {
   const size_t lds = dress_lds_bytes(W, cfg.anti_cap, E, cfg.tape_self != nullptr);
-  static bool attr_set[2] = {false, false};
-  (void)attr_set;
   hipFuncSetAttribute((const void*)k_dress<W, E>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
-  hipLaunchKernelGGL((k_dress<W, E>), dim3(cfg.grid), dim3(kBlock), lds, s, in, out, P, cfg);
+  hipLaunchKernelGGL((k_dress<W, E>), dim3(cfg.grid), dim3(kDB), lds, s, in, out, P, cfg);
 }
 
 void launch_dress(int W, const StoreDev& in, const StoreDev& out, const Entangler& P,

@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libiqcc.so")
+# IQCC_LIB points the binding at another build of the library (developer override)
+LIB_PATH = os.environ.get("IQCC_LIB", os.path.join(HERE, "libiqcc.so"))
 
 IQCC_OK = 0
 IQCC_ERR_INVALID_ARG = -1
