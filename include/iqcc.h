@@ -148,6 +148,19 @@ int iqcc_dress(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px, const ui
                double tau, double eps, const double *theta, const double *phi, double *energy,
                iqcc_store *out, void *stream);
 
+/* iqcc_dress with the energy carried forward: energy_in (DEVICE scalar) holds
+ * <Omega|in|Omega> for the same theta, phi; *energy_out (DEVICE scalar, may be
+ * the same address) receives <Omega|out|Omega>.  By Eq. 5 the terms that commute
+ * with P keep their coefficients, and the energy is linear in the coefficients
+ * (Eq. 3), so the pass evaluates <Omega|K|Omega> only for anticommuting terms,
+ * their images K*P and commuting terms removed by compression, and adds that
+ * change to *energy_in.  The result equals the full sum up to rounding order.
+ * All four energy arguments are required; otherwise as iqcc_dress. */
+int iqcc_dress_energy_update(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px,
+                             const uint64_t *pz, double tau, double eps, const double *theta,
+                             const double *phi, const double *energy_in, double *energy_out,
+                             iqcc_store *out, void *stream);
+
 /* Raw dressing (no merge, no compression) of flat device rows: for each input
  * row i (in order) emits row 2i = (A, c or RN(cos*c)) and, for anticommuting
  * rows only, row 2i+1 = (Q, s*RN(sin*c)).  Rows 2i+1 of commuting inputs are

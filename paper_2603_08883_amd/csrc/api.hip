@@ -403,8 +403,8 @@ int iqcc_store_export(iqcc_ctx* ctx, const iqcc_store* st, uint64_t* x, uint64_t
 
 static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
                       double tau, double eps, const double* theta, const double* phi,
-                      double* energy, iqcc_store* out, int64_t* tape_self, int64_t* tape_partner,
-                      void* stream) {
+                      const double* energy_in, double* energy, iqcc_store* out,
+                      int64_t* tape_self, int64_t* tape_partner, void* stream) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
   if (!in || !out || !px || !pz) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
@@ -440,6 +440,9 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
     LAUNCH_CHECK(ctx);
   }
   cfg.lut = fused ? ctx->lut : nullptr;
+  // with the input's energy known, the fused pass accumulates only the change
+  const bool delta = fused && energy_in;
+  cfg.delta = delta ? 1 : 0;
   cfg.e_partial = ctx->partial;
   cfg.tape_self = tape_self;
   cfg.tape_partner = tape_partner;
@@ -448,7 +451,7 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
   LAUNCH_CHECK(ctx);
   if (want_e) {
     if (!fused) launch_energy(W, out->d, grid, ctx->lut, ctx->partial, s);
-    launch_finalize_sum(ctx->partial, grid, nullptr, energy, s);
+    launch_finalize_sum(ctx->partial, grid, nullptr, energy, s, delta ? energy_in : nullptr);
     LAUNCH_CHECK(ctx);
   }
   return IQCC_OK;
@@ -457,7 +460,18 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
 int iqcc_dress(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
                double tau, double eps, const double* theta, const double* phi, double* energy,
                iqcc_store* out, void* stream) {
-  return dress_impl(ctx, in, px, pz, tau, eps, theta, phi, energy, out, nullptr, nullptr, stream);
+  return dress_impl(ctx, in, px, pz, tau, eps, theta, phi, nullptr, energy, out, nullptr, nullptr,
+                    stream);
+}
+
+int iqcc_dress_energy_update(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px,
+                             const uint64_t* pz, double tau, double eps, const double* theta,
+                             const double* phi, const double* energy_in, double* energy_out,
+                             iqcc_store* out, void* stream) {
+  if (ctx && (!theta || !phi || !energy_in || !energy_out))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "theta, phi, energy_in and energy_out are required");
+  return dress_impl(ctx, in, px, pz, tau, eps, theta, phi, energy_in, energy_out, out, nullptr,
+                    nullptr, stream);
 }
 
 int iqcc_store_rows(const iqcc_store* st, int64_t* rows) {
@@ -470,7 +484,7 @@ int iqcc_dress_taped(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, co
                      double tau, double eps, iqcc_store* out, int64_t* tape_self,
                      int64_t* tape_partner, void* stream) {
   if (ctx && (!tape_self || !tape_partner)) return fail(ctx, IQCC_ERR_INVALID_ARG, "tape arrays are null");
-  return dress_impl(ctx, in, px, pz, tau, eps, nullptr, nullptr, nullptr, out, tape_self,
+  return dress_impl(ctx, in, px, pz, tau, eps, nullptr, nullptr, nullptr, nullptr, out, tape_self,
                     tape_partner, stream);
 }
 

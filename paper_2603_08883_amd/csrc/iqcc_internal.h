@@ -260,6 +260,7 @@ struct DressConfig {
   int anti_cap;
   int grid;
   const double* lut;   // null: no fused energy
+  int delta;           // 1: e_partial accumulates only the change of the energy
   double* e_partial;   // [grid]
   int64_t* tape_self;     // null, or per input arena row: output row of K (-1 dropped)
   int64_t* tape_partner;  //   and output row of K^P (-1 absent/dropped, -2 commuting)
@@ -287,8 +288,9 @@ size_t dress_lds_bytes(int W, int anti_cap, bool energy, bool tape);
 void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double* c, int64_t n,
                       int64_t ld, const Entangler& P, double C, double S, uint64_t* ox,
                       uint64_t* oz, double* oc, int8_t* flag, int64_t ld_out, hipStream_t s);
+// *out = (base ? *base : 0) + (scale ? *scale : 1) * sum(partial[0..n)); out may alias base.
 void launch_finalize_sum(const double* partial, int n, const double* scale, double* out,
-                         hipStream_t s);
+                         hipStream_t s, const double* base = nullptr);
 
 void launch_energy(int W, const StoreDev& st, int grid, const double* lut, double* e_partial,
                    hipStream_t s);

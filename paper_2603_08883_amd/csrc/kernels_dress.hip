@@ -15,9 +15,15 @@
 // is 0) and each coefficient is a single IEEE addition.  Commuting terms
 // stream straight through.  Bucket b's outputs fill its region from the front
 // (child 0) and, when the step doubles the bucket count, from the back
-// (child 1).  The energy of every output is formed while the input term is in
-// registers: <K> = A * B and <K^P> = A * B', where B, B' run over the few
-// 3-qubit groups P touches and A over the rest of K.
+// (child 1).
+//
+// Output positions come from per-wave reservations: each wave ranks its lanes
+// per output category with ballots and takes a block of rows with one LDS
+// atomic per counter word, so the streaming passes have no workgroup barrier
+// (rows within a category are in wave-arrival order; the set of terms is
+// unique).  The energy of an anticommuting term is formed once, after
+// compaction into LDS: <K> = A * B and <K^P> = A * B', where B, B' run over
+// the few 3-qubit groups P touches and A over the rest of K.
 #include "iqcc_internal.h"
 
 #pragma clang fp contract(off)
@@ -26,8 +32,6 @@ namespace iqcc {
 
 constexpr int kDB = 512;                  // threads per dressing workgroup
 constexpr int kDW = kDB / 64;             // waves per dressing workgroup
-constexpr int kFieldBits = 12;            // packed per-category counters (<= 1024 per round)
-constexpr uint64_t kFieldMask = (1u << kFieldBits) - 1;
 
 __host__ __device__ inline int next_pow2_int(int v) {
   int p = 1;
@@ -39,11 +43,10 @@ size_t dress_lds_bytes(int W, int cap, bool energy, bool tape) {
   size_t o = energy ? (size_t)W * kGroupsPerWord * kLutEntries * 8 : 0;
   o += (size_t)W * cap * 8 * 2;                  // keys
   o += (size_t)cap * 8;                          // coefficients
-  if (energy) o += (size_t)cap * 8 * 2;          // <K>, <K^P>
   o += (size_t)next_pow2_int(2 * cap) * 4;       // hash table
   o += (size_t)cap * 2;                          // partner
   o += ((size_t)cap + 7) & ~(size_t)7;           // side
-  o += 8 * 8 + 8 * 8 + 8 * 8 + 256 * 4;          // scan, reduce, misc, round stack
+  o += 8 * 8 + 8 * 8 + 8 * 8 + 256 * 4 + 4 * 8;  // scan, reduce, misc, round stack, counters
   if (tape) o += (size_t)cap * 8 * 2;            // tape: input row, own output row
   return o;
 }
@@ -54,8 +57,6 @@ struct Smem {
   uint64_t* ax;
   uint64_t* az;
   double* ac;
-  double* ek;     // <K> of each anticommuting entry
-  double* ekp;    // <K^P>
   int* tab;
   int16_t* partner;
   uint8_t* side;
@@ -63,6 +64,7 @@ struct Smem {
   double* red;
   int64_t* misc;
   int* stack;
+  unsigned long long* ctr;   // per-pair output counters: [c00|c01<<32, c10|c11<<32, anti]
   int64_t* arow;   // tape: input row of each anticommuting entry
   int64_t* orow;   // tape: output row of its own key (-1 if dropped)
   int cap, ts;
@@ -77,8 +79,6 @@ __device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap, bool tape
   s.ax = (uint64_t*)(smem + o); o += (size_t)W * cap * 8;
   s.az = (uint64_t*)(smem + o); o += (size_t)W * cap * 8;
   s.ac = (double*)(smem + o); o += (size_t)cap * 8;
-  s.ek = (double*)(smem + o); o += ENERGY ? (size_t)cap * 8 : 0;
-  s.ekp = (double*)(smem + o); o += ENERGY ? (size_t)cap * 8 : 0;
   s.ts = next_pow2_int(2 * cap);
   s.tab = (int*)(smem + o); o += (size_t)s.ts * 4;
   s.partner = (int16_t*)(smem + o); o += (size_t)cap * 2;
@@ -87,6 +87,7 @@ __device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap, bool tape
   s.red = (double*)(smem + o); o += 64;
   s.misc = (int64_t*)(smem + o); o += 64;
   s.stack = (int*)(smem + o); o += 256 * 4;
+  s.ctr = (unsigned long long*)(smem + o); o += 4 * 8;
   // tape rows (only carved, and only touched, when the step records a tape)
   s.arow = (int64_t*)(smem + o); o += tape ? (size_t)cap * 8 : 0;
   s.orow = (int64_t*)(smem + o);
@@ -94,21 +95,13 @@ __device__ __forceinline__ Smem<W> carve(unsigned char* smem, int cap, bool tape
   return s;
 }
 
+// Output category of a term: 2 * side + child (side: which bucket of the
+// pair, child: which half after a split).  Category 4: anticommuting, to LDS.
 struct PairState {
   int64_t n0, n1, off0, off1, ntot;
   int64_t reg0, reg1, bound0, bound1;
-  int64_t c00, c01, c10, c11;   // outputs written per (side, child); category = 2*side + child
   uint32_t b0, b1;
   bool self;
-  __device__ __forceinline__ int64_t cnt(int cat) const {
-    return cat == 0 ? c00 : cat == 1 ? c01 : cat == 2 ? c10 : c11;
-  }
-  __device__ __forceinline__ void add_packed(uint64_t total) {
-    c00 += (int64_t)(total & kFieldMask);
-    c01 += (int64_t)((total >> kFieldBits) & kFieldMask);
-    c10 += (int64_t)((total >> (2 * kFieldBits)) & kFieldMask);
-    c11 += (int64_t)((total >> (3 * kFieldBits)) & kFieldMask);
-  }
   __device__ __forceinline__ int64_t row(int cat, int64_t k) const {
     const int64_t reg = (cat >> 1) ? reg1 : reg0;
     const int64_t bound = (cat >> 1) ? bound1 : bound0;
@@ -165,6 +158,54 @@ __device__ __forceinline__ uint32_t rep_hash(const Entangler& P, const uint64_t*
   return table_hash<W>(rx, rz);
 }
 
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ unsigned long long wave_bcast0(unsigned long long v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Row positions for up to two entries per lane (categories a and b in
+// [0, 2 * NWORD), -1 for none) from the LDS counters ctr[0..NWORD), which hold
+// two 32-bit fields each (category 2k in the low field of word k, 2k + 1 in
+// the high field).  Within a wave, all a-entries of a category precede its
+// b-entries, each in lane order; the wave's block comes from one LDS atomic
+// per counter word it touches.  Must be called by the whole wave (every lane
+// active, wave-uniform control flow).  Returns the number of b-entries of the
+// wave (wave-uniform).
+template <int NWORD, bool TWO>
+__device__ __forceinline__ uint32_t wave_positions(unsigned long long* ctr, int a, int b,
+                                                   uint32_t& pa, uint32_t& pb) {
+  uint32_t nb = 0;
+#pragma unroll
+  for (int k = 0; k < NWORD; ++k) {
+    const uint64_t ma0 = __ballot(a == 2 * k);
+    const uint64_t ma1 = __ballot(a == 2 * k + 1);
+    const uint64_t mb0 = TWO ? __ballot(b == 2 * k) : 0ull;
+    const uint64_t mb1 = TWO ? __ballot(b == 2 * k + 1) : 0ull;
+    if ((ma0 | ma1 | mb0 | mb1) == 0) continue;
+    const uint32_t na0 = (uint32_t)__popcll(ma0), na1 = (uint32_t)__popcll(ma1);
+    const uint32_t nb0 = (uint32_t)__popcll(mb0), nb1 = (uint32_t)__popcll(mb1);
+    nb += nb0 + nb1;
+    const unsigned long long inc = (unsigned long long)(na0 + nb0) |
+                                   ((unsigned long long)(na1 + nb1) << 32);
+    unsigned long long old = 0;
+    if ((threadIdx.x & 63) == 0) old = atomicAdd(&ctr[k], inc);
+    old = wave_bcast0(old);
+    const uint32_t lo = (uint32_t)old, hi = (uint32_t)(old >> 32);
+    if (a == 2 * k) pa = lo + lanes_below(ma0);
+    if (a == 2 * k + 1) pa = hi + lanes_below(ma1);
+    if (TWO) {
+      if (b == 2 * k) pb = lo + na0 + lanes_below(mb0);
+      if (b == 2 * k + 1) pb = hi + na1 + lanes_below(mb1);
+    }
+  }
+  return nb;
+}
+
 // <K> and <K^P> of the product state: A over the non-identity groups of K
 // that P does not touch (four independent lookups per iteration), B and B'
 // over P's groups for K and K^P.
@@ -212,20 +253,19 @@ __device__ __forceinline__ void expect_split(const double* lut, const Entangler&
   ekp = a * b2;
 }
 
-// One pass over the pair's input terms (one term per thread per round).
-// Commuting terms are written to the output when `full`; anticommuting terms
-// whose representative hash falls in residue class `rem` mod `mod` are
-// appended to the LDS list (up to cap).  Returns the number of such
-// anticommuting terms (block-uniform).
+// One pass over the pair's input terms, each wave on its own 64-term slices
+// (no workgroup barrier).  Commuting terms are written to the output when
+// `full`; anticommuting terms whose representative hash falls in residue
+// class `rem` mod `mod` are appended to the LDS list (up to cap; the count is
+// in ctr[2] afterwards).
 template <int W, bool ENERGY>
-__device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
-                             const Smem<W>& sm, PairState& ps, int split, int m, bool full,
-                             uint32_t mod, uint32_t rem, double eps, int64_t* tape_self,
-                             int64_t* tape_partner, double& eacc) {
-  const int tid = threadIdx.x;
-  int64_t n_anti = 0;
-  for (int64_t i0 = 0; i0 < ps.ntot; i0 += kDB) {
-    const int64_t idx = i0 + tid;
+__device__ void scan_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
+                          const Smem<W>& sm, const PairState& ps, int split, int m, bool full,
+                          uint32_t mod, uint32_t rem, double eps, int delta,
+                          int64_t* tape_self, int64_t* tape_partner, double& eacc) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i0 = (threadIdx.x & ~63); i0 < ps.ntot; i0 += kDB) {
+    const int64_t idx = i0 + lane;
     const bool valid = idx < ps.ntot;
     const int kside = idx >= ps.n0;
     const int64_t krow = kside ? ps.off1 + (idx - ps.n0) : ps.off0 + idx;
@@ -235,6 +275,7 @@ __device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Enta
     for (int w = 0; w < W; ++w) kx[w] = kz[w] = 0;
     if (valid) load_key<W>(in, krow, kx, kz, kc);
     int cat = -1;
+    bool dropped = false;   // a commuting term removed by compression
     if (valid) {
       if (anticommutes<W>(kx, kz, P.px, P.pz)) {
         if (mod == 1 || (round_hash(rep_hash<W>(P, kx, kz)) & (mod - 1)) == rem) cat = 4;
@@ -243,58 +284,52 @@ __device__ int64_t scan_pair(const StoreDev& in, const StoreDev& out, const Enta
           // commuting terms keep their coefficient; compression applies to them too
           const int child = split ? (int)((bucket_hash<W>(kx, kz) >> m) & 1u) : 0;
           cat = kside * 2 + child;
-        } else if (tape_self) {
-          tape_self[krow] = -1;
-          tape_partner[krow] = -2;
+        } else {
+          dropped = true;
+          if (tape_self) {
+            tape_self[krow] = -1;
+            tape_partner[krow] = -2;
+          }
         }
       }
     }
-    double ek = 0.0, ekp = 0.0;
-    if (ENERGY && cat >= 0) expect_split<W>(sm.lut, P, kx, kz, ek, ekp);
-    uint64_t total;
-    const uint64_t ex = block_exclusive_scan_n<kDW>(cat >= 0 ? 1ull << (kFieldBits * cat) : 0ull,
-                                                    sm.scan, total);
-    if (cat >= 0) {
-      const int64_t k = (int64_t)((ex >> (kFieldBits * cat)) & kFieldMask);
-      if (cat == 4) {
-        const int64_t slot = n_anti + k;
-        if (slot < sm.cap) {
+    // Energy of commuting terms: every kept one, or (delta) only those that
+    // compression removes.  Anticommuting terms are evaluated after the join.
+    if (ENERGY && (delta ? dropped : (cat >= 0 && cat < 4))) {
+      const double ek = expect_lut<W>(sm.lut, kx, kz);
+      eacc += dropped ? -(kc * ek) : kc * ek;
+    }
+    uint32_t pos = 0, unused = 0;
+    wave_positions<3, false>(sm.ctr, cat, -1, pos, unused);
+    if (cat == 4) {
+      if ((int)pos < sm.cap) {
 #pragma unroll
-          for (int w = 0; w < W; ++w) {
-            sm.ax[w * sm.cap + slot] = kx[w];
-            sm.az[w * sm.cap + slot] = kz[w];
-          }
-          sm.ac[slot] = kc;
-          sm.side[slot] = (uint8_t)kside;
-          if (ENERGY) {
-            sm.ek[slot] = ek;
-            sm.ekp[slot] = ekp;
-          }
-          if (tape_self) sm.arow[slot] = krow;
+        for (int w = 0; w < W; ++w) {
+          sm.ax[w * sm.cap + pos] = kx[w];
+          sm.az[w * sm.cap + pos] = kz[w];
         }
-      } else {
-        const int64_t orow = ps.row(cat, ps.cnt(cat) + k);
-        store_key<W>(out, orow, kx, kz, kc);
-        if (ENERGY) eacc += kc * ek;
-        if (tape_self) {
-          tape_self[krow] = orow;
-          tape_partner[krow] = -2;
-        }
+        sm.ac[pos] = kc;
+        sm.side[pos] = (uint8_t)kside;
+        if (tape_self) sm.arow[pos] = krow;
+      }
+    } else if (cat >= 0) {
+      const int64_t orow = ps.row(cat, pos);
+      store_key<W>(out, orow, kx, kz, kc);
+      if (tape_self) {
+        tape_self[krow] = orow;
+        tape_partner[krow] = -2;
       }
     }
-    ps.add_packed(total);
-    n_anti += (int64_t)((total >> (kFieldBits * 4)) & kFieldMask);
   }
-  return n_anti;
 }
 
 // Join the n (<= cap) anticommuting terms held in LDS and emit the rotated
 // and new terms.
 template <int W, bool ENERGY>
 __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>& sm,
-                          PairState& ps, int n, int split, int m, double C, double S,
-                          double eps, int64_t* tape_self, int64_t* tape_partner,
-                          double& eacc) {
+                          const PairState& ps, int n, int split, int m, double C, double S,
+                          double eps, int delta, int64_t* tape_self, int64_t* tape_partner,
+                          double& eacc, int64_t& fresh) {
   const int tid = threadIdx.x;
   const uint32_t tmask = (uint32_t)sm.ts - 1;
   for (int i = tid; i < sm.ts; i += kDB) sm.tab[i] = -1;
@@ -340,11 +375,12 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
   }
   __syncthreads();
   const int child_p = split ? (int)((P.hp >> m) & 1u) : 0;
-  for (int i0 = 0; i0 < n; i0 += kDB) {
-    const int i = i0 + tid;
+  const int lane = threadIdx.x & 63;
+  for (int i0 = (threadIdx.x & ~63); i0 < n; i0 += kDB) {   // wave-uniform
+    const int i = i0 + lane;
     const bool valid = i < n;
     uint64_t kx[W], kz[W];
-    double v_own = 0.0, v_new = 0.0;
+    double v_own = 0.0, v_new = 0.0, a = 0.0;
     int cat_own = -1, cat_new = -1;
     if (valid) {
 #pragma unroll
@@ -352,7 +388,7 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
         kx[w] = sm.ax[w * sm.cap + i];
         kz[w] = sm.az[w * sm.cap + i];
       }
-      const double a = sm.ac[i];
+      a = sm.ac[i];
       const int side = sm.side[i];
       const int j = sm.partner[i];
       const int child = split ? (int)((bucket_hash<W>(kx, kz) >> m) & 1u) : 0;
@@ -379,24 +415,24 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
         }
       }
       if (!(fabs(v_own) < eps)) cat_own = side * 2 + child;
+      if (ENERGY) {
+        // <K> and <K^P>; (delta) A's contribution before the step is removed
+        double ek, ekp;
+        expect_split<W>(sm.lut, P, kx, kz, ek, ekp);
+        if (cat_own >= 0) eacc += v_own * ek;
+        if (cat_new >= 0) eacc += v_new * ekp;
+        if (delta) eacc -= a * ek;
+      }
     }
-    uint64_t packed = 0;
-    if (cat_own >= 0) packed += 1ull << (kFieldBits * cat_own);
-    if (cat_new >= 0) packed += 1ull << (kFieldBits * cat_new);
-    uint64_t total;
-    uint64_t ex = block_exclusive_scan_n<kDW>(packed, sm.scan, total);
+    uint32_t own_pos = 0, new_pos = 0;
+    fresh += wave_positions<2, true>(sm.ctr, cat_own, cat_new, own_pos, new_pos);
     int64_t own_row = -1, new_row = -1;
     if (cat_own >= 0) {
-      const int64_t k = (int64_t)((ex >> (kFieldBits * cat_own)) & kFieldMask);
-      ex += 1ull << (kFieldBits * cat_own);
-      own_row = ps.row(cat_own, ps.cnt(cat_own) + k);
+      own_row = ps.row(cat_own, own_pos);
       store_key<W>(out, own_row, kx, kz, v_own);
-      if (ENERGY) eacc += v_own * sm.ek[i];
     }
     if (cat_new >= 0) {
-      atomicAdd((unsigned long long*)&sm.misc[3], 1ull);
-      const int64_t k = (int64_t)((ex >> (kFieldBits * cat_new)) & kFieldMask);
-      new_row = ps.row(cat_new, ps.cnt(cat_new) + k);
+      new_row = ps.row(cat_new, new_pos);
       uint64_t qx[W], qz[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
@@ -404,14 +440,12 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
         qz[w] = kz[w] ^ P.pz[w];
       }
       store_key<W>(out, new_row, qx, qz, v_new);
-      if (ENERGY) eacc += v_new * sm.ekp[i];
     }
     if (tape_self && valid) {
       sm.orow[i] = own_row;
       tape_self[sm.arow[i]] = own_row;
       if (sm.partner[i] < 0) tape_partner[sm.arow[i]] = new_row;
     }
-    ps.add_packed(total);
   }
   __syncthreads();
   if (tape_self) {
@@ -471,7 +505,8 @@ __device__ int64_t reserve_rows(const StoreDev& in, const StoreDev& out, int64_t
 // Per-workgroup totals of one step, flushed to the output store's device
 // counters once at the end (same-address global atomics serialise in L2).
 struct StepCounts {
-  int64_t produced = 0, anti = 0, fresh = 0;
+  int64_t produced = 0, anti = 0;   // thread 0 of the workgroup
+  int64_t fresh = 0;                // per wave (lane 0 flushes)
 };
 
 // Everything one workgroup does for bucket pair `pi` of one dressing step;
@@ -495,12 +530,11 @@ __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Enta
   const bool bad = base < 0;
   if (tid == 0) {
     sm.misc[2] = 0;   // round stack depth
-    sm.misc[3] = 0;   // new terms of this pair
+    sm.ctr[0] = sm.ctr[1] = sm.ctr[2] = 0;
   }
   __syncthreads();
   ps.reg0 = base;
   ps.reg1 = base + ps.bound0;
-  ps.c00 = ps.c01 = ps.c10 = ps.c11 = 0;
   int64_t pair_anti = 0;
   if (!bad) {
     // The first pass writes the commuting terms and collects all
@@ -512,13 +546,14 @@ __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Enta
     bool full = true;
     uint32_t mod = 1, rem = 0;
     for (;;) {
-      const int64_t na = scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, full, mod, rem, cfg.eps,
-                                              cfg.tape_self, cfg.tape_partner, eacc);
+      scan_pair<W, ENERGY>(in, out, P, sm, ps, split, m, full, mod, rem, cfg.eps, cfg.delta,
+                           cfg.tape_self, cfg.tape_partner, eacc);
       __syncthreads();
+      const int64_t na = (int64_t)(uint32_t)sm.ctr[2];
       if (full) pair_anti = na;
       if (na <= sm.cap) {
-        emit_anti<W, ENERGY>(out, P, sm, ps, (int)na, split, m, cfg.C, cfg.S, cfg.eps,
-                             cfg.tape_self, cfg.tape_partner, eacc);
+        emit_anti<W, ENERGY>(out, P, sm, ps, (int)na, split, m, cfg.C, cfg.S, cfg.eps, cfg.delta,
+                             cfg.tape_self, cfg.tape_partner, eacc, counts.fresh);
       } else if (tid == 0) {
         int t = (int)sm.misc[2];
         if (full) {
@@ -545,7 +580,11 @@ __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Enta
       rem = (uint32_t)stk[2 * (sp - 1) + 1];
       full = false;
       __syncthreads();
-      if (tid == 0) sm.misc[2] = sp - 1;
+      if (tid == 0) {
+        sm.misc[2] = sp - 1;
+        sm.ctr[2] = 0;   // the next round counts its own class
+      }
+      __syncthreads();
     }
   }
   // bucket table of the output
@@ -554,9 +593,10 @@ __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Enta
     const int nside = ps.self ? 1 : 2;
     for (int s = 0; s < nside; ++s) {
       const uint32_t b = s ? ps.b1 : ps.b0;
+      const unsigned long long word = sm.ctr[s];
       for (int ch = 0; ch < 1 + split; ++ch) {
         const uint32_t ob = b + ((uint32_t)ch << m);
-        const int64_t k = bad ? 0 : ps.cnt(2 * s + ch);
+        const int64_t k = bad ? 0 : (int64_t)(uint32_t)(ch ? word >> 32 : word);
         out.cnt[ob] = k;
         out.off[ob] = ps.row(2 * s + ch, k - 1) - (ch ? 0 : k - 1);
         produced += k;
@@ -564,7 +604,6 @@ __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Enta
     }
     counts.produced += produced;
     counts.anti += pair_anti;
-    counts.fresh += sm.misc[3];
   }
   __syncthreads();
 }
@@ -573,8 +612,9 @@ __device__ __forceinline__ void flush_counts(const StoreDev& out, const StepCoun
   if (threadIdx.x == 0) {
     if (counts.produced) atomicAdd((unsigned long long*)out.total, (unsigned long long)counts.produced);
     if (counts.anti) atomicAdd((unsigned long long*)&out.stats[0], (unsigned long long)counts.anti);
-    if (counts.fresh) atomicAdd((unsigned long long*)&out.stats[1], (unsigned long long)counts.fresh);
   }
+  if ((threadIdx.x & 63) == 0 && counts.fresh)
+    atomicAdd((unsigned long long*)&out.stats[1], (unsigned long long)counts.fresh);
 }
 
 template <int W, bool ENERGY>

@@ -47,17 +47,21 @@ void launch_build_lut(int W, int nq, const double* theta, const double* phi, dou
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of per-workgroup partials: out = scale * sum.
 // ---------------------------------------------------------------------------
-__global__ void k_finalize_sum(const double* partial, int n, const double* scale, double* out) {
+__global__ void k_finalize_sum(const double* partial, int n, const double* scale,
+                               const double* base, double* out) {
   __shared__ double red[kWaves];
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) *out = scale ? s * *scale : s;
+  if (threadIdx.x == 0) {
+    if (scale) s *= *scale;
+    *out = base ? *base + s : s;
+  }
 }
 
 void launch_finalize_sum(const double* partial, int n, const double* scale, double* out,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize_sum, dim3(1), dim3(kBlock), 0, s, partial, n, scale, out);
+                         hipStream_t s, const double* base) {
+  hipLaunchKernelGGL(k_finalize_sum, dim3(1), dim3(kBlock), 0, s, partial, n, scale, base, out);
 }
 
 // ---------------------------------------------------------------------------

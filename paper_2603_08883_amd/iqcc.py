@@ -62,6 +62,7 @@ def lib():
         "iqcc_store_stats": (i32, [P, P, ct.POINTER(i64), ct.POINTER(i64), P]),
         "iqcc_store_lookup": (i32, [P, P, P, P, i64, i64, P, P, P]),
         "iqcc_dress": (i32, [P, P, P, P, d, d, P, P, P, P, P]),
+        "iqcc_dress_energy_update": (i32, [P, P, P, P, d, d, P, P, P, P, P, P]),
         "iqcc_dress_raw": (i32, [P, i32, P, P, P, i64, i64, P, P, d, P, P, P, P, i64, P]),
         "iqcc_merge_truncate": (i32, [P, P, P, P, i64, i64, d, P, P]),
         "iqcc_qmf_energy": (i32, [P, P, P, P, P, P]),
@@ -90,7 +91,7 @@ def exported_symbols():
         "iqcc_set_param", "iqcc_get_param", "iqcc_store_create", "iqcc_store_destroy",
         "iqcc_store_shape", "iqcc_store_load", "iqcc_store_count", "iqcc_store_export",
         "iqcc_store_stats", "iqcc_store_lookup",
-        "iqcc_dress", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
+        "iqcc_dress", "iqcc_dress_energy_update", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
         "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
         "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
         "iqcc_dress_batched", "iqcc_batch_create", "iqcc_batch_launch", "iqcc_batch_destroy",
@@ -219,6 +220,16 @@ def iqcc_dress(ctx, store_in, px, pz, tau: float, eps: float, store_out, theta=N
     az, pzp = _words(pz)
     _check(lib().iqcc_dress(ctx, store_in, pxp, pzp, float(tau), float(eps), _ptr(theta),
                             _ptr(phi), _ptr(energy), store_out, _stream(stream)), ctx)
+
+
+def iqcc_dress_energy_update(ctx, store_in, px, pz, tau: float, eps: float, store_out, theta, phi,
+                             energy_in, energy_out, stream=None):
+    """Dressing step with the energy carried forward: energy_out = <out> given energy_in = <in>."""
+    ax, pxp = _words(px)
+    az, pzp = _words(pz)
+    _check(lib().iqcc_dress_energy_update(ctx, store_in, pxp, pzp, float(tau), float(eps),
+                                          _ptr(theta), _ptr(phi), _ptr(energy_in),
+                                          _ptr(energy_out), store_out, _stream(stream)), ctx)
 
 
 def iqcc_dress_raw(ctx, n_qubits, x, z, c, px, pz, tau, stream=None):

@@ -7,8 +7,9 @@ times (default knobs, fused energy, ping-pong stores).
   one by one by the oracle's point query of the chain (bit-exact), and keys
   K ^ P_j around them are checked both ways (present/absent and value) through
   the device lookup.
-* The energy fused into every dressing step equals the stand-alone energy
-  kernel on that step's output (property that holds at any size).
+* The energy fused into every dressing step (computed in full on even steps,
+  carried forward from the previous step on odd ones) equals the stand-alone
+  energy kernel on that step's output (property that holds at any size).
 """
 import numpy as np
 import pytest
@@ -46,8 +47,13 @@ def test_full_size_chain(workload):
     ox, oz, oc = x, z, c
     for j, ((px, pz), t) in enumerate(zip(ents, taus)):
         dst = outs[j % 2]
-        describe(j, "full-size dress", n=src.count())
-        iqcc.iqcc_dress(ctx.handle, src.handle, px, pz, t, EPS, dst.handle, tht, pht, e[j:j + 1])
+        describe(j, "full-size dress", n=src.count(), update=j % 2)
+        if j % 2:
+            # odd steps carry the energy forward from the previous step's result
+            iqcc.iqcc_dress_energy_update(ctx.handle, src.handle, px, pz, t, EPS, dst.handle, tht, pht,
+                                          e[j - 1:j], e[j:j + 1])
+        else:
+            iqcc.iqcc_dress(ctx.handle, src.handle, px, pz, t, EPS, dst.handle, tht, pht, e[j:j + 1])
         n = dst.count()
         # fused energy == stand-alone energy kernel on the same output
         e2 = iqcc.iqcc_qmf_energy(ctx.handle, dst.handle, tht, pht)

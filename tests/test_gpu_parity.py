@@ -34,7 +34,11 @@ def _angles(nq, seed):
 
 
 def _chain_compare(ctx, nq, x, z, c, ents, taus, eps, th, ph, max_terms, compare_every=1,
-                   params=None):
+                   params=None, update=False):
+    """Dress step by step on the GPU and in the oracle; compare every few steps.
+
+    update=True carries the energy forward with iqcc_dress_energy_update (the
+    input energy from iqcc_qmf_energy on H0, then each step's own result)."""
     params = params or {}
     old = {k: iqcc.iqcc_get_param(ctx.handle, k) for k in params}
     for k, v in params.items():
@@ -44,10 +48,16 @@ def _chain_compare(ctx, nq, x, z, c, ents, taus, eps, th, ph, max_terms, compare
         b = iqcc.Store(ctx, nq, max_terms)
         tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
         e = torch.zeros((), dtype=torch.float64, device="cuda")
+        if update:
+            iqcc.iqcc_qmf_energy(ctx.handle, a.handle, tht, pht, e)
         ox, oz, oc = x, z, c
         for j, ((px, pz), t) in enumerate(zip(ents, taus)):
-            describe(j, "dress", nq=nq, n=len(oc), tau=t, eps=eps, params=params)
-            iqcc.iqcc_dress(ctx.handle, a.handle, px, pz, t, eps, b.handle, tht, pht, e)
+            describe(j, "dress", nq=nq, n=len(oc), tau=t, eps=eps, params=params, update=update)
+            if update:
+                iqcc.iqcc_dress_energy_update(ctx.handle, a.handle, px, pz, t, eps, b.handle, tht, pht,
+                                              e, e)
+            else:
+                iqcc.iqcc_dress(ctx.handle, a.handle, px, pz, t, eps, b.handle, tht, pht, e)
             torch.cuda.synchronize()
             ox, oz, oc = O.dress(nq, ox, oz, oc, px, pz, t, eps)
             if j % compare_every == 0 or j == len(taus) - 1:
@@ -94,34 +104,54 @@ def test_dress_c1(ctx):
     _chain_compare(ctx, nq, x, z, c, [(px, pz)], [0.1], 0.0, th, ph, 4 * len(c))
 
 
-def test_chain_c2(ctx):
+@pytest.mark.parametrize("update", [False, True])
+def test_chain_c2(ctx, update):
     """40 qubits, 10 DIS entanglers, |c| < 1e-8 dropped after each step."""
     nq = 40
     x, z, c = I.hamiltonian_dense(nq, 1)
     cx, cz = I.dis_candidates(x, nq, 10, 8, I.rng_for(1, I.PURPOSE_ENTANGLERS))
     taus = I.taus(10, I.rng_for(1, I.PURPOSE_TAUS))
     th, ph = I.qmf_angles(nq, I.rng_for(1, I.PURPOSE_ANGLES))
-    _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), taus, 1e-8, th, ph, 2 * 10**7)
+    _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), taus, 1e-8, th, ph, 2 * 10**7, update=update)
 
 
-def test_chain_two_words(ctx):
+@pytest.mark.parametrize("update", [False, True])
+def test_chain_two_words(ctx, update):
     """124 qubits (two words per key), banded integrals with band 2, 6 steps."""
     nq = 124
     x, z, c = I.hamiltonian_banded(nq, 7, band=2)
     cx, cz = I.dis_candidates(x, nq, 6, 8, np.random.default_rng(70))
     taus = I.taus(6, np.random.default_rng(71))
     th, ph = I.qmf_angles(nq, np.random.default_rng(72))
-    _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), taus, 1e-8, th, ph, 4 * 10**6)
+    _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), taus, 1e-8, th, ph, 4 * 10**6, update=update)
 
 
-def test_chain_overflow_rounds(ctx):
+@pytest.mark.parametrize("update", [False, True])
+def test_chain_overflow_rounds(ctx, update):
     """Tiny LDS capacity and large buckets force the hash-round path."""
     nq = 40
     x, z, c = I.hamiltonian_dense(nq, 1)
     cx, cz = I.dis_candidates(x, nq, 3, 8, np.random.default_rng(5))
     th, ph = I.qmf_angles(nq, np.random.default_rng(6))
     _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), [0.15, -0.12, 0.08], 1e-8, th, ph, 4 * 10**6,
-                   params={"anti_cap": 16, "load_bucket_terms": 4096, "split_bucket_terms": 10**6})
+                   params={"anti_cap": 16, "load_bucket_terms": 4096, "split_bucket_terms": 10**6},
+                   update=update)
+
+
+def test_energy_update_drops_commuting_terms(ctx):
+    """Commuting terms below eps are removed; the carried energy must lose them.
+
+    Every third coefficient of the 12-qubit Hamiltonian is scaled below eps,
+    so the first step drops commuting and anticommuting terms alike."""
+    nq = 12
+    x, z, c = I.hamiltonian_dense(nq, 9)
+    c = c.copy()
+    c[::3] *= 1e-10
+    th, ph = I.qmf_angles(nq, np.random.default_rng(13))
+    cx, cz = I.dis_candidates(x, nq, 3, 6, np.random.default_rng(14))
+    for eps in (1e-8, 1e-3):
+        _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), [0.3, -0.2, 0.1], eps, th, ph, 4 * len(c),
+                       update=True)
 
 
 def test_chain_split_every_step(ctx):
@@ -148,6 +178,11 @@ def test_edge_cases(ctx):
     # single term, and an empty Hamiltonian
     _chain_compare(ctx, nq, x[:1], z[:1], c[:1], [(cx[0], cz[0])], [0.3], 0.0, th, ph, 16)
     _chain_compare(ctx, nq, x[:0], z[:0], c[:0], [(cx[0], cz[0])], [0.3], 0.0, th, ph, 16)
+    # the same with the energy carried forward
+    _chain_compare(ctx, nq, x, z, c, [ident], [0.3], 0.0, th, ph, 4 * len(c), update=True)
+    _chain_compare(ctx, nq, x, z, c, [(cx[0], cz[0])], [0.0], 0.0, th, ph, 4 * len(c), update=True)
+    _chain_compare(ctx, nq, x, z, c, [(cx[0], cz[0])], [0.3], 1e9, th, ph, 4 * len(c), update=True)
+    _chain_compare(ctx, nq, x[:0], z[:0], c[:0], [(cx[0], cz[0])], [0.3], 0.0, th, ph, 16, update=True)
 
 
 def test_invalid_arguments(ctx):
