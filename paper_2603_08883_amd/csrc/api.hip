@@ -15,11 +15,12 @@ struct iqcc_ctx {
   int device = 0;
   int n_cu = 1;
   size_t lds_per_block = 65536;
+  size_t lds_per_cu = 65536;
   std::string err;
   // tuning knobs
   int64_t load_bucket_terms = 256;
-  int64_t split_bucket_terms = 384;
-  int64_t anti_cap = 512;
+  int64_t split_bucket_terms = 768;
+  int64_t anti_cap = 1024;
   int64_t grid_per_cu = 2;
   int64_t fuse_energy = 1;
   int64_t dis_tile = 256;
@@ -101,7 +102,15 @@ int ensure_partial(iqcc_ctx* ctx, int64_t n) {
   return IQCC_OK;
 }
 
-int grid_of(const iqcc_ctx* ctx) { return (int)(ctx->n_cu * ctx->grid_per_cu); }
+// Persistent dressing grid: grid_per_cu workgroups per CU, but no more than
+// fit in one CU's LDS at once (pairs are dealt out statically, so a workgroup
+// that is not resident would start late and finish last).
+static int dress_grid(const iqcc_ctx* ctx, size_t lds_bytes) {
+  int64_t per_cu = ctx->grid_per_cu;
+  const int64_t fit = lds_bytes ? (int64_t)(ctx->lds_per_cu / lds_bytes) : per_cu;
+  if (fit < per_cu) per_cu = fit > 0 ? fit : 1;
+  return (int)(ctx->n_cu * per_cu);
+}
 
 bool padding_clear(int nq, int W, const uint64_t* x, const uint64_t* z) {
   for (int w = 0; w < W; ++w) {
@@ -184,6 +193,10 @@ int iqcc_ctx_create(iqcc_ctx** out, int device) {
       ctx->lds_per_block = (size_t)v;
     else if (prop.sharedMemPerBlock > 0)
       ctx->lds_per_block = prop.sharedMemPerBlock;
+    ctx->lds_per_cu = ctx->lds_per_block;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) == hipSuccess &&
+        (size_t)v > ctx->lds_per_cu)
+      ctx->lds_per_cu = (size_t)v;
   }
   if (hipMalloc(&ctx->lut, sizeof(double) * kMaxWords * kGroupsPerWord * kLutEntries) != hipSuccess) {
     delete ctx;
@@ -422,7 +435,12 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
   const int W = in->W;
   Entangler P = make_entangler(W, px, pz);
   hipStream_t s = as_stream(stream);
-  const int grid = grid_of(ctx);
+  const bool fused = want_e && ctx->fuse_energy;
+  const size_t lds = dress_lds_bytes(W, (int)ctx->anti_cap, fused, tape_self != nullptr);
+  if (lds > ctx->lds_per_block)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "anti_cap %d needs more LDS than a workgroup has",
+                (int)ctx->anti_cap);
+  const int grid = dress_grid(ctx, lds);
   rc = ensure_partial(ctx, grid);
   if (rc) return rc;
   DressConfig cfg{};
@@ -432,9 +450,6 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
   cfg.split_thr = ctx->split_bucket_terms;
   cfg.anti_cap = (int)ctx->anti_cap;
   cfg.grid = grid;
-  const bool fused = want_e && ctx->fuse_energy;
-  if (dress_lds_bytes(W, cfg.anti_cap, fused, tape_self != nullptr) > ctx->lds_per_block)
-    return fail(ctx, IQCC_ERR_INVALID_ARG, "anti_cap %d needs more LDS than a workgroup has", cfg.anti_cap);
   if (want_e) {
     launch_build_lut(W, in->nq, theta, phi, ctx->lut, s);
     LAUNCH_CHECK(ctx);
@@ -565,9 +580,10 @@ static int batch_build(iqcc_ctx* ctx, int n_ham, const iqcc_store* const* ins,
   b->cfg.eps = eps;
   b->cfg.split_thr = ctx->split_bucket_terms;
   b->cfg.anti_cap = (int)ctx->anti_cap;
-  b->cfg.grid = grid_of(ctx);
-  if (dress_lds_bytes(W, b->cfg.anti_cap, false, false) > ctx->lds_per_block)
+  const size_t lds = dress_lds_bytes(W, b->cfg.anti_cap, false, false);
+  if (lds > ctx->lds_per_block)
     return fail(ctx, IQCC_ERR_INVALID_ARG, "anti_cap needs more LDS than a workgroup has");
+  b->cfg.grid = dress_grid(ctx, lds);
   set_dress_batch_attributes(W, b->cfg.anti_cap);
   return IQCC_OK;
 }
