@@ -151,6 +151,26 @@ __device__ __forceinline__ double block_sum(double v, double* tmp) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t div3_small(uint32_t b) { return (b * 11u) >> 5; }  // b < 32
 
+// Bit 3g of the result is set when 3-qubit group g of a 32-bit half word has a
+// non-identity qubit (nz = x | z of the half).
+__device__ __forceinline__ uint32_t group_starts(uint32_t nz) {
+  return (nz | (nz >> 1) | (nz >> 2)) & 0x49249249u;
+}
+
+// Table entry of the lowest remaining group in t (then cleared from t): group
+// g * 64 + (x bits | z bits << 3).  Once t is empty it returns entry 0 of
+// group 0, which is 1.0, so callers can run a fixed number of lookups without
+// branching.
+__device__ __forceinline__ uint32_t next_group_entry(uint32_t& t, uint32_t xh, uint32_t zh) {
+  const uint32_t sh = (uint32_t)__builtin_ctz(t | 0x80000000u);   // 31 only when t == 0
+  const uint32_t g = div3_small(sh);
+  const uint32_t off = g * kLutEntries + (__builtin_amdgcn_ubfe(xh, sh, 3) |
+                                          (__builtin_amdgcn_ubfe(zh, sh, 3) << 3));
+  const uint32_t e = t ? off : 0u;
+  t &= t - 1;
+  return e;
+}
+
 template <int W>
 __device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* x,
                                              const uint64_t* z) {
@@ -159,22 +179,12 @@ __device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* 
   for (int h = 0; h < 2 * W; ++h) {
     const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
     const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
-    uint32_t nz = xh | zh;
+    uint32_t t = group_starts(xh | zh);
     const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
-    while (nz) {
+    while (t) {
       uint32_t e[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        // entry 0 of group 0 is 1.0 and serves as the identity once nz is empty
-        uint32_t off = 0;
-        if (nz) {
-          const uint32_t g = div3_small((uint32_t)__builtin_ctz(nz));
-          const uint32_t sh = 3 * g;
-          off = g * kLutEntries + (__builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3));
-          nz &= ~(7u << sh);
-        }
-        e[k] = off;
-      }
+      for (int k = 0; k < 4; ++k) e[k] = next_group_entry(t, xh, zh);
       p0 *= lh[e[0]];
       p1 *= lh[e[1]];
       p2 *= lh[e[2]];

@@ -114,10 +114,10 @@ __device__ __forceinline__ void load_key(const StoreDev& st, int64_t row, uint64
                                          uint64_t* kz, double& c) {
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    kx[w] = __builtin_nontemporal_load(&st.x[w * st.cap + row]);
-    kz[w] = __builtin_nontemporal_load(&st.z[w * st.cap + row]);
+    kx[w] = st.x[w * st.cap + row];
+    kz[w] = st.z[w * st.cap + row];
   }
-  c = __builtin_nontemporal_load(&st.c[row]);
+  c = st.c[row];
 }
 
 template <int W>
@@ -125,10 +125,10 @@ __device__ __forceinline__ void store_key(const StoreDev& st, int64_t row, const
                                           const uint64_t* kz, double c) {
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    __builtin_nontemporal_store(kx[w], &st.x[w * st.cap + row]);
-    __builtin_nontemporal_store(kz[w], &st.z[w * st.cap + row]);
+    st.x[w * st.cap + row] = kx[w];
+    st.z[w * st.cap + row] = kz[w];
   }
-  __builtin_nontemporal_store(c, &st.c[row]);
+  st.c[row] = c;
 }
 
 template <int W>
@@ -219,20 +219,11 @@ __device__ __forceinline__ void expect_split(const double* lut, const Entangler&
     const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
     const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
     const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
-    uint32_t nz = (xh | zh) & ~P.gbits[h];
-    while (nz) {
+    uint32_t t = group_starts((xh | zh) & ~P.gbits[h]);
+    while (t) {
       uint32_t e[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        uint32_t off = 0;   // entry 0 of group 0 is 1.0: the identity once nz is empty
-        if (nz) {
-          const uint32_t g = div3_small((uint32_t)__builtin_ctz(nz));
-          const uint32_t sh = 3 * g;
-          off = g * kLutEntries + (__builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3));
-          nz &= ~(7u << sh);
-        }
-        e[k] = off;
-      }
+      for (int k = 0; k < 4; ++k) e[k] = next_group_entry(t, xh, zh);
       p0 *= lh[e[0]];
       p1 *= lh[e[1]];
       p2 *= lh[e[2]];
@@ -240,12 +231,13 @@ __device__ __forceinline__ void expect_split(const double* lut, const Entangler&
     }
     const uint32_t pxh = (uint32_t)(P.px[h >> 1] >> (32 * (h & 1)));
     const uint32_t pzh = (uint32_t)(P.pz[h >> 1] >> (32 * (h & 1)));
-    for (int t = P.gstart[h]; t < P.gstart[h + 1]; ++t) {
-      const uint32_t sh = 3 * (uint32_t)P.glist[t];
-      const uint32_t ix = __builtin_amdgcn_ubfe(xh, sh, 3), iz = __builtin_amdgcn_ubfe(zh, sh, 3);
-      const uint32_t base = (uint32_t)P.glist[t] * kLutEntries;
-      b *= lh[base + (ix | (iz << 3))];
-      b2 *= lh[base + ((ix ^ __builtin_amdgcn_ubfe(pxh, sh, 3)) | ((iz ^ __builtin_amdgcn_ubfe(pzh, sh, 3)) << 3))];
+    for (int q = P.gstart[h]; q < P.gstart[h + 1]; ++q) {
+      const uint32_t g = P.glist[q];
+      const uint32_t sh = 3 * g;
+      const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
+      const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
+      b *= lh[g * kLutEntries + code];
+      b2 *= lh[g * kLutEntries + (code ^ pcode)];
     }
   }
   const double a = (p0 * p1) * (p2 * p3);
