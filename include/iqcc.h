@@ -264,6 +264,48 @@ int iqcc_dis_gradients(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
                        const double *phi, const uint64_t *cx, const uint64_t *cz,
                        int64_t n_cand, int64_t ld_cand, int mode, double *g, void *stream);
 
+/* ---- one iQCC iteration (Sec. II, iterative procedure) -------------------- */
+
+/* *energy_anti (DEVICE scalar) = sum over the terms K of h that anticommute with
+ * P (HOST words px, pz) of c_K <Omega|K|Omega>.  With a = E - energy_anti,
+ * b = energy_anti and c = the DIS gradient of P (Eq. 7), dressing h with P at
+ * amplitude tau (Eq. 5) gives exactly E(tau) = a + b cos(tau) + c sin(tau). */
+int iqcc_qmf_energy_anti(iqcc_ctx *ctx, const iqcc_store *h, const uint64_t *px,
+                         const uint64_t *pz, const double *theta, const double *phi,
+                         double *energy_anti, void *stream);
+
+/* Synchronising: the distinct flip sets F (x parts, the positions of X or Y)
+ * of the terms of h with 1 <= |F| <= w_max, in ascending order of their words
+ * (most significant word first), written to the HOST array fx as rows of
+ * n_words words.  *n receives the count; IQCC_ERR_CAPACITY (fx untouched) when
+ * it exceeds cap.  Matching a flip set of H is the second DIS condition of
+ * App. A. */
+int iqcc_flip_sets(iqcc_ctx *ctx, const iqcc_store *h, int w_max, uint64_t *fx, int64_t cap,
+                   int64_t *n);
+
+/* Synchronising: one iteration of the iQCC procedure on the Hamiltonian *h.
+ *  1. candidates: for every flip set F of *h (iqcc_flip_sets order, |F| <= w_max)
+ *     and every qubit q of F in ascending order, the generator with Y on q and
+ *     X on the rest of F (one Y: odd Y parity; flip set of a term: App. A);
+ *  2. DIS gradients of all candidates in one batched launch (Eq. 7);
+ *  3. the n_select candidates of largest |g| (ties: ascending canonical key,
+ *     x words then z words, most significant first; zero gradients are never
+ *     taken), in that order;
+ *  4. for each of them on the current Hamiltonian: b = iqcc_qmf_energy_anti,
+ *     c = its DIS gradient, tau = atan2(-c, -b) (0 when b = c = 0), which
+ *     minimises E(tau) = a + b cos(tau) + c sin(tau); dress with (P, tau) and
+ *     compress with eps (as iqcc_dress).
+ * *h and *spare (distinct stores of the same n_qubits, *spare at least as
+ * large) are swapped as the steps ping-pong; on return *h holds the result.
+ * HOST outputs: sel_x, sel_z [n_select][n_words] (applied generators), sel_g
+ * [n_select] (their screening gradients), sel_tau [n_select], energy
+ * [n_select + 1] (energy before the first step and after each), the number of
+ * candidates and the number of generators applied (<= n_select). */
+int iqcc_qcc_iteration(iqcc_ctx *ctx, iqcc_store **h, iqcc_store **spare, const double *theta,
+                       const double *phi, int w_max, int n_select, double eps, uint64_t *sel_x,
+                       uint64_t *sel_z, double *sel_g, double *sel_tau, double *energy,
+                       int64_t *n_candidates, int *n_applied);
+
 #ifdef __cplusplus
 }
 #endif

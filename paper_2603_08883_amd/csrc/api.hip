@@ -5,6 +5,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <algorithm>
+#include <vector>
 
 #include "../../include/iqcc.h"
 #include "iqcc_internal.h"
@@ -761,6 +763,232 @@ int iqcc_dis_gradients(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, 
   }
   LAUNCH_CHECK(ctx);
   return IQCC_OK;
+}
+
+
+// ---- one iQCC iteration (Sec. II, iterative procedure; App. A) -------------
+
+int iqcc_qmf_energy_anti(iqcc_ctx* ctx, const iqcc_store* h, const uint64_t* px, const uint64_t* pz,
+                         const double* theta, const double* phi, double* energy_anti,
+                         void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h || !px || !pz || !theta || !phi || !energy_anti)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  if (!padding_clear(h->nq, h->W, px, pz))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "generator has bits beyond n_qubits");
+  hipStream_t s = as_stream(stream);
+  const int grid = (int)(ctx->n_cu * 4);
+  rc = ensure_partial(ctx, grid);
+  if (rc) return rc;
+  PauliKey P{};
+  for (int w = 0; w < h->W; ++w) {
+    P.x[w] = px[w];
+    P.z[w] = pz[w];
+  }
+  launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
+  launch_energy_anti(h->W, h->d, P, grid, ctx->lut, ctx->partial, s);
+  launch_finalize_sum(ctx->partial, grid, nullptr, energy_anti, s);
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+namespace {
+
+// a < b in canonical order: x words from the most significant down, then z
+bool canon_less(int W, const uint64_t* ax, const uint64_t* az, const uint64_t* bx,
+                const uint64_t* bz) {
+  for (int w = W - 1; w >= 0; --w)
+    if (ax[w] != bx[w]) return ax[w] < bx[w];
+  for (int w = W - 1; w >= 0; --w)
+    if (az[w] != bz[w]) return az[w] < bz[w];
+  return false;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) hipFree(p);
+  }
+};
+
+}  // namespace
+
+namespace {
+
+// Distinct flip sets with 1 <= |F| <= w_max of h's terms, canonical order, as
+// rows of W words in `out`.
+int flip_sets_impl(iqcc_ctx* ctx, const iqcc_store* h, int w_max, std::vector<uint64_t>& out) {
+  const int W = h->W;
+  out.clear();
+  int64_t live = 0;
+  int rc = iqcc_store_count(ctx, h, &live, nullptr);
+  if (rc) return rc;
+  if (live == 0) return IQCC_OK;
+  // rows (F, 0, 1.0) for every term with 1 <= |F| <= w_max, made unique by the merge
+  const int64_t ld = live;
+  DevBuf rows, cnt;
+  HIP_TRY(ctx, hipMalloc(&rows.p, (size_t)ld * (16 * W + 8)));
+  HIP_TRY(ctx, hipMalloc(&cnt.p, 64));
+  HIP_TRY(ctx, hipMemset(cnt.p, 0, 64));
+  uint64_t* rx = (uint64_t*)rows.p;
+  uint64_t* rz = rx + (size_t)W * ld;
+  double* rc1 = (double*)(rz + (size_t)W * ld);
+  launch_flip_rows(W, h->d, w_max, rx, rz, rc1, ld, (unsigned long long*)cnt.p,
+                   (int)(ctx->n_cu * 4), nullptr);
+  LAUNCH_CHECK(ctx);
+  unsigned long long nrows = 0;
+  HIP_TRY(ctx, hipMemcpy(&nrows, cnt.p, 8, hipMemcpyDeviceToHost));
+  if (nrows == 0) return IQCC_OK;
+  iqcc_store* u = nullptr;
+  rc = iqcc_store_create(ctx, h->nq, (int64_t)nrows, &u);
+  if (rc) return rc;
+  rc = iqcc_merge_truncate(ctx, rx, rz, rc1, (int64_t)nrows, ld, 0.0, u, nullptr);
+  int64_t nu = 0;
+  if (!rc) rc = iqcc_store_export(ctx, u, rx, rz, rc1, ld, ld, &nu, nullptr);
+  std::vector<uint64_t> hx;
+  if (!rc) {
+    hx.resize((size_t)W * nu);
+    for (int w = 0; w < W; ++w)
+      if (hipMemcpy(hx.data() + (size_t)w * nu, rx + (size_t)w * ld, sizeof(uint64_t) * nu,
+                    hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(ctx, IQCC_ERR_HIP, "flip-set copy failed");
+  }
+  iqcc_store_destroy(ctx, u);
+  if (rc) return rc;
+  std::vector<int64_t> order(nu);
+  for (int64_t i = 0; i < nu; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    for (int w = W - 1; w >= 0; --w) {
+      const uint64_t va = hx[(size_t)w * nu + a], vb = hx[(size_t)w * nu + b];
+      if (va != vb) return va < vb;
+    }
+    return false;
+  });
+  out.resize((size_t)nu * W);
+  for (int64_t i = 0; i < nu; ++i)
+    for (int w = 0; w < W; ++w) out[i * W + w] = hx[(size_t)w * nu + order[i]];
+  return IQCC_OK;
+}
+
+}  // namespace
+
+int iqcc_flip_sets(iqcc_ctx* ctx, const iqcc_store* h, int w_max, uint64_t* fx, int64_t cap,
+                   int64_t* n) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h || !n || w_max < 1 || cap < 0) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad flip-set arguments");
+  std::vector<uint64_t> F;
+  rc = flip_sets_impl(ctx, h, w_max, F);
+  if (rc) return rc;
+  const int64_t nu = (int64_t)(F.size() / h->W);
+  *n = nu;
+  if (nu > cap) return fail(ctx, IQCC_ERR_CAPACITY, "%lld flip sets, room for %lld", (long long)nu,
+                            (long long)cap);
+  if (nu > 0 && !fx) return fail(ctx, IQCC_ERR_INVALID_ARG, "null output");
+  std::copy(F.begin(), F.end(), fx);
+  return IQCC_OK;
+}
+
+int iqcc_qcc_iteration(iqcc_ctx* ctx, iqcc_store** h, iqcc_store** spare, const double* theta,
+                       const double* phi, int w_max, int n_select, double eps, uint64_t* sel_x,
+                       uint64_t* sel_z, double* sel_g, double* sel_tau, double* energy,
+                       int64_t* n_candidates, int* n_applied) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h || !spare || !*h || !*spare || *h == *spare || !theta || !phi || !sel_x || !sel_z ||
+      !sel_g || !sel_tau || !energy || !n_candidates || !n_applied || n_select < 0 || w_max < 1)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad iteration arguments");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(ctx, IQCC_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  const int W = (*h)->W;
+  *n_applied = 0;
+  *n_candidates = 0;
+  DevBuf dscal;
+  HIP_TRY(ctx, hipMalloc(&dscal.p, 64));
+  double* d_e = (double*)dscal.p;   // [0] energy, [1] next energy, [2] b, [3] c
+  rc = iqcc_qmf_energy(ctx, *h, theta, phi, d_e, nullptr);
+  if (rc) return rc;
+  double e_cur = 0.0;
+  HIP_TRY(ctx, hipMemcpy(&e_cur, d_e, 8, hipMemcpyDeviceToHost));
+  energy[0] = e_cur;
+  // 1. flip sets, 2. DIS candidates: Y on one qubit of F, X on the rest of F
+  std::vector<uint64_t> F;
+  rc = flip_sets_impl(ctx, *h, w_max, F);
+  if (rc) return rc;
+  const int64_t nf = (int64_t)(F.size() / W);
+  std::vector<uint64_t> cx, cz;
+  for (int64_t f = 0; f < nf; ++f)
+    for (int w = 0; w < W; ++w)
+      for (uint64_t v = F[f * W + w]; v; v &= v - 1) {
+        for (int u = 0; u < W; ++u) {
+          cx.push_back(F[f * W + u]);
+          cz.push_back(u == w ? (v & (~v + 1)) : 0ull);
+        }
+      }
+  const int64_t nc = (int64_t)(cx.size() / W);
+  *n_candidates = nc;
+  if (nc == 0 || n_select == 0) return IQCC_OK;
+  // 3. gradients of all candidates in one batched launch
+  DevBuf dc;
+  HIP_TRY(ctx, hipMalloc(&dc.p, (size_t)nc * (16 * W + 8)));
+  uint64_t* dcx = (uint64_t*)dc.p;
+  uint64_t* dcz = dcx + (size_t)W * nc;
+  double* dg = (double*)(dcz + (size_t)W * nc);
+  {
+    std::vector<uint64_t> px((size_t)W * nc), pz((size_t)W * nc);
+    for (int64_t i = 0; i < nc; ++i)
+      for (int w = 0; w < W; ++w) {
+        px[(size_t)w * nc + i] = cx[i * W + w];
+        pz[(size_t)w * nc + i] = cz[i * W + w];
+      }
+    HIP_TRY(ctx, hipMemcpy(dcx, px.data(), sizeof(uint64_t) * W * nc, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(dcz, pz.data(), sizeof(uint64_t) * W * nc, hipMemcpyHostToDevice));
+  }
+  rc = iqcc_dis_gradients(ctx, *h, theta, phi, dcx, dcz, nc, nc, IQCC_DIS_BATCHED, dg, nullptr);
+  if (rc) return rc;
+  std::vector<double> g(nc);
+  HIP_TRY(ctx, hipMemcpy(g.data(), dg, sizeof(double) * nc, hipMemcpyDeviceToHost));
+  // the n_select largest |g| (ties: canonical key ascending); zero gradients are never taken
+  std::vector<int64_t> idx(nc);
+  for (int64_t i = 0; i < nc; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    const double ga = std::fabs(g[a]), gb = std::fabs(g[b]);
+    if (ga != gb) return ga > gb;
+    return canon_less(W, &cx[a * W], &cz[a * W], &cx[b * W], &cz[b * W]);
+  });
+  // 4. one closed-form step per selected generator, in rank order
+  for (int k = 0; k < n_select && k < nc; ++k) {
+    const int64_t i = idx[k];
+    if (!(std::fabs(g[i]) > 0.0)) break;
+    const uint64_t* px = &cx[i * W];
+    const uint64_t* pz = &cz[i * W];
+    rc = iqcc_qmf_energy_anti(ctx, *h, px, pz, theta, phi, d_e + 2, nullptr);
+    if (rc) return rc;
+    rc = iqcc_dis_gradients(ctx, *h, theta, phi, dcx + i, dcz + i, 1, nc, IQCC_DIS_PLAIN, d_e + 3,
+                            nullptr);
+    if (rc) return rc;
+    double bc[2];
+    HIP_TRY(ctx, hipMemcpy(bc, d_e + 2, 16, hipMemcpyDeviceToHost));
+    // E(tau) = (E - b) + b cos(tau) + c sin(tau) is smallest at (cos, sin) = -(b, c) / |(b, c)|
+    const double tau = (bc[0] == 0.0 && bc[1] == 0.0) ? 0.0 : std::atan2(-bc[1], -bc[0]);
+    rc = iqcc_dress_energy_update(ctx, *h, px, pz, tau, eps, theta, phi, d_e, d_e + 1, *spare,
+                                  nullptr);
+    if (rc) return rc;
+    std::swap(*h, *spare);
+    double e_next = 0.0;
+    HIP_TRY(ctx, hipMemcpy(&e_next, d_e + 1, 8, hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(d_e, d_e + 1, 8, hipMemcpyDeviceToDevice));
+    for (int w = 0; w < W; ++w) {
+      sel_x[k * W + w] = px[w];
+      sel_z[k * W + w] = pz[w];
+    }
+    sel_g[k] = g[i];
+    sel_tau[k] = tau;
+    energy[k + 1] = e_next;
+    *n_applied = k + 1;
+  }
+  int64_t nout = 0;
+  return iqcc_store_count(ctx, *h, &nout, nullptr);
 }
 
 }  // extern "C"

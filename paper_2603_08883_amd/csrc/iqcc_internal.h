@@ -302,6 +302,14 @@ void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double*
 void launch_finalize_sum(const double* partial, int n, const double* scale, double* out,
                          hipStream_t s, const double* base = nullptr);
 
+// A Pauli key passed by value to a kernel.
+struct PauliKey {
+  uint64_t x[kMaxWords], z[kMaxWords];
+};
+void launch_flip_rows(int W, const StoreDev& st, int w_max, uint64_t* ox, uint64_t* oz, double* oc,
+                      int64_t ld, unsigned long long* count, int grid, hipStream_t s);
+void launch_energy_anti(int W, const StoreDev& st, const PauliKey& P, int grid, const double* lut,
+                        double* partial, hipStream_t s);
 void launch_energy(int W, const StoreDev& st, int grid, const double* lut, double* e_partial,
                    hipStream_t s);
 void launch_energy_backward(int W, int nq, const StoreDev& st, int grid, const double* theta,

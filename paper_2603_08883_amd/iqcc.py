@@ -76,6 +76,10 @@ def lib():
         "iqcc_batch_create": (i32, [P, i32, P, P, P, P, P, d, ct.POINTER(P)]),
         "iqcc_batch_launch": (i32, [P, P, P]),
         "iqcc_batch_destroy": (i32, [P, P]),
+        "iqcc_qmf_energy_anti": (i32, [P, P, P, P, P, P, P, P]),
+        "iqcc_flip_sets": (i32, [P, P, i32, P, i64, ct.POINTER(i64)]),
+        "iqcc_qcc_iteration": (i32, [P, ct.POINTER(P), ct.POINTER(P), P, P, i32, i32, d, P, P, P, P, P,
+                                     ct.POINTER(i64), ct.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -95,6 +99,7 @@ def exported_symbols():
         "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
         "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
         "iqcc_dress_batched", "iqcc_batch_create", "iqcc_batch_launch", "iqcc_batch_destroy",
+        "iqcc_qmf_energy_anti", "iqcc_flip_sets", "iqcc_qcc_iteration",
     ]
 
 
@@ -379,6 +384,54 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def iqcc_qmf_energy_anti(ctx, store, px, pz, theta, phi, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device="cuda")
+    ax, pxp = _words(px)
+    az, pzp = _words(pz)
+    _check(lib().iqcc_qmf_energy_anti(ctx, store, pxp, pzp, _ptr(theta), _ptr(phi), _ptr(out),
+                                      _stream(stream)), ctx)
+    return out
+
+
+def iqcc_flip_sets(ctx, store, w_max: int):
+    """Distinct flip sets (1 <= |F| <= w_max) as a (n, W) uint64 host array."""
+    nq, W = iqcc_store_shape(store)
+    n = ct.c_int64()
+    rc = lib().iqcc_flip_sets(ctx, store, int(w_max), None, 0, ct.byref(n))
+    if rc not in (IQCC_OK, IQCC_ERR_CAPACITY):
+        _check(rc, ctx)
+    out = np.zeros((max(n.value, 1), W), dtype=np.uint64)
+    _check(lib().iqcc_flip_sets(ctx, store, int(w_max), out.ctypes.data_as(ct.c_void_p), n.value,
+                                ct.byref(n)), ctx)
+    return out[:n.value]
+
+
+def iqcc_qcc_iteration(ctx, h: "Store", spare: "Store", theta, phi, w_max: int, n_select: int,
+                       eps: float):
+    """One iQCC iteration; swaps the handles of h and spare as the steps ping-pong.
+
+    Returns dict(sel_x, sel_z (n_applied, W), sel_g, sel_tau, energy (n_applied + 1),
+    n_candidates)."""
+    W = iqcc_store_shape(h.handle)[1]
+    k = max(int(n_select), 1)
+    sx = np.zeros((k, W), np.uint64); sz = np.zeros((k, W), np.uint64)
+    sg = np.zeros(k); st = np.zeros(k); en = np.zeros(k + 1)
+    nc = ct.c_int64(); na = ct.c_int32()
+    hh, hs = h.handle, spare.handle          # c_void_p handles, swapped in place by the call
+    rc = lib().iqcc_qcc_iteration(ctx, ct.byref(hh), ct.byref(hs), _ptr(theta), _ptr(phi), int(w_max),
+                                  int(n_select), float(eps), sx.ctypes.data_as(ct.c_void_p),
+                                  sz.ctypes.data_as(ct.c_void_p), sg.ctypes.data_as(ct.c_void_p),
+                                  st.ctypes.data_as(ct.c_void_p), en.ctypes.data_as(ct.c_void_p),
+                                  ct.byref(nc), ct.byref(na))
+    h.handle, spare.handle = hh, hs
+    _check(rc, ctx)
+    a = na.value
+    return {"sel_x": sx[:a], "sel_z": sz[:a], "sel_g": sg[:a], "sel_tau": st[:a],
+            "energy": en[:a + 1], "n_candidates": nc.value}
 
 
 class Store:
