@@ -264,6 +264,20 @@ int iqcc_dis_gradients(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
                        const double *phi, const uint64_t *cx, const uint64_t *cz,
                        int64_t n_cand, int64_t ld_cand, int mode, double *g, void *stream);
 
+/* ---- term-limit compression ---------------------------------------------- */
+
+/* Synchronising: out = the max_terms terms of `in` with the largest |c|; when
+ * several terms share the |c| at the boundary, those with the smaller canonical
+ * key (x words, then z words, most significant word first) are kept, so the
+ * result is unique.  All terms are kept when `in` has at most max_terms.  This
+ * is the "maximum terms" limit of the Ru-catalyst runs (Results, the run tables
+ * and the discussion of the coefficient cutoff and the term limit), applied
+ * next to the coefficient cutoff of iqcc_dress.
+ * out keeps in's bucket table and arena rows (each bucket's kept terms in
+ * input order), so it must be a different store at least as large as `in`. */
+int iqcc_truncate_top(iqcc_ctx *ctx, const iqcc_store *in, int64_t max_terms, iqcc_store *out,
+                      void *stream);
+
 /* ---- one iQCC iteration (Sec. II, iterative procedure) -------------------- */
 
 /* *energy_anti (DEVICE scalar) = sum over the terms K of h that anticommute with

@@ -202,6 +202,17 @@ def canonical(x, z, c):
     return x[o], z[o], c[o]
 
 
+def truncate_top(x, z, c, max_terms):
+    """The max_terms terms of largest |c|; at equal |c| the smaller canonical key
+    (x words, then z words, most significant first) comes first.  Rows are
+    returned in canonical order."""
+    x, z, c = _rows(x, z, c)
+    W = x.shape[1]
+    keys = [z[:, w] for w in range(W)] + [x[:, w] for w in range(W)] + [-np.abs(c)]
+    o = np.lexsort(keys)[:max(0, int(max_terms))]
+    return canonical(x[o], z[o], c[o])
+
+
 def chain_point(nq, x0, z0, c0, ents, taus, eps, qx, qz):
     """Coefficient of each query key after the whole chain, one key at a time.
 

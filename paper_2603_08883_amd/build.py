@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libiqcc.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "kernels_store.hip", "kernels_dress.hip", "kernels_energy.hip",
-           "kernels_dis.hip", "kernels_merge.hip", "kernels_chain.hip", "kernels_qcc.hip"]
+           "kernels_dis.hip", "kernels_merge.hip", "kernels_chain.hip", "kernels_qcc.hip",
+           "kernels_select.hip"]
 ARCH = os.environ.get("IQCC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

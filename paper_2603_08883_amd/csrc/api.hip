@@ -991,4 +991,56 @@ int iqcc_qcc_iteration(iqcc_ctx* ctx, iqcc_store** h, iqcc_store** spare, const 
   return iqcc_store_count(ctx, *h, &nout, nullptr);
 }
 
+
+// ---- term-limit compression -------------------------------------------------
+
+int iqcc_truncate_top(iqcc_ctx* ctx, const iqcc_store* in, int64_t max_terms, iqcc_store* out,
+                      void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!in || !out || in == out || max_terms < 0) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad arguments");
+  if (in->nq != out->nq) return fail(ctx, IQCC_ERR_INVALID_ARG, "qubit counts differ");
+  if (out->d.cap < in->d.cap || out->d.mcap < in->d.mcap)
+    return fail(ctx, IQCC_ERR_CAPACITY, "output store is smaller than the input store");
+  hipStream_t s = as_stream(stream);
+  int64_t n = 0;
+  rc = iqcc_store_count(ctx, in, &n, stream);
+  if (rc) return rc;
+  const int W = in->W;
+  const int grid = (int)(ctx->n_cu * 4);
+  DevBuf dss, dhist;
+  HIP_TRY(ctx, hipMalloc(&dss.p, sizeof(SelState)));
+  HIP_TRY(ctx, hipMalloc(&dhist.p, 2048 * sizeof(unsigned)));
+  SelState* ss = (SelState*)dss.p;
+  SelState h{};
+  h.need = max_terms;
+  HIP_TRY(ctx, hipMemcpyAsync(ss, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipMemsetAsync(dhist.p, 0, 2048 * sizeof(unsigned), s));
+  launch_zero_counters(out->d, s);
+  int keep_all = n <= max_terms ? 1 : max_terms == 0 ? -1 : 0;
+  DevBuf keys, kcount;
+  if (keep_all == 0) {
+    launch_abs_select(W, in->d, ss, (unsigned*)dhist.p, grid, s);
+    LAUNCH_CHECK(ctx);
+    HIP_TRY(ctx, hipMemcpyAsync(&h, ss, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (h.need < h.ties) {
+      // not every term equal to the threshold fits: the smaller canonical keys go first
+      HIP_TRY(ctx, hipMalloc(&keys.p, (size_t)h.ties * 2 * W * sizeof(uint64_t)));
+      HIP_TRY(ctx, hipMalloc(&kcount.p, 64));
+      HIP_TRY(ctx, hipMemsetAsync(kcount.p, 0, 64, s));
+      launch_collect_ties(W, in->d, ss, (uint64_t*)keys.p, h.ties, (unsigned long long*)kcount.p,
+                          grid, s);
+      launch_key_select(W, (const uint64_t*)keys.p, h.ties, ss, (unsigned*)dhist.p, s);
+      const int one = 1;
+      HIP_TRY(ctx, hipMemcpyAsync(&ss->key_mode, &one, sizeof(int), hipMemcpyHostToDevice, s));
+      LAUNCH_CHECK(ctx);
+    }
+  }
+  launch_select_compact(W, in->d, out->d, ss, keep_all, grid, s);
+  LAUNCH_CHECK(ctx);
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  return IQCC_OK;
+}
+
 }  // extern "C"

@@ -302,6 +302,27 @@ void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double*
 void launch_finalize_sum(const double* partial, int n, const double* scale, double* out,
                          hipStream_t s, const double* base = nullptr);
 
+// Device state of the term-limit selection (kernels_select.hip).
+struct SelState {
+  uint64_t prefix;               // digits fixed so far
+  int64_t need;                  // terms still to take among those matching the prefix
+  int64_t passed;                // terms in bins passed over so far
+  uint64_t T;                    // |c| bits of the M-th largest term
+  int64_t ties;                  // terms with |c| bits == T
+  int key_mode;                  // 1: keep only ties with canonical key <= kthr
+  int pad;
+  uint64_t kthr[2 * kMaxWords];  // canonical key threshold among the ties
+};
+void launch_abs_select(int W, const StoreDev& st, SelState* ss, unsigned* hist, int grid,
+                       hipStream_t s);
+void launch_collect_ties(int W, const StoreDev& st, const SelState* ss, uint64_t* keys, int64_t cap,
+                         unsigned long long* count, int grid, hipStream_t s);
+void launch_key_select(int W, const uint64_t* keys, int64_t n, SelState* ss, unsigned* hist,
+                       hipStream_t s);
+// keep_all: 1 every term, 0 the selection in ss, -1 none
+void launch_select_compact(int W, const StoreDev& in, const StoreDev& out, const SelState* ss,
+                           int keep_all, int grid, hipStream_t s);
+
 // A Pauli key passed by value to a kernel.
 struct PauliKey {
   uint64_t x[kMaxWords], z[kMaxWords];

@@ -1,0 +1,246 @@
+// Term-limit compression: keep the M terms of largest |c| (the "maximum terms"
+// limit of the paper's Ru-catalyst runs, Results, next to the coefficient
+// cutoff; ties broken by the smaller canonical key so that the kept set is
+// unique).
+//
+// Radix selection on the IEEE bits of |c|, which order non-negative doubles
+// like their values: six digit passes (11, 11, 11, 11, 11, 9 bits, most
+// significant first) each build a histogram of the digit over the terms whose
+// higher digits equal the prefix chosen so far, and a one-thread kernel picks
+// the digit where the running count from the top reaches the number still
+// needed.  That fixes the threshold T (the M-th largest |c|), the number of
+// terms above it and the number to take among the terms equal to T.  When not
+// all ties are taken, the tie keys are collected and the same selection runs
+// on their canonical key words (x words, then z words, most significant
+// first), from the bottom.  A last pass copies every bucket's kept terms, in
+// input order, to the same rows of the output arena.
+#include "iqcc_internal.h"
+
+namespace iqcc {
+
+constexpr int kSelBins = 2048;
+
+__device__ __forceinline__ uint64_t abs_bits(double c) {
+  return (uint64_t)__double_as_longlong(c) & 0x7fffffffffffffffull;
+}
+
+// |c| digit histogram over the live terms of st whose bits above `shift + width`
+// equal `prefix` (all terms when `first`).
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_abs_hist(StoreDev st, const SelState* ss, int shift,
+                                                     int width, int first, unsigned* hist) {
+  __shared__ unsigned h[kSelBins];
+  for (int i = threadIdx.x; i < kSelBins; i += kBlock) h[i] = 0;
+  __syncthreads();
+  const uint64_t prefix = ss->prefix;
+  const int64_t B = 1ll << *st.m;
+  const uint64_t dmask = (1ull << width) - 1;
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = st.cnt[b], off = st.off[b];
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      const uint64_t u = abs_bits(st.c[off + i]);
+      if (first || (u >> (shift + width)) == prefix) atomicAdd(&h[(u >> shift) & dmask], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSelBins; i += kBlock)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Pick the digit at which the count reaches ss->need, scanning from the
+// largest digit down (descending) or from 0 up, and clear the histogram.  The
+// histogram is staged in LDS by the block; one thread scans it.
+__global__ __launch_bounds__(kBlock) void k_pick_digit(SelState* ss, unsigned* hist, int width,
+                                                       int descending, int last, int key_word) {
+  __shared__ unsigned h[kSelBins];
+  const int nb = 1 << width;
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    h[k] = hist[k];
+    hist[k] = 0;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  int64_t before = 0;
+  int pick = descending ? nb - 1 : 0;
+  for (int k = 0; k < nb; ++k) {
+    const int d = descending ? nb - 1 - k : k;
+    if (before + (int64_t)h[d] >= ss->need) {
+      pick = d;
+      break;
+    }
+    before += h[d];
+  }
+  const int64_t at = h[pick];
+  ss->need -= before;
+  ss->passed += before;
+  ss->prefix = (ss->prefix << width) | (uint64_t)pick;
+  if (last) {
+    if (key_word < 0) {
+      ss->T = ss->prefix;
+      ss->ties = at;
+    } else {
+      ss->kthr[key_word] = ss->prefix;
+    }
+    ss->prefix = 0;
+  }
+}
+
+// Canonical key word q of a term: x[W-1], ..., x[0], z[W-1], ..., z[0].
+template <int W>
+__device__ __forceinline__ uint64_t canon_word(const StoreDev& st, int64_t row, int q) {
+  return q < W ? st.x[(W - 1 - q) * st.cap + row] : st.z[(2 * W - 1 - q) * st.cap + row];
+}
+
+// Keys of the terms with |c| bits == T, as rows of 2W canonical words.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_collect_ties(StoreDev st, const SelState* ss,
+                                                         uint64_t* keys, int64_t cap,
+                                                         unsigned long long* count) {
+  const uint64_t T = ss->T;
+  const int64_t B = 1ll << *st.m;
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = st.cnt[b], off = st.off[b];
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      if (abs_bits(st.c[off + i]) != T) continue;
+      const int64_t r = (int64_t)atomicAdd(count, 1ull);
+      if (r < cap)
+        for (int q = 0; q < 2 * W; ++q) keys[r * 2 * W + q] = canon_word<W>(st, off + i, q);
+    }
+  }
+}
+
+// Digit histogram of key word q over the tie keys whose earlier words equal
+// kthr[0..q) and whose bits of word q above shift + width equal the prefix.
+__global__ __launch_bounds__(kBlock) void k_key_hist(const uint64_t* keys, int64_t n, int nw,
+                                                     const SelState* ss, int q, int shift,
+                                                     int width, int first, unsigned* hist) {
+  __shared__ unsigned h[kSelBins];
+  for (int i = threadIdx.x; i < kSelBins; i += kBlock) h[i] = 0;
+  __syncthreads();
+  const uint64_t dmask = (1ull << width) - 1;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const uint64_t* k = keys + i * nw;
+    bool match = true;
+    for (int p = 0; p < q; ++p) match = match && k[p] == ss->kthr[p];
+    if (match && (first || (k[q] >> (shift + width)) == ss->prefix))
+      atomicAdd(&h[(k[q] >> shift) & dmask], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSelBins; i += kBlock)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Copy the kept terms of every bucket, in input order, to the same rows of
+// the output arena; the output keeps the input's bucket table shape.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_select_compact(StoreDev in, StoreDev out,
+                                                           const SelState* ss, int keep_all) {
+  __shared__ uint64_t scan_tmp[kWaves];
+  const uint64_t T = ss->T;
+  const int key_mode = ss->key_mode;
+  const int m = *in.m;
+  const int64_t B = 1ll << m;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *out.m = m;
+    *out.top = *in.top;
+  }
+  int64_t kept = 0;
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = in.cnt[b], off = in.off[b];
+    int64_t w = 0;
+    for (int64_t i0 = 0; i0 < n; i0 += kBlock) {
+      const int64_t i = i0 + threadIdx.x;
+      bool keep = false;
+      if (i < n && keep_all >= 0) {
+        if (keep_all) {
+          keep = true;
+        } else {
+          const uint64_t u = abs_bits(in.c[off + i]);
+          keep = u > T;
+          if (u == T) {
+            keep = true;
+            if (key_mode) {
+              // keep ties whose canonical key is <= kthr
+              for (int q = 0; q < 2 * W; ++q) {
+                const uint64_t v = canon_word<W>(in, off + i, q);
+                if (v != ss->kthr[q]) {
+                  keep = v < ss->kthr[q];
+                  break;
+                }
+              }
+            }
+          }
+        }
+      }
+      uint64_t tot;
+      const uint64_t pos = block_exclusive_scan(keep ? 1ull : 0ull, scan_tmp, tot);
+      if (keep) {
+        const int64_t r = off + w + (int64_t)pos;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          out.x[q * out.cap + r] = in.x[q * in.cap + off + i];
+          out.z[q * out.cap + r] = in.z[q * in.cap + off + i];
+        }
+        out.c[r] = in.c[off + i];
+      }
+      w += (int64_t)tot;
+    }
+    if (threadIdx.x == 0) {
+      out.off[b] = off;
+      out.cnt[b] = w;
+    }
+    kept += w;
+  }
+  if (threadIdx.x == 0 && kept) atomicAdd((unsigned long long*)out.total, (unsigned long long)kept);
+}
+
+static const int kDigitWidth[6] = {11, 11, 11, 11, 11, 9};
+static const int kDigitShift[6] = {53, 42, 31, 20, 9, 0};
+
+void launch_abs_select(int W, const StoreDev& st, SelState* ss, unsigned* hist, int grid,
+                       hipStream_t s) {
+  for (int p = 0; p < 6; ++p) {
+    const int sh = kDigitShift[p], wd = kDigitWidth[p], first = p == 0;
+    switch (W) {
+      case 1: hipLaunchKernelGGL(k_abs_hist<1>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, first, hist); break;
+      case 2: hipLaunchKernelGGL(k_abs_hist<2>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, first, hist); break;
+      case 3: hipLaunchKernelGGL(k_abs_hist<3>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, first, hist); break;
+      default: hipLaunchKernelGGL(k_abs_hist<4>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, first, hist); break;
+    }
+    hipLaunchKernelGGL(k_pick_digit, dim3(1), dim3(kBlock), 0, s, ss, hist, wd, 1, p == 5, -1);
+  }
+}
+
+void launch_collect_ties(int W, const StoreDev& st, const SelState* ss, uint64_t* keys, int64_t cap,
+                         unsigned long long* count, int grid, hipStream_t s) {
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_collect_ties<1>, dim3(grid), dim3(kBlock), 0, s, st, ss, keys, cap, count); break;
+    case 2: hipLaunchKernelGGL(k_collect_ties<2>, dim3(grid), dim3(kBlock), 0, s, st, ss, keys, cap, count); break;
+    case 3: hipLaunchKernelGGL(k_collect_ties<3>, dim3(grid), dim3(kBlock), 0, s, st, ss, keys, cap, count); break;
+    default: hipLaunchKernelGGL(k_collect_ties<4>, dim3(grid), dim3(kBlock), 0, s, st, ss, keys, cap, count); break;
+  }
+}
+
+void launch_key_select(int W, const uint64_t* keys, int64_t n, SelState* ss, unsigned* hist,
+                       hipStream_t s) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  const int grid = (int)(g < 1 ? 1 : g > 1024 ? 1024 : g);
+  for (int q = 0; q < 2 * W; ++q)
+    for (int p = 0; p < 6; ++p) {
+      hipLaunchKernelGGL(k_key_hist, dim3(grid), dim3(kBlock), 0, s, keys, n, 2 * W, ss, q,
+                         kDigitShift[p], kDigitWidth[p], p == 0, hist);
+      hipLaunchKernelGGL(k_pick_digit, dim3(1), dim3(kBlock), 0, s, ss, hist, kDigitWidth[p], 0, p == 5, q);
+    }
+}
+
+void launch_select_compact(int W, const StoreDev& in, const StoreDev& out, const SelState* ss,
+                           int keep_all, int grid, hipStream_t s) {
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_select_compact<1>, dim3(grid), dim3(kBlock), 0, s, in, out, ss, keep_all); break;
+    case 2: hipLaunchKernelGGL(k_select_compact<2>, dim3(grid), dim3(kBlock), 0, s, in, out, ss, keep_all); break;
+    case 3: hipLaunchKernelGGL(k_select_compact<3>, dim3(grid), dim3(kBlock), 0, s, in, out, ss, keep_all); break;
+    default: hipLaunchKernelGGL(k_select_compact<4>, dim3(grid), dim3(kBlock), 0, s, in, out, ss, keep_all); break;
+  }
+}
+
+}  // namespace iqcc

@@ -44,6 +44,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2603_08883_amd.build`")
+    # PyTorch brings its own HIP runtime; load it first so that libiqcc binds to
+    # the same runtime instance (a second runtime loaded earlier under the same
+    # soname would be picked up by torch instead and hide the devices from it).
+    import torch  # noqa: F401
     L = ct.CDLL(LIB_PATH)
     P, i64, i32, d = ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double
     sig = {
@@ -77,6 +81,7 @@ def lib():
         "iqcc_batch_launch": (i32, [P, P, P]),
         "iqcc_batch_destroy": (i32, [P, P]),
         "iqcc_qmf_energy_anti": (i32, [P, P, P, P, P, P, P, P]),
+        "iqcc_truncate_top": (i32, [P, P, i64, P, P]),
         "iqcc_flip_sets": (i32, [P, P, i32, P, i64, ct.POINTER(i64)]),
         "iqcc_qcc_iteration": (i32, [P, ct.POINTER(P), ct.POINTER(P), P, P, i32, i32, d, P, P, P, P, P,
                                      ct.POINTER(i64), ct.POINTER(i32)]),
@@ -99,7 +104,7 @@ def exported_symbols():
         "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
         "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
         "iqcc_dress_batched", "iqcc_batch_create", "iqcc_batch_launch", "iqcc_batch_destroy",
-        "iqcc_qmf_energy_anti", "iqcc_flip_sets", "iqcc_qcc_iteration",
+        "iqcc_qmf_energy_anti", "iqcc_flip_sets", "iqcc_qcc_iteration", "iqcc_truncate_top",
     ]
 
 
@@ -395,6 +400,11 @@ def iqcc_qmf_energy_anti(ctx, store, px, pz, theta, phi, out=None, stream=None):
     _check(lib().iqcc_qmf_energy_anti(ctx, store, pxp, pzp, _ptr(theta), _ptr(phi), _ptr(out),
                                       _stream(stream)), ctx)
     return out
+
+
+def iqcc_truncate_top(ctx, store_in, max_terms: int, store_out, stream=None):
+    """Keep the max_terms terms of largest |c| (ties: smaller canonical key)."""
+    _check(lib().iqcc_truncate_top(ctx, store_in, int(max_terms), store_out, _stream(stream)), ctx)
 
 
 def iqcc_flip_sets(ctx, store, w_max: int):
