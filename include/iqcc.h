@@ -78,6 +78,9 @@ const char *iqcc_version(void);
  *                        pair; larger pairs are processed in hash rounds
  *                        (16 .. 8192)
  *   "grid_per_cu"        persistent workgroups per compute unit (1 .. 16)
+ *   "batch_split_bucket_terms", "batch_anti_cap"
+ *                        the same two settings for batched dressing of many
+ *                        small Hamiltonians (iqcc_dress_batched, iqcc_batch_*)
  *   "fuse_energy"        1: dressing evaluates the energy of its output in the
  *                        same pass when angles are given; 0: separate pass
  *   "dis_tile"           DIS candidates held per workgroup tile (1 .. 256)

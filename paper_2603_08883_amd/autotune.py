@@ -1,7 +1,8 @@
 """Autotuner for bucket and tile sizes of the dressing kernels.
 
 Times candidate settings of the library's knobs ("anti_cap", "grid_per_cu",
-"split_bucket_terms", "load_bucket_terms") on the caller's own workload through
+"split_bucket_terms", their batched-dressing counterparts "batch_anti_cap" and
+"batch_split_bucket_terms") on the caller's own workload through
 the C ABI, keeps the fastest, and caches the choice in a JSON file keyed by
 (device architecture, words per key, log2 of the term count, workload kind).
 Only timing and bookkeeping happen here; every measured call runs in libiqcc.
@@ -20,8 +21,8 @@ from . import iqcc
 CACHE = os.environ.get("IQCC_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "iqcc", "autotune.json"))
 
-BATCH_SPACE = {"anti_cap": [256, 512, 1024], "grid_per_cu": [1, 2, 4],
-               "split_bucket_terms": [384]}
+BATCH_SPACE = {"batch_anti_cap": [256, 512, 1024], "grid_per_cu": [1, 2, 4],
+               "batch_split_bucket_terms": [256, 384, 768]}
 CHAIN_SPACE = {"anti_cap": [512, 1024], "grid_per_cu": [1, 2, 4],
                "split_bucket_terms": [256, 384, 768]}
 

@@ -24,6 +24,8 @@ struct iqcc_ctx {
   int64_t split_bucket_terms = 768;
   int64_t anti_cap = 1024;
   int64_t grid_per_cu = 2;
+  int64_t batch_split_bucket_terms = 384;   // many small Hamiltonians: more, smaller pairs
+  int64_t batch_anti_cap = 512;
   int64_t fuse_energy = 1;
   int64_t dis_tile = 256;
   // device scratch
@@ -226,6 +228,8 @@ int iqcc_set_param(iqcc_ctx* ctx, const char* name, int64_t v) {
       {"split_bucket_terms", &ctx->split_bucket_terms, 1, 1 << 20},
       {"anti_cap", &ctx->anti_cap, 16, 8192},
       {"grid_per_cu", &ctx->grid_per_cu, 1, 16},
+      {"batch_split_bucket_terms", &ctx->batch_split_bucket_terms, 1, 1 << 20},
+      {"batch_anti_cap", &ctx->batch_anti_cap, 16, 8192},
       {"fuse_energy", &ctx->fuse_energy, 0, 1},
       {"dis_tile", &ctx->dis_tile, 1, 256},
   };
@@ -244,6 +248,8 @@ int iqcc_get_param(const iqcc_ctx* ctx, const char* name, int64_t* v) {
   const struct { const char* n; int64_t p; } tab[] = {
       {"load_bucket_terms", ctx->load_bucket_terms}, {"split_bucket_terms", ctx->split_bucket_terms},
       {"anti_cap", ctx->anti_cap}, {"grid_per_cu", ctx->grid_per_cu},
+      {"batch_split_bucket_terms", ctx->batch_split_bucket_terms},
+      {"batch_anti_cap", ctx->batch_anti_cap},
       {"fuse_energy", ctx->fuse_energy}, {"dis_tile", ctx->dis_tile},
       {"n_cu", ctx->n_cu},
   };
@@ -580,8 +586,8 @@ static int batch_build(iqcc_ctx* ctx, int n_ham, const iqcc_store* const* ins,
   if (e != hipSuccess) return fail(ctx, IQCC_ERR_HIP, "batch allocation: %s", hipGetErrorString(e));
   b->cfg = DressConfig{};
   b->cfg.eps = eps;
-  b->cfg.split_thr = ctx->split_bucket_terms;
-  b->cfg.anti_cap = (int)ctx->anti_cap;
+  b->cfg.split_thr = ctx->batch_split_bucket_terms;
+  b->cfg.anti_cap = (int)ctx->batch_anti_cap;
   const size_t lds = dress_lds_bytes(W, b->cfg.anti_cap, false, false);
   if (lds > ctx->lds_per_block)
     return fail(ctx, IQCC_ERR_INVALID_ARG, "anti_cap needs more LDS than a workgroup has");

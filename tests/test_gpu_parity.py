@@ -126,6 +126,16 @@ def test_chain_two_words(ctx, update):
     _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), taus, 1e-8, th, ph, 4 * 10**6, update=update)
 
 
+@pytest.mark.parametrize("nq,update", [(150, False), (200, True)])
+def test_chain_three_and_four_words(ctx, nq, update):
+    """Keys of three (150 qubits) and four (200 qubits) words per plane."""
+    x, z, c = I.hamiltonian_banded(nq, 7, band=1)
+    cx, cz = I.dis_candidates(x, nq, 3, 8, np.random.default_rng(nq))
+    th, ph = I.qmf_angles(nq, np.random.default_rng(nq + 1))
+    _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), [0.1, -0.15, 0.12], 1e-8, th, ph,
+                   4 * len(c), update=update)
+
+
 @pytest.mark.parametrize("update", [False, True])
 def test_chain_overflow_rounds(ctx, update):
     """Tiny LDS capacity and large buckets force the hash-round path."""
