@@ -48,40 +48,55 @@ __global__ __launch_bounds__(kBlock) void k_abs_hist(StoreDev st, const SelState
 }
 
 // Pick the digit at which the count reaches ss->need, scanning from the
-// largest digit down (descending) or from 0 up, and clear the histogram.  The
-// histogram is staged in LDS by the block; one thread scans it.
+// largest digit down (descending) or from 0 up, and clear the histogram.  Each
+// thread owns 8 consecutive digits in scan order; a block scan of the per-thread
+// sums finds the thread whose digits contain the crossing, and that thread
+// resolves it.
 __global__ __launch_bounds__(kBlock) void k_pick_digit(SelState* ss, unsigned* hist, int width,
                                                        int descending, int last, int key_word) {
-  __shared__ unsigned h[kSelBins];
+  __shared__ uint64_t scan_tmp[kWaves];
   const int nb = 1 << width;
-  for (int k = threadIdx.x; k < nb; k += kBlock) {
-    h[k] = hist[k];
-    hist[k] = 0;
+  constexpr int kPer = kSelBins / kBlock;   // 8 digits per thread
+  unsigned v[kPer];
+  uint64_t mine = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int r = threadIdx.x * kPer + k;   // rank in scan order
+    const int d = descending ? nb - 1 - r : r;
+    v[k] = r < nb ? hist[d] : 0u;
+    if (r < nb) hist[d] = 0u;
+    mine += v[k];
   }
+  uint64_t total;
+  const uint64_t before_mine = block_exclusive_scan(mine, scan_tmp, total);
+  const int64_t need = ss->need;
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  int64_t before = 0;
-  int pick = descending ? nb - 1 : 0;
-  for (int k = 0; k < nb; ++k) {
-    const int d = descending ? nb - 1 - k : k;
-    if (before + (int64_t)h[d] >= ss->need) {
-      pick = d;
-      break;
+  // the thread whose range holds the crossing (need >= 1 and need <= total)
+  if ((int64_t)before_mine < need && (int64_t)(before_mine + mine) >= need) {
+    int64_t before = (int64_t)before_mine;
+    int pick_r = threadIdx.x * kPer + kPer - 1;
+    unsigned at = v[kPer - 1];
+    for (int k = 0; k < kPer; ++k) {
+      if (before + (int64_t)v[k] >= need) {
+        pick_r = threadIdx.x * kPer + k;
+        at = v[k];
+        break;
+      }
+      before += v[k];
     }
-    before += h[d];
-  }
-  const int64_t at = h[pick];
-  ss->need -= before;
-  ss->passed += before;
-  ss->prefix = (ss->prefix << width) | (uint64_t)pick;
-  if (last) {
-    if (key_word < 0) {
-      ss->T = ss->prefix;
-      ss->ties = at;
-    } else {
-      ss->kthr[key_word] = ss->prefix;
+    const int pick = descending ? nb - 1 - pick_r : pick_r;
+    ss->need = need - before;
+    ss->passed += before;
+    ss->prefix = (ss->prefix << width) | (uint64_t)pick;
+    if (last) {
+      if (key_word < 0) {
+        ss->T = ss->prefix;
+        ss->ties = at;
+      } else {
+        ss->kthr[key_word] = ss->prefix;
+      }
+      ss->prefix = 0;
     }
-    ss->prefix = 0;
   }
 }
 
