@@ -267,6 +267,25 @@ int iqcc_dis_gradients(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
                        const double *phi, const uint64_t *cx, const uint64_t *cz,
                        int64_t n_cand, int64_t ld_cand, int mode, double *g, void *stream);
 
+/* ---- sortless dressing (App. D): the comparison path ---------------------- */
+
+/* Synchronising: the same dressing step as iqcc_dress (Eq. 5, merge D = H + I,
+ * compression |c| < eps) on a flat Hamiltonian that is globally sorted in
+ * canonical order (x words, then z words, most significant word first) and has
+ * unique keys, following the paper's sortless dressing: partition H by the key
+ * bits P flips (each partition stays sorted), dress each partition, merge the
+ * images into the partition they land in, and restore the global order by a
+ * multiway merge.  x, z: DEVICE word planes (leading dimension ld >= n), c:
+ * DEVICE coefficients; the result (sorted, unique) goes to the DEVICE arrays
+ * ox, oz (leading dimension ld_out >= cap), oc, and *n_out (HOST) receives its
+ * size (IQCC_ERR_CAPACITY when it exceeds cap).  The entangler may flip at
+ * most 20 key bits (popcount of its x and z words).  Working memory is
+ * allocated per call. */
+int iqcc_sortless_dress(iqcc_ctx *ctx, int n_qubits, const uint64_t *x, const uint64_t *z,
+                        const double *c, int64_t n, int64_t ld, const uint64_t *px,
+                        const uint64_t *pz, double tau, double eps, uint64_t *ox, uint64_t *oz,
+                        double *oc, int64_t cap, int64_t ld_out, int64_t *n_out, void *stream);
+
 /* ---- term-limit compression ---------------------------------------------- */
 
 /* Synchronising: out = the max_terms terms of `in` with the largest |c|; when

@@ -1049,4 +1049,41 @@ int iqcc_truncate_top(iqcc_ctx* ctx, const iqcc_store* in, int64_t max_terms, iq
   return IQCC_OK;
 }
 
+
+// ---- sortless dressing (App. D), the comparison path -------------------------
+
+int iqcc_sortless_dress(iqcc_ctx* ctx, int n_qubits, const uint64_t* x, const uint64_t* z,
+                        const double* c, int64_t n, int64_t ld, const uint64_t* px,
+                        const uint64_t* pz, double tau, double eps, uint64_t* ox, uint64_t* oz,
+                        double* oc, int64_t cap, int64_t ld_out, int64_t* n_out, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (n_qubits < 1 || n_qubits > 64 * kMaxWords || n < 0 || ld < n || cap < 0 || ld_out < cap ||
+      !px || !pz || !n_out || (n > 0 && (!x || !z || !c)) || (cap > 0 && (!ox || !oz || !oc)))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad sortless-dressing arguments");
+  if (n >= (int64_t)1 << 32) return fail(ctx, IQCC_ERR_INVALID_ARG, "at most 2^32 - 1 terms");
+  if (!std::isfinite(tau)) return fail(ctx, IQCC_ERR_INVALID_ARG, "tau is not finite");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(ctx, IQCC_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  const int W = (n_qubits + 63) / 64;
+  if (!padding_clear(n_qubits, W, px, pz))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
+  PauliKey P{};
+  int nbits = 0;
+  for (int w = 0; w < W; ++w) {
+    P.x[w] = px[w];
+    P.z[w] = pz[w];
+    nbits += __builtin_popcountll(px[w]) + __builtin_popcountll(pz[w]);
+  }
+  if (nbits > 20) return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler flips %d key bits (at most 20)", nbits);
+  *n_out = 0;
+  if (n == 0) return IQCC_OK;
+  const hipError_t e = sortless_dress_run(W, x, z, c, n, ld, P, nbits, std::cos(tau), std::sin(tau),
+                                          eps, ox, oz, oc, cap, ld_out, n_out, as_stream(stream));
+  if (e == hipErrorInvalidValue && *n_out > cap)
+    return fail(ctx, IQCC_ERR_CAPACITY, "result has %lld terms, room for %lld", (long long)*n_out,
+                (long long)cap);
+  if (e != hipSuccess) return fail(ctx, IQCC_ERR_HIP, "sortless dressing: %s", hipGetErrorString(e));
+  return IQCC_OK;
+}
+
 }  // extern "C"

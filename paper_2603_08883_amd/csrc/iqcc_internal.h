@@ -327,6 +327,13 @@ void launch_select_compact(int W, const StoreDev& in, const StoreDev& out, const
 struct PauliKey {
   uint64_t x[kMaxWords], z[kMaxWords];
 };
+// Sortless dressing of a flat, canonically sorted Hamiltonian (kernels_sortless.hip).
+// nbits = popcount(P.x) + popcount(P.z); synchronises; hipErrorInvalidValue when the
+// result exceeds cap (*n_out is set).
+hipError_t sortless_dress_run(int W, const uint64_t* x, const uint64_t* z, const double* c, int64_t n,
+                              int64_t ld, const PauliKey& P, int nbits, double C, double S, double eps,
+                              uint64_t* ox, uint64_t* oz, double* oc, int64_t cap, int64_t ld_out,
+                              int64_t* n_out, hipStream_t s);
 void launch_flip_rows(int W, const StoreDev& st, int w_max, uint64_t* ox, uint64_t* oz, double* oc,
                       int64_t ld, unsigned long long* count, int grid, hipStream_t s);
 void launch_energy_anti(int W, const StoreDev& st, const PauliKey& P, int grid, const double* lut,

@@ -82,6 +82,8 @@ def lib():
         "iqcc_batch_destroy": (i32, [P, P]),
         "iqcc_qmf_energy_anti": (i32, [P, P, P, P, P, P, P, P]),
         "iqcc_truncate_top": (i32, [P, P, i64, P, P]),
+        "iqcc_sortless_dress": (i32, [P, i32, P, P, P, i64, i64, P, P, d, d, P, P, P, i64, i64,
+                                      ct.POINTER(i64), P]),
         "iqcc_flip_sets": (i32, [P, P, i32, P, i64, ct.POINTER(i64)]),
         "iqcc_qcc_iteration": (i32, [P, ct.POINTER(P), ct.POINTER(P), P, P, i32, i32, d, P, P, P, P, P,
                                      ct.POINTER(i64), ct.POINTER(i32)]),
@@ -105,6 +107,7 @@ def exported_symbols():
         "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
         "iqcc_dress_batched", "iqcc_batch_create", "iqcc_batch_launch", "iqcc_batch_destroy",
         "iqcc_qmf_energy_anti", "iqcc_flip_sets", "iqcc_qcc_iteration", "iqcc_truncate_top",
+        "iqcc_sortless_dress",
     ]
 
 
@@ -400,6 +403,26 @@ def iqcc_qmf_energy_anti(ctx, store, px, pz, theta, phi, out=None, stream=None):
     _check(lib().iqcc_qmf_energy_anti(ctx, store, pxp, pzp, _ptr(theta), _ptr(phi), _ptr(out),
                                       _stream(stream)), ctx)
     return out
+
+
+def iqcc_sortless_dress(ctx, n_qubits, x, z, c, px, pz, tau, eps, cap=None, stream=None):
+    """Sortless dressing of a canonically sorted flat Hamiltonian (device planes
+    x, z of shape (W, n) int64, c (n,) float64); returns (ox, oz, oc) trimmed."""
+    import torch
+    n = int(c.numel())
+    W = int(x.shape[0])
+    cap = int(cap if cap is not None else max(2 * n, 1))
+    ox = torch.empty((W, cap), dtype=torch.int64, device="cuda")
+    oz = torch.empty((W, cap), dtype=torch.int64, device="cuda")
+    oc = torch.empty((cap,), dtype=torch.float64, device="cuda")
+    ax, pxp = _words(px)
+    az, pzp = _words(pz)
+    nout = ct.c_int64()
+    _check(lib().iqcc_sortless_dress(ctx, int(n_qubits), _ptr(x), _ptr(z), _ptr(c), n, int(x.stride(0)) if n else 0,
+                                     pxp, pzp, float(tau), float(eps), _ptr(ox), _ptr(oz), _ptr(oc), cap, cap,
+                                     ct.byref(nout), _stream(stream)), ctx)
+    k = nout.value
+    return ox[:, :k], oz[:, :k], oc[:k]
 
 
 def iqcc_truncate_top(ctx, store_in, max_terms: int, store_out, stream=None):
