@@ -1,12 +1,12 @@
 /*
  * iqcc.h -- C ABI of the MI355X (gfx950) iQCC hot-path library, libiqcc.so.
  *
- * What the library computes (paper: "Parallel iQCC ...", arXiv 2603.08883):
+ * What the library computes (the parallel iQCC paper, arXiv 2603.08883):
  *   H = sum_k C_k P_k                                   (Sec. II, Eq. 2)
  *   H' = e^{i tau P/2} H e^{-i tau P/2}                 (Sec. II, Eq. 5, closed form)
  *      = merge of the raw terms D = H + I                (App. D, sortless dressing)
  *      followed by dropping terms with |c| < eps         (App. A, iterative procedure,
- *                                                         "compress small terms")
+ *                                                         optional compression step)
  *   E = <Omega| H |Omega>, QMF product state            (Sec. II, Eq. 3)
  *   g_a = Im <Omega| H P_a |Omega>                      (Sec. II, Eq. 7; App. A DIS)
  *   dE/dtheta_j, dE/dphi_j                              (derivative of Eq. 3 energy)
@@ -292,7 +292,7 @@ int iqcc_sortless_dress(iqcc_ctx *ctx, int n_qubits, const uint64_t *x, const ui
  * several terms share the |c| at the boundary, those with the smaller canonical
  * key (x words, then z words, most significant word first) are kept, so the
  * result is unique.  All terms are kept when `in` has at most max_terms.  This
- * is the "maximum terms" limit of the Ru-catalyst runs (Results, the run tables
+ * is the maximum-terms limit of the Ru-catalyst runs (Results, the run tables
  * and the discussion of the coefficient cutoff and the term limit), applied
  * next to the coefficient cutoff of iqcc_dress.
  * out keeps in's bucket table and arena rows (each bucket's kept terms in

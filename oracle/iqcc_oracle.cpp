@@ -17,7 +17,7 @@
 //  * Merge (sortless-dressing appendix, D = H + I): equal words are combined by
 //    adding coefficients, in input order after a stable sort on the canonical
 //    key (x[W-1..0], z[W-1..0] compared as unsigned words).
-//  * Compression (iterative-procedure step "compress small terms"): drop a term
+//  * Compression (the optional compression step of the iterative procedure): drop a term
 //    when |c| < eps (strict).
 //  * QMF energy (Eq. 3 and the energy functional of App. A):
 //    E = sum_k C_k prod_j <sigma_kj>_j with <X> = sin t cos f, <Y> = sin t sin f,

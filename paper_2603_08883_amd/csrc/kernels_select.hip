@@ -1,4 +1,4 @@
-// Term-limit compression: keep the M terms of largest |c| (the "maximum terms"
+// Term-limit compression: keep the M terms of largest |c| (the maximum-terms
 // limit of the paper's Ru-catalyst runs, Results, next to the coefficient
 // cutoff; ties broken by the smaller canonical key so that the kept set is
 // unique).
