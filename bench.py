@@ -221,6 +221,53 @@ def sortless_leg(ctx, wl, fused_chain_ms, fused_final_terms):
             "fused_over_sortless_speedup": dt * 1e3 / fused_chain_ms}
 
 
+def poly_leg(ctx, n_gen=4, budget_s=10.0):
+    """Exact energy polynomial of the 4 largest-gradient DIS generators of the
+    40-qubit Hamiltonian (3^4 grid chains sharing prefixes, no compression) and
+    its coordinate-descent minimum, against the oracle on a bounded number of
+    grid chains."""
+    import torch
+    from paper_2603_08883_amd import inputs as I
+    from paper_2603_08883_amd import iqcc
+    from oracle import oracle as O
+    from oracle import qcc as Q
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    th, ph = I.qmf_angles(nq, I.rng_for(1, I.PURPOSE_ANGLES))
+    tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
+    h = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    cx, cz = Q.dis_generators(Q.flip_sets(x, 2))
+    g = iqcc.iqcc_dis_gradients(ctx.handle, h.handle, tht, pht, iqcc.to_device_words(cx),
+                                iqcc.to_device_words(cz)).cpu().numpy()
+    pick = np.argsort(-np.abs(g), kind="stable")[:n_gen]
+    pxs, pzs = cx[pick], cz[pick]
+    work = [iqcc.Store(ctx, nq, 2 * len(c) * 2 ** (k + 1)) for k in range(n_gen)]
+    iqcc.iqcc_energy_trig_poly(ctx.handle, h.handle, pxs, pzs, tht, pht, work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    coef = iqcc.iqcc_energy_trig_poly(ctx.handle, h.handle, pxs, pzs, tht, pht, work)
+    tau, e = iqcc.iqcc_trig_poly_minimize(coef, np.zeros(n_gen), sweeps=200)
+    dt = time.perf_counter() - t0
+    # oracle: full chains for a few grid points
+    k, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < budget_s and k < 3 ** n_gen:
+        hx, hz, hc = x, z, c
+        for j in range(n_gen):
+            hx, hz, hc = O.dress(nq, hx, hz, hc, pxs[j], pzs[j], Q.GRID[(k // 3 ** j) % 3], 0.0)
+        O.qmf_energy(nq, hx, hz, hc, th, ph)
+        k += 1
+    odt = time.perf_counter() - t1
+    h.close()
+    for w in work:
+        w.close()
+    return {"workload": f"40-qubit dense JW Hamiltonian ({len(c)} terms), {n_gen} largest-gradient DIS "
+                        f"generators, {3 ** n_gen} grid chains without compression",
+            "ms": dt * 1e3, "energy_at_zero": float(iqcc.iqcc_trig_poly_eval(coef, np.zeros(n_gen))),
+            "minimum": e, "taus": [float(v) for v in tau],
+            "cpu_oracle": {"kind": "oracle", "cores": 1, "sample": f"{k} of {3 ** n_gen} grid chains, {odt:.1f} s",
+                           "ms_extrapolated": odt / max(k, 1) * 3 ** n_gen * 1e3}}
+
+
 def qcc_leg(ctx, budget_s=10.0):
     """One iQCC iteration (screen all DIS candidates of the flip sets with
     |F| <= 4, take the 4 largest gradients, closed-form amplitude and dressing
@@ -291,6 +338,7 @@ def main():
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-qcc", action="store_true")
     ap.add_argument("--no-sortless", action="store_true")
+    ap.add_argument("--no-poly", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (scale for profiler byte counters)")
@@ -584,6 +632,11 @@ def main():
         log(f"batch: graph {tg*1e3:.3f} ms vs {len(hs)} plain calls {tp*1e3:.3f} ms")
         for s_ in ins + outs:
             s_.close()
+
+    if not args.no_poly:
+        result["energy_polynomial"] = poly_leg(ctx)
+        log(f"energy polynomial {result['energy_polynomial']['ms']:.1f} ms")
+        torch.cuda.empty_cache()
 
     if not args.no_qcc:
         result["qcc_iteration"] = qcc_leg(ctx)

@@ -342,6 +342,32 @@ int iqcc_qcc_iteration(iqcc_ctx *ctx, iqcc_store **h, iqcc_store **spare, const 
                        uint64_t *sel_z, double *sel_g, double *sel_tau, double *energy,
                        int64_t *n_candidates, int *n_applied);
 
+/* ---- several generators at once (Eqs. 5 and 6) ----------------------------- */
+
+/* Synchronising.  Dressing h with P_1 at tau_1, then P_2 at tau_2, ..., P_n at
+ * tau_n (Eq. 6, no compression) turns every term into a sum over branches in
+ * which each generator contributes 1, cos(tau_k) or sin(tau_k) (Eq. 5), so the
+ * QMF energy is exactly the trigonometric polynomial
+ *   E(tau) = sum_s coef[s] prod_k f_{s_k}(tau_k),  f_0 = 1, f_1 = cos, f_2 = sin,
+ *   s = s_0 + 3 s_1 + ... + 3^(n-1) s_(n-1).
+ * The 3^n coefficients (HOST array, 1 <= n <= 8) are obtained from the energies
+ * of the dressed Hamiltonians on the grid tau_k in {0, pi/2, pi} (3^n chains,
+ * sharing prefixes) and one 3x3 inverse per axis.  px, pz: HOST [n][n_words];
+ * work: n distinct stores (same n_qubits, large enough for each prefix of the
+ * chain), overwritten. */
+int iqcc_energy_trig_poly(iqcc_ctx *ctx, const iqcc_store *h, int n, const uint64_t *px,
+                          const uint64_t *pz, const double *theta, const double *phi,
+                          iqcc_store *const *work, double *coef);
+
+/* HOST only: value of that polynomial at tau[0..n). */
+double iqcc_trig_poly_eval(int n, const double *coef, const double *tau);
+
+/* HOST only: coordinate descent on the polynomial; each coordinate update is
+ * the exact minimiser of a + b cos(tau_k) + c sin(tau_k) with the other
+ * amplitudes fixed.  tau (in: start, out: result); stops after `sweeps` sweeps
+ * or when a sweep does not lower the energy; *energy receives E(tau). */
+int iqcc_trig_poly_minimize(int n, const double *coef, double *tau, int sweeps, double *energy);
+
 #ifdef __cplusplus
 }
 #endif

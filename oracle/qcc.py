@@ -19,6 +19,12 @@ of ``iqcc_oracle.cpp`` (through ``oracle.py``) and plain numpy / Python:
    b = sum over anticommuting terms of c_k <P_k>, a = E - b, and c = dE/dtau at
    0, the DIS gradient of P.  The minimum is at (cos tau, sin tau) = -(b, c) /
    |(b, c)|, i.e. tau = atan2(-c, -b).  Dress with that tau and compress.
+
+Several generators at once (Eqs. 5 and 6): without compression, dressing with
+P_1..P_n splits every term into branches that carry 1, cos(tau_k) or
+sin(tau_k) per generator, so E(tau_1..tau_n) is a trigonometric polynomial with
+3^n coefficients; they follow from the energies on the grid {0, pi/2, pi}^n by
+inverting the 3x3 basis matrix along every axis.
 """
 from __future__ import annotations
 
@@ -126,3 +132,41 @@ def qcc_iteration(nq, x, z, c, theta, phi, w_max, n_select, eps):
     res["sel_tau"] = np.array(res["sel_tau"])
     res["energy"] = np.array(energies)
     return res, (x, z, c)
+
+
+# --- several generators at once -------------------------------------------
+
+GRID = (0.0, 0.5 * math.pi, math.pi)
+
+
+def energy_trig_poly(nq, x, z, c, pxs, pzs, theta, phi):
+    """3^n coefficients of E(tau_1..tau_n) in the basis (1, cos, sin) per
+    generator (index s = s_0 + 3 s_1 + ...), from the oracle energies of the
+    dressed chains (no compression) on the grid {0, pi/2, pi}^n."""
+    n = len(pxs)
+    E = np.zeros([3] * n)
+    for t in np.ndindex(*([3] * n)):
+        hx, hz, hc = x, z, c
+        for k in range(n):
+            hx, hz, hc = O.dress(nq, hx, hz, hc, pxs[k], pzs[k], GRID[t[k]], 0.0)
+        E[t] = O.qmf_energy(nq, hx, hz, hc, theta, phi)
+    M = np.array([[1.0, math.cos(a), math.sin(a)] for a in GRID])
+    Mi = np.linalg.inv(M)
+    coef = E
+    for k in range(n):
+        coef = np.moveaxis(np.tensordot(Mi, coef, axes=([1], [k])), 0, k)
+    # flatten with axis 0 least significant
+    return np.transpose(coef, list(range(n))[::-1]).reshape(-1)
+
+
+def trig_poly_eval(coef, tau):
+    n = len(tau)
+    f = [np.array([1.0, math.cos(t), math.sin(t)]) for t in tau]
+    total = []
+    for s in range(3 ** n):
+        p, v = coef[s], s
+        for k in range(n):
+            p *= f[k][v % 3]
+            v //= 3
+        total.append(p)
+    return math.fsum(total)

@@ -1086,4 +1086,144 @@ int iqcc_sortless_dress(iqcc_ctx* ctx, int n_qubits, const uint64_t* x, const ui
   return IQCC_OK;
 }
 
+
+// ---- several generators at once: exact energy polynomial (Eqs. 5, 6) ---------
+
+namespace {
+
+// f_b(tau) for the basis (1, cos, sin) at the grid angles 0, pi/2, pi, computed
+// exactly as the dressing computes its cos and sin.
+void grid_basis(double M[3][3]) {
+  const double t[3] = {0.0, 0.5 * M_PI, M_PI};
+  for (int r = 0; r < 3; ++r) {
+    M[r][0] = 1.0;
+    M[r][1] = std::cos(t[r]);
+    M[r][2] = std::sin(t[r]);
+  }
+}
+
+bool invert3(const double A[3][3], double B[3][3]) {
+  const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                     A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                     A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  if (det == 0.0) return false;
+  B[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / det;
+  B[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / det;
+  B[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / det;
+  B[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / det;
+  B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / det;
+  B[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / det;
+  B[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / det;
+  B[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / det;
+  B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / det;
+  return true;
+}
+
+}  // namespace
+
+int iqcc_energy_trig_poly(iqcc_ctx* ctx, const iqcc_store* h, int n, const uint64_t* px,
+                          const uint64_t* pz, const double* theta, const double* phi,
+                          iqcc_store* const* work, double* coef) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h || n < 1 || n > 8 || !px || !pz || !theta || !phi || !work || !coef)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad trigonometric-polynomial arguments");
+  const int W = h->W;
+  for (int k = 0; k < n; ++k) {
+    if (!work[k] || work[k] == h) return fail(ctx, IQCC_ERR_INVALID_ARG, "work store %d is invalid", k);
+    for (int j = 0; j < k; ++j)
+      if (work[j] == work[k]) return fail(ctx, IQCC_ERR_INVALID_ARG, "work stores alias");
+  }
+  const int64_t npts = (int64_t)std::pow(3.0, n);
+  std::vector<double> grid(npts);
+  DevBuf de;
+  HIP_TRY(ctx, hipMalloc(&de.p, 8));
+  const double tgrid[3] = {0.0, 0.5 * M_PI, M_PI};
+  // depth-first over the grid: level k dresses work[k-1] (or h) into work[k]
+  std::vector<int> digit(n, 0);
+  int level = 0;
+  int64_t done = 0;
+  while (done < npts) {
+    for (; level < n; ++level) {
+      const iqcc_store* src = level == 0 ? h : work[level - 1];
+      rc = iqcc_dress(ctx, src, px + (size_t)level * W, pz + (size_t)level * W, tgrid[digit[level]], 0.0,
+                      nullptr, nullptr, nullptr, work[level], nullptr);
+      if (rc) return rc;
+    }
+    rc = iqcc_qmf_energy(ctx, work[n - 1], theta, phi, (double*)de.p, nullptr);
+    if (rc) return rc;
+    int64_t idx = 0;
+    for (int k = n - 1; k >= 0; --k) idx = idx * 3 + digit[k];
+    HIP_TRY(ctx, hipMemcpy(&grid[idx], de.p, 8, hipMemcpyDeviceToHost));
+    ++done;
+    // next grid point: increment the last digit, carrying upwards
+    int k = n - 1;
+    while (k >= 0 && digit[k] == 2) digit[k--] = 0;
+    if (k < 0) break;
+    ++digit[k];
+    level = k;
+  }
+  // E(grid t) = sum_s coef[s] prod_k M[t_k][s_k]: apply M^-1 along every axis
+  double M[3][3], Mi[3][3];
+  grid_basis(M);
+  if (!invert3(M, Mi)) return fail(ctx, IQCC_ERR_INVALID_ARG, "singular grid");
+  std::vector<double> a = grid, b(npts);
+  int64_t stride = 1;
+  for (int k = 0; k < n; ++k, stride *= 3) {
+    for (int64_t i = 0; i < npts; ++i) {
+      const int64_t d = (i / stride) % 3;
+      const int64_t base = i - d * stride;
+      b[i] = Mi[d][0] * a[base] + Mi[d][1] * a[base + stride] + Mi[d][2] * a[base + 2 * stride];
+    }
+    std::swap(a, b);
+  }
+  std::copy(a.begin(), a.end(), coef);
+  return IQCC_OK;
+}
+
+double iqcc_trig_poly_eval(int n, const double* coef, const double* tau) {
+  const int64_t npts = (int64_t)std::pow(3.0, n);
+  double e = 0.0;
+  for (int64_t s = 0; s < npts; ++s) {
+    double p = coef[s];
+    int64_t v = s;
+    for (int k = 0; k < n; ++k, v /= 3) {
+      const int d = (int)(v % 3);
+      p *= d == 0 ? 1.0 : d == 1 ? std::cos(tau[k]) : std::sin(tau[k]);
+    }
+    e += p;
+  }
+  return e;
+}
+
+int iqcc_trig_poly_minimize(int n, const double* coef, double* tau, int sweeps, double* energy) {
+  if (n < 1 || n > 8 || !coef || !tau || !energy || sweeps < 0) return IQCC_ERR_INVALID_ARG;
+  const int64_t npts = (int64_t)std::pow(3.0, n);
+  double e = iqcc_trig_poly_eval(n, coef, tau);
+  for (int sw = 0; sw < sweeps; ++sw) {
+    const double e0 = e;
+    for (int k = 0; k < n; ++k) {
+      // with the other amplitudes fixed, E = a + b cos(tau_k) + c sin(tau_k)
+      double abc[3] = {0.0, 0.0, 0.0};
+      int64_t pk = 1;
+      for (int j = 0; j < k; ++j) pk *= 3;
+      for (int64_t s = 0; s < npts; ++s) {
+        double p = coef[s];
+        int64_t v = s;
+        for (int j = 0; j < n; ++j, v /= 3) {
+          if (j == k) continue;
+          const int d = (int)(v % 3);
+          p *= d == 0 ? 1.0 : d == 1 ? std::cos(tau[j]) : std::sin(tau[j]);
+        }
+        abc[(s / pk) % 3] += p;
+      }
+      if (abc[1] != 0.0 || abc[2] != 0.0) tau[k] = std::atan2(-abc[2], -abc[1]);
+    }
+    e = iqcc_trig_poly_eval(n, coef, tau);
+    if (!(e < e0)) break;
+  }
+  *energy = e;
+  return IQCC_OK;
+}
+
 }  // extern "C"

@@ -82,6 +82,9 @@ def lib():
         "iqcc_batch_destroy": (i32, [P, P]),
         "iqcc_qmf_energy_anti": (i32, [P, P, P, P, P, P, P, P]),
         "iqcc_truncate_top": (i32, [P, P, i64, P, P]),
+        "iqcc_energy_trig_poly": (i32, [P, P, i32, P, P, P, P, P, P]),
+        "iqcc_trig_poly_eval": (d, [i32, P, P]),
+        "iqcc_trig_poly_minimize": (i32, [i32, P, P, i32, ct.POINTER(d)]),
         "iqcc_sortless_dress": (i32, [P, i32, P, P, P, i64, i64, P, P, d, d, P, P, P, i64, i64,
                                       ct.POINTER(i64), P]),
         "iqcc_flip_sets": (i32, [P, P, i32, P, i64, ct.POINTER(i64)]),
@@ -107,7 +110,8 @@ def exported_symbols():
         "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
         "iqcc_dress_batched", "iqcc_batch_create", "iqcc_batch_launch", "iqcc_batch_destroy",
         "iqcc_qmf_energy_anti", "iqcc_flip_sets", "iqcc_qcc_iteration", "iqcc_truncate_top",
-        "iqcc_sortless_dress",
+        "iqcc_sortless_dress", "iqcc_energy_trig_poly", "iqcc_trig_poly_eval",
+        "iqcc_trig_poly_minimize",
     ]
 
 
@@ -423,6 +427,34 @@ def iqcc_sortless_dress(ctx, n_qubits, x, z, c, px, pz, tau, eps, cap=None, stre
                                      ct.byref(nout), _stream(stream)), ctx)
     k = nout.value
     return ox[:, :k], oz[:, :k], oc[:k]
+
+
+def iqcc_energy_trig_poly(ctx, store, pxs, pzs, theta, phi, work):
+    """3^n coefficients of E(tau_1..tau_n); pxs, pzs (n, W) host words, work: n Stores."""
+    pxs = np.ascontiguousarray(pxs, np.uint64); pzs = np.ascontiguousarray(pzs, np.uint64)
+    n = pxs.shape[0]
+    coef = np.zeros(3 ** n)
+    arr = (ct.c_void_p * n)(*[w.handle for w in work])
+    _check(lib().iqcc_energy_trig_poly(ctx, store, n, pxs.ctypes.data_as(ct.c_void_p),
+                                       pzs.ctypes.data_as(ct.c_void_p), _ptr(theta), _ptr(phi), arr,
+                                       coef.ctypes.data_as(ct.c_void_p)), ctx)
+    return coef
+
+
+def iqcc_trig_poly_eval(coef, tau):
+    coef = np.ascontiguousarray(coef, np.float64); tau = np.ascontiguousarray(tau, np.float64)
+    return lib().iqcc_trig_poly_eval(len(tau), coef.ctypes.data_as(ct.c_void_p), tau.ctypes.data_as(ct.c_void_p))
+
+
+def iqcc_trig_poly_minimize(coef, tau0, sweeps=100):
+    coef = np.ascontiguousarray(coef, np.float64)
+    tau = np.array(tau0, dtype=np.float64)
+    e = ct.c_double()
+    rc = lib().iqcc_trig_poly_minimize(len(tau), coef.ctypes.data_as(ct.c_void_p),
+                                       tau.ctypes.data_as(ct.c_void_p), int(sweeps), ct.byref(e))
+    if rc:
+        raise IqccError(rc, "invalid polynomial arguments")
+    return tau, e.value
 
 
 def iqcc_truncate_top(ctx, store_in, max_terms: int, store_out, stream=None):
