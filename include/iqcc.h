@@ -81,6 +81,8 @@ const char *iqcc_version(void);
  *   "batch_split_bucket_terms", "batch_anti_cap"
  *                        the same two settings for batched dressing of many
  *                        small Hamiltonians (iqcc_dress_batched, iqcc_batch_*)
+ *   "energy_grid_per_cu" workgroups per compute unit of the stand-alone energy
+ *                        kernel (1 .. 32)
  *   "fuse_energy"        1: dressing evaluates the energy of its output in the
  *                        same pass when angles are given; 0: separate pass
  *   "dis_tile"           DIS candidates held per workgroup tile (1 .. 256)

@@ -26,6 +26,7 @@ struct iqcc_ctx {
   int64_t grid_per_cu = 2;
   int64_t batch_split_bucket_terms = 384;   // many small Hamiltonians: more, smaller pairs
   int64_t batch_anti_cap = 512;
+  int64_t energy_grid_per_cu = 16;         // stand-alone energy kernel
   int64_t fuse_energy = 1;
   int64_t dis_tile = 256;
   // device scratch
@@ -230,6 +231,7 @@ int iqcc_set_param(iqcc_ctx* ctx, const char* name, int64_t v) {
       {"grid_per_cu", &ctx->grid_per_cu, 1, 16},
       {"batch_split_bucket_terms", &ctx->batch_split_bucket_terms, 1, 1 << 20},
       {"batch_anti_cap", &ctx->batch_anti_cap, 16, 8192},
+      {"energy_grid_per_cu", &ctx->energy_grid_per_cu, 1, 32},
       {"fuse_energy", &ctx->fuse_energy, 0, 1},
       {"dis_tile", &ctx->dis_tile, 1, 256},
   };
@@ -250,6 +252,7 @@ int iqcc_get_param(const iqcc_ctx* ctx, const char* name, int64_t* v) {
       {"anti_cap", ctx->anti_cap}, {"grid_per_cu", ctx->grid_per_cu},
       {"batch_split_bucket_terms", ctx->batch_split_bucket_terms},
       {"batch_anti_cap", ctx->batch_anti_cap},
+      {"energy_grid_per_cu", ctx->energy_grid_per_cu},
       {"fuse_energy", ctx->fuse_energy}, {"dis_tile", ctx->dis_tile},
       {"n_cu", ctx->n_cu},
   };
@@ -711,7 +714,7 @@ int iqcc_qmf_energy(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, con
   if (rc) return rc;
   if (!h || !theta || !phi || !energy) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
   hipStream_t s = as_stream(stream);
-  const int grid = (int)(ctx->n_cu * 4);
+  const int grid = (int)(ctx->n_cu * ctx->energy_grid_per_cu);
   rc = ensure_partial(ctx, grid);
   if (rc) return rc;
   launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
