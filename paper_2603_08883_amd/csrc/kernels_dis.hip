@@ -5,8 +5,12 @@
 //
 // Batched form: one launch; a workgroup holds a tile of up to 256 candidates,
 // one per thread, and streams a share of the terms through LDS; every lane of
-// a wave reads the same staged term (LDS broadcast).  Per-workgroup partial
-// sums are reduced over term shares in a fixed order.
+// a wave reads the same staged term (LDS broadcast).  Q = K P_a differs from K
+// only on the 3-qubit groups P_a touches, so with <K> formed once per staged
+// term, <Q> = <K> * prod_{g of P_a} f_g(Q) / prod_{g of P_a} f_g(K): a few
+// lookups per (term, candidate) pair instead of the whole product.  When a
+// factor of K on those groups is exactly zero the full product of Q is used.
+// Per-workgroup partial sums are reduced over term shares in a fixed order.
 // Plain form: one launch per candidate streaming all terms (reference form).
 #include "iqcc_internal.h"
 
@@ -21,15 +25,18 @@ __global__ __launch_bounds__(kBlock) void k_dis_batched(StoreDev st, const doubl
                                                         double* partial) {
   __shared__ double lut[W * kGroupsPerWord * kLutEntries];
   __shared__ uint64_t tx[W][kBlock], tz[W][kBlock];
-  __shared__ double tc[kBlock];
+  __shared__ double tc[kBlock], tk[kBlock];
   for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
   const int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = a < n_cand;
   uint64_t ax[W], az[W];
+  uint32_t pg[2 * W];   // start bits of the groups P_a touches, per 32-bit half
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     ax[w] = active ? cx[w * ld_cand + a] : 0;
     az[w] = active ? cz[w * ld_cand + a] : 0;
+    pg[2 * w] = group_starts((uint32_t)(ax[w] | az[w]));
+    pg[2 * w + 1] = group_starts((uint32_t)((ax[w] | az[w]) >> 32));
   }
   __syncthreads();
   const int64_t B = 1ll << *st.m;
@@ -39,12 +46,16 @@ __global__ __launch_bounds__(kBlock) void k_dis_batched(StoreDev st, const doubl
     for (int64_t i0 = 0; i0 < n; i0 += kBlock) {
       const int64_t i = i0 + threadIdx.x;
       if (i < n) {
+        uint64_t kx[W], kz[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          tx[w][threadIdx.x] = st.x[w * st.cap + off + i];
-          tz[w][threadIdx.x] = st.z[w * st.cap + off + i];
+          kx[w] = st.x[w * st.cap + off + i];
+          kz[w] = st.z[w * st.cap + off + i];
+          tx[w][threadIdx.x] = kx[w];
+          tz[w][threadIdx.x] = kz[w];
         }
         tc[threadIdx.x] = st.c[off + i];
+        tk[threadIdx.x] = expect_lut<W>(lut, kx, kz);   // <K>, shared by the whole tile
       }
       __syncthreads();
       const int cnt = (int)((n - i0) < kBlock ? (n - i0) : kBlock);
@@ -73,7 +84,24 @@ __global__ __launch_bounds__(kBlock) void k_dis_batched(StoreDev st, const doubl
               qz[w] = kz[w] ^ az[w];
             }
             const int e = product_phase<W>(kx, kz, ax, az);
-            const double v = tc[j] * expect_lut<W>(lut, qx, qz);
+            // factors of K and of Q on the groups of P_a
+            double fk = 1.0, fq = 1.0;
+#pragma unroll
+            for (int h = 0; h < 2 * W; ++h) {
+              const uint32_t kxh = (uint32_t)(kx[h >> 1] >> (32 * (h & 1)));
+              const uint32_t kzh = (uint32_t)(kz[h >> 1] >> (32 * (h & 1)));
+              const uint32_t qxh = (uint32_t)(qx[h >> 1] >> (32 * (h & 1)));
+              const uint32_t qzh = (uint32_t)(qz[h >> 1] >> (32 * (h & 1)));
+              const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
+              for (uint32_t t = pg[h]; t; t &= t - 1) {
+                const uint32_t sh = (uint32_t)__builtin_ctz(t);
+                const uint32_t base = div3_small(sh) * kLutEntries;
+                fk *= lh[base + (__builtin_amdgcn_ubfe(kxh, sh, 3) | (__builtin_amdgcn_ubfe(kzh, sh, 3) << 3))];
+                fq *= lh[base + (__builtin_amdgcn_ubfe(qxh, sh, 3) | (__builtin_amdgcn_ubfe(qzh, sh, 3) << 3))];
+              }
+            }
+            const double q = fk != 0.0 ? (tk[j] / fk) * fq : expect_lut<W>(lut, qx, qz);
+            const double v = tc[j] * q;
             acc += (e == 1) ? v : -v;
           }
         }

@@ -254,6 +254,31 @@ def test_dis_gradients_match_oracle(ctx, mode):
     assert np.abs(ref).max() > 1e-6
 
 
+@pytest.mark.parametrize("nq,angles", [(40, "z-eigen"), (40, "mixed"), (124, "random"), (124, "mixed")])
+def test_dis_gradients_special_angles(ctx, nq, angles):
+    """Batched screening where factors of a term vanish exactly (theta = 0 or pi
+    gives sin theta = 0, so X and Y factors are 0) or nearly (theta = pi/2)."""
+    if nq == 40:
+        x, z, c = I.hamiltonian_dense(nq, 1)
+    else:
+        x, z, c = I.hamiltonian_banded(nq, 7, band=2)
+    rng = np.random.default_rng(nq + len(angles))
+    th, ph = I.qmf_angles(nq, rng)
+    if angles == "z-eigen":
+        th = np.where(rng.random(nq) < 0.5, 0.0, np.pi)
+    elif angles == "mixed":
+        k = rng.random(nq)
+        th = np.where(k < 0.3, 0.0, np.where(k < 0.5, np.pi / 2, th))
+    cx, cz = I.dis_candidates(x, nq, 200, 12, rng)
+    s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    tht, pht = torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()
+    describe(0, "dis special angles", nq=nq, angles=angles)
+    g = iqcc.iqcc_dis_gradients(ctx.handle, s.handle, tht, pht, iqcc.to_device_words(cx),
+                                iqcc.to_device_words(cz), iqcc.IQCC_DIS_BATCHED).cpu().numpy()
+    ref = O.dis_gradients(nq, x, z, c, th, ph, cx, cz)
+    assert np.abs(g - ref).max() <= E_TOL
+
+
 def test_merge_truncate_matches_oracle(ctx):
     """General multiset merge: raw dressing rows, shuffled, plus heavy duplicates."""
     nq = 40
