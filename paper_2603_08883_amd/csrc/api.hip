@@ -756,19 +756,22 @@ int iqcc_dis_gradients(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, 
   hipStream_t s = as_stream(stream);
   launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
   if (mode == IQCC_DIS_BATCHED) {
-    const int64_t tiles = (n_cand + kBlock - 1) / kBlock;
+    // candidate tiles x bucket ranges: about 8 workgroups per CU in total
+    const int64_t tiles = (n_cand + dis_tile() - 1) / dis_tile();
     int64_t gt = (ctx->n_cu * 8 + tiles - 1) / tiles;
     if (gt < 1) gt = 1;
     if (gt > 4096) gt = 4096;
-    rc = ensure_partial(ctx, gt * n_cand);
+    const int64_t n_part = (gt * n_cand + 1) & ~int64_t(1);   // tables start 16-byte aligned
+    rc = ensure_partial(ctx, n_part + dis_tables_doubles(h->W));
     if (rc) return rc;
     launch_dis(h->W, h->d, ctx->lut, cx, cz, n_cand, ld_cand, 0, (int)ctx->dis_tile, 0,
-               ctx->partial, (int)gt, g, s);
+               ctx->partial, (int)gt, g, s, theta, phi, h->nq, ctx->partial + n_part);
   } else {
     const int grid = (int)(ctx->n_cu * 4);
     rc = ensure_partial(ctx, grid);
     if (rc) return rc;
-    launch_dis(h->W, h->d, ctx->lut, cx, cz, n_cand, ld_cand, 1, 1, grid, ctx->partial, 0, g, s);
+    launch_dis(h->W, h->d, ctx->lut, cx, cz, n_cand, ld_cand, 1, 1, grid, ctx->partial, 0, g, s,
+               theta, phi, h->nq, nullptr);
   }
   LAUNCH_CHECK(ctx);
   return IQCC_OK;

@@ -350,7 +350,10 @@ void launch_backward_finalize(int nq, int grid, const double* acc, const double*
 void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx,
                 const uint64_t* cz, int64_t n_cand, int64_t ld_cand, int mode, int tile,
                 int grid, double* partial /*[grid_terms][n_cand]*/, int grid_terms,
-                double* g, hipStream_t s);
+                double* g, hipStream_t s, const double* theta, const double* phi, int nq,
+                double* tables /*dis_tables_doubles(W), batched mode*/);
+int64_t dis_tables_doubles(int W);
+int64_t dis_tile();   // candidates per workgroup of the batched kernel
 
 void launch_dress_backward(int W, const StoreDev& in, const Entangler& P, double C, double S,
                            const int64_t* tape_self, const int64_t* tape_partner,

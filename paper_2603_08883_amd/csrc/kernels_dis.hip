@@ -3,14 +3,20 @@
 // so only terms that anticommute with P_a contribute, with +<Q_k> for e = 1
 // and -<Q_k> for e = 3.
 //
-// Batched form: one launch; a workgroup holds a tile of up to 256 candidates,
-// one per thread, and streams a share of the terms through LDS; every lane of
-// a wave reads the same staged term (LDS broadcast).  Q = K P_a differs from K
-// only on the 3-qubit groups P_a touches, so with <K> formed once per staged
-// term, <Q> = <K> * prod_{g of P_a} f_g(Q) / prod_{g of P_a} f_g(K): a few
-// lookups per (term, candidate) pair instead of the whole product.  When a
-// factor of K on those groups is exactly zero the full product of Q is used.
-// Per-workgroup partial sums are reduced over term shares in a fixed order.
+// Batched form: the QMF state is a product state, so for a term K and a
+// candidate P_a the ratio <Q>/<K> (Q = K P_a) only involves the qubits in the
+// support of P_a, and so does the phase e (a sum of per-qubit parts).  A table
+// per (qubit, Pauli of P_a there, Pauli of K there) gives the factor ratio
+// b_q(Q)/b_q(K), the qubit's share of e and whether b_q(K) is exactly zero.
+// Each term carries PK = product of its non-zero qubit factors and ZK = the
+// number of zero factors; then <Q> = PK * prod(ratios) when every zero factor
+// of K lies in the support of P_a, else 0.  One table lookup per support qubit
+// and term, no division in the loop and no special case at zero factors.
+// A workgroup holds a tile of candidates and a contiguous range of buckets;
+// lanes hold terms (kR per lane, pre-split into 2-bit qubit codes) and the
+// candidate loop is uniform, so the support of P_a is walked in scalar
+// registers.  Sums over lanes and waves, then over bucket ranges, are taken in
+// a fixed order.
 // Plain form: one launch per candidate streaming all terms (reference form).
 #include "iqcc_internal.h"
 
@@ -18,99 +24,201 @@
 
 namespace iqcc {
 
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_dis_batched(StoreDev st, const double* lut_g,
-                                                        const uint64_t* cx, const uint64_t* cz,
-                                                        int64_t n_cand, int64_t ld_cand,
-                                                        double* partial) {
-  __shared__ double lut[W * kGroupsPerWord * kLutEntries];
-  __shared__ uint64_t tx[W][kBlock], tz[W][kBlock];
-  __shared__ double tc[kBlock], tk[kBlock];
-  for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
-  const int64_t a = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool active = a < n_cand;
-  uint64_t ax[W], az[W];
-  uint32_t pg[2 * W];   // start bits of the groups P_a touches, per 32-bit half
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    ax[w] = active ? cx[w * ld_cand + a] : 0;
-    az[w] = active ? cz[w * ld_cand + a] : 0;
-    pg[2 * w] = group_starts((uint32_t)(ax[w] | az[w]));
-    pg[2 * w + 1] = group_starts((uint32_t)((ax[w] | az[w]) >> 32));
+constexpr int kDisB = 512;          // threads per workgroup of the batched kernel
+constexpr int kDisWaves = kDisB / 64;
+constexpr int kDisR = 4;            // terms per lane
+constexpr int kDisTile = 256;       // candidates per workgroup
+constexpr int kDisChunk = kDisB;    // buckets whose prefix sums are staged at once
+
+// Per-qubit tables for the batched kernel, q < 64 W:
+//   ent[(q * 4 + p) * 4 + k] = {ratio, meta} for the Pauli k of K and p of P
+//   (bit 0 = x, bit 1 = z): ratio = b_q(k ^ p) / b_q(k) (b_q(k ^ p) when
+//   b_q(k) = 0), meta = [b_q(k) == 0] | (phase part << 12);
+//   fac[q * 4 + k] = b_q(k).
+struct DisEnt {
+  double ratio;
+  uint32_t meta;
+  uint32_t pad;
+};
+
+__global__ void k_dis_tables(int W, int nq, const double* theta, const double* phi,
+                             DisEnt* ent, double* fac) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 64 * W) return;
+  double b[4] = {1.0, 1.0, 1.0, 1.0};
+  if (q < nq) {
+    double st, ct, sp, cp;
+    sincos(theta[q], &st, &ct);
+    sincos(phi[q], &sp, &cp);
+    b[1] = st * cp;   // X
+    b[2] = ct;        // Z
+    b[3] = st * sp;   // Y
   }
-  __syncthreads();
-  const int64_t B = 1ll << *st.m;
-  double acc = 0.0;
-  for (int64_t b = blockIdx.y; b < B; b += gridDim.y) {
-    const int64_t n = st.cnt[b], off = st.off[b];
-    for (int64_t i0 = 0; i0 < n; i0 += kBlock) {
-      const int64_t i = i0 + threadIdx.x;
-      if (i < n) {
-        uint64_t kx[W], kz[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          kx[w] = st.x[w * st.cap + off + i];
-          kz[w] = st.z[w * st.cap + off + i];
-          tx[w][threadIdx.x] = kx[w];
-          tz[w][threadIdx.x] = kz[w];
-        }
-        tc[threadIdx.x] = st.c[off + i];
-        tk[threadIdx.x] = expect_lut<W>(lut, kx, kz);   // <K>, shared by the whole tile
-      }
-      __syncthreads();
-      const int cnt = (int)((n - i0) < kBlock ? (n - i0) : kBlock);
-      if (active) {
-        for (int j0 = 0; j0 < cnt; j0 += 64) {
-          // which of the next 64 staged terms anticommute with this lane's
-          // candidate (every lane reads the same term: LDS broadcast)
-          const int jn = (cnt - j0) < 64 ? (cnt - j0) : 64;
-          uint64_t mask = 0;
-          for (int j = 0; j < jn; ++j) {
-            uint64_t t = 0;
-#pragma unroll
-            for (int w = 0; w < W; ++w) t ^= (tx[w][j0 + j] & az[w]) ^ (tz[w][j0 + j] & ax[w]);
-            mask |= (uint64_t)(__popcll(t) & 1) << j;
-          }
-          // only the anticommuting terms of this lane
-          while (mask) {
-            const int j = j0 + __builtin_ctzll(mask);
-            mask &= mask - 1;
-            uint64_t kx[W], kz[W], qx[W], qz[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-              kx[w] = tx[w][j];
-              kz[w] = tz[w][j];
-              qx[w] = kx[w] ^ ax[w];
-              qz[w] = kz[w] ^ az[w];
-            }
-            const int e = product_phase<W>(kx, kz, ax, az);
-            // factors of K and of Q on the groups of P_a
-            double fk = 1.0, fq = 1.0;
-#pragma unroll
-            for (int h = 0; h < 2 * W; ++h) {
-              const uint32_t kxh = (uint32_t)(kx[h >> 1] >> (32 * (h & 1)));
-              const uint32_t kzh = (uint32_t)(kz[h >> 1] >> (32 * (h & 1)));
-              const uint32_t qxh = (uint32_t)(qx[h >> 1] >> (32 * (h & 1)));
-              const uint32_t qzh = (uint32_t)(qz[h >> 1] >> (32 * (h & 1)));
-              const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
-              for (uint32_t t = pg[h]; t; t &= t - 1) {
-                const uint32_t sh = (uint32_t)__builtin_ctz(t);
-                const uint32_t base = div3_small(sh) * kLutEntries;
-                fk *= lh[base + (__builtin_amdgcn_ubfe(kxh, sh, 3) | (__builtin_amdgcn_ubfe(kzh, sh, 3) << 3))];
-                fq *= lh[base + (__builtin_amdgcn_ubfe(qxh, sh, 3) | (__builtin_amdgcn_ubfe(qzh, sh, 3) << 3))];
-              }
-            }
-            const double q = fk != 0.0 ? (tk[j] / fk) * fq : expect_lut<W>(lut, qx, qz);
-            const double v = tc[j] * q;
-            acc += (e == 1) ? v : -v;
-          }
-        }
-      }
-      __syncthreads();
+  for (int k = 0; k < 4; ++k) fac[q * 4 + k] = b[k];
+  for (int p = 0; p < 4; ++p) {
+    for (int k = 0; k < 4; ++k) {
+      const int x1 = k & 1, z1 = k >> 1, x2 = p & 1, z2 = p >> 1;
+      const int ph = (x1 * z1 + x2 * z2 + 2 * z1 * x2 - (x1 ^ x2) * (z1 ^ z2)) & 3;
+      const bool zero = b[k] == 0.0;
+      DisEnt e;
+      e.ratio = zero ? b[k ^ p] : b[k ^ p] / b[k];
+      e.meta = (zero ? 1u : 0u) | ((uint32_t)ph << 12);
+      e.pad = 0;
+      ent[(q * 4 + p) * 4 + k] = e;
     }
   }
-  if (active) partial[(int64_t)blockIdx.y * n_cand + a] = acc;
 }
+
+// Spread the 16 bits of v to the even bits of a 32-bit word.
+__device__ __forceinline__ uint32_t spread16(uint32_t v) {
+  v &= 0xffffu;
+  v = (v | (v << 8)) & 0x00ff00ffu;
+  v = (v | (v << 4)) & 0x0f0f0f0fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+template <int W>
+__global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt* ent_g,
+                                                       const double* fac_g, const uint64_t* cx,
+                                                       const uint64_t* cz, int64_t n_cand,
+                                                       int64_t ld_cand, double* partial) {
+  constexpr int NQ = 64 * W;
+  constexpr int NS = 4 * W;   // 16-qubit slots
+  __shared__ DisEnt ent[NQ * 16];
+  __shared__ double fac[NQ * 4];
+  __shared__ double acc[kDisWaves][kDisTile];
+  __shared__ int64_t pre[kDisChunk + 1];
+  __shared__ int64_t boff[kDisChunk];
+  __shared__ uint64_t scan_tmp[kDisWaves];
+  for (int i = threadIdx.x; i < NQ * 16; i += kDisB) ent[i] = ent_g[i];
+  for (int i = threadIdx.x; i < NQ * 4; i += kDisB) fac[i] = fac_g[i];
+  for (int i = threadIdx.x; i < kDisWaves * kDisTile; i += kDisB) (&acc[0][0])[i] = 0.0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t a0 = (int64_t)blockIdx.x * kDisTile;
+  const int tile = (int)((n_cand - a0) < kDisTile ? (n_cand - a0) : kDisTile);
+  const int64_t B = 1ll << *st.m;
+  const int64_t b_lo = B * blockIdx.y / gridDim.y, b_hi = B * (blockIdx.y + 1) / gridDim.y;
+  const char* ent_base = reinterpret_cast<const char*>(ent);
+
+  for (int64_t cb = b_lo; cb < b_hi; cb += kDisChunk) {
+    const int nb = (int)((b_hi - cb) < kDisChunk ? (b_hi - cb) : kDisChunk);
+    __syncthreads();   // tables ready / previous chunk done with pre, boff
+    uint64_t total;
+    const uint64_t n_b = threadIdx.x < nb ? (uint64_t)st.cnt[cb + threadIdx.x] : 0ull;
+    const uint64_t ex = block_exclusive_scan_n<kDisWaves>(n_b, scan_tmp, total);
+    if (threadIdx.x < nb) {
+      pre[threadIdx.x] = (int64_t)ex;
+      boff[threadIdx.x] = st.off[cb + threadIdx.x];
+    }
+    if (threadIdx.x == 0) pre[nb] = (int64_t)total;
+    __syncthreads();
+    const int64_t n_chunk = (int64_t)total;
+    for (int64_t j0 = 0; j0 < n_chunk; j0 += (int64_t)kDisB * kDisR) {
+      // --- stage kDisR terms per lane: 2-bit qubit codes, c * PK and ZK ---
+      uint32_t code[kDisR][NS];
+      double cpk[kDisR];
+      uint32_t zk[kDisR];
+#pragma unroll
+      for (int r = 0; r < kDisR; ++r) {
+        const int64_t j = j0 + (int64_t)r * kDisB + threadIdx.x;
+        uint64_t kx[W], kz[W];
+        double c = 0.0;
+        if (j < n_chunk) {
+          int lo = 0, hi = nb - 1;   // last bucket with pre <= j (pre[0] = 0)
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= j) lo = mid; else hi = mid - 1;
+          }
+          const int64_t i = boff[lo] + (j - pre[lo]);
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            kx[w] = st.x[w * st.cap + i];
+            kz[w] = st.z[w * st.cap + i];
+          }
+          c = st.c[i];
+        } else {
+#pragma unroll
+          for (int w = 0; w < W; ++w) kx[w] = kz[w] = 0ull;
+        }
+        double pk = 1.0;
+        uint32_t nz = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          for (uint64_t t = kx[w] | kz[w]; t; t &= t - 1) {
+            const int bq = __builtin_ctzll(t);
+            const int k = (int)((kx[w] >> bq) & 1) | (int)(((kz[w] >> bq) & 1) << 1);
+            const double f = fac[(64 * w + bq) * 4 + k];
+            if (f == 0.0) ++nz; else pk *= f;
+          }
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const uint32_t xs = (uint32_t)(kx[w] >> (16 * s4)), zs = (uint32_t)(kz[w] >> (16 * s4));
+            code[r][4 * w + s4] = spread16(xs) | (spread16(zs) << 1);
+          }
+        }
+        cpk[r] = c * pk;
+        zk[r] = nz;
+      }
+      // --- candidates of the tile (uniform loop) ---
+      for (int t = 0; t < tile; ++t) {
+        const int64_t a = a0 + t;
+        double prod[kDisR];
+        uint32_t msum[kDisR];
+#pragma unroll
+        for (int r = 0; r < kDisR; ++r) {
+          prod[r] = 1.0;
+          msum[r] = 0;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const uint64_t ax = cx[w * ld_cand + a], az = cz[w * ld_cand + a];
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const uint32_t xs = (uint32_t)(ax >> (16 * s4)) & 0xffffu;
+            const uint32_t zs = (uint32_t)(az >> (16 * s4)) & 0xffffu;
+            for (uint32_t m = xs | zs; m; m &= m - 1) {
+              const uint32_t qb = (uint32_t)__builtin_ctz(m);
+              const uint32_t q = 64 * w + 16 * s4 + qb;
+              const uint32_t p = ((xs >> qb) & 1u) | (((zs >> qb) & 1u) << 1);
+              const char* row = ent_base + (size_t)((q * 4 + p) * 4) * sizeof(DisEnt);
+#pragma unroll
+              for (int r = 0; r < kDisR; ++r) {
+                const uint32_t k = __builtin_amdgcn_ubfe(code[r][4 * w + s4], 2 * qb, 2);
+                const DisEnt e = *reinterpret_cast<const DisEnt*>(row + k * sizeof(DisEnt));
+                prod[r] *= e.ratio;
+                msum[r] += e.meta;
+              }
+            }
+          }
+        }
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < kDisR; ++r) {
+          const uint32_t e = (msum[r] >> 12) & 3u;
+          const bool live = (msum[r] & 0xfffu) == zk[r] && (e & 1u);
+          const double u = cpk[r] * prod[r];
+          v += live ? (e == 1u ? u : -u) : 0.0;
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+        if (lane == 0) acc[wid][t] += v;
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < tile; t += kDisB) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kDisWaves; ++w) s += acc[w][t];
+    partial[(int64_t)blockIdx.y * n_cand + a0 + t] = s;
+  }
+}
+
+int64_t dis_tables_doubles(int W) { return 64 * W * 16 * 2 + 64 * W * 4; }
+
+int64_t dis_tile() { return kDisTile; }
 
 __global__ void k_dis_reduce(const double* partial, int rows, int64_t n_cand, double* g) {
   for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n_cand;
@@ -175,17 +283,22 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
 
 void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx,
                 const uint64_t* cz, int64_t n_cand, int64_t ld_cand, int mode, int tile,
-                int grid, double* partial, int grid_terms, double* g, hipStream_t s) {
+                int grid, double* partial, int grid_terms, double* g, hipStream_t s,
+                const double* theta, const double* phi, int nq, double* tables) {
   (void)tile;
   if (n_cand <= 0) return;
   if (mode == 0) {
-    const int64_t tiles = (n_cand + kBlock - 1) / kBlock;
+    DisEnt* ent = reinterpret_cast<DisEnt*>(tables);
+    double* fac = tables + dis_tables_doubles(W) - 64 * W * 4;
+    hipLaunchKernelGGL(k_dis_tables, dim3((64 * W + 255) / 256), dim3(256), 0, s, W, nq, theta, phi,
+                       ent, fac);
+    const int64_t tiles = (n_cand + kDisTile - 1) / kDisTile;
     dim3 gr((unsigned)tiles, (unsigned)grid_terms);
     switch (W) {
-      case 1: hipLaunchKernelGGL(k_dis_batched<1>, gr, dim3(kBlock), 0, s, st, lut, cx, cz, n_cand, ld_cand, partial); break;
-      case 2: hipLaunchKernelGGL(k_dis_batched<2>, gr, dim3(kBlock), 0, s, st, lut, cx, cz, n_cand, ld_cand, partial); break;
-      case 3: hipLaunchKernelGGL(k_dis_batched<3>, gr, dim3(kBlock), 0, s, st, lut, cx, cz, n_cand, ld_cand, partial); break;
-      default: hipLaunchKernelGGL(k_dis_batched<4>, gr, dim3(kBlock), 0, s, st, lut, cx, cz, n_cand, ld_cand, partial); break;
+      case 1: hipLaunchKernelGGL(k_dis_batched<1>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, partial); break;
+      case 2: hipLaunchKernelGGL(k_dis_batched<2>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, partial); break;
+      case 3: hipLaunchKernelGGL(k_dis_batched<3>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, partial); break;
+      default: hipLaunchKernelGGL(k_dis_batched<4>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, partial); break;
     }
     int64_t blocks = (n_cand + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_dis_reduce, dim3((unsigned)blocks), dim3(kBlock), 0, s, partial, grid_terms, n_cand, g);
