@@ -79,11 +79,46 @@ __device__ __forceinline__ uint32_t spread16(uint32_t v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wave with DPP moves (no LDS traffic); the total
+// lands in lane 63.  Fixed pairing order, so the result is reproducible.
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
+  const uint64_t u = __double_as_longlong(v);
+  int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+  switch (ctrl_sel) {   // constant after inlining
+    case 0: lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+            hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false); break;
+    case 1: lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false); break;
+    case 2: lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);  // row_half_mirror
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false); break;
+    case 3: lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false);  // row_mirror
+            hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false); break;
+    case 4: lo = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xA, 0xF, false);  // row_bcast:15 -> rows 1, 3
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xA, 0xF, false); break;
+    default: lo = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xC, 0xF, false); // row_bcast:31 -> rows 2, 3
+             hi = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xC, 0xF, false); break;
+  }
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double wave_sum_to_lane63(double v) {
+  v += dpp_f64(v, 0);   // pairs within quads
+  v += dpp_f64(v, 1);   // quads: every lane holds its quad's sum
+  v += dpp_f64(v, 2);   // half rows
+  v += dpp_f64(v, 3);   // rows of 16
+  v += dpp_f64(v, 4);   // rows 1 and 3 add rows 0 and 2 (other rows add +0)
+  v += dpp_f64(v, 5);   // rows 2 and 3 add rows 0..1
+  return v;
+}
+
 template <int W>
-__global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt* ent_g,
-                                                       const double* fac_g, const uint64_t* cx,
-                                                       const uint64_t* cz, int64_t n_cand,
-                                                       int64_t ld_cand, double* partial) {
+__global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt* __restrict__ ent_g,
+                                                       const double* __restrict__ fac_g,
+                                                       const uint64_t* __restrict__ cx,
+                                                       const uint64_t* __restrict__ cz,
+                                                       int64_t n_cand, int64_t ld_cand,
+                                                       double* __restrict__ partial) {
+  constexpr int R = kDisR;
   constexpr int NQ = 64 * W;
   constexpr int NS = 4 * W;   // 16-qubit slots
   __shared__ DisEnt ent[NQ * 16];
@@ -115,13 +150,13 @@ __global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt
     if (threadIdx.x == 0) pre[nb] = (int64_t)total;
     __syncthreads();
     const int64_t n_chunk = (int64_t)total;
-    for (int64_t j0 = 0; j0 < n_chunk; j0 += (int64_t)kDisB * kDisR) {
-      // --- stage kDisR terms per lane: 2-bit qubit codes, c * PK and ZK ---
-      uint32_t code[kDisR][NS];
-      double cpk[kDisR];
-      uint32_t zk[kDisR];
+    for (int64_t j0 = 0; j0 < n_chunk; j0 += (int64_t)kDisB * R) {
+      // --- stage R terms per lane: 2-bit qubit codes, c * PK and ZK ---
+      uint32_t code[R][NS];
+      double cpk[R];
+      uint32_t zk[R];
 #pragma unroll
-      for (int r = 0; r < kDisR; ++r) {
+      for (int r = 0; r < R; ++r) {
         const int64_t j = j0 + (int64_t)r * kDisB + threadIdx.x;
         uint64_t kx[W], kz[W];
         double c = 0.0;
@@ -159,15 +194,15 @@ __global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt
           }
         }
         cpk[r] = c * pk;
-        zk[r] = nz;
+        zk[r] = nz | (1u << 12);   // meta sum of a live pair with e = 1; e = 3 adds 2 << 12
       }
       // --- candidates of the tile (uniform loop) ---
       for (int t = 0; t < tile; ++t) {
         const int64_t a = a0 + t;
-        double prod[kDisR];
-        uint32_t msum[kDisR];
+        double prod[R];
+        uint32_t msum[R];
 #pragma unroll
-        for (int r = 0; r < kDisR; ++r) {
+        for (int r = 0; r < R; ++r) {
           prod[r] = 1.0;
           msum[r] = 0;
         }
@@ -184,7 +219,7 @@ __global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt
               const uint32_t p = ((xs >> qb) & 1u) | (((zs >> qb) & 1u) << 1);
               const char* row = ent_base + (size_t)((q * 4 + p) * 4) * sizeof(DisEnt);
 #pragma unroll
-              for (int r = 0; r < kDisR; ++r) {
+              for (int r = 0; r < R; ++r) {
                 const uint32_t k = __builtin_amdgcn_ubfe(code[r][4 * w + s4], 2 * qb, 2);
                 const DisEnt e = *reinterpret_cast<const DisEnt*>(row + k * sizeof(DisEnt));
                 prod[r] *= e.ratio;
@@ -195,15 +230,14 @@ __global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt
         }
         double v = 0.0;
 #pragma unroll
-        for (int r = 0; r < kDisR; ++r) {
-          const uint32_t e = (msum[r] >> 12) & 3u;
-          const bool live = (msum[r] & 0xfffu) == zk[r] && (e & 1u);
-          const double u = cpk[r] * prod[r];
-          v += live ? (e == 1u ? u : -u) : 0.0;
+        for (int r = 0; r < R; ++r) {
+          // live: every zero factor of K in the support, and e odd (+ for 1, - for 3)
+          const uint32_t m = msum[r] & 0x3fffu;
+          const double f = m == zk[r] ? 1.0 : (m == zk[r] + (2u << 12) ? -1.0 : 0.0);
+          v = fma(f, cpk[r] * prod[r], v);   // exact product by +-1 or 0
         }
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-        if (lane == 0) acc[wid][t] += v;
+        v = wave_sum_to_lane63(v);
+        if (lane == 63) acc[wid][t] += v;
       }
     }
   }

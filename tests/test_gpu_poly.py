@@ -46,3 +46,17 @@ def test_energy_polynomial_matches_oracle(ctx, nq, cfg, n):
     h.close()
     for w in work:
         w.close()
+
+
+def test_energy_polynomial_rejects_bad_arguments(ctx):
+    x, z, c = I.hamiltonian_dense(12, 9)
+    th, ph = I.qmf_angles(12, np.random.default_rng(1))
+    tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
+    h = iqcc.Store(ctx, 12, 2 * len(c)).load_numpy(x, z, c)
+    w = iqcc.Store(ctx, 12, 8 * len(c))
+    cx, cz = Q.dis_generators(Q.flip_sets(x, 2))
+    with pytest.raises(iqcc.IqccError):        # the same work store twice
+        iqcc.iqcc_energy_trig_poly(ctx.handle, h.handle, cx[:2], cz[:2], tht, pht, [w, w])
+    with pytest.raises(iqcc.IqccError):        # more than 8 generators
+        iqcc.iqcc_energy_trig_poly(ctx.handle, h.handle, cx[:9], cz[:9], tht, pht, [w] * 9)
+    h.close(); w.close()

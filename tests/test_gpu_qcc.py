@@ -97,3 +97,17 @@ def test_outer_loop_converges(ctx):
     last = hist[-1]
     assert len(hist) == 6 or abs(last["energy"][-1] - last["energy"][0]) < 1e-6 or len(last["sel_tau"]) == 0
     h.close(); spare.close()
+
+
+def test_iteration_rejects_bad_arguments(ctx):
+    x, z, c = I.hamiltonian_dense(12, 9)
+    th, ph = I.qmf_angles(12, np.random.default_rng(1))
+    tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
+    h = iqcc.Store(ctx, 12, 4 * len(c)).load_numpy(x, z, c)
+    with pytest.raises(iqcc.IqccError):        # h and spare are the same store
+        iqcc.iqcc_qcc_iteration(ctx.handle, h, h, tht, pht, 4, 2, 1e-8)
+    spare = iqcc.Store(ctx, 12, 4 * len(c))
+    with pytest.raises(iqcc.IqccError):        # w_max < 1
+        iqcc.iqcc_qcc_iteration(ctx.handle, h, spare, tht, pht, 0, 2, 1e-8)
+    assert iqcc.iqcc_flip_sets(ctx.handle, h.handle, 64).shape[1] == 1
+    h.close(); spare.close()

@@ -60,3 +60,13 @@ def test_truncated_store_dresses_like_oracle(ctx):
     tx, tz, tc = O.truncate_top(x, z, c, M)
     assert_same_terms(d.to_numpy(), O.dress(nq, tx, tz, tc, px[0], pz[0], 0.13, 1e-8), "dress after truncation")
     a.close(); b.close(); d.close()
+
+
+def test_truncate_top_rejects_bad_arguments(ctx):
+    x, z, c = I.hamiltonian_dense(12, 9)
+    a = iqcc.Store(ctx, 12, 2 * len(c)).load_numpy(x, z, c)
+    small = iqcc.Store(ctx, 12, 8)
+    for args in ((a.handle, 10, a.handle), (a.handle, -1, small.handle), (a.handle, 10, small.handle)):
+        with pytest.raises(iqcc.IqccError):
+            iqcc.iqcc_truncate_top(ctx.handle, *args)
+    a.close(); small.close()

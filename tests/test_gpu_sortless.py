@@ -66,3 +66,18 @@ def test_sortless_chain_and_degenerate_cases(ctx):
     _check_exact(_run(ctx, nq, x, z, c, cx[0], cz[0], 0.3, 1e9), O.dress(nq, x, z, c, cx[0], cz[0], 0.3, 1e9), "all dropped")
     _check_exact(_run(ctx, nq, x[:1], z[:1], c[:1], cx[0], cz[0], 0.3, 0.0),
                  O.dress(nq, x[:1], z[:1], c[:1], cx[0], cz[0], 0.3, 0.0), "one term")
+
+
+def test_sortless_rejects_bad_arguments(ctx):
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    x, z, c = O.canonical(x, z, c)
+    dx, dz = iqcc.to_device_words(x), iqcc.to_device_words(z)
+    dc = torch.from_numpy(np.ascontiguousarray(c)).cuda()
+    wide = np.array([(1 << 21) - 1], np.uint64)          # flips 21 key bits
+    with pytest.raises(iqcc.IqccError):
+        iqcc.iqcc_sortless_dress(ctx.handle, nq, dx, dz, dc, wide, np.zeros(1, np.uint64), 0.1, 0.0)
+    with pytest.raises(iqcc.IqccError) as ei:            # no room for the result
+        iqcc.iqcc_sortless_dress(ctx.handle, nq, dx, dz, dc, np.array([3], np.uint64),
+                                 np.array([1], np.uint64), 0.1, 0.0, cap=10)
+    assert ei.value.code == iqcc.IQCC_ERR_CAPACITY
