@@ -172,7 +172,7 @@ __device__ __forceinline__ uint32_t next_group_entry(uint32_t& t, uint32_t xh, u
 }
 
 template <int W>
-__device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* x,
+__device__ __forceinline__ double expect_lut_sparse(const double* lut, const uint64_t* x,
                                              const uint64_t* z) {
   double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0;
 #pragma unroll
@@ -192,6 +192,40 @@ __device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* 
     }
   }
   return (p0 * p1) * (p2 * p3);
+}
+
+template <int W>
+__device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* x,
+                                             const uint64_t* z) {
+  if constexpr (W > 2) {
+    return expect_lut_sparse<W>(lut, x, z);   // fewer registers for wide keys
+  } else {
+    // every group of every half word, identity groups included (table entry 0
+    // is 1.0): no per-group branch or select; each iteration issues four
+    // independent lookups per half word, so the product takes three LDS round
+    // trips
+    double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0;
+    uint32_t xh[2 * W], zh[2 * W];
+#pragma unroll
+    for (int h = 0; h < 2 * W; ++h) {
+      xh[h] = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
+      zh[h] = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
+    }
+#pragma unroll 1
+    for (int g = 0; g < 12; g += 4) {
+      const uint32_t s0 = 3 * g;
+#pragma unroll
+      for (int h = 0; h < 2 * W; ++h) {
+        const double* lg = lut + (h * kGroupsPerHalf + g) * kLutEntries;
+        p0 *= lg[__builtin_amdgcn_ubfe(xh[h], s0, 3) | (__builtin_amdgcn_ubfe(zh[h], s0, 3) << 3)];
+        p1 *= lg[kLutEntries + (__builtin_amdgcn_ubfe(xh[h], s0 + 3, 3) | (__builtin_amdgcn_ubfe(zh[h], s0 + 3, 3) << 3))];
+        p2 *= lg[2 * kLutEntries + (__builtin_amdgcn_ubfe(xh[h], s0 + 6, 3) | (__builtin_amdgcn_ubfe(zh[h], s0 + 6, 3) << 3))];
+        if (g + 3 < kGroupsPerHalf)
+          p3 *= lg[3 * kLutEntries + (__builtin_amdgcn_ubfe(xh[h], s0 + 9, 3) | (__builtin_amdgcn_ubfe(zh[h], s0 + 9, 3) << 3))];
+      }
+    }
+    return (p0 * p1) * (p2 * p3);
+  }
 }
 
 // Anticommutation of K with P: parity of |xK & zP| + |zK & xP|.

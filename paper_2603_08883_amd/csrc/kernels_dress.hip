@@ -206,43 +206,87 @@ __device__ __forceinline__ uint32_t wave_positions(unsigned long long* ctr, int 
   return nb;
 }
 
-// <K> and <K^P> of the product state: A over the non-identity groups of K
-// that P does not touch (four independent lookups per iteration), B and B'
-// over P's groups for K and K^P.
+// <K> and <K^P> of the product state: A over the groups of K that P does not
+// touch, B and B' over P's groups for K and K^P (two of P's groups per LDS
+// round trip).
 template <int W>
 __device__ __forceinline__ void expect_split(const double* lut, const Entangler& P,
                                              const uint64_t* x, const uint64_t* z, double& ek,
                                              double& ekp) {
-  double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0, b = 1.0, b2 = 1.0;
+  double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0, b = 1.0, b2 = 1.0, c1 = 1.0, c2 = 1.0;
+  if constexpr (W > 2) {
+    // A over the non-identity groups of K outside P's groups (fewer registers
+    // for wide keys)
+#pragma unroll
+    for (int h = 0; h < 2 * W; ++h) {
+      const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
+      const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
+      const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
+      uint32_t t = group_starts((xh | zh) & ~P.gbits[h]);
+      while (t) {
+        uint32_t e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = next_group_entry(t, xh, zh);
+        p0 *= lh[e[0]];
+        p1 *= lh[e[1]];
+        p2 *= lh[e[2]];
+        p3 *= lh[e[3]];
+      }
+    }
+  } else {
+    // A: every group of every half word with P's groups masked to the identity
+    // (table entry 0 = 1.0); each iteration issues 4 independent lookups per
+    // half word, so the whole product takes three LDS round trips
+    uint32_t xa[2 * W], za[2 * W];
+#pragma unroll
+    for (int h = 0; h < 2 * W; ++h) {
+      xa[h] = (uint32_t)(x[h >> 1] >> (32 * (h & 1))) & ~P.gbits[h];
+      za[h] = (uint32_t)(z[h >> 1] >> (32 * (h & 1))) & ~P.gbits[h];
+    }
+#pragma unroll 1
+    for (int g = 0; g < 12; g += 4) {
+      const uint32_t s0 = 3 * g;
+#pragma unroll
+      for (int h = 0; h < 2 * W; ++h) {
+        const double* lg = lut + (h * kGroupsPerHalf + g) * kLutEntries;
+        p0 *= lg[__builtin_amdgcn_ubfe(xa[h], s0, 3) | (__builtin_amdgcn_ubfe(za[h], s0, 3) << 3)];
+        p1 *= lg[kLutEntries + (__builtin_amdgcn_ubfe(xa[h], s0 + 3, 3) | (__builtin_amdgcn_ubfe(za[h], s0 + 3, 3) << 3))];
+        p2 *= lg[2 * kLutEntries + (__builtin_amdgcn_ubfe(xa[h], s0 + 6, 3) | (__builtin_amdgcn_ubfe(za[h], s0 + 6, 3) << 3))];
+        if (g + 3 < kGroupsPerHalf)
+          p3 *= lg[3 * kLutEntries + (__builtin_amdgcn_ubfe(xa[h], s0 + 9, 3) | (__builtin_amdgcn_ubfe(za[h], s0 + 9, 3) << 3))];
+      }
+    }
+  }
 #pragma unroll
   for (int h = 0; h < 2 * W; ++h) {
     const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
     const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
     const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
-    uint32_t t = group_starts((xh | zh) & ~P.gbits[h]);
-    while (t) {
-      uint32_t e[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) e[k] = next_group_entry(t, xh, zh);
-      p0 *= lh[e[0]];
-      p1 *= lh[e[1]];
-      p2 *= lh[e[2]];
-      p3 *= lh[e[3]];
-    }
     const uint32_t pxh = (uint32_t)(P.px[h >> 1] >> (32 * (h & 1)));
     const uint32_t pzh = (uint32_t)(P.pz[h >> 1] >> (32 * (h & 1)));
-    for (int q = P.gstart[h]; q < P.gstart[h + 1]; ++q) {
-      const uint32_t g = P.glist[q];
-      const uint32_t sh = 3 * g;
-      const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
-      const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
-      b *= lh[g * kLutEntries + code];
-      b2 *= lh[g * kLutEntries + (code ^ pcode)];
+    const int q1 = P.gstart[h + 1];
+    for (int q = P.gstart[h]; q < q1; q += 2) {   // two of P's groups per round trip
+      {
+        const uint32_t g = P.glist[q];
+        const uint32_t sh = 3 * g;
+        const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
+        const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
+        b *= lh[g * kLutEntries + code];
+        b2 *= lh[g * kLutEntries + (code ^ pcode)];
+      }
+      if (q + 1 < q1) {
+        const uint32_t g = P.glist[q + 1];
+        const uint32_t sh = 3 * g;
+        const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
+        const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
+        c1 *= lh[g * kLutEntries + code];
+        c2 *= lh[g * kLutEntries + (code ^ pcode)];
+      }
     }
   }
   const double a = (p0 * p1) * (p2 * p3);
-  ek = a * b;
-  ekp = a * b2;
+  ek = a * (b * c1);
+  ekp = a * (b2 * c2);
 }
 
 // One pass over the pair's input terms, each wave on its own 64-term slices

@@ -64,6 +64,27 @@ void launch_finalize_sum(const double* partial, int n, const double* scale, doub
   hipLaunchKernelGGL(k_finalize_sum, dim3(1), dim3(kBlock), 0, s, partial, n, scale, base, out);
 }
 
+// <K> from every 3-qubit group of every half word, identity groups included
+// (their table entry 0 is 1.0): a fixed, branch-free sequence of independent
+// lookups whose addresses take two VALU operations each.
+template <int W>
+__device__ __forceinline__ double expect_dense(const double* lut, const uint64_t* x,
+                                               const uint64_t* z) {
+  double p[4] = {1.0, 1.0, 1.0, 1.0};
+#pragma unroll
+  for (int h = 0; h < 2 * W; ++h) {
+    const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
+    const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
+    const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
+#pragma unroll
+    for (int g = 0; g < kGroupsPerHalf; ++g) {
+      const uint32_t code = __builtin_amdgcn_ubfe(xh, 3 * g, 3) | (__builtin_amdgcn_ubfe(zh, 3 * g, 3) << 3);
+      p[g & 3] *= lh[g * kLutEntries + code];
+    }
+  }
+  return (p[0] * p[1]) * (p[2] * p[3]);
+}
+
 // ---------------------------------------------------------------------------
 // Energy of a store: workgroup g takes buckets g, g + grid, ...
 // ---------------------------------------------------------------------------
@@ -100,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(StoreDev st, const double* lu
         }
       }
 #pragma unroll
-      for (int r = 0; r < kEItems; ++r) acc += kc[r] * expect_lut<W>(lut, kx[r], kz[r]);
+      for (int r = 0; r < kEItems; ++r) acc += kc[r] * expect_dense<W>(lut, kx[r], kz[r]);
     }
   }
   const double s = block_sum(acc, red);
