@@ -1032,7 +1032,19 @@ int iqcc_truncate_top(iqcc_ctx* ctx, const iqcc_store* in, int64_t max_terms, iq
   int keep_all = n <= max_terms ? 1 : max_terms == 0 ? -1 : 0;
   DevBuf keys, kcount;
   if (keep_all == 0) {
-    launch_abs_select(W, in->d, ss, (unsigned*)dhist.p, grid, s);
+    launch_abs_select_first(W, in->d, ss, (unsigned*)dhist.p, grid, s);
+    LAUNCH_CHECK(ctx);
+    HIP_TRY(ctx, hipMemcpyAsync(&h, ss, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    // the terms that share the first digit: their |c| bits go to the reused
+    // partial-sum buffer, followed by the append counter
+    const int64_t ncand = h.at > 0 ? h.at : 1;
+    rc = ensure_partial(ctx, ncand + 1);
+    if (rc) return rc;
+    uint64_t* cand = (uint64_t*)ctx->partial;
+    unsigned long long* ccount = (unsigned long long*)(ctx->partial + ncand);
+    HIP_TRY(ctx, hipMemsetAsync(ccount, 0, sizeof(unsigned long long), s));
+    launch_abs_select_rest(W, in->d, ss, (unsigned*)dhist.p, grid, cand, ncand, ccount, s);
     LAUNCH_CHECK(ctx);
     HIP_TRY(ctx, hipMemcpyAsync(&h, ss, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));

@@ -343,12 +343,19 @@ struct SelState {
   int64_t passed;                // terms in bins passed over so far
   uint64_t T;                    // |c| bits of the M-th largest term
   int64_t ties;                  // terms with |c| bits == T
+  int64_t at;                    // terms in the digit picked last
   int key_mode;                  // 1: keep only ties with canonical key <= kthr
   int pad;
   uint64_t kthr[2 * kMaxWords];  // canonical key threshold among the ties
 };
-void launch_abs_select(int W, const StoreDev& st, SelState* ss, unsigned* hist, int grid,
-                       hipStream_t s);
+// First |c| digit over every term (sets ss->at, the terms that share it);
+// then the remaining digits, copying the |c| bits of those terms to cand
+// (capacity >= ss->at) on the second pass and reading only them afterwards.
+void launch_abs_select_first(int W, const StoreDev& st, SelState* ss, unsigned* hist, int grid,
+                             hipStream_t s);
+void launch_abs_select_rest(int W, const StoreDev& st, SelState* ss, unsigned* hist, int grid,
+                            uint64_t* cand, int64_t cand_cap, unsigned long long* cand_count,
+                            hipStream_t s);
 void launch_collect_ties(int W, const StoreDev& st, const SelState* ss, uint64_t* keys, int64_t cap,
                          unsigned long long* count, int grid, hipStream_t s);
 void launch_key_select(int W, const uint64_t* keys, int64_t n, SelState* ss, unsigned* hist,

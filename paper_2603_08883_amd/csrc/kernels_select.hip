@@ -8,7 +8,9 @@
 // significant first) each build a histogram of the digit over the terms whose
 // higher digits equal the prefix chosen so far, and a one-thread kernel picks
 // the digit where the running count from the top reaches the number still
-// needed.  That fixes the threshold T (the M-th largest |c|), the number of
+// needed.  After the first digit only the terms that share it can matter, so
+// the second pass copies their |c| bits aside and the later passes read those
+// alone.  That fixes the threshold T (the M-th largest |c|), the number of
 // terms above it and the number to take among the terms equal to T.  When not
 // all ties are taken, the tie keys are collected and the same selection runs
 // on their canonical key words (x words, then z words, most significant
@@ -41,6 +43,79 @@ __global__ __launch_bounds__(kBlock) void k_abs_hist(StoreDev st, const SelState
       const uint64_t u = abs_bits(st.c[off + i]);
       if (first || (u >> (shift + width)) == prefix) atomicAdd(&h[(u >> shift) & dmask], 1u);
     }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSelBins; i += kBlock)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Second digit pass: the histogram of k_abs_hist, and the |c| bits of every
+// term that matches the prefix appended to cand.  Matches are staged in LDS
+// and flushed with one global atomic per ~kCandStage values, so the append
+// counter is not a point of contention.
+constexpr int kCandStage = 2048;
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_abs_hist_collect(StoreDev st, const SelState* ss,
+                                                             int shift, int width, unsigned* hist,
+                                                             uint64_t* cand, int64_t cap,
+                                                             unsigned long long* count) {
+  __shared__ unsigned h[kSelBins];
+  __shared__ uint64_t stage[kCandStage];
+  __shared__ uint64_t scan_tmp[kWaves];
+  __shared__ unsigned long long gbase;
+  for (int i = threadIdx.x; i < kSelBins; i += kBlock) h[i] = 0;
+  __syncthreads();
+  const uint64_t prefix = ss->prefix;
+  const int64_t B = 1ll << *st.m;
+  const uint64_t dmask = (1ull << width) - 1;
+  int nst = 0;   // staged values (block-uniform)
+  auto flush = [&]() {
+    if (threadIdx.x == 0) gbase = atomicAdd(count, (unsigned long long)nst);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nst; k += kBlock)
+      if ((int64_t)(gbase + k) < cap) cand[gbase + k] = stage[k];
+    __syncthreads();
+    nst = 0;
+  };
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = st.cnt[b], off = st.off[b];
+    for (int64_t i0 = 0; i0 < n; i0 += kBlock) {   // block-uniform
+      const int64_t i = i0 + threadIdx.x;
+      uint64_t u = 0;
+      bool match = false;
+      if (i < n) {
+        u = abs_bits(st.c[off + i]);
+        match = (u >> (shift + width)) == prefix;
+      }
+      if (match) atomicAdd(&h[(u >> shift) & dmask], 1u);
+      uint64_t tot;
+      const uint64_t pos = block_exclusive_scan(match ? 1ull : 0ull, scan_tmp, tot);
+      if (nst + (int)tot > kCandStage) flush();
+      if (match) stage[nst + (int)pos] = u;
+      nst += (int)tot;
+    }
+  }
+  __syncthreads();
+  if (nst) flush();
+  for (int i = threadIdx.x; i < kSelBins; i += kBlock)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Later digit passes over the collected |c| bits only.
+__global__ __launch_bounds__(kBlock) void k_cand_hist(const uint64_t* cand, int64_t cap,
+                                                      const unsigned long long* count,
+                                                      const SelState* ss, int shift, int width,
+                                                      unsigned* hist) {
+  __shared__ unsigned h[kSelBins];
+  for (int i = threadIdx.x; i < kSelBins; i += kBlock) h[i] = 0;
+  __syncthreads();
+  const uint64_t prefix = ss->prefix;
+  const uint64_t dmask = (1ull << width) - 1;
+  const int64_t n = (int64_t)*count < cap ? (int64_t)*count : cap;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const uint64_t u = cand[i];
+    if ((u >> (shift + width)) == prefix) atomicAdd(&h[(u >> shift) & dmask], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kSelBins; i += kBlock)
@@ -87,6 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_pick_digit(SelState* ss, unsigned* h
     const int pick = descending ? nb - 1 - pick_r : pick_r;
     ss->need = need - before;
     ss->passed += before;
+    ss->at = at;
     ss->prefix = (ss->prefix << width) | (uint64_t)pick;
     if (last) {
       if (key_word < 0) {
@@ -212,17 +288,37 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(StoreDev in, StoreDev
 static const int kDigitWidth[6] = {11, 11, 11, 11, 11, 9};
 static const int kDigitShift[6] = {53, 42, 31, 20, 9, 0};
 
-void launch_abs_select(int W, const StoreDev& st, SelState* ss, unsigned* hist, int grid,
-                       hipStream_t s) {
-  for (int p = 0; p < 6; ++p) {
-    const int sh = kDigitShift[p], wd = kDigitWidth[p], first = p == 0;
+void launch_abs_select_first(int W, const StoreDev& st, SelState* ss, unsigned* hist, int grid,
+                             hipStream_t s) {
+  const int sh = kDigitShift[0], wd = kDigitWidth[0];
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_abs_hist<1>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, 1, hist); break;
+    case 2: hipLaunchKernelGGL(k_abs_hist<2>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, 1, hist); break;
+    case 3: hipLaunchKernelGGL(k_abs_hist<3>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, 1, hist); break;
+    default: hipLaunchKernelGGL(k_abs_hist<4>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, 1, hist); break;
+  }
+  hipLaunchKernelGGL(k_pick_digit, dim3(1), dim3(kBlock), 0, s, ss, hist, wd, 1, 0, -1);
+}
+
+void launch_abs_select_rest(int W, const StoreDev& st, SelState* ss, unsigned* hist, int grid,
+                            uint64_t* cand, int64_t cand_cap, unsigned long long* cand_count,
+                            hipStream_t s) {
+  {
+    const int sh = kDigitShift[1], wd = kDigitWidth[1];
     switch (W) {
-      case 1: hipLaunchKernelGGL(k_abs_hist<1>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, first, hist); break;
-      case 2: hipLaunchKernelGGL(k_abs_hist<2>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, first, hist); break;
-      case 3: hipLaunchKernelGGL(k_abs_hist<3>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, first, hist); break;
-      default: hipLaunchKernelGGL(k_abs_hist<4>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, first, hist); break;
+      case 1: hipLaunchKernelGGL(k_abs_hist_collect<1>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, hist, cand, cand_cap, cand_count); break;
+      case 2: hipLaunchKernelGGL(k_abs_hist_collect<2>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, hist, cand, cand_cap, cand_count); break;
+      case 3: hipLaunchKernelGGL(k_abs_hist_collect<3>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, hist, cand, cand_cap, cand_count); break;
+      default: hipLaunchKernelGGL(k_abs_hist_collect<4>, dim3(grid), dim3(kBlock), 0, s, st, ss, sh, wd, hist, cand, cand_cap, cand_count); break;
     }
-    hipLaunchKernelGGL(k_pick_digit, dim3(1), dim3(kBlock), 0, s, ss, hist, wd, 1, p == 5, -1);
+    hipLaunchKernelGGL(k_pick_digit, dim3(1), dim3(kBlock), 0, s, ss, hist, wd, 1, 0, -1);
+  }
+  int64_t g = (cand_cap + kBlock - 1) / kBlock;
+  const int cgrid = (int)(g < 1 ? 1 : g > grid ? grid : g);
+  for (int p = 2; p < 6; ++p) {
+    hipLaunchKernelGGL(k_cand_hist, dim3(cgrid), dim3(kBlock), 0, s, cand, cand_cap, cand_count, ss,
+                       kDigitShift[p], kDigitWidth[p], hist);
+    hipLaunchKernelGGL(k_pick_digit, dim3(1), dim3(kBlock), 0, s, ss, hist, kDigitWidth[p], 1, p == 5, -1);
   }
 }
 
