@@ -140,28 +140,35 @@ void launch_energy(int W, const StoreDev& st, int grid, const double* lut, doubl
 
 // ---------------------------------------------------------------------------
 // Backward w.r.t. the Bloch angles.
-// For every term and every non-identity qubit q of it, the product of all
-// other factors ("others") is formed from prefix and suffix products over the
-// 3-qubit groups (never by division) and added into S[q][sigma_q] (LDS, FP64
-// atomics).  dE/dtheta_q = sum_sigma S[q][sigma] db_sigma/dtheta, likewise phi.
+// dE/dtheta_q = sum_sigma S[q][sigma] db_sigma/dtheta (likewise phi), where
+// S[q][sigma] adds, over the terms with sigma on qubit q, c times the product
+// of the term's other factors.  Each term forms PK, the product of its
+// non-zero qubit factors, and ZK, the number of zero ones; the other factors
+// of qubit q then multiply to PK / b_q when b_q != 0 and ZK = 0, to PK when
+// b_q = 0 and ZK = 1, and to 0 otherwise (exact zeros never divide).  The
+// division is a multiplication by a tabulated 1 / b_q.  Contributions go to
+// S in LDS with FP64 atomics; per-workgroup S are reduced in a fixed order.
 // acc layout per workgroup: [3 * nq] with sigma order X, Z, Y.
 // ---------------------------------------------------------------------------
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_energy_bwd(StoreDev st, int nq, const double* theta,
                                                        const double* phi, const double* lut_g,
                                                        double* acc_g) {
-  constexpr int G = W * kGroupsPerWord;
-  __shared__ double lut[G * kLutEntries];
+  (void)lut_g;
   __shared__ double fac[kMaxWords * 64 * 4];   // per qubit: factor of I, X, Z, Y
+  __shared__ double inv[kMaxWords * 64 * 4];   // 1 / factor (0 where the factor is 0)
   __shared__ double acc[kMaxWords * 64 * 3];
-  for (int i = threadIdx.x; i < G * kLutEntries; i += kBlock) lut[i] = lut_g[i];
   for (int q = threadIdx.x; q < 64 * W; q += kBlock) {
     double st_ = 0, ct = 1, sp = 0, cp = 1;
     if (q < nq) {
       sincos(theta[q], &st_, &ct);
       sincos(phi[q], &sp, &cp);
     }
-    for (int op = 0; op < 4; ++op) fac[4 * q + op] = bloch_factor(op, st_, ct, sp, cp);
+    for (int op = 0; op < 4; ++op) {
+      const double f = bloch_factor(op, st_, ct, sp, cp);
+      fac[4 * q + op] = f;
+      inv[4 * q + op] = f != 0.0 ? 1.0 / f : 0.0;
+    }
     for (int k = 0; k < 3; ++k) acc[3 * q + k] = 0.0;
   }
   __syncthreads();
@@ -176,44 +183,30 @@ __global__ __launch_bounds__(kBlock) void k_energy_bwd(StoreDev st, int nq, cons
         kz[w] = st.z[w * st.cap + off + i];
       }
       const double c = st.c[off + i];
-      double L[G];
+      double pk = 1.0;
+      int zk = 0;
 #pragma unroll
-      for (int gi = 0; gi < G; ++gi) {
-        const int h = gi / kGroupsPerHalf, sh = 3 * (gi % kGroupsPerHalf);
-        const uint32_t xh = (uint32_t)(kx[h >> 1] >> (32 * (h & 1)));
-        const uint32_t zh = (uint32_t)(kz[h >> 1] >> (32 * (h & 1)));
-        const uint32_t idx = ((xh >> sh) & 7u) | (((zh >> sh) & 7u) << 3);
-        L[gi] = idx ? lut[gi * kLutEntries + idx] : 1.0;
-      }
-      double suf[G + 1];
-      suf[G] = 1.0;
-#pragma unroll
-      for (int g = G - 1; g >= 0; --g) suf[g] = suf[g + 1] * L[g];
-      double pre = c;
-#pragma unroll
-      for (int gi = 0; gi < G; ++gi) {
-        const int h = gi / kGroupsPerHalf, sh = 3 * (gi % kGroupsPerHalf);
-        const uint32_t xh = (uint32_t)(kx[h >> 1] >> (32 * (h & 1)));
-        const uint32_t zh = (uint32_t)(kz[h >> 1] >> (32 * (h & 1)));
-        const uint32_t xb = (xh >> sh) & 7u, zb = (zh >> sh) & 7u;
-        if (xb | zb) {
-          const double others = pre * suf[gi + 1];
-          const int q0 = 32 * h + sh;
-          int op[3];
-          double f[3];
-#pragma unroll
-          for (int t = 0; t < 3; ++t) {
-            op[t] = (int)((xb >> t) & 1u) | (int)(((zb >> t) & 1u) << 1);
-            f[t] = (sh + t < 32) ? fac[4 * (q0 + t) + op[t]] : 1.0;
-          }
-#pragma unroll
-          for (int t = 0; t < 3; ++t) {
-            if (op[t] == 0 || sh + t >= 32) continue;
-            const double inner = (t == 0 ? 1.0 : f[0]) * (t == 1 ? 1.0 : f[1]) * (t == 2 ? 1.0 : f[2]);
-            atomicAdd(&acc[3 * (q0 + t) + (op[t] - 1)], others * inner);
-          }
+      for (int w = 0; w < W; ++w) {
+        for (uint64_t t = kx[w] | kz[w]; t; t &= t - 1) {
+          const int bq = __builtin_ctzll(t);
+          const int op = (int)((kx[w] >> bq) & 1) | (int)(((kz[w] >> bq) & 1) << 1);
+          const double f = fac[4 * (64 * w + bq) + op];
+          if (f == 0.0) ++zk; else pk *= f;
         }
-        pre *= L[gi];
+      }
+      if (zk > 1) continue;   // every qubit's other factors include a zero
+      const double cpk = c * pk;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        for (uint64_t t = kx[w] | kz[w]; t; t &= t - 1) {
+          const int bq = __builtin_ctzll(t);
+          const int op = (int)((kx[w] >> bq) & 1) | (int)(((kz[w] >> bq) & 1) << 1);
+          const int q4 = 4 * (64 * w + bq) + op;
+          const bool zero = fac[q4] == 0.0;
+          if (zero != (zk == 1)) continue;   // a zero elsewhere, or a zero here and not alone
+          const double others = zero ? cpk : cpk * inv[q4];
+          atomicAdd(&acc[3 * (64 * w + bq) + (op - 1)], others);
+        }
       }
     }
   }
