@@ -239,6 +239,30 @@ def test_energy_backward_matches_oracle(ctx):
         assert np.abs(dp.cpu().numpy() - 1.5 * rp).max() <= E_TOL
 
 
+@pytest.mark.parametrize("angles", ["z-eigen", "mixed"])
+def test_energy_backward_special_angles(ctx, angles):
+    """Angle gradients where qubit factors vanish exactly (theta = 0 zeroes the
+    X and Y factors), so terms with one zero factor and with several occur."""
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    rng = np.random.default_rng(7 + len(angles))
+    th, ph = I.qmf_angles(nq, rng)
+    k = rng.random(nq)
+    if angles == "z-eigen":
+        th = np.where(k < 0.5, 0.0, np.pi)
+    else:
+        th = np.where(k < 0.3, 0.0, np.where(k < 0.5, np.pi / 2, th))
+    tht, pht = torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()
+    s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    describe(0, "energy_backward special angles", nq=nq, angles=angles)
+    dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht)
+    rt, rp = O.qmf_grad_angles(nq, x, z, c, th, ph)
+    assert np.abs(dt.cpu().numpy() - rt).max() <= E_TOL
+    assert np.abs(dp.cpu().numpy() - rp).max() <= E_TOL
+    if angles == "mixed":   # at z-eigenstates every term keeps >= 2 vanishing factors here
+        assert np.abs(rt).max() > 1e-6
+
+
 @pytest.mark.parametrize("mode", [iqcc.IQCC_DIS_BATCHED, iqcc.IQCC_DIS_PLAIN])
 def test_dis_gradients_match_oracle(ctx, mode):
     nq = 40
