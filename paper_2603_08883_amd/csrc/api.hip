@@ -731,7 +731,7 @@ int iqcc_qmf_energy_backward(iqcc_ctx* ctx, const iqcc_store* h, const double* t
   if (rc) return rc;
   if (!h || !theta || !phi || !dtheta || !dphi) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
   hipStream_t s = as_stream(stream);
-  const int grid = (int)(ctx->n_cu * 6);
+  const int grid = (int)(ctx->n_cu * energy_bwd_blocks_per_cu(h->W));
   rc = ensure_partial(ctx, (int64_t)grid * 3 * h->nq);
   if (rc) return rc;
   launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);

@@ -142,85 +142,177 @@ void launch_energy(int W, const StoreDev& st, int grid, const double* lut, doubl
 // Backward w.r.t. the Bloch angles.
 // dE/dtheta_q = sum_sigma S[q][sigma] db_sigma/dtheta (likewise phi), where
 // S[q][sigma] adds, over the terms with sigma on qubit q, c times the product
-// of the term's other factors.  Each term forms PK, the product of its
-// non-zero qubit factors, and ZK, the number of zero ones; the other factors
-// of qubit q then multiply to PK / b_q when b_q != 0 and ZK = 0, to PK when
-// b_q = 0 and ZK = 1, and to 0 otherwise (exact zeros never divide).  The
-// division is a multiplication by a tabulated 1 / b_q.  Contributions go to
-// S in LDS with FP64 atomics; per-workgroup S are reduced in a fixed order.
-// acc layout per workgroup: [3 * nq] with sigma order X, Z, Y.
+// of the term's other factors.
+//
+// The product of a term is taken over its 3-qubit groups (the energy table),
+// so the derivative is first formed per group table entry:
+//   T[e] = sum over the terms whose group g has code e of c * prod_{g' != g} L_g',
+// then, once per workgroup, S[q][sigma] = sum over the codes e of q's group
+// with sigma at q's position of T[e] * (product of the other qubits' factors
+// of that code).  Per term: ZK, the number of zero group factors, and PK, the
+// product of the non-zero ones, formed as one division by the product of
+// their tabulated reciprocals.  The other groups of group g then multiply to
+// PK * (1 / L_g) when L_g != 0 and ZK = 0, to PK when L_g = 0 and ZK = 1, and
+// to 0 otherwise (exact zeros never divide).  Only the term's non-identity
+// groups are visited for T.  T lives in LDS and takes FP64 atomics (one per
+// non-identity group of a term); per-workgroup S are reduced in a fixed
+// order.  acc layout per workgroup: [3 * nq] with sigma order X, Z, Y.
 // ---------------------------------------------------------------------------
+constexpr int kBwdBlock = 512;
+
+// LDS tables of the backward hold one pad entry after every group's 64
+// entries, so that the same code of different groups falls in different
+// banks (entry e sits at e + e / 64).
+__host__ __device__ constexpr int bwd_padded(int n) { return n + n / kLutEntries; }
+
+size_t energy_bwd_lds_bytes(int W) {
+  return (size_t)2 * bwd_padded(W * kGroupsPerWord * kLutEntries) * 8 + (size_t)W * 64 * 4 * 8;
+}
+
+// Workgroups per CU that the LDS of one CU holds (160 KiB), at most four
+// 512-thread workgroups (32 waves).
+int energy_bwd_blocks_per_cu(int W) {
+  const int k = (int)((size_t)160 * 1024 / energy_bwd_lds_bytes(W));
+  return k < 1 ? 1 : k > 4 ? 4 : k;
+}
+
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_energy_bwd(StoreDev st, int nq, const double* theta,
-                                                       const double* phi, const double* lut_g,
-                                                       double* acc_g) {
-  (void)lut_g;
-  __shared__ double fac[kMaxWords * 64 * 4];   // per qubit: factor of I, X, Z, Y
-  __shared__ double inv[kMaxWords * 64 * 4];   // 1 / factor (0 where the factor is 0)
-  __shared__ double acc[kMaxWords * 64 * 3];
-  for (int q = threadIdx.x; q < 64 * W; q += kBlock) {
+__global__ __launch_bounds__(kBwdBlock) void k_energy_bwd(StoreDev st, int nq, const double* theta,
+                                                          const double* phi, const double* lut_g,
+                                                          double* acc_g) {
+  constexpr int NE = W * kGroupsPerWord * kLutEntries;
+  constexpr int NP = bwd_padded(NE);
+  constexpr int HP = bwd_padded(kGroupsPerHalf * kLutEntries);   // padded entries per half word
+  extern __shared__ __align__(16) unsigned char smem_bwd[];
+  double* rec = (double*)smem_bwd;     // 1 / L per table entry (0 where L is 0)
+  double* tg = rec + NP;               // T per table entry
+  double* fac = tg + NP;               // per qubit: factor of I, X, Z, Y
+  for (int i = threadIdx.x; i < NP; i += kBwdBlock) {
+    const int g = i / (kLutEntries + 1), k = i % (kLutEntries + 1);
+    const double l = k < kLutEntries ? lut_g[g * kLutEntries + k] : 1.0;
+    const double r = 1.0 / l;
+    // a factor whose reciprocal overflows (|L| below 2^-1024) counts as a zero
+    rec[i] = (l != 0.0 && r - r == 0.0) ? r : 0.0;
+    tg[i] = 0.0;
+  }
+  for (int q = threadIdx.x; q < 64 * W; q += kBwdBlock) {
     double st_ = 0, ct = 1, sp = 0, cp = 1;
     if (q < nq) {
       sincos(theta[q], &st_, &ct);
       sincos(phi[q], &sp, &cp);
     }
-    for (int op = 0; op < 4; ++op) {
-      const double f = bloch_factor(op, st_, ct, sp, cp);
-      fac[4 * q + op] = f;
-      inv[4 * q + op] = f != 0.0 ? 1.0 / f : 0.0;
-    }
-    for (int k = 0; k < 3; ++k) acc[3 * q + k] = 0.0;
+    for (int op = 0; op < 4; ++op) fac[4 * q + op] = bloch_factor(op, st_, ct, sp, cp);
   }
   __syncthreads();
   const int64_t B = 1ll << *st.m;
   for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
     const int64_t n = st.cnt[b], off = st.off[b];
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    for (int64_t i = threadIdx.x; i < n; i += kBwdBlock) {
       uint64_t kx[W], kz[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        kx[w] = st.x[w * st.cap + off + i];
-        kz[w] = st.z[w * st.cap + off + i];
+        kx[w] = __builtin_nontemporal_load(&st.x[w * st.cap + off + i]);
+        kz[w] = __builtin_nontemporal_load(&st.z[w * st.cap + off + i]);
       }
-      const double c = st.c[off + i];
-      double pk = 1.0;
+      const double c = __builtin_nontemporal_load(&st.c[off + i]);
+      // ZK, the number of zero group factors, and R, the product of the
+      // reciprocals of the others: every group of every half word in a fixed
+      // order (identity groups read 1.0), the same group in every lane at a time
+      double r[4] = {1.0, 1.0, 1.0, 1.0};
       int zk = 0;
-#pragma unroll
+#pragma unroll 1
       for (int w = 0; w < W; ++w) {
-        for (uint64_t t = kx[w] | kz[w]; t; t &= t - 1) {
-          const int bq = __builtin_ctzll(t);
-          const int op = (int)((kx[w] >> bq) & 1) | (int)(((kz[w] >> bq) & 1) << 1);
-          const double f = fac[4 * (64 * w + bq) + op];
-          if (f == 0.0) ++zk; else pk *= f;
+        uint64_t xw = kx[0], zw = kz[0];
+#pragma unroll
+        for (int u = 1; u < W; ++u) {
+          xw = u == w ? kx[u] : xw;
+          zw = u == w ? kz[u] : zw;
+        }
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const uint32_t xh = (uint32_t)(xw >> (32 * hh));
+          const uint32_t zh = (uint32_t)(zw >> (32 * hh));
+          const double* rh = rec + (2 * w + hh) * HP;
+#pragma unroll
+          for (int g = 0; g < kGroupsPerHalf; ++g) {
+            const uint32_t code = __builtin_amdgcn_ubfe(xh, 3 * g, 3) | (__builtin_amdgcn_ubfe(zh, 3 * g, 3) << 3);
+            const double v = rh[g * (kLutEntries + 1) + code];
+            zk += v == 0.0;
+            r[g & 3] *= v == 0.0 ? 1.0 : v;
+          }
         }
       }
-      if (zk > 1) continue;   // every qubit's other factors include a zero
-      const double cpk = c * pk;
+      if (zk > 1) continue;   // every group's other factors include a zero
+      const double cpk = c / ((r[0] * r[1]) * (r[2] * r[3]));   // c times PK
+      const bool one_zero = zk == 1;
+      // T over the term's non-identity groups only
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        for (uint64_t t = kx[w] | kz[w]; t; t &= t - 1) {
-          const int bq = __builtin_ctzll(t);
-          const int op = (int)((kx[w] >> bq) & 1) | (int)(((kz[w] >> bq) & 1) << 1);
-          const int q4 = 4 * (64 * w + bq) + op;
-          const bool zero = fac[q4] == 0.0;
-          if (zero != (zk == 1)) continue;   // a zero elsewhere, or a zero here and not alone
-          const double others = zero ? cpk : cpk * inv[q4];
-          atomicAdd(&acc[3 * (64 * w + bq) + (op - 1)], others);
+      for (int h = 0; h < 2 * W; ++h) {
+        const uint32_t xh = (uint32_t)(kx[h >> 1] >> (32 * (h & 1)));
+        const uint32_t zh = (uint32_t)(kz[h >> 1] >> (32 * (h & 1)));
+        const double* rh = rec + h * HP;
+        double* th = tg + h * HP;
+        uint32_t t = group_starts(xh | zh);
+        while (t) {
+          // entry 0 (code 0 of group 0) only comes from an exhausted t
+          const uint32_t e0 = next_group_entry(t, xh, zh);
+          const uint32_t e1 = next_group_entry(t, xh, zh);
+          const uint32_t p0 = e0 + (e0 >> 6), p1 = e1 + (e1 >> 6);
+          const double v0 = rh[p0], v1 = rh[p1];
+          const bool z0 = v0 == 0.0, z1 = v1 == 0.0;
+          const double o0 = z0 ? cpk : cpk * v0;
+          const double o1 = z1 ? cpk : cpk * v1;
+          if (e0 != 0 && z0 == one_zero) atomicAdd(&th[p0], o0);
+          if (e1 != 0 && z1 == one_zero) atomicAdd(&th[p1], o1);
         }
       }
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < 3 * nq; k += kBlock) acc_g[(int64_t)blockIdx.x * 3 * nq + k] = acc[k];
+  // S[q][sigma] from T: the codes of q's group with sigma at q's position,
+  // each weighted by the product of the group's other factors of that code
+  for (int k = threadIdx.x; k < 3 * nq; k += kBwdBlock) {
+    const int q = k / 3, op = k % 3 + 1;   // op: 1 = X, 2 = Z, 3 = Y
+    const int h = q >> 5, bit = q & 31;
+    const int g = (int)div3_small((uint32_t)bit), r = bit - 3 * g;
+    const double* th = tg + h * HP + g * (kLutEntries + 1);
+    double s = 0.0;
+    for (int code = 1; code < kLutEntries; ++code) {
+      if ((((code >> r) & 1) | (((code >> (3 + r)) & 1) << 1)) != op) continue;
+      double other = 1.0;
+      bool valid = true;
+      for (int r2 = 0; r2 < 3; ++r2) {
+        if (r2 == r) continue;
+        const int o2 = ((code >> r2) & 1) | (((code >> (3 + r2)) & 1) << 1);
+        if (3 * g + r2 >= 32) {   // position past the half word: no qubit
+          valid = valid && o2 == 0;
+          continue;
+        }
+        other *= fac[4 * (32 * h + 3 * g + r2) + o2];
+      }
+      if (valid) s += th[code] * other;
+    }
+    acc_g[(int64_t)blockIdx.x * 3 * nq + k] = s;
+  }
+}
+
+template <int W>
+static void launch_bwd_w(int nq, const StoreDev& st, int grid, const double* theta,
+                         const double* phi, const double* lut, double* acc, hipStream_t s) {
+  const size_t lds = energy_bwd_lds_bytes(W);
+  hipFuncSetAttribute((const void*)k_energy_bwd<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds);
+  hipLaunchKernelGGL(k_energy_bwd<W>, dim3(grid), dim3(kBwdBlock), lds, s, st, nq, theta, phi,
+                     lut, acc);
 }
 
 void launch_energy_backward(int W, int nq, const StoreDev& st, int grid, const double* theta,
                             const double* phi, const double* lut, double* acc, hipStream_t s) {
   switch (W) {
-    case 1: hipLaunchKernelGGL(k_energy_bwd<1>, dim3(grid), dim3(kBlock), 0, s, st, nq, theta, phi, lut, acc); break;
-    case 2: hipLaunchKernelGGL(k_energy_bwd<2>, dim3(grid), dim3(kBlock), 0, s, st, nq, theta, phi, lut, acc); break;
-    case 3: hipLaunchKernelGGL(k_energy_bwd<3>, dim3(grid), dim3(kBlock), 0, s, st, nq, theta, phi, lut, acc); break;
-    default: hipLaunchKernelGGL(k_energy_bwd<4>, dim3(grid), dim3(kBlock), 0, s, st, nq, theta, phi, lut, acc); break;
+    case 1: launch_bwd_w<1>(nq, st, grid, theta, phi, lut, acc, s); break;
+    case 2: launch_bwd_w<2>(nq, st, grid, theta, phi, lut, acc, s); break;
+    case 3: launch_bwd_w<3>(nq, st, grid, theta, phi, lut, acc, s); break;
+    default: launch_bwd_w<4>(nq, st, grid, theta, phi, lut, acc, s); break;
   }
 }
 

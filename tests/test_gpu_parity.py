@@ -239,13 +239,20 @@ def test_energy_backward_matches_oracle(ctx):
         assert np.abs(dp.cpu().numpy() - 1.5 * rp).max() <= E_TOL
 
 
-@pytest.mark.parametrize("angles", ["z-eigen", "mixed"])
-def test_energy_backward_special_angles(ctx, angles):
+@pytest.mark.parametrize("nq,angles", [(40, "z-eigen"), (40, "mixed"), (124, "z-eigen"), (124, "mixed"),
+                                       (150, "mixed"), (200, "mixed")])
+def test_energy_backward_special_angles(ctx, nq, angles):
     """Angle gradients where qubit factors vanish exactly (theta = 0 zeroes the
-    X and Y factors), so terms with one zero factor and with several occur."""
-    nq = 40
-    x, z, c = I.hamiltonian_dense(nq, 1)
-    rng = np.random.default_rng(7 + len(angles))
+    X and Y factors), so terms with one zero factor and with several occur;
+    keys of one to four words per plane."""
+    if nq == 40:
+        x, z, c = I.hamiltonian_dense(nq, 1)
+    elif nq <= 128:
+        x, z, c = I.hamiltonian_banded(nq, 7, band=2)
+    else:   # three- and four-word keys: a sample of the terms
+        x, z, c = I.hamiltonian_banded(nq, 7, band=1)
+        x, z, c = x[::4], z[::4], c[::4]
+    rng = np.random.default_rng(7 + len(angles) + nq)
     th, ph = I.qmf_angles(nq, rng)
     k = rng.random(nq)
     if angles == "z-eigen":
@@ -259,7 +266,7 @@ def test_energy_backward_special_angles(ctx, angles):
     rt, rp = O.qmf_grad_angles(nq, x, z, c, th, ph)
     assert np.abs(dt.cpu().numpy() - rt).max() <= E_TOL
     assert np.abs(dp.cpu().numpy() - rp).max() <= E_TOL
-    if angles == "mixed":   # at z-eigenstates every term keeps >= 2 vanishing factors here
+    if angles == "mixed":   # at z-eigenstates most terms keep >= 2 vanishing factors
         assert np.abs(rt).max() > 1e-6
 
 
