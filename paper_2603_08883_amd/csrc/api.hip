@@ -11,6 +11,10 @@
 #include "../../include/iqcc.h"
 #include "iqcc_internal.h"
 
+namespace iqcc {
+int energy_bwd_blocks_per_cu(int W);   // kernels_energy.hip: workgroups per CU the LDS holds
+}
+
 using namespace iqcc;
 
 struct iqcc_ctx {

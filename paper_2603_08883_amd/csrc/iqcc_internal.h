@@ -381,7 +381,6 @@ void launch_energy_anti(int W, const StoreDev& st, const PauliKey& P, int grid, 
                         double* partial, hipStream_t s);
 void launch_energy(int W, const StoreDev& st, int grid, const double* lut, double* e_partial,
                    hipStream_t s);
-int energy_bwd_blocks_per_cu(int W);
 void launch_energy_backward(int W, int nq, const StoreDev& st, int grid, const double* theta,
                             const double* phi, const double* lut, double* acc /*[grid][3*nq]*/,
                             hipStream_t s);
