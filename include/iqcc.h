@@ -252,10 +252,14 @@ int iqcc_qmf_energy(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
 
 /* Backward of iqcc_qmf_energy: dtheta[j] = dE_scale * dE/dtheta_j and
  * dphi[j] = dE_scale * dE/dphi_j (DEVICE arrays of n_qubits), where dE_scale
- * is the DEVICE scalar upstream gradient (NULL means 1). */
+ * is the DEVICE scalar upstream gradient (NULL means 1).  lambda (NULL, or a
+ * DEVICE array of iqcc_store_rows entries) receives, for every live row r,
+ * dE_scale * <Omega| P_r |Omega>: the cotangent of each coefficient, as
+ * iqcc_expectations computes it (same values up to the rounding of the
+ * product; rows that hold no term are left untouched). */
 int iqcc_qmf_energy_backward(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
                              const double *phi, const double *dE_scale, double *dtheta,
-                             double *dphi, void *stream);
+                             double *dphi, double *lambda, void *stream);
 
 /* ---- DIS gradient screening (Eq. 7, App. A) ------------------------------- */
 

@@ -6,8 +6,8 @@ H^(j) = compress(e^{i tau_j P_j/2} H^(j-1) e^{-i tau_j P_j/2})   (Sec. II, Eqs. 
 Forward: the dressing chain runs on the GPU through iqcc_dress_taped, which
 keeps every intermediate Hamiltonian and a tape of output rows in HBM, then
 iqcc_qmf_energy evaluates the energy.  Backward: iqcc_qmf_energy_backward gives
-dE/dtheta and dE/dphi; iqcc_expectations seeds the coefficient cotangent
-lambda = dE/dc = <P_K>, and iqcc_dress_backward carries it back through the
+dE/dtheta and dE/dphi and, in the same pass, the coefficient cotangent
+lambda = dE/dc = <P_K>; iqcc_dress_backward carries it back through the
 steps in reverse, producing dE/dtau_j.  Compression decisions of the forward
 pass are held fixed (the derivative of the chain with frozen drop masks).
 All arithmetic runs in libiqcc; this module only sequences calls.
@@ -111,9 +111,8 @@ class QMFChainEnergy(torch.autograd.Function):
         else:
             final = chain.stores[-1] if chain.ents else chain.h0
         g = gE.detach().to(device="cuda", dtype=torch.float64).reshape(())
-        dth, dph = iqcc.iqcc_qmf_energy_backward(chain.ctx.handle, final.handle, theta, phi, g)
         lam = torch.empty(iqcc.iqcc_store_rows(final.handle), dtype=torch.float64, device="cuda")
-        iqcc.iqcc_expectations(chain.ctx.handle, final.handle, theta, phi, lam, scale=g)
+        dth, dph = iqcc.iqcc_qmf_energy_backward(chain.ctx.handle, final.handle, theta, phi, g, lam)
         dtau = chain.backward_taus(fctx.tau_list, lam)
         return dth, dph, dtau.to(taus.device), None
 

@@ -11,10 +11,6 @@
 #include "../../include/iqcc.h"
 #include "iqcc_internal.h"
 
-namespace iqcc {
-int energy_bwd_blocks_per_cu(int W);   // kernels_energy.hip: workgroups per CU the LDS holds
-}
-
 using namespace iqcc;
 
 struct iqcc_ctx {
@@ -730,7 +726,7 @@ int iqcc_qmf_energy(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, con
 
 int iqcc_qmf_energy_backward(iqcc_ctx* ctx, const iqcc_store* h, const double* theta,
                              const double* phi, const double* dE, double* dtheta, double* dphi,
-                             void* stream) {
+                             double* lambda, void* stream) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
   if (!h || !theta || !phi || !dtheta || !dphi) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
@@ -739,7 +735,7 @@ int iqcc_qmf_energy_backward(iqcc_ctx* ctx, const iqcc_store* h, const double* t
   rc = ensure_partial(ctx, (int64_t)grid * 3 * h->nq);
   if (rc) return rc;
   launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
-  launch_energy_backward(h->W, h->nq, h->d, grid, theta, phi, ctx->lut, ctx->partial, s);
+  launch_energy_backward(h->W, h->nq, h->d, grid, theta, phi, ctx->lut, dE, lambda, ctx->partial, s);
   launch_backward_finalize(h->nq, grid, ctx->partial, theta, phi, dE, dtheta, dphi, s);
   LAUNCH_CHECK(ctx);
   return IQCC_OK;

@@ -381,8 +381,10 @@ void launch_energy_anti(int W, const StoreDev& st, const PauliKey& P, int grid, 
                         double* partial, hipStream_t s);
 void launch_energy(int W, const StoreDev& st, int grid, const double* lut, double* e_partial,
                    hipStream_t s);
+int energy_bwd_blocks_per_cu(int W);
 void launch_energy_backward(int W, int nq, const StoreDev& st, int grid, const double* theta,
-                            const double* phi, const double* lut, double* acc /*[grid][3*nq]*/,
+                            const double* phi, const double* lut, const double* dE,
+                            double* lam /*null or [arena rows]*/, double* acc /*[grid][3*nq]*/,
                             hipStream_t s);
 void launch_backward_finalize(int nq, int grid, const double* acc, const double* theta,
                               const double* phi, const double* dE, double* dtheta, double* dphi,

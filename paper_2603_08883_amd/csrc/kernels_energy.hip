@@ -151,7 +151,8 @@ void launch_energy(int W, const StoreDev& st, int grid, const double* lut, doubl
 // with sigma at q's position of T[e] * (product of the other qubits' factors
 // of that code).  Per term: ZK, the number of zero group factors, and PK, the
 // product of the non-zero ones, formed as one division by the product of
-// their tabulated reciprocals.  The other groups of group g then multiply to
+// their tabulated reciprocals (the term's <K> is PK when ZK = 0, else 0; it
+// is written per row when the caller asks for the coefficient cotangents).  The other groups of group g then multiply to
 // PK * (1 / L_g) when L_g != 0 and ZK = 0, to PK when L_g = 0 and ZK = 1, and
 // to 0 otherwise (exact zeros never divide).  Only the term's non-identity
 // groups are visited for T.  T lives in LDS and takes FP64 atomics (one per
@@ -179,6 +180,7 @@ int energy_bwd_blocks_per_cu(int W) {
 template <int W>
 __global__ __launch_bounds__(kBwdBlock) void k_energy_bwd(StoreDev st, int nq, const double* theta,
                                                           const double* phi, const double* lut_g,
+                                                          const double* dE, double* lam,
                                                           double* acc_g) {
   constexpr int NE = W * kGroupsPerWord * kLutEntries;
   constexpr int NP = bwd_padded(NE);
@@ -204,6 +206,7 @@ __global__ __launch_bounds__(kBwdBlock) void k_energy_bwd(StoreDev st, int nq, c
     for (int op = 0; op < 4; ++op) fac[4 * q + op] = bloch_factor(op, st_, ct, sp, cp);
   }
   __syncthreads();
+  const double scale = dE ? *dE : 1.0;
   const int64_t B = 1ll << *st.m;
   for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
     const int64_t n = st.cnt[b], off = st.off[b];
@@ -242,8 +245,11 @@ __global__ __launch_bounds__(kBwdBlock) void k_energy_bwd(StoreDev st, int nq, c
           }
         }
       }
+      const double pk = 1.0 / ((r[0] * r[1]) * (r[2] * r[3]));   // PK
+      // dE/dc of the term: <K> = PK without zero factors, else 0
+      if (lam) lam[off + i] = zk == 0 ? scale * pk : 0.0;
       if (zk > 1) continue;   // every group's other factors include a zero
-      const double cpk = c / ((r[0] * r[1]) * (r[2] * r[3]));   // c times PK
+      const double cpk = c * pk;
       const bool one_zero = zk == 1;
       // T over the term's non-identity groups only
 #pragma unroll
@@ -298,21 +304,23 @@ __global__ __launch_bounds__(kBwdBlock) void k_energy_bwd(StoreDev st, int nq, c
 
 template <int W>
 static void launch_bwd_w(int nq, const StoreDev& st, int grid, const double* theta,
-                         const double* phi, const double* lut, double* acc, hipStream_t s) {
+                         const double* phi, const double* lut, const double* dE, double* lam,
+                         double* acc, hipStream_t s) {
   const size_t lds = energy_bwd_lds_bytes(W);
   hipFuncSetAttribute((const void*)k_energy_bwd<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   hipLaunchKernelGGL(k_energy_bwd<W>, dim3(grid), dim3(kBwdBlock), lds, s, st, nq, theta, phi,
-                     lut, acc);
+                     lut, dE, lam, acc);
 }
 
 void launch_energy_backward(int W, int nq, const StoreDev& st, int grid, const double* theta,
-                            const double* phi, const double* lut, double* acc, hipStream_t s) {
+                            const double* phi, const double* lut, const double* dE, double* lam,
+                            double* acc, hipStream_t s) {
   switch (W) {
-    case 1: launch_bwd_w<1>(nq, st, grid, theta, phi, lut, acc, s); break;
-    case 2: launch_bwd_w<2>(nq, st, grid, theta, phi, lut, acc, s); break;
-    case 3: launch_bwd_w<3>(nq, st, grid, theta, phi, lut, acc, s); break;
-    default: launch_bwd_w<4>(nq, st, grid, theta, phi, lut, acc, s); break;
+    case 1: launch_bwd_w<1>(nq, st, grid, theta, phi, lut, dE, lam, acc, s); break;
+    case 2: launch_bwd_w<2>(nq, st, grid, theta, phi, lut, dE, lam, acc, s); break;
+    case 3: launch_bwd_w<3>(nq, st, grid, theta, phi, lut, dE, lam, acc, s); break;
+    default: launch_bwd_w<4>(nq, st, grid, theta, phi, lut, dE, lam, acc, s); break;
   }
 }
 

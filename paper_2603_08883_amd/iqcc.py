@@ -70,7 +70,7 @@ def lib():
         "iqcc_dress_raw": (i32, [P, i32, P, P, P, i64, i64, P, P, d, P, P, P, P, i64, P]),
         "iqcc_merge_truncate": (i32, [P, P, P, P, i64, i64, d, P, P]),
         "iqcc_qmf_energy": (i32, [P, P, P, P, P, P]),
-        "iqcc_qmf_energy_backward": (i32, [P, P, P, P, P, P, P, P]),
+        "iqcc_qmf_energy_backward": (i32, [P, P, P, P, P, P, P, P, P]),
         "iqcc_dis_gradients": (i32, [P, P, P, P, P, P, i64, i64, i32, P, P]),
         "iqcc_store_rows": (i32, [P, ct.POINTER(i64)]),
         "iqcc_dress_taped": (i32, [P, P, P, P, d, d, P, P, P, P]),
@@ -280,12 +280,13 @@ def iqcc_qmf_energy(ctx, store, theta, phi, energy=None, stream=None):
     return energy
 
 
-def iqcc_qmf_energy_backward(ctx, store, theta, phi, dE=None, stream=None):
+def iqcc_qmf_energy_backward(ctx, store, theta, phi, dE=None, lam=None, stream=None):
+    """dE/dtheta, dE/dphi (scaled by dE); `lam`, if given, receives dE * <P_r> per row."""
     import torch
     dtheta = torch.empty_like(theta)
     dphi = torch.empty_like(phi)
     _check(lib().iqcc_qmf_energy_backward(ctx, store, _ptr(theta), _ptr(phi), _ptr(dE), _ptr(dtheta),
-                                          _ptr(dphi), _stream(stream)), ctx)
+                                          _ptr(dphi), _ptr(lam), _stream(stream)), ctx)
     return dtheta, dphi
 
 

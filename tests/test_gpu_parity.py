@@ -233,10 +233,48 @@ def test_energy_backward_matches_oracle(ctx):
         s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
         describe(0, "energy_backward", nq=nq, n=len(c))
         dE = torch.tensor(1.5, dtype=torch.float64, device="cuda")
-        dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht, dE)
+        lam = _nan_rows(s)
+        dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht, dE, lam)
         rt, rp = O.qmf_grad_angles(nq, x, z, c, th, ph)
         assert np.abs(dt.cpu().numpy() - 1.5 * rt).max() <= E_TOL
         assert np.abs(dp.cpu().numpy() - 1.5 * rp).max() <= E_TOL
+        _check_cotangents(ctx, s, tht, pht, dE, lam)
+
+
+def _nan_rows(store):
+    return torch.full((iqcc.iqcc_store_rows(store.handle),), float("nan"), dtype=torch.float64,
+                      device="cuda")
+
+
+def _check_cotangents(ctx, store, tht, pht, dE, lam):
+    """The per-row coefficient cotangents written by the backward equal dE * <P_r>
+    of the stand-alone expectation kernel on exactly the live rows."""
+    ref = _nan_rows(store)
+    iqcc.iqcc_expectations(ctx.handle, store.handle, tht, pht, ref, scale=dE)
+    live = ~torch.isnan(ref)
+    assert torch.equal(live, ~torch.isnan(lam))
+    assert int(live.sum()) == store.count()
+    assert (lam[live] - ref[live]).abs().max().item() <= 1e-14 * max(1.0, ref[live].abs().max().item())
+
+
+def test_energy_backward_degenerate(ctx):
+    """An empty store and a store holding only the identity term have zero
+    angle gradients; the identity's cotangent is 1."""
+    nq = 70
+    th, ph = I.qmf_angles(nq, np.random.default_rng(3))
+    tht, pht = torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()
+    W = I.n_words(nq)
+    for n in (0, 1):
+        x = np.zeros((n, W), np.uint64)
+        z = np.zeros((n, W), np.uint64)
+        c = np.full(n, 0.75)
+        s = iqcc.Store(ctx, nq, 16).load_numpy(x, z, c)
+        describe(0, "energy_backward degenerate", nq=nq, n=n)
+        lam = _nan_rows(s)
+        dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht, None, lam)
+        assert dt.abs().max().item() == 0.0 and dp.abs().max().item() == 0.0
+        live = lam[~torch.isnan(lam)]
+        assert live.numel() == n and (n == 0 or live.item() == 1.0)
 
 
 @pytest.mark.parametrize("nq,angles", [(40, "z-eigen"), (40, "mixed"), (124, "z-eigen"), (124, "mixed"),
@@ -262,10 +300,12 @@ def test_energy_backward_special_angles(ctx, nq, angles):
     tht, pht = torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()
     s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
     describe(0, "energy_backward special angles", nq=nq, angles=angles)
-    dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht)
+    lam = _nan_rows(s)
+    dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht, None, lam)
     rt, rp = O.qmf_grad_angles(nq, x, z, c, th, ph)
     assert np.abs(dt.cpu().numpy() - rt).max() <= E_TOL
     assert np.abs(dp.cpu().numpy() - rp).max() <= E_TOL
+    _check_cotangents(ctx, s, tht, pht, None, lam)
     if angles == "mixed":   # at z-eigenstates most terms keep >= 2 vanishing factors
         assert np.abs(rt).max() > 1e-6
 
