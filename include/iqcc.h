@@ -219,11 +219,12 @@ int iqcc_store_rows(const iqcc_store *store, int64_t *rows);
  * for every live row r of `in`, tape_self[r] = output row of its key (-1 if
  * compression dropped it) and tape_partner[r] = output row of key ^ P for
  * anticommuting rows (-1 if absent or dropped), -2 for commuting rows.  Both
- * are DEVICE int64 arrays of iqcc_store_rows(in) entries (caller-owned); the
- * tape stays valid while `in` and `out` are unchanged. */
+ * are DEVICE int32 arrays of iqcc_store_rows(in) entries (caller-owned); the
+ * tape stays valid while `in` and `out` are unchanged.  The arena of `out`
+ * must hold fewer than 2^31 rows (IQCC_ERR_INVALID_ARG otherwise). */
 int iqcc_dress_taped(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px, const uint64_t *pz,
-                     double tau, double eps, iqcc_store *out, int64_t *tape_self,
-                     int64_t *tape_partner, void *stream);
+                     double tau, double eps, iqcc_store *out, int32_t *tape_self,
+                     int32_t *tape_partner, void *stream);
 
 /* Backward of one taped dressing step with the compression decisions of the
  * forward pass held fixed.  lambda_out: DEVICE cotangent dE/dc per row of
@@ -233,8 +234,8 @@ int iqcc_dress_taped(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px, co
  *   lambda_in[A] = lambda_out[A]                                      (commuting A)
  *   dtau = sum_A -sin(t) c_A lambda_out[A] + s_A cos(t) c_A lambda_out[A^P]. */
 int iqcc_dress_backward(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px,
-                        const uint64_t *pz, double tau, const int64_t *tape_self,
-                        const int64_t *tape_partner, const double *lambda_out,
+                        const uint64_t *pz, double tau, const int32_t *tape_self,
+                        const int32_t *tape_partner, const double *lambda_out,
                         double *lambda_in, double *dtau, void *stream);
 
 /* out[r] = scale * <Omega| P_r |Omega> for every live row r of the store

@@ -58,8 +58,8 @@ class DressingChain:
             rows = iqcc.iqcc_store_rows(src.handle)
             tp = self.tapes[j]
             if tp is None or tp[0].numel() < rows:
-                tp = (torch.empty(rows, dtype=torch.int64, device="cuda"),
-                      torch.empty(rows, dtype=torch.int64, device="cuda"))
+                tp = (torch.empty(rows, dtype=torch.int32, device="cuda"),
+                      torch.empty(rows, dtype=torch.int32, device="cuda"))
                 self.tapes[j] = tp
             iqcc.iqcc_dress_taped(self.ctx.handle, src.handle, px, pz, float(t), self.eps,
                                   self.stores[j].handle, tp[0], tp[1])

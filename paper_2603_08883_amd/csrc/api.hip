@@ -428,7 +428,7 @@ int iqcc_store_export(iqcc_ctx* ctx, const iqcc_store* st, uint64_t* x, uint64_t
 static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
                       double tau, double eps, const double* theta, const double* phi,
                       const double* energy_in, double* energy, iqcc_store* out,
-                      int64_t* tape_self, int64_t* tape_partner, void* stream) {
+                      int32_t* tape_self, int32_t* tape_partner, void* stream) {
   int rc = check_ctx(ctx);
   if (rc) return rc;
   if (!in || !out || !px || !pz) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
@@ -443,6 +443,8 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
     return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
   if (out->d.cap < in->d.cap || out->d.mcap < in->d.mcap)
     return fail(ctx, IQCC_ERR_CAPACITY, "output store is smaller than the input store");
+  if (tape_self && out->d.cap > (int64_t)INT32_MAX)
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "a taped step needs an output arena below 2^31 rows");
   const int W = in->W;
   Entangler P = make_entangler(W, px, pz);
   hipStream_t s = as_stream(stream);
@@ -507,16 +509,16 @@ int iqcc_store_rows(const iqcc_store* st, int64_t* rows) {
 }
 
 int iqcc_dress_taped(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
-                     double tau, double eps, iqcc_store* out, int64_t* tape_self,
-                     int64_t* tape_partner, void* stream) {
+                     double tau, double eps, iqcc_store* out, int32_t* tape_self,
+                     int32_t* tape_partner, void* stream) {
   if (ctx && (!tape_self || !tape_partner)) return fail(ctx, IQCC_ERR_INVALID_ARG, "tape arrays are null");
   return dress_impl(ctx, in, px, pz, tau, eps, nullptr, nullptr, nullptr, nullptr, out, tape_self,
                     tape_partner, stream);
 }
 
 int iqcc_dress_backward(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px,
-                        const uint64_t* pz, double tau, const int64_t* tape_self,
-                        const int64_t* tape_partner, const double* lambda_out,
+                        const uint64_t* pz, double tau, const int32_t* tape_self,
+                        const int32_t* tape_partner, const double* lambda_out,
                         double* lambda_in, double* dtau, void* stream) {
   int rc = check_ctx(ctx);
   if (rc) return rc;

@@ -306,8 +306,8 @@ struct DressConfig {
   const double* lut;   // null: no fused energy
   int delta;           // 1: e_partial accumulates only the change of the energy
   double* e_partial;   // [grid]
-  int64_t* tape_self;     // null, or per input arena row: output row of K (-1 dropped)
-  int64_t* tape_partner;  //   and output row of K^P (-1 absent/dropped, -2 commuting)
+  int32_t* tape_self;     // null, or per input arena row: output row of K (-1 dropped)
+  int32_t* tape_partner;  //   and output row of K^P (-1 absent/dropped, -2 commuting)
 };
 void launch_dress(int W, const StoreDev& in, const StoreDev& out, const Entangler& P,
                   const DressConfig& cfg, hipStream_t s);
@@ -399,7 +399,7 @@ int64_t dis_tables_doubles(int W);
 int64_t dis_tile();   // candidates per workgroup of the batched kernel
 
 void launch_dress_backward(int W, const StoreDev& in, const Entangler& P, double C, double S,
-                           const int64_t* tape_self, const int64_t* tape_partner,
+                           const int32_t* tape_self, const int32_t* tape_partner,
                            const double* lam_out, double* lam_in, double* partial, int grid,
                            hipStream_t s);
 void launch_expectations(int W, const StoreDev& st, const double* lut, const double* scale,

@@ -21,8 +21,8 @@ namespace iqcc {
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_dress_backward(StoreDev in, Entangler P, double C,
-                                                           double S, const int64_t* tape_self,
-                                                           const int64_t* tape_partner,
+                                                           double S, const int32_t* tape_self,
+                                                           const int32_t* tape_partner,
                                                            const double* lam_out, double* lam_in,
                                                            double* partial) {
   __shared__ double red[kWaves];
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_dress_backward(StoreDev in, Entangle
 }
 
 void launch_dress_backward(int W, const StoreDev& in, const Entangler& P, double C, double S,
-                           const int64_t* tape_self, const int64_t* tape_partner,
+                           const int32_t* tape_self, const int32_t* tape_partner,
                            const double* lam_out, double* lam_in, double* partial, int grid,
                            hipStream_t s) {
   switch (W) {

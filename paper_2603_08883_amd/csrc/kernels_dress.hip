@@ -298,7 +298,7 @@ template <int W, bool ENERGY>
 __device__ void scan_pair(const StoreDev& in, const StoreDev& out, const Entangler& P,
                           const Smem<W>& sm, const PairState& ps, int split, int m, bool full,
                           uint32_t mod, uint32_t rem, double eps, int delta,
-                          int64_t* tape_self, int64_t* tape_partner, double& eacc) {
+                          int32_t* tape_self, int32_t* tape_partner, double& eacc) {
   const int lane = threadIdx.x & 63;
   for (int64_t i0 = (threadIdx.x & ~63); i0 < ps.ntot; i0 += kDB) {
     const int64_t idx = i0 + lane;
@@ -352,7 +352,7 @@ __device__ void scan_pair(const StoreDev& in, const StoreDev& out, const Entangl
       const int64_t orow = ps.row(cat, pos);
       store_key<W>(out, orow, kx, kz, kc);
       if (tape_self) {
-        tape_self[krow] = orow;
+        tape_self[krow] = (int32_t)orow;
         tape_partner[krow] = -2;
       }
     }
@@ -364,7 +364,7 @@ __device__ void scan_pair(const StoreDev& in, const StoreDev& out, const Entangl
 template <int W, bool ENERGY>
 __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>& sm,
                           const PairState& ps, int n, int split, int m, double C, double S,
-                          double eps, int delta, int64_t* tape_self, int64_t* tape_partner,
+                          double eps, int delta, int32_t* tape_self, int32_t* tape_partner,
                           double& eacc, int64_t& fresh) {
   const int tid = threadIdx.x;
   const uint32_t tmask = (uint32_t)sm.ts - 1;
@@ -479,8 +479,8 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
     }
     if (tape_self && valid) {
       sm.orow[i] = own_row;
-      tape_self[sm.arow[i]] = own_row;
-      if (sm.partner[i] < 0) tape_partner[sm.arow[i]] = new_row;
+      tape_self[sm.arow[i]] = (int32_t)own_row;
+      if (sm.partner[i] < 0) tape_partner[sm.arow[i]] = (int32_t)new_row;
     }
   }
   __syncthreads();
@@ -488,7 +488,7 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
     // the partner K^P of a paired entry is the other member's own output row
     for (int i = tid; i < n; i += kDB) {
       const int j = sm.partner[i];
-      if (j >= 0) tape_partner[sm.arow[i]] = sm.orow[j];
+      if (j >= 0) tape_partner[sm.arow[i]] = (int32_t)sm.orow[j];
     }
     __syncthreads();
   }

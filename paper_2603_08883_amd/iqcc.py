@@ -306,8 +306,19 @@ def iqcc_store_rows(store) -> int:
     return r.value
 
 
+def _check_tape(store_in, *tapes):
+    """Tapes are int32 device arrays with one entry per arena row of the input."""
+    import torch
+    rows = iqcc_store_rows(store_in)
+    for t in tapes:
+        if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous() or t.numel() < rows:
+            raise IqccError(IQCC_ERR_INVALID_ARG,
+                            f"tape must be a contiguous int32 device array of >= {rows} entries")
+
+
 def iqcc_dress_taped(ctx, store_in, px, pz, tau, eps, store_out, tape_self, tape_partner,
                      stream=None):
+    _check_tape(store_in, tape_self, tape_partner)
     ax, pxp = _words(px)
     az, pzp = _words(pz)
     _check(lib().iqcc_dress_taped(ctx, store_in, pxp, pzp, float(tau), float(eps), store_out,
@@ -316,6 +327,7 @@ def iqcc_dress_taped(ctx, store_in, px, pz, tau, eps, store_out, tape_self, tape
 
 def iqcc_dress_backward(ctx, store_in, px, pz, tau, tape_self, tape_partner, lambda_out,
                         lambda_in, dtau, stream=None):
+    _check_tape(store_in, tape_self, tape_partner)
     ax, pxp = _words(px)
     az, pzp = _words(pz)
     _check(lib().iqcc_dress_backward(ctx, store_in, pxp, pzp, float(tau), _ptr(tape_self),

@@ -110,3 +110,23 @@ def test_optimisation_decreases_energy(ctx):
     assert all(b <= a + 1e-12 for a, b in zip(energies, energies[1:]))
     assert energies[-1] < energies[0] - 1e-3
     chain.close()
+
+
+def test_tape_arguments_checked(ctx):
+    """Tapes are int32 arrays of one entry per input arena row; anything else is
+    rejected on the host before a kernel runs."""
+    nq = 12
+    x, z, c = I.hamiltonian_dense(nq, 9)
+    cx, cz = I.dis_candidates(x, nq, 1, 6, np.random.default_rng(4))
+    a = iqcc.Store(ctx, nq, 4 * len(c)).load_numpy(x, z, c)
+    b = iqcc.Store(ctx, nq, 4 * len(c))
+    rows = iqcc.iqcc_store_rows(a.handle)
+    describe(0, "tape argument checks", nq=nq, rows=rows)
+    for bad in (torch.empty(rows, dtype=torch.int64, device="cuda"),
+                torch.empty(rows - 1, dtype=torch.int32, device="cuda"),
+                torch.empty(rows, dtype=torch.int32)):
+        good = torch.empty(rows, dtype=torch.int32, device="cuda")
+        with pytest.raises(iqcc.IqccError):
+            iqcc.iqcc_dress_taped(ctx.handle, a.handle, cx[0], cz[0], 0.1, 0.0, b.handle, bad, good)
+        with pytest.raises(iqcc.IqccError):
+            iqcc.iqcc_dress_taped(ctx.handle, a.handle, cx[0], cz[0], 0.1, 0.0, b.handle, good, bad)
