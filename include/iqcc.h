@@ -217,11 +217,13 @@ int iqcc_store_rows(const iqcc_store *store, int64_t *rows);
 
 /* iqcc_dress without energy that also records a tape for the backward pass:
  * for every live row r of `in`, tape_self[r] = output row of its key (-1 if
- * compression dropped it) and tape_partner[r] = output row of key ^ P for
- * anticommuting rows (-1 if absent or dropped), -2 for commuting rows.  Both
- * are DEVICE int32 arrays of iqcc_store_rows(in) entries (caller-owned); the
- * tape stays valid while `in` and `out` are unchanged.  The arena of `out`
- * must hold fewer than 2^31 rows (IQCC_ERR_INVALID_ARG otherwise). */
+ * compression dropped it); tape_partner[r] = -1 for a commuting row, and for
+ * an anticommuting row 2 * (t + 1) + b, where t is the output row of key ^ P
+ * (-1 if absent or dropped) and b = 1 when P K = i^3 (K ^ P) (the sign s_K of
+ * Eq. 5's new term is +1), else 0.  Both are DEVICE int32 arrays of
+ * iqcc_store_rows(in) entries (caller-owned); the tape stays valid while `in`
+ * and `out` are unchanged.  The arena of `out` must hold fewer than 2^30 rows
+ * (IQCC_ERR_INVALID_ARG otherwise). */
 int iqcc_dress_taped(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px, const uint64_t *pz,
                      double tau, double eps, iqcc_store *out, int32_t *tape_self,
                      int32_t *tape_partner, void *stream);
@@ -232,7 +234,9 @@ int iqcc_dress_taped(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px, co
  * DEVICE output per row of `in`; *dtau (DEVICE scalar) = dE/dtau of this step:
  *   lambda_in[A] = cos(t) lambda_out[A] + s_A sin(t) lambda_out[A^P]  (anticommuting A)
  *   lambda_in[A] = lambda_out[A]                                      (commuting A)
- *   dtau = sum_A -sin(t) c_A lambda_out[A] + s_A cos(t) c_A lambda_out[A^P]. */
+ *   dtau = sum_A -sin(t) c_A lambda_out[A] + s_A cos(t) c_A lambda_out[A^P].
+ * The rows of A^P and the signs s_A come from the tape of iqcc_dress_taped;
+ * px, pz name the step's entangler and are only checked against n_qubits. */
 int iqcc_dress_backward(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px,
                         const uint64_t *pz, double tau, const int32_t *tape_self,
                         const int32_t *tape_partner, const double *lambda_out,

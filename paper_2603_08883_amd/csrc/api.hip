@@ -443,8 +443,8 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
     return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
   if (out->d.cap < in->d.cap || out->d.mcap < in->d.mcap)
     return fail(ctx, IQCC_ERR_CAPACITY, "output store is smaller than the input store");
-  if (tape_self && out->d.cap > (int64_t)INT32_MAX)
-    return fail(ctx, IQCC_ERR_INVALID_ARG, "a taped step needs an output arena below 2^31 rows");
+  if (tape_self && out->d.cap >= ((int64_t)1 << 30))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "a taped step needs an output arena below 2^30 rows");
   const int W = in->W;
   Entangler P = make_entangler(W, px, pz);
   hipStream_t s = as_stream(stream);
@@ -527,12 +527,11 @@ int iqcc_dress_backward(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px,
   if (!std::isfinite(tau)) return fail(ctx, IQCC_ERR_INVALID_ARG, "tau is not finite");
   if (!padding_clear(in->nq, in->W, px, pz))
     return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
-  Entangler P = make_entangler(in->W, px, pz);
   hipStream_t s = as_stream(stream);
   const int grid = (int)(ctx->n_cu * 4);
   rc = ensure_partial(ctx, grid);
   if (rc) return rc;
-  launch_dress_backward(in->W, in->d, P, std::cos(tau), std::sin(tau), tape_self, tape_partner,
+  launch_dress_backward(in->W, in->d, std::cos(tau), std::sin(tau), tape_self, tape_partner,
                         lambda_out, lambda_in, ctx->partial, grid, s);
   launch_finalize_sum(ctx->partial, grid, nullptr, dtau, s);
   LAUNCH_CHECK(ctx);

@@ -398,7 +398,7 @@ void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx
 int64_t dis_tables_doubles(int W);
 int64_t dis_tile();   // candidates per workgroup of the batched kernel
 
-void launch_dress_backward(int W, const StoreDev& in, const Entangler& P, double C, double S,
+void launch_dress_backward(int W, const StoreDev& in, double C, double S,
                            const int32_t* tape_self, const int32_t* tape_partner,
                            const double* lam_out, double* lam_in, double* partial, int grid,
                            hipStream_t s);

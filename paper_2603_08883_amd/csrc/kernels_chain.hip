@@ -12,7 +12,8 @@
 // and the step's amplitude receives
 //   dE/dt += sum_A  -sin(t) c[A] lambda'[A] + s_A cos(t) c[A] lambda'[A^P].
 // The tape recorded by the forward kernel gives, for every input row, the
-// output rows of A and A^P, so no key lookup is needed here.
+// output rows of A and A^P and the sign s_A, so no key is read or looked up
+// here.
 #include "iqcc_internal.h"
 
 #pragma clang fp contract(off)
@@ -20,7 +21,7 @@
 namespace iqcc {
 
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_dress_backward(StoreDev in, Entangler P, double C,
+__global__ __launch_bounds__(kBlock) void k_dress_backward(StoreDev in, double C,
                                                            double S, const int32_t* tape_self,
                                                            const int32_t* tape_partner,
                                                            const double* lam_out, double* lam_in,
@@ -32,20 +33,16 @@ __global__ __launch_bounds__(kBlock) void k_dress_backward(StoreDev in, Entangle
     const int64_t n = in.cnt[b], off = in.off[b];
     for (int64_t i = threadIdx.x; i < n; i += kBlock) {
       const int64_t row = off + i;
-      const int64_t ts = tape_self[row], tp = tape_partner[row];
+      const int32_t ts = tape_self[row], enc = tape_partner[row];
       const double la = ts >= 0 ? lam_out[ts] : 0.0;
-      if (tp == -2) {
+      if (enc < 0) {   // commuting
         lam_in[row] = la;
         continue;
       }
+      // anticommuting: enc = 2 * (output row of K^P + 1) + [s_K = +1]
+      const int32_t tp = (enc >> 1) - 1;
       const double lp = tp >= 0 ? lam_out[tp] : 0.0;
-      uint64_t kx[W], kz[W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        kx[w] = in.x[w * in.cap + row];
-        kz[w] = in.z[w * in.cap + row];
-      }
-      const double s = product_phase<W>(P.px, P.pz, kx, kz) == 3 ? 1.0 : -1.0;
+      const double s = (enc & 1) ? 1.0 : -1.0;
       const double c = in.c[row];
       lam_in[row] = __dadd_rn(__dmul_rn(C, la), s * __dmul_rn(S, lp));
       acc += __dadd_rn(-__dmul_rn(__dmul_rn(S, c), la), s * __dmul_rn(__dmul_rn(C, c), lp));
@@ -55,15 +52,15 @@ __global__ __launch_bounds__(kBlock) void k_dress_backward(StoreDev in, Entangle
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-void launch_dress_backward(int W, const StoreDev& in, const Entangler& P, double C, double S,
+void launch_dress_backward(int W, const StoreDev& in, double C, double S,
                            const int32_t* tape_self, const int32_t* tape_partner,
                            const double* lam_out, double* lam_in, double* partial, int grid,
                            hipStream_t s) {
   switch (W) {
-    case 1: hipLaunchKernelGGL(k_dress_backward<1>, dim3(grid), dim3(kBlock), 0, s, in, P, C, S, tape_self, tape_partner, lam_out, lam_in, partial); break;
-    case 2: hipLaunchKernelGGL(k_dress_backward<2>, dim3(grid), dim3(kBlock), 0, s, in, P, C, S, tape_self, tape_partner, lam_out, lam_in, partial); break;
-    case 3: hipLaunchKernelGGL(k_dress_backward<3>, dim3(grid), dim3(kBlock), 0, s, in, P, C, S, tape_self, tape_partner, lam_out, lam_in, partial); break;
-    default: hipLaunchKernelGGL(k_dress_backward<4>, dim3(grid), dim3(kBlock), 0, s, in, P, C, S, tape_self, tape_partner, lam_out, lam_in, partial); break;
+    case 1: hipLaunchKernelGGL(k_dress_backward<1>, dim3(grid), dim3(kBlock), 0, s, in, C, S, tape_self, tape_partner, lam_out, lam_in, partial); break;
+    case 2: hipLaunchKernelGGL(k_dress_backward<2>, dim3(grid), dim3(kBlock), 0, s, in, C, S, tape_self, tape_partner, lam_out, lam_in, partial); break;
+    case 3: hipLaunchKernelGGL(k_dress_backward<3>, dim3(grid), dim3(kBlock), 0, s, in, C, S, tape_self, tape_partner, lam_out, lam_in, partial); break;
+    default: hipLaunchKernelGGL(k_dress_backward<4>, dim3(grid), dim3(kBlock), 0, s, in, C, S, tape_self, tape_partner, lam_out, lam_in, partial); break;
   }
 }
 

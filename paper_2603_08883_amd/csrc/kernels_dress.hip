@@ -324,7 +324,7 @@ __device__ void scan_pair(const StoreDev& in, const StoreDev& out, const Entangl
           dropped = true;
           if (tape_self) {
             tape_self[krow] = -1;
-            tape_partner[krow] = -2;
+            tape_partner[krow] = -1;   // commuting
           }
         }
       }
@@ -353,7 +353,7 @@ __device__ void scan_pair(const StoreDev& in, const StoreDev& out, const Entangl
       store_key<W>(out, orow, kx, kz, kc);
       if (tape_self) {
         tape_self[krow] = (int32_t)orow;
-        tape_partner[krow] = -2;
+        tape_partner[krow] = -1;   // commuting
       }
     }
   }
@@ -418,6 +418,7 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
     uint64_t kx[W], kz[W];
     double v_own = 0.0, v_new = 0.0, a = 0.0;
     int cat_own = -1, cat_new = -1;
+    int sa = 0;   // 1 when s_K = +1 (P K = i^3 (K^P)), for the tape
     if (valid) {
 #pragma unroll
       for (int w = 0; w < W; ++w) {
@@ -438,11 +439,13 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
           jz[w] = sm.az[w * sm.cap + j];
         }
         const int ej = product_phase<W>(P.px, P.pz, jx, jz);
+        sa = ej == 3 ? 0 : 1;   // the two members of a pair have opposite signs
         const double sj = __dmul_rn(S, sm.ac[j]);
         v_own = __dadd_rn(rot, ej == 3 ? sj : -sj);
       } else {
         v_own = rot;
         const int e = product_phase<W>(P.px, P.pz, kx, kz);
+        sa = e == 3 ? 1 : 0;
         const double si = __dmul_rn(S, a);
         v_new = e == 3 ? si : -si;
         if (!(fabs(v_new) < eps)) {
@@ -478,9 +481,11 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
       store_key<W>(out, new_row, qx, qz, v_new);
     }
     if (tape_self && valid) {
+      // tape_partner of an anticommuting row: 2 * (output row of K^P + 1) + [s_K = +1]
       sm.orow[i] = own_row;
       tape_self[sm.arow[i]] = (int32_t)own_row;
-      if (sm.partner[i] < 0) tape_partner[sm.arow[i]] = (int32_t)new_row;
+      if (sm.partner[i] < 0) tape_partner[sm.arow[i]] = (int32_t)(2 * (new_row + 1) + sa);
+      else sm.side[i] = (uint8_t)(sm.side[i] | (sa << 1));   // only this lane reads side[i]
     }
   }
   __syncthreads();
@@ -488,7 +493,7 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
     // the partner K^P of a paired entry is the other member's own output row
     for (int i = tid; i < n; i += kDB) {
       const int j = sm.partner[i];
-      if (j >= 0) tape_partner[sm.arow[i]] = (int32_t)sm.orow[j];
+      if (j >= 0) tape_partner[sm.arow[i]] = (int32_t)(2 * (sm.orow[j] + 1) + ((sm.side[i] >> 1) & 1));
     }
     __syncthreads();
   }
