@@ -324,13 +324,20 @@ void launch_energy_backward(int W, int nq, const StoreDev& st, int grid, const d
   }
 }
 
+// One workgroup per qubit: S[q][sigma] summed over the per-workgroup
+// partials in a fixed order, then the chain rule through the Bloch factors.
 __global__ void k_backward_finalize(int nq, int grid, const double* acc, const double* theta,
                                     const double* phi, const double* dE, double* dtheta,
                                     double* dphi) {
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
-    double S[3] = {0.0, 0.0, 0.0};
-    for (int g = 0; g < grid; ++g)
-      for (int k = 0; k < 3; ++k) S[k] += acc[(int64_t)g * 3 * nq + 3 * q + k];
+  __shared__ double red[kWaves];
+  const int q = blockIdx.x;
+  double S[3];
+  for (int k = 0; k < 3; ++k) {
+    double v = 0.0;
+    for (int g = threadIdx.x; g < grid; g += kBlock) v += acc[(int64_t)g * 3 * nq + 3 * q + k];
+    S[k] = block_sum(v, red);   // valid in thread 0
+  }
+  if (threadIdx.x == 0) {
     double st, ct, sp, cp;
     sincos(theta[q], &st, &ct);
     sincos(phi[q], &sp, &cp);
@@ -346,7 +353,8 @@ __global__ void k_backward_finalize(int nq, int grid, const double* acc, const d
 void launch_backward_finalize(int nq, int grid, const double* acc, const double* theta,
                               const double* phi, const double* dE, double* dtheta, double* dphi,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_backward_finalize, dim3(1), dim3(kBlock), 0, s, nq, grid, acc, theta, phi,
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(k_backward_finalize, dim3(nq), dim3(kBlock), 0, s, nq, grid, acc, theta, phi,
                      dE, dtheta, dphi);
 }
 
