@@ -95,6 +95,28 @@ def profiled_traffic(ctx):
         return None
 
 
+def measured_copy_gbps():
+    """Bandwidth of a plain device-to-device copy of 4 GiB (bytes read + bytes
+    written per second): the practical HBM ceiling next to the 8 TB/s peak."""
+    import torch
+    src = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 5
+    nbytes = 2 * src.numel() * 8
+    del src, dst
+    torch.cuda.empty_cache()
+    return nbytes / (ms * 1e-3) / 1e9
+
+
 def autograd_leg(ctx, stream, wl):
     """dE/d(theta, phi, tau) of the full 124-qubit chain through the autograd
     Function (taped forward + reverse sweep), against the same gradient from
@@ -394,6 +416,9 @@ def main():
         result["calib_copy_bytes"] = 2 * src_t.numel() * 8
         del src_t, dst_t
 
+    copy_gbps = measured_copy_gbps()
+    log(f"device copy {copy_gbps:.0f} GB/s (read + write)")
+
     wl = None
     if not (args.no_chain and args.no_autograd):
         t = time.perf_counter()
@@ -503,7 +528,9 @@ def main():
                          "alg_bytes_per_launch": alg_bytes / N_STEPS_CHAIN,
                          "traffic_over_alg_bytes": (traffic / (alg_bytes / N_STEPS_CHAIN)
                                                     if traffic else None),
-                         "avg_launch_ms": kernel_s / N_STEPS_CHAIN * 1e3},
+                         "avg_launch_ms": kernel_s / N_STEPS_CHAIN * 1e3,
+                         "measured_copy_gbps": copy_gbps,
+                         "frac_of_measured_copy": achieved / copy_gbps},
             "per_step_ms": [round(v * 1e3, 4) for v in per_step],
             "final_energy": float(energies[-1].item()),
             "energy": {"mode": "carried forward from step to step (only changed terms "
@@ -530,6 +557,7 @@ def main():
             "workload": f"stand-alone energy of the final 124-qubit Hamiltonian ({n_fin0} terms)",
             "ms": t_e * 1e3, "hbm_gbps_algorithmic": bt * n_fin0 / t_e / 1e9,
             "roofline_frac": bt * n_fin0 / t_e / 1e9 / HBM_PEAK_GBPS,
+            "frac_of_measured_copy": bt * n_fin0 / t_e / 1e9 / copy_gbps,
             "matches_fused_energy": abs(float(e1.item()) - float(energies[-1].item())) <= 1e-10}
         other = s1 if final is s2 else s2
         n_fin = final.count()
