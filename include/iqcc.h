@@ -86,26 +86,55 @@ const char *iqcc_version(void);
  *   "fuse_energy"        1: dressing evaluates the energy of its output in the
  *                        same pass when angles are given; 0: separate pass
  *   "dis_tile"           DIS candidates held per workgroup tile (1 .. 256)
+ *   "dis_bucket_ranges"  bucket ranges (workgroups along the terms) of the
+ *                        batched DIS launch; 0 = about 8 workgroups per CU
+ *                        in total (0 .. 4096)
  * Returns IQCC_ERR_INVALID_ARG for an unknown name or out-of-range value. */
 int iqcc_set_param(iqcc_ctx *ctx, const char *name, int64_t value);
 int iqcc_get_param(const iqcc_ctx *ctx, const char *name, int64_t *value);
 
 /* ---- term stores ---------------------------------------------------------- */
 
+/* Store flags.  IQCC_STORE_INPLACE: the arena has two halves, so the store can
+ * be dressed in place (iqcc_dress_inplace): one half holds the live terms
+ * with free rows after each bucket, the other receives a fresh layout when a
+ * step doubles the bucket count or a bucket outgrows its free rows.  Device
+ * memory about 10*max_terms*(16*W + 8) bytes instead of 2*max_terms*(16*W+8). */
+#define IQCC_STORE_INPLACE 1u
+
 /* Create an empty store for `n_qubits` (1..256) qubits able to hold up to
  * `max_terms` terms as the output of a dressing step (the device arena holds
  * 2*max_terms rows because a step reserves, per bucket pair, the worst-case
  * output size 2*(n_b + n_b')).  Device memory: about
- * 2*max_terms*(16*W + 8) bytes plus the bucket table. */
+ * 2*max_terms*(16*W + 8) bytes plus the bucket table, allocated by the
+ * library (synchronising). */
 int iqcc_store_create(iqcc_ctx *ctx, int n_qubits, int64_t max_terms, iqcc_store **store);
+/* As iqcc_store_create with store flags (0 or IQCC_STORE_INPLACE). */
+int iqcc_store_create_ex(iqcc_ctx *ctx, int n_qubits, int64_t max_terms, uint32_t flags,
+                         iqcc_store **store);
+/* HOST only: *bytes = device memory a store of these parameters needs
+ * (header, bucket table and arena in one block).  IQCC_ERR_INVALID_ARG for
+ * n_qubits < 1, max_terms outside 1..2^38 or unknown flags. */
+int iqcc_store_bytes(int n_qubits, int64_t max_terms, uint32_t flags, int64_t *bytes);
+/* Create a store inside caller-owned DEVICE memory `mem` of `bytes` bytes
+ * (256-byte aligned, at least iqcc_store_bytes; e.g. a torch tensor).  The
+ * library never frees it; destroy the store before releasing the memory.
+ * The empty-store initialisation is enqueued on `stream` (no synchronisation).
+ * IQCC_ERR_CAPACITY if `bytes` is too small. */
+int iqcc_store_wrap(iqcc_ctx *ctx, int n_qubits, int64_t max_terms, uint32_t flags, void *mem,
+                    int64_t bytes, iqcc_store **store, void *stream);
+/* Destroy a store (NULL is allowed); frees its memory only when the library
+ * allocated it (iqcc_store_create*). */
 int iqcc_store_destroy(iqcc_ctx *ctx, iqcc_store *store);
 /* Number of qubits / words of a store. */
 int iqcc_store_shape(const iqcc_store *store, int *n_qubits, int *n_words);
 
 /* Replace the contents of `store` with n rows of device arrays x, z (word
- * planes, leading dimension ld >= n) and c.  Keys must be unique (not checked
- * unless the IQCC_DEBUG_VALIDATE environment variable is set, which adds a
- * synchronising check).  Chooses the bucket count from "load_bucket_terms". */
+ * planes, leading dimension ld >= n) and c.  Keys must be unique and bits at
+ * qubits >= n_qubits zero; this is not checked unless the IQCC_DEBUG_VALIDATE
+ * environment variable is set, which adds a synchronising host-side check of
+ * both (IQCC_ERR_INVALID_ARG, store unchanged, on a duplicate key or a set
+ * padding bit).  Chooses the bucket count from "load_bucket_terms". */
 int iqcc_store_load(iqcc_ctx *ctx, iqcc_store *store, const uint64_t *x, const uint64_t *z,
                     const double *c, int64_t n, int64_t ld, void *stream);
 
@@ -165,6 +194,21 @@ int iqcc_dress_energy_update(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t
                              const uint64_t *pz, double tau, double eps, const double *theta,
                              const double *phi, const double *energy_in, double *energy_out,
                              iqcc_store *out, void *stream);
+
+/* Synchronising sizing call for a dressing step of `in` by P (HOST words px,
+ * pz; Eq. 5): *n_anti = number of terms of `in` that anticommute with P.
+ * The raw output of the step (before the merge D = H + I of App. D) has
+ * count + n_anti rows, and the merged output at most that many. */
+int iqcc_dress_count(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px, const uint64_t *pz,
+                     int64_t *n_anti, void *stream);
+
+/* Pauli products P1 P2 = i^e P3 of n pairs of words (DEVICE word planes with
+ * leading dimension ld >= n, n_qubits qubits): x3 = x1 ^ x2, z3 = z1 ^ z2 and
+ * e[i] in 0..3 (DEVICE int8) with the Hermitian-Y encoding.  Exported for
+ * tests of the phase rule that dressing and DIS gradients use (Eqs. 5, 7). */
+int iqcc_pauli_products(iqcc_ctx *ctx, int n_qubits, const uint64_t *x1, const uint64_t *z1,
+                        const uint64_t *x2, const uint64_t *z2, int64_t n, int64_t ld,
+                        uint64_t *x3, uint64_t *z3, int8_t *e, void *stream);
 
 /* Raw dressing (no merge, no compression) of flat device rows: for each input
  * row i (in order) emits row 2i = (A, c or RN(cos*c)) and, for anticommuting
@@ -241,6 +285,29 @@ int iqcc_dress_backward(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px,
                         const uint64_t *pz, double tau, const int32_t *tape_self,
                         const int32_t *tape_partner, const double *lambda_out,
                         double *lambda_in, double *dtau, void *stream);
+
+/* The whole taped chain of Eq. 6 in one call: outs[j] = step j applied to
+ * outs[j-1] (outs[-1] = h0) with entangler j (HOST px, pz [n_steps][n_words]),
+ * amplitude taus[j] (HOST) and compression eps, recording the tapes of
+ * iqcc_dress_taped in tape_self[j], tape_partner[j] (DEVICE int32 arrays of
+ * iqcc_store_rows of the step's input).  outs: n_steps distinct stores, none
+ * equal to h0, each large enough for its step.  Asynchronous. */
+int iqcc_chain_forward(iqcc_ctx *ctx, const iqcc_store *h0, int n_steps, const uint64_t *px,
+                       const uint64_t *pz, const double *taus, double eps,
+                       iqcc_store *const *outs, int32_t *const *tape_self,
+                       int32_t *const *tape_partner, void *stream);
+
+/* Reverse sweep of iqcc_chain_forward (same h0, entanglers, taus, outs and
+ * tapes; compression decisions held fixed).  lambda_final: DEVICE dE/dc per
+ * row of outs[n_steps-1]; dtau: DEVICE [n_steps] receives dE/dtau_j;
+ * lambda_h0 (DEVICE, iqcc_store_rows(h0) entries, or NULL) receives dE/dc per
+ * row of h0; work0, work1: DEVICE buffers of at least the largest
+ * iqcc_store_rows among h0 and outs.  Asynchronous. */
+int iqcc_chain_backward(iqcc_ctx *ctx, const iqcc_store *h0, int n_steps, const uint64_t *px,
+                        const uint64_t *pz, const double *taus, iqcc_store *const *outs,
+                        int32_t *const *tape_self, int32_t *const *tape_partner,
+                        const double *lambda_final, double *work0, double *work1,
+                        double *lambda_h0, double *dtau, void *stream);
 
 /* out[r] = scale * <Omega| P_r |Omega> for every live row r of the store
  * (DEVICE array of iqcc_store_rows entries; scale a DEVICE scalar or NULL = 1):
@@ -370,7 +437,8 @@ int iqcc_energy_trig_poly(iqcc_ctx *ctx, const iqcc_store *h, int n, const uint6
                           const uint64_t *pz, const double *theta, const double *phi,
                           iqcc_store *const *work, double *coef);
 
-/* HOST only: value of that polynomial at tau[0..n). */
+/* HOST only: value of that polynomial at tau[0..n) (NaN for n outside 1..8 or
+ * a null array). */
 double iqcc_trig_poly_eval(int n, const double *coef, const double *tau);
 
 /* HOST only: coordinate descent on the polynomial; each coordinate update is

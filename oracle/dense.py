@@ -173,3 +173,37 @@ def random_pauli_sum(nq, n_terms, rng, even_y=False):
 
 def pauli_keys_small(nq):
     return list(itertools.product(range(1 << nq), repeat=2))
+
+
+def pauli_basis(nq):
+    """All 4^n Pauli matrices with their keys (x, z) as ints, n <= 5."""
+    keys, mats = [], []
+    for x, z in all_pauli_keys(nq):
+        keys.append((int(x[0]), int(z[0])))
+        mats.append(pauli_matrix(nq, x, z))
+    return keys, np.array(mats)
+
+
+def masked_chain_energy(nq, H, ents, taus, eps, psi, masks=None):
+    """Energy of the dressing chain in dense arithmetic with compression.
+
+    After each conjugation M <- U^dagger M U the Pauli components
+    c_Q = Re tr(Q M) / 2^n with |c_Q| < eps are removed (strict, as the
+    compression step of the iterative procedure).  With `masks` given (one
+    boolean array over the 4^n basis per step) those kept/removed decisions are
+    used instead of being taken from the coefficients, which defines the
+    derivative with the compression decisions frozen.  Returns (E, masks,
+    kept-key sets per step)."""
+    dim = 1 << nq
+    keys, B = pauli_basis(nq)
+    M = H
+    used, kept = [], []
+    for j, ((px, pz), t) in enumerate(zip(ents, taus)):
+        M = dress_matrix(nq, M, px, pz, t)
+        coef = np.real(np.einsum("kab,ba->k", B, M)) / dim
+        mask = (np.abs(coef) >= eps) if masks is None else masks[j]
+        coef = np.where(mask, coef, 0.0)
+        M = np.einsum("k,kab->ab", coef, B)
+        used.append(mask)
+        kept.append({keys[i] for i in np.flatnonzero(mask & (coef != 0.0))})
+    return energy(M, psi), used, kept

@@ -76,7 +76,8 @@ class DressingChain:
             lam_in = torch.empty(iqcc.iqcc_store_rows(src.handle), dtype=torch.float64, device="cuda")
             px, pz = self.ents[j]
             iqcc.iqcc_dress_backward(self.ctx.handle, src.handle, px, pz, float(taus[j]),
-                                     self.tapes[j][0], self.tapes[j][1], lam, lam_in, dtau[j:j + 1])
+                                     self.tapes[j][0], self.tapes[j][1], lam, lam_in, dtau[j:j + 1],
+                                     store_out=self.stores[j].handle)
             lam = lam_in
         return dtau
 

@@ -29,6 +29,7 @@ struct iqcc_ctx {
   int64_t energy_grid_per_cu = 16;         // stand-alone energy kernel
   int64_t fuse_energy = 1;
   int64_t dis_tile = 256;
+  int64_t dis_bucket_ranges = 0;           // 0: about 8 workgroups per CU in total
   // device scratch
   double* lut = nullptr;        // kMaxWords * 22 * 64
   double* partial = nullptr;    // n_partial
@@ -51,8 +52,11 @@ struct iqcc_batch {
 struct iqcc_store {
   int nq = 0, W = 0;
   int64_t max_terms = 0;
+  uint32_t flags = 0;
   StoreDev d{};
-  void* block = nullptr;  // one allocation for counters
+  void* mem = nullptr;    // the store's device memory (header, bucket table, arena)
+  bool owned = false;     // true: allocated by iqcc_store_create*, freed by destroy
+  double floor = 0.0;     // every live |c| is >= floor (0: unknown)
 };
 
 namespace {
@@ -126,6 +130,48 @@ bool padding_clear(int nq, int W, const uint64_t* x, const uint64_t* z) {
   return true;
 }
 
+// Debug check of rows about to be loaded (synchronising, host side): no bit
+// set at a qubit >= nq, and no key twice.
+int validate_rows(iqcc_ctx* ctx, int nq, int W, const uint64_t* x, const uint64_t* z, int64_t n,
+                  int64_t ld, hipStream_t s) {
+  if (n <= 0) return IQCC_OK;
+  std::vector<uint64_t> hx((size_t)W * n), hz((size_t)W * n);
+  for (int w = 0; w < W; ++w) {
+    HIP_TRY(ctx, hipMemcpyAsync(hx.data() + (size_t)w * n, x + (size_t)w * ld, 8 * (size_t)n,
+                                hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipMemcpyAsync(hz.data() + (size_t)w * n, z + (size_t)w * ld, 8 * (size_t)n,
+                                hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  std::vector<int64_t> order(n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t kx[kMaxWords], kz[kMaxWords];
+    for (int w = 0; w < W; ++w) {
+      kx[w] = hx[(size_t)w * n + i];
+      kz[w] = hz[(size_t)w * n + i];
+    }
+    if (!padding_clear(nq, W, kx, kz))
+      return fail(ctx, IQCC_ERR_INVALID_ARG, "row %lld has a bit beyond n_qubits", (long long)i);
+    order[i] = i;
+  }
+  auto word = [&](int64_t r, int q) {   // x words, then z words
+    return q < W ? hx[(size_t)q * n + r] : hz[(size_t)(q - W) * n + r];
+  };
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    for (int q = 0; q < 2 * W; ++q)
+      if (word(a, q) != word(b, q)) return word(a, q) < word(b, q);
+    return false;
+  });
+  for (int64_t i = 1; i < n; ++i) {
+    bool same = true;
+    for (int q = 0; q < 2 * W && same; ++q) same = word(order[i - 1], q) == word(order[i], q);
+    if (same)
+      return fail(ctx, IQCC_ERR_INVALID_ARG, "rows %lld and %lld have the same key",
+                  (long long)order[i - 1], (long long)order[i]);
+  }
+  return IQCC_OK;
+}
+
 int check_ctx(iqcc_ctx* ctx) {
   if (!ctx) return IQCC_ERR_INVALID_ARG;
   ctx->err.clear();
@@ -171,6 +217,125 @@ int ilog2_ceil(int64_t v) {
   int m = 0;
   while ((1ll << m) < v) ++m;
   return m;
+}
+
+}  // namespace
+
+namespace {
+
+// Device memory of a store, one block: a 256-byte header of device scalars,
+// the bucket table (off, cnt, lim) and the arena planes x[W][cap], z[W][cap],
+// c[cap]; every array starts on a 256-byte boundary.
+struct StoreLayout {
+  int W = 0, mcap = 0, nhalves = 1;
+  int64_t half_rows = 0, cap = 0;
+  size_t off = 0, cnt = 0, lim = 0, x = 0, z = 0, c = 0, bytes = 0;
+};
+
+constexpr size_t kHeaderBytes = 256;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool store_layout(int n_qubits, int64_t max_terms, uint32_t flags, StoreLayout& L) {
+  if (n_qubits < 1 || n_qubits > 64 * kMaxWords) return false;
+  if (max_terms < 1 || max_terms > (1ll << 38)) return false;
+  if (flags & ~(uint32_t)IQCC_STORE_INPLACE) return false;
+  L.W = (n_qubits + 63) / 64;
+  L.mcap = ilog2_ceil(max_terms / 16 + 1) + 1;
+  if (L.mcap > kMaxBucketBits) L.mcap = kMaxBucketBits;
+  if (flags & IQCC_STORE_INPLACE) {
+    // two halves: a relayout of up to max_terms input terms reserves at most
+    // 4 * max_terms rows (worst case with 2x slack), the rest of the live half
+    // is the pool for buckets that outgrow their region
+    L.nhalves = 2;
+    L.half_rows = 5 * max_terms + 1024;
+  } else {
+    L.nhalves = 1;
+    L.half_rows = 2 * max_terms + 1024;
+  }
+  L.cap = L.nhalves * L.half_rows;
+  const size_t B = (size_t)1 << L.mcap;
+  size_t o = kHeaderBytes;
+  L.off = o; o = align256(o + 8 * B);
+  L.cnt = o; o = align256(o + 8 * B);
+  L.lim = o; o = align256(o + 8 * B);
+  L.x = o; o = align256(o + 8 * (size_t)L.W * L.cap);
+  L.z = o; o = align256(o + 8 * (size_t)L.W * L.cap);
+  L.c = o; o = align256(o + 8 * (size_t)L.cap);
+  L.bytes = o;
+  return true;
+}
+
+iqcc_store* store_from_memory(int n_qubits, int64_t max_terms, uint32_t flags, const StoreLayout& L,
+                              void* mem, bool owned) {
+  iqcc_store* st = new iqcc_store();
+  st->nq = n_qubits;
+  st->W = L.W;
+  st->max_terms = max_terms;
+  st->flags = flags;
+  st->mem = mem;
+  st->owned = owned;
+  char* b = (char*)mem;
+  st->d.total = (int64_t*)(b + 0);
+  st->d.top = (int64_t*)(b + 8);
+  st->d.m = (int*)(b + 16);
+  st->d.err = (int*)(b + 20);
+  st->d.stats = (int64_t*)(b + 24);
+  st->d.half = (int*)(b + 40);
+  st->d.off = (int64_t*)(b + L.off);
+  st->d.cnt = (int64_t*)(b + L.cnt);
+  st->d.lim = (int64_t*)(b + L.lim);
+  st->d.x = (uint64_t*)(b + L.x);
+  st->d.z = (uint64_t*)(b + L.z);
+  st->d.c = (double*)(b + L.c);
+  st->d.cap = L.cap;
+  st->d.half_rows = L.half_rows;
+  st->d.nhalves = L.nhalves;
+  st->d.mcap = L.mcap;
+  return st;
+}
+
+// An empty store: every scalar 0 and bucket 0 (the only bucket at m = 0) empty.
+hipError_t store_clear(iqcc_store* st, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(st->mem, 0, kHeaderBytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(st->d.off, 0, 8, s);
+  if (e == hipSuccess) e = hipMemsetAsync(st->d.cnt, 0, 8, s);
+  if (e == hipSuccess) e = hipMemsetAsync(st->d.lim, 0, 8, s);
+  return e;
+}
+
+int store_open(iqcc_ctx* ctx, int n_qubits, int64_t max_terms, uint32_t flags, void* mem,
+               int64_t bytes, iqcc_store** out, hipStream_t s) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!out) return fail(ctx, IQCC_ERR_INVALID_ARG, "store output pointer is null");
+  *out = nullptr;
+  if (n_qubits > 64 * kMaxWords) return fail(ctx, IQCC_ERR_UNSUPPORTED, "more than 256 qubits");
+  StoreLayout L;
+  if (!store_layout(n_qubits, max_terms, flags, L))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad n_qubits, max_terms or flags");
+  bool owned = false;
+  if (!mem) {
+    hipError_t e = hipMalloc(&mem, L.bytes);
+    if (e != hipSuccess)
+      return fail(ctx, IQCC_ERR_HIP, "store allocation (%lld rows, %zu bytes) failed: %s",
+                  (long long)L.cap, L.bytes, hipGetErrorString(e));
+    owned = true;
+  } else {
+    if (bytes < (int64_t)L.bytes)
+      return fail(ctx, IQCC_ERR_CAPACITY, "store needs %zu bytes, got %lld", L.bytes, (long long)bytes);
+    if (((uintptr_t)mem & 255) != 0) return fail(ctx, IQCC_ERR_INVALID_ARG, "store memory is not 256-byte aligned");
+  }
+  iqcc_store* st = store_from_memory(n_qubits, max_terms, flags, L, mem, owned);
+  hipError_t e = store_clear(st, s);
+  if (e == hipSuccess && owned) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    if (owned) hipFree(mem);
+    delete st;
+    return fail(ctx, IQCC_ERR_HIP, "store initialisation failed: %s", hipGetErrorString(e));
+  }
+  *out = st;
+  return IQCC_OK;
 }
 
 }  // namespace
@@ -234,6 +399,7 @@ int iqcc_set_param(iqcc_ctx* ctx, const char* name, int64_t v) {
       {"energy_grid_per_cu", &ctx->energy_grid_per_cu, 1, 32},
       {"fuse_energy", &ctx->fuse_energy, 0, 1},
       {"dis_tile", &ctx->dis_tile, 1, 256},
+      {"dis_bucket_ranges", &ctx->dis_bucket_ranges, 0, 4096},
   };
   for (auto& t : tab) {
     if (std::strcmp(t.n, name) == 0) {
@@ -254,6 +420,7 @@ int iqcc_get_param(const iqcc_ctx* ctx, const char* name, int64_t* v) {
       {"batch_anti_cap", ctx->batch_anti_cap},
       {"energy_grid_per_cu", ctx->energy_grid_per_cu},
       {"fuse_energy", ctx->fuse_energy}, {"dis_tile", ctx->dis_tile},
+      {"dis_bucket_ranges", ctx->dis_bucket_ranges},
       {"n_cu", ctx->n_cu},
   };
   for (auto& t : tab)
@@ -263,60 +430,37 @@ int iqcc_get_param(const iqcc_ctx* ctx, const char* name, int64_t* v) {
 
 // ---- stores -----------------------------------------------------------------
 
-int iqcc_store_create(iqcc_ctx* ctx, int n_qubits, int64_t max_terms, iqcc_store** out) {
-  int rc = check_ctx(ctx);
-  if (rc) return rc;
-  if (!out) return fail(ctx, IQCC_ERR_INVALID_ARG, "store output pointer is null");
-  *out = nullptr;
-  if (n_qubits < 1) return fail(ctx, IQCC_ERR_INVALID_ARG, "n_qubits must be >= 1");
-  if (n_qubits > 64 * kMaxWords) return fail(ctx, IQCC_ERR_UNSUPPORTED, "more than 256 qubits");
-  if (max_terms < 1 || max_terms > (1ll << 40)) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad max_terms");
-  iqcc_store* st = new iqcc_store();
-  st->nq = n_qubits;
-  st->W = (n_qubits + 63) / 64;
-  st->max_terms = max_terms;
-  int64_t cap = 2 * max_terms + 1024;
-  int mcap = ilog2_ceil(max_terms / 16 + 1) + 1;
-  if (mcap > kMaxBucketBits) mcap = kMaxBucketBits;
-  st->d.cap = cap;
-  st->d.mcap = mcap;
-  const int64_t B = 1ll << mcap;
-  hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = hipMalloc(&st->d.x, sizeof(uint64_t) * st->W * cap);
-  if (e == hipSuccess) e = hipMalloc(&st->d.z, sizeof(uint64_t) * st->W * cap);
-  if (e == hipSuccess) e = hipMalloc(&st->d.c, sizeof(double) * cap);
-  if (e == hipSuccess) e = hipMalloc(&st->d.off, sizeof(int64_t) * B);
-  if (e == hipSuccess) e = hipMalloc(&st->d.cnt, sizeof(int64_t) * B);
-  if (e == hipSuccess) e = hipMalloc(&st->block, 64);
-  if (e != hipSuccess) {
-    iqcc_store_destroy(ctx, st);
-    return fail(ctx, IQCC_ERR_HIP, "store allocation (%lld rows) failed: %s", (long long)cap,
-                hipGetErrorString(e));
-  }
-  char* blk = (char*)st->block;
-  st->d.total = (int64_t*)(blk + 0);
-  st->d.top = (int64_t*)(blk + 8);
-  st->d.m = (int*)(blk + 16);
-  st->d.err = (int*)(blk + 20);
-  st->d.stats = (int64_t*)(blk + 24);
-  hipMemset(st->block, 0, 64);
-  hipMemset(st->d.off, 0, sizeof(int64_t) * B);
-  hipMemset(st->d.cnt, 0, sizeof(int64_t) * B);
-  hipDeviceSynchronize();
-  *out = st;
+int iqcc_store_bytes(int n_qubits, int64_t max_terms, uint32_t flags, int64_t* bytes) {
+  if (!bytes) return IQCC_ERR_INVALID_ARG;
+  if (n_qubits > 64 * kMaxWords) return IQCC_ERR_UNSUPPORTED;
+  StoreLayout L;
+  if (!store_layout(n_qubits, max_terms, flags, L)) return IQCC_ERR_INVALID_ARG;
+  *bytes = (int64_t)L.bytes;
   return IQCC_OK;
+}
+
+int iqcc_store_create(iqcc_ctx* ctx, int n_qubits, int64_t max_terms, iqcc_store** out) {
+  return store_open(ctx, n_qubits, max_terms, 0u, nullptr, 0, out, nullptr);
+}
+
+int iqcc_store_create_ex(iqcc_ctx* ctx, int n_qubits, int64_t max_terms, uint32_t flags,
+                         iqcc_store** out) {
+  return store_open(ctx, n_qubits, max_terms, flags, nullptr, 0, out, nullptr);
+}
+
+int iqcc_store_wrap(iqcc_ctx* ctx, int n_qubits, int64_t max_terms, uint32_t flags, void* mem,
+                    int64_t bytes, iqcc_store** out, void* stream) {
+  if (ctx && !mem) return fail(ctx, IQCC_ERR_INVALID_ARG, "store memory is null");
+  return store_open(ctx, n_qubits, max_terms, flags, mem, bytes, out, as_stream(stream));
 }
 
 int iqcc_store_destroy(iqcc_ctx* ctx, iqcc_store* st) {
   if (!st) return IQCC_OK;
   if (ctx) hipSetDevice(ctx->device);
-  hipDeviceSynchronize();
-  if (st->d.x) hipFree(st->d.x);
-  if (st->d.z) hipFree(st->d.z);
-  if (st->d.c) hipFree(st->d.c);
-  if (st->d.off) hipFree(st->d.off);
-  if (st->d.cnt) hipFree(st->d.cnt);
-  if (st->block) hipFree(st->block);
+  if (st->owned) {
+    hipDeviceSynchronize();
+    hipFree(st->mem);
+  }
   delete st;
   return IQCC_OK;
 }
@@ -339,15 +483,16 @@ int iqcc_store_load(iqcc_ctx* ctx, iqcc_store* st, const uint64_t* x, const uint
   int m = 0;
   while (m < st->d.mcap && (n >> m) > ctx->load_bucket_terms) ++m;
   const int64_t B = 1ll << m;
+  hipStream_t s = as_stream(stream);
+  if (getenv("IQCC_DEBUG_VALIDATE")) {
+    rc = validate_rows(ctx, st->nq, st->W, x, z, n, ld, s);
+    if (rc) return rc;
+  }
   rc = ensure_scratch(ctx, B + B / 1024 + 16);
   if (rc) return rc;
-  hipStream_t s = as_stream(stream);
+  st->floor = 0.0;
   launch_store_load(st->W, st->d, x, z, c, n, ld, m, ctx->scratch, s);
   LAUNCH_CHECK(ctx);
-  if (getenv("IQCC_DEBUG_VALIDATE")) {
-    // unique keys: export and compare neighbours on the host (debug only)
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-  }
   return IQCC_OK;
 }
 
@@ -357,7 +502,7 @@ int iqcc_store_count(iqcc_ctx* ctx, const iqcc_store* st, int64_t* n, void* stre
   if (!st || !n) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
   char buf[64];
   hipStream_t s = as_stream(stream);
-  HIP_TRY(ctx, hipMemcpyAsync(buf, st->block, 64, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(buf, st->mem, 64, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
   int64_t total;
   int err;
@@ -377,7 +522,7 @@ int iqcc_store_stats(iqcc_ctx* ctx, const iqcc_store* st, int64_t* n_anti, int64
   if (!st || !n_anti || !n_new) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
   char buf[64];
   hipStream_t s = as_stream(stream);
-  HIP_TRY(ctx, hipMemcpyAsync(buf, st->block, 64, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(buf, st->mem, 64, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
   std::memcpy(n_anti, buf + 24, 8);
   std::memcpy(n_new, buf + 32, 8);
@@ -402,7 +547,7 @@ int iqcc_store_export(iqcc_ctx* ctx, const iqcc_store* st, uint64_t* x, uint64_t
   if (!st || !n) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
   char buf[64];
   hipStream_t s = as_stream(stream);
-  HIP_TRY(ctx, hipMemcpyAsync(buf, st->block, 64, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipMemcpyAsync(buf, st->mem, 64, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
   int64_t total;
   int m, err;
@@ -477,6 +622,7 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
   launch_zero_counters(out->d, s);
   launch_dress(W, in->d, out->d, P, cfg, s);
   LAUNCH_CHECK(ctx);
+  out->floor = eps;
   if (want_e) {
     if (!fused) launch_energy(W, out->d, grid, ctx->lut, ctx->partial, s);
     launch_finalize_sum(ctx->partial, grid, nullptr, energy, s, delta ? energy_in : nullptr);
@@ -535,6 +681,91 @@ int iqcc_dress_backward(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px,
                         lambda_out, lambda_in, ctx->partial, grid, s);
   launch_finalize_sum(ctx->partial, grid, nullptr, dtau, s);
   LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+int iqcc_dress_count(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, const uint64_t* pz,
+                     int64_t* n_anti, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!in || !px || !pz || !n_anti) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  if (!padding_clear(in->nq, in->W, px, pz))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
+  hipStream_t s = as_stream(stream);
+  rc = ensure_scratch(ctx, 1);
+  if (rc) return rc;
+  HIP_TRY(ctx, hipMemsetAsync(ctx->scratch, 0, 8, s));
+  launch_count_anti(in->W, in->d, make_entangler(in->W, px, pz), (unsigned long long*)ctx->scratch,
+                    (int)(ctx->n_cu * 4), s);
+  LAUNCH_CHECK(ctx);
+  int64_t v = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&v, ctx->scratch, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  *n_anti = v;
+  return IQCC_OK;
+}
+
+int iqcc_pauli_products(iqcc_ctx* ctx, int nq, const uint64_t* x1, const uint64_t* z1,
+                        const uint64_t* x2, const uint64_t* z2, int64_t n, int64_t ld, uint64_t* x3,
+                        uint64_t* z3, int8_t* e, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (nq < 1 || nq > 64 * kMaxWords) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad n_qubits");
+  if (n < 0 || ld < n) return fail(ctx, IQCC_ERR_INVALID_ARG, "bad sizes");
+  if (n > 0 && (!x1 || !z1 || !x2 || !z2 || !x3 || !z3 || !e))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  launch_pauli_products((nq + 63) / 64, x1, z1, x2, z2, n, ld, x3, z3, e, as_stream(stream));
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+int iqcc_chain_forward(iqcc_ctx* ctx, const iqcc_store* h0, int n_steps, const uint64_t* px,
+                       const uint64_t* pz, const double* taus, double eps, iqcc_store* const* outs,
+                       int32_t* const* tape_self, int32_t* const* tape_partner, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h0 || n_steps < 0 || (n_steps > 0 && (!px || !pz || !taus || !outs || !tape_self || !tape_partner)))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad chain arguments");
+  for (int j = 0; j < n_steps; ++j) {
+    if (!outs[j] || outs[j] == h0 || !tape_self[j] || !tape_partner[j])
+      return fail(ctx, IQCC_ERR_INVALID_ARG, "chain step %d: null or aliased store/tape", j);
+    for (int k = 0; k < j; ++k)
+      if (outs[k] == outs[j]) return fail(ctx, IQCC_ERR_INVALID_ARG, "chain steps %d and %d share a store", k, j);
+  }
+  const int W = h0->W;
+  const iqcc_store* src = h0;
+  for (int j = 0; j < n_steps; ++j) {
+    rc = iqcc_dress_taped(ctx, src, px + (size_t)j * W, pz + (size_t)j * W, taus[j], eps, outs[j],
+                          tape_self[j], tape_partner[j], stream);
+    if (rc) return rc;
+    src = outs[j];
+  }
+  return IQCC_OK;
+}
+
+int iqcc_chain_backward(iqcc_ctx* ctx, const iqcc_store* h0, int n_steps, const uint64_t* px,
+                        const uint64_t* pz, const double* taus, iqcc_store* const* outs,
+                        int32_t* const* tape_self, int32_t* const* tape_partner,
+                        const double* lambda_final, double* work0, double* work1, double* lambda_h0,
+                        double* dtau, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h0 || n_steps < 0 ||
+      (n_steps > 0 && (!px || !pz || !taus || !outs || !tape_self || !tape_partner || !lambda_final ||
+                       !work0 || !work1 || !dtau)))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "bad chain arguments");
+  const int W = h0->W;
+  const double* lam_out = lambda_final;
+  for (int j = n_steps - 1; j >= 0; --j) {
+    if (!outs[j] || !tape_self[j] || !tape_partner[j])
+      return fail(ctx, IQCC_ERR_INVALID_ARG, "chain step %d: null store/tape", j);
+    const iqcc_store* src = j ? outs[j - 1] : h0;
+    double* lam_in = (j == 0 && lambda_h0) ? lambda_h0 : ((n_steps - 1 - j) % 2 ? work1 : work0);
+    rc = iqcc_dress_backward(ctx, src, px + (size_t)j * W, pz + (size_t)j * W, taus[j],
+                             tape_self[j], tape_partner[j], lam_out, lam_in, dtau + j, stream);
+    if (rc) return rc;
+    lam_out = lam_in;
+  }
   return IQCC_OK;
 }
 
@@ -758,8 +989,9 @@ int iqcc_dis_gradients(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, 
   launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
   if (mode == IQCC_DIS_BATCHED) {
     // candidate tiles x bucket ranges: about 8 workgroups per CU in total
-    const int64_t tiles = (n_cand + dis_tile() - 1) / dis_tile();
-    int64_t gt = (ctx->n_cu * 8 + tiles - 1) / tiles;
+    // unless "dis_bucket_ranges" fixes the number of ranges
+    const int64_t tiles = (n_cand + ctx->dis_tile - 1) / ctx->dis_tile;
+    int64_t gt = ctx->dis_bucket_ranges ? ctx->dis_bucket_ranges : (ctx->n_cu * 8 + tiles - 1) / tiles;
     if (gt < 1) gt = 1;
     if (gt > 4096) gt = 4096;
     const int64_t n_part = (gt * n_cand + 1) & ~int64_t(1);   // tables start 16-byte aligned
@@ -1201,6 +1433,7 @@ int iqcc_energy_trig_poly(iqcc_ctx* ctx, const iqcc_store* h, int n, const uint6
 }
 
 double iqcc_trig_poly_eval(int n, const double* coef, const double* tau) {
+  if (n < 1 || n > 8 || !coef || !tau) return std::nan("");
   const int64_t npts = (int64_t)std::pow(3.0, n);
   double e = 0.0;
   for (int64_t s = 0; s < npts; ++s) {

@@ -260,15 +260,27 @@ struct StoreDev {
   uint64_t* z;       // [W][cap]
   double* c;         // [cap]
   int64_t cap;       // arena rows (= leading dimension)
-  int64_t* off;      // [2^mcap]
-  int64_t* cnt;      // [2^mcap]
+  int64_t* off;      // [2^mcap] first row of each bucket
+  int64_t* cnt;      // [2^mcap] live rows of each bucket
+  int64_t* lim;      // [2^mcap] growth region of each bucket (see bucket_room)
   int* m;            // device scalar: bucket bits
   int64_t* total;    // device scalar: live terms
   int64_t* top;      // device scalar: arena rows reserved
   int* err;          // device scalar: 1 = arena overflow, 2 = bucket table overflow
   int64_t* stats;    // device [2]: anticommuting input terms, new terms of the last step
+  int* half;         // device scalar: arena half that holds the live rows (in-place stores)
+  int64_t half_rows; // rows per half (= cap for a store without the in-place layout)
   int mcap;          // bucket table holds 2^mcap buckets
+  int nhalves;       // 1, or 2 for a store that can be dressed in place
 };
+
+// Growth region of a bucket whose live rows are [off, off + cnt):
+//   lim >= 0: the bucket grows upward; its region ends at row lim;
+//   lim <  0: it grows downward; its region starts at row ~lim (= -lim - 1).
+// Rows of the region outside the live rows belong to no other bucket.
+__host__ __device__ __forceinline__ int64_t bucket_room(int64_t off, int64_t cnt, int64_t lim) {
+  return lim >= 0 ? lim - off - cnt : off - ~lim;
+}
 
 struct Entangler {
   uint64_t px[kMaxWords];
@@ -307,7 +319,9 @@ struct DressConfig {
   int delta;           // 1: e_partial accumulates only the change of the energy
   double* e_partial;   // [grid]
   int32_t* tape_self;     // null, or per input arena row: output row of K (-1 dropped)
-  int32_t* tape_partner;  //   and output row of K^P (-1 absent/dropped, -2 commuting)
+  int32_t* tape_partner;  //   and -1 for a commuting row; for an anticommuting row
+                          //   2 * (output row of K^P + 1) + [s_K = +1], where the
+                          //   output row is -1 when K^P is absent or dropped
 };
 void launch_dress(int W, const StoreDev& in, const StoreDev& out, const Entangler& P,
                   const DressConfig& cfg, hipStream_t s);
@@ -329,6 +343,11 @@ void set_dress_batch_attributes(int W, int anti_cap);
 void launch_dress_batch(int W, int n_ham, const BatchItem* items, BatchPlan* plan,
                         const DressConfig& cfg, int64_t* queue, hipStream_t s);
 size_t dress_lds_bytes(int W, int anti_cap, bool energy, bool tape);
+void launch_count_anti(int W, const StoreDev& st, const Entangler& P, unsigned long long* out,
+                       int grid, hipStream_t s);
+void launch_pauli_products(int W, const uint64_t* x1, const uint64_t* z1, const uint64_t* x2,
+                           const uint64_t* z2, int64_t n, int64_t ld, uint64_t* x3, uint64_t* z3,
+                           int8_t* e, hipStream_t s);
 void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double* c, int64_t n,
                       int64_t ld, const Entangler& P, double C, double S, uint64_t* ox,
                       uint64_t* oz, double* oc, int8_t* flag, int64_t ld_out, hipStream_t s);

@@ -117,6 +117,7 @@ __global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt
                                                        const uint64_t* __restrict__ cx,
                                                        const uint64_t* __restrict__ cz,
                                                        int64_t n_cand, int64_t ld_cand,
+                                                       int tile_size,
                                                        double* __restrict__ partial) {
   constexpr int R = kDisR;
   constexpr int NQ = 64 * W;
@@ -131,8 +132,8 @@ __global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt
   for (int i = threadIdx.x; i < NQ * 4; i += kDisB) fac[i] = fac_g[i];
   for (int i = threadIdx.x; i < kDisWaves * kDisTile; i += kDisB) (&acc[0][0])[i] = 0.0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t a0 = (int64_t)blockIdx.x * kDisTile;
-  const int tile = (int)((n_cand - a0) < kDisTile ? (n_cand - a0) : kDisTile);
+  const int64_t a0 = (int64_t)blockIdx.x * tile_size;   // tile_size <= kDisTile
+  const int tile = (int)((n_cand - a0) < tile_size ? (n_cand - a0) : tile_size);
   const int64_t B = 1ll << *st.m;
   const int64_t b_lo = B * blockIdx.y / gridDim.y, b_hi = B * (blockIdx.y + 1) / gridDim.y;
   const char* ent_base = reinterpret_cast<const char*>(ent);
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(kDisB) void k_dis_batched(StoreDev st, const DisEnt
 
 int64_t dis_tables_doubles(int W) { return 64 * W * 16 * 2 + 64 * W * 4; }
 
-int64_t dis_tile() { return kDisTile; }
+int64_t dis_tile() { return kDisTile; }   // the largest tile the batched kernel holds
 
 __global__ void k_dis_reduce(const double* partial, int rows, int64_t n_cand, double* g) {
   for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n_cand;
@@ -263,11 +264,14 @@ __global__ void k_dis_reduce(const double* partial, int rows, int64_t n_cand, do
   }
 }
 
+// Plain form: one candidate per launch.  Each wave streams whole buckets
+// (64 consecutive rows per load, four loads in flight per lane), so short
+// buckets keep every lane busy.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* lut_g,
                                                     const uint64_t* cx, const uint64_t* cz,
                                                     int64_t ld_cand, int64_t a, double* partial) {
-  constexpr int R = 4;   // terms per thread per load round
+  constexpr int R = 4;   // rows per lane per round
   __shared__ double lut[W * kGroupsPerWord * kLutEntries];
   __shared__ double red[kWaves];
   for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
@@ -278,26 +282,29 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
     pz[w] = cz[w * ld_cand + a];
   }
   __syncthreads();
+  const int lane = threadIdx.x & 63;
   const int64_t B = 1ll << *st.m;
+  const int64_t waves = (int64_t)gridDim.x * kWaves;
   double acc = 0.0;
-  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+  for (int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); b < B; b += waves) {
     const int64_t n = st.cnt[b], off = st.off[b];
-    for (int64_t i0 = 0; i0 < n; i0 += kBlock * R) {
+    for (int64_t i0 = 0; i0 < n; i0 += 64 * R) {
       uint64_t kx[R][W], kz[R][W];
-      bool ok[R];
+      double kc[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int64_t i = i0 + r * kBlock + threadIdx.x;
-        ok[r] = i < n;
+        const int64_t i = i0 + r * 64 + lane;
+        const bool ok = i < n;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          kx[r][w] = ok[r] ? st.x[w * st.cap + off + i] : 0;
-          kz[r][w] = ok[r] ? st.z[w * st.cap + off + i] : 0;
+          kx[r][w] = ok ? st.x[w * st.cap + off + i] : 0;
+          kz[r][w] = ok ? st.z[w * st.cap + off + i] : 0;
         }
+        kc[r] = ok ? st.c[off + i] : 0.0;
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (ok[r] && anticommutes<W>(kx[r], kz[r], px, pz)) {
+        if (anticommutes<W>(kx[r], kz[r], px, pz)) {   // padding rows (key 0) commute
           const int e = product_phase<W>(kx[r], kz[r], px, pz);
           uint64_t qx[W], qz[W];
 #pragma unroll
@@ -305,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
             qx[w] = kx[r][w] ^ px[w];
             qz[w] = kz[r][w] ^ pz[w];
           }
-          const double v = st.c[off + i0 + r * kBlock + threadIdx.x] * expect_lut<W>(lut, qx, qz);
+          const double v = kc[r] * expect_lut<W>(lut, qx, qz);
           acc += (e == 1) ? v : -v;
         }
       }
@@ -319,20 +326,20 @@ void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx
                 const uint64_t* cz, int64_t n_cand, int64_t ld_cand, int mode, int tile,
                 int grid, double* partial, int grid_terms, double* g, hipStream_t s,
                 const double* theta, const double* phi, int nq, double* tables) {
-  (void)tile;
   if (n_cand <= 0) return;
+  if (tile < 1 || tile > kDisTile) tile = kDisTile;
   if (mode == 0) {
     DisEnt* ent = reinterpret_cast<DisEnt*>(tables);
     double* fac = tables + dis_tables_doubles(W) - 64 * W * 4;
     hipLaunchKernelGGL(k_dis_tables, dim3((64 * W + 255) / 256), dim3(256), 0, s, W, nq, theta, phi,
                        ent, fac);
-    const int64_t tiles = (n_cand + kDisTile - 1) / kDisTile;
+    const int64_t tiles = (n_cand + tile - 1) / tile;
     dim3 gr((unsigned)tiles, (unsigned)grid_terms);
     switch (W) {
-      case 1: hipLaunchKernelGGL(k_dis_batched<1>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, partial); break;
-      case 2: hipLaunchKernelGGL(k_dis_batched<2>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, partial); break;
-      case 3: hipLaunchKernelGGL(k_dis_batched<3>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, partial); break;
-      default: hipLaunchKernelGGL(k_dis_batched<4>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, partial); break;
+      case 1: hipLaunchKernelGGL(k_dis_batched<1>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, tile, partial); break;
+      case 2: hipLaunchKernelGGL(k_dis_batched<2>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, tile, partial); break;
+      case 3: hipLaunchKernelGGL(k_dis_batched<3>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, tile, partial); break;
+      default: hipLaunchKernelGGL(k_dis_batched<4>, gr, dim3(kDisB), 0, s, st, ent, fac, cx, cz, n_cand, ld_cand, tile, partial); break;
     }
     int64_t blocks = (n_cand + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_dis_reduce, dim3((unsigned)blocks), dim3(kBlock), 0, s, partial, grid_terms, n_cand, g);

@@ -635,13 +635,26 @@ __device__ void process_pair(const StoreDev& in, const StoreDev& out, const Enta
     for (int s = 0; s < nside; ++s) {
       const uint32_t b = s ? ps.b1 : ps.b0;
       const unsigned long long word = sm.ctr[s];
-      for (int ch = 0; ch < 1 + split; ++ch) {
-        const uint32_t ob = b + ((uint32_t)ch << m);
-        const int64_t k = bad ? 0 : (int64_t)(uint32_t)(ch ? word >> 32 : word);
-        out.cnt[ob] = k;
-        out.off[ob] = ps.row(2 * s + ch, k - 1) - (ch ? 0 : k - 1);
-        produced += k;
+      const int64_t reg = bad ? 0 : (s ? ps.reg1 : ps.reg0);
+      const int64_t bound = bad ? 0 : (s ? ps.bound1 : ps.bound0);
+      const int64_t k0 = bad ? 0 : (int64_t)(uint32_t)word;
+      const int64_t k1 = (bad || !split) ? 0 : (int64_t)(uint32_t)(word >> 32);
+      // child 0 fills the side's region from the front and grows upward;
+      // child 1 fills it from the back and grows downward; the gap between
+      // them is shared half and half
+      out.cnt[b] = k0;
+      out.off[b] = reg;
+      if (split) {
+        const int64_t mid = reg + k0 + (bound - k0 - k1) / 2;
+        const uint32_t ob = b + (1u << m);
+        out.lim[b] = mid;
+        out.cnt[ob] = k1;
+        out.off[ob] = reg + bound - k1;
+        out.lim[ob] = ~mid;
+      } else {
+        out.lim[b] = reg + bound;
       }
+      produced += k0 + k1;
     }
     counts.produced += produced;
     counts.anti += pair_anti;
@@ -887,6 +900,81 @@ void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double*
     case 2: hipLaunchKernelGGL(k_dress_raw<2>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, P, C, S, ox, oz, oc, flag, ld_out); break;
     case 3: hipLaunchKernelGGL(k_dress_raw<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, P, C, S, ox, oz, oc, flag, ld_out); break;
     default: hipLaunchKernelGGL(k_dress_raw<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, P, C, S, ox, oz, oc, flag, ld_out); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sizing count: terms of the store that anticommute with P (one integer
+// atomic per workgroup, so the count is exact and order-independent).
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_count_anti(StoreDev st, Entangler P,
+                                                       unsigned long long* out) {
+  __shared__ uint64_t tmp[kWaves];
+  const int64_t B = 1ll << *st.m;
+  uint64_t mine = 0;
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = st.cnt[b], off = st.off[b];
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      uint64_t kx[W], kz[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        kx[w] = st.x[w * st.cap + off + i];
+        kz[w] = st.z[w * st.cap + off + i];
+      }
+      mine += anticommutes<W>(kx, kz, P.px, P.pz) ? 1u : 0u;
+    }
+  }
+  uint64_t total;
+  block_exclusive_scan(mine, tmp, total);
+  if (threadIdx.x == 0 && total) atomicAdd(out, (unsigned long long)total);
+}
+
+void launch_count_anti(int W, const StoreDev& st, const Entangler& P, unsigned long long* out,
+                       int grid, hipStream_t s) {
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_count_anti<1>, dim3(grid), dim3(kBlock), 0, s, st, P, out); break;
+    case 2: hipLaunchKernelGGL(k_count_anti<2>, dim3(grid), dim3(kBlock), 0, s, st, P, out); break;
+    case 3: hipLaunchKernelGGL(k_count_anti<3>, dim3(grid), dim3(kBlock), 0, s, st, P, out); break;
+    default: hipLaunchKernelGGL(k_count_anti<4>, dim3(grid), dim3(kBlock), 0, s, st, P, out); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P1 P2 = i^e P3 for n pairs of words (the phase rule of product_phase).
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void k_pauli_products(const uint64_t* x1, const uint64_t* z1, const uint64_t* x2,
+                                 const uint64_t* z2, int64_t n, int64_t ld, uint64_t* x3,
+                                 uint64_t* z3, int8_t* e) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t ax[W], az[W], bx[W], bz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      ax[w] = x1[w * ld + i]; az[w] = z1[w * ld + i];
+      bx[w] = x2[w * ld + i]; bz[w] = z2[w * ld + i];
+    }
+    e[i] = (int8_t)product_phase<W>(ax, az, bx, bz);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      x3[w * ld + i] = ax[w] ^ bx[w];
+      z3[w * ld + i] = az[w] ^ bz[w];
+    }
+  }
+}
+
+void launch_pauli_products(int W, const uint64_t* x1, const uint64_t* z1, const uint64_t* x2,
+                           const uint64_t* z2, int64_t n, int64_t ld, uint64_t* x3, uint64_t* z3,
+                           int8_t* e, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  switch (W) {
+    case 1: hipLaunchKernelGGL(k_pauli_products<1>, dim3(blocks), dim3(kBlock), 0, s, x1, z1, x2, z2, n, ld, x3, z3, e); break;
+    case 2: hipLaunchKernelGGL(k_pauli_products<2>, dim3(blocks), dim3(kBlock), 0, s, x1, z1, x2, z2, n, ld, x3, z3, e); break;
+    case 3: hipLaunchKernelGGL(k_pauli_products<3>, dim3(blocks), dim3(kBlock), 0, s, x1, z1, x2, z2, n, ld, x3, z3, e); break;
+    default: hipLaunchKernelGGL(k_pauli_products<4>, dim3(blocks), dim3(kBlock), 0, s, x1, z1, x2, z2, n, ld, x3, z3, e); break;
   }
 }
 

@@ -167,6 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_buckets(Staging<W> st, const i
     if (threadIdx.x == 0) {
       out.off[b] = base;
       out.cnt[b] = written;
+      out.lim[b] = base + n;   // the rows reserved for the bucket's input
       if (written) atomicAdd((unsigned long long*)out.total, (unsigned long long)written);
     }
     __syncthreads();

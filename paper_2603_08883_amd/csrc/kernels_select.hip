@@ -279,6 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_select_compact(StoreDev in, StoreDev
     if (threadIdx.x == 0) {
       out.off[b] = off;
       out.cnt[b] = w;
+      out.lim[b] = off + n;   // the input bucket's rows
     }
     kept += w;
   }

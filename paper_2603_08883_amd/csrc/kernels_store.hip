@@ -8,6 +8,7 @@ namespace iqcc {
 
 __global__ void k_zero_counters(StoreDev st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *st.half = 0;
     *st.total = 0;
     *st.top = 0;
     *st.err = 0;
@@ -141,8 +142,16 @@ __global__ void k_load_scatter(const uint64_t* __restrict__ x, const uint64_t* _
   }
 }
 
+// Loaded buckets are packed: each bucket's region is exactly its rows.
+__global__ void k_set_packed_lim(StoreDev st, int64_t B) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < B;
+       b += (int64_t)gridDim.x * blockDim.x)
+    st.lim[b] = st.off[b] + st.cnt[b];
+}
+
 __global__ void k_load_finish(StoreDev st, int m, int64_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *st.half = 0;
     *st.m = m;
     *st.total = n;
     *st.top = n;
@@ -179,6 +188,11 @@ int launch_store_load(int W, StoreDev st, const uint64_t* x, const uint64_t* z, 
       case 3: hipLaunchKernelGGL(k_load_scatter<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
       default: hipLaunchKernelGGL(k_load_scatter<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
     }
+  }
+  {
+    int64_t lb = (B + kBlock - 1) / kBlock;
+    if (lb > 4096) lb = 4096;
+    hipLaunchKernelGGL(k_set_packed_lim, dim3((unsigned)lb), dim3(kBlock), 0, s, st, B);
   }
   hipLaunchKernelGGL(k_load_finish, dim3(1), dim3(64), 0, s, st, m, n);
   return 0;

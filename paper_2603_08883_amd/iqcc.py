@@ -27,6 +27,7 @@ IQCC_ERR_HIP = -3
 IQCC_ERR_UNSUPPORTED = -4
 IQCC_DIS_BATCHED = 0
 IQCC_DIS_PLAIN = 1
+IQCC_STORE_INPLACE = 1
 
 _lib = None
 
@@ -58,6 +59,13 @@ def lib():
         "iqcc_set_param": (i32, [P, ct.c_char_p, i64]),
         "iqcc_get_param": (i32, [P, ct.c_char_p, ct.POINTER(i64)]),
         "iqcc_store_create": (i32, [P, i32, i64, ct.POINTER(P)]),
+        "iqcc_store_create_ex": (i32, [P, i32, i64, ct.c_uint32, ct.POINTER(P)]),
+        "iqcc_store_bytes": (i32, [i32, i64, ct.c_uint32, ct.POINTER(i64)]),
+        "iqcc_store_wrap": (i32, [P, i32, i64, ct.c_uint32, P, i64, ct.POINTER(P), P]),
+        "iqcc_dress_count": (i32, [P, P, P, P, ct.POINTER(i64), P]),
+        "iqcc_pauli_products": (i32, [P, i32, P, P, P, P, i64, i64, P, P, P, P]),
+        "iqcc_chain_forward": (i32, [P, P, i32, P, P, P, d, P, P, P, P]),
+        "iqcc_chain_backward": (i32, [P, P, i32, P, P, P, P, P, P, P, P, P, P, P, P]),
         "iqcc_store_destroy": (i32, [P, P]),
         "iqcc_store_shape": (i32, [P, ct.POINTER(i32), ct.POINTER(i32)]),
         "iqcc_store_load": (i32, [P, P, P, P, P, i64, i64, P]),
@@ -103,6 +111,8 @@ def exported_symbols():
     return [
         "iqcc_version", "iqcc_last_error", "iqcc_ctx_create", "iqcc_ctx_destroy",
         "iqcc_set_param", "iqcc_get_param", "iqcc_store_create", "iqcc_store_destroy",
+        "iqcc_store_create_ex", "iqcc_store_bytes", "iqcc_store_wrap", "iqcc_dress_count",
+        "iqcc_pauli_products", "iqcc_chain_forward", "iqcc_chain_backward",
         "iqcc_store_shape", "iqcc_store_load", "iqcc_store_count", "iqcc_store_export",
         "iqcc_store_stats", "iqcc_store_lookup",
         "iqcc_dress", "iqcc_dress_energy_update", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
@@ -132,10 +142,64 @@ def _ptr(t):
     return ct.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _words(a):
-    """uint64 numpy words of a host Pauli key (W,) for the entangler argument."""
+def _bad(msg):
+    raise IqccError(IQCC_ERR_INVALID_ARG, msg)
+
+
+def _dev(t, name, dtype, min_numel=1, optional=False):
+    """Device pointer of a contiguous CUDA tensor of `dtype` with at least
+    min_numel elements (None passes through when optional)."""
+    import torch
+    if t is None:
+        if optional:
+            return None
+        _bad(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        _bad(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        _bad(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        _bad(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        _bad(f"{name} must be contiguous")
+    if t.numel() < min_numel:
+        _bad(f"{name} needs at least {min_numel} elements, has {t.numel()}")
+    return ct.c_void_p(t.data_ptr())
+
+
+def _f64(t, name, min_numel=1, optional=False):
+    import torch
+    return _dev(t, name, torch.float64, min_numel, optional)
+
+
+def _planes(t, name, W):
+    """(W, n) int64 word planes on the GPU, each plane contiguous: (pointer, n, ld)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or not t.is_cuda:
+        _bad(f"{name} must be an int64 GPU tensor of shape (W, n)")
+    if t.dim() != 2 or t.shape[0] != W:
+        _bad(f"{name} must have shape ({W}, n), got {tuple(t.shape)}")
+    if t.shape[1] > 0 and (t.stride(1) != 1 or t.stride(0) < t.shape[1]):
+        _bad(f"{name} planes must be contiguous rows")
+    ld = int(t.stride(0)) if t.shape[1] > 0 else 1
+    return ct.c_void_p(t.data_ptr()), int(t.shape[1]), ld
+
+
+def _words(a, W=None):
+    """uint64 numpy words of a host Pauli key (exactly W words) for the entangler argument."""
     a = np.ascontiguousarray(np.asarray(a, dtype=np.uint64).reshape(-1))
+    if W is not None and a.size != W:
+        _bad(f"a Pauli key of this store has {W} words, got {a.size}")
     return a, a.ctypes.data_as(ct.c_void_p)
+
+
+def _nq(store):
+    return iqcc_store_shape(store)
+
+
+def _angles(store, theta, phi, optional=False):
+    nq, _ = _nq(store)
+    return (_f64(theta, "theta", nq, optional), _f64(phi, "phi", nq, optional))
 
 
 # ---------------------------------------------------------------------------
@@ -168,9 +232,27 @@ def iqcc_get_param(ctx, name: str) -> int:
     return v.value
 
 
-def iqcc_store_create(ctx, n_qubits: int, max_terms: int):
+def iqcc_store_create(ctx, n_qubits: int, max_terms: int, flags: int = 0):
     h = ct.c_void_p()
-    _check(lib().iqcc_store_create(ctx, int(n_qubits), int(max_terms), ct.byref(h)), ctx)
+    _check(lib().iqcc_store_create_ex(ctx, int(n_qubits), int(max_terms), int(flags), ct.byref(h)), ctx)
+    return h
+
+
+def iqcc_store_bytes(n_qubits: int, max_terms: int, flags: int = 0) -> int:
+    b = ct.c_int64()
+    rc = lib().iqcc_store_bytes(int(n_qubits), int(max_terms), int(flags), ct.byref(b))
+    if rc != IQCC_OK:
+        raise IqccError(rc, "invalid store parameters")
+    return b.value
+
+
+def iqcc_store_wrap(ctx, n_qubits: int, max_terms: int, flags: int, mem, stream=None):
+    """Store inside caller-owned device memory `mem` (a uint8 CUDA tensor)."""
+    import torch
+    p = _dev(mem, "mem", torch.uint8, 1)
+    h = ct.c_void_p()
+    _check(lib().iqcc_store_wrap(ctx, int(n_qubits), int(max_terms), int(flags), p, int(mem.numel()),
+                                 ct.byref(h), _stream(stream)), ctx)
     return h
 
 
@@ -186,9 +268,15 @@ def iqcc_store_shape(store):
 
 def iqcc_store_load(ctx, store, x, z, c, stream=None):
     """x, z: int64 (W, n) device tensors; c: float64 (n,) device tensor."""
-    n = int(c.numel())
-    ld = int(x.shape[1]) if x.dim() == 2 else n
-    _check(lib().iqcc_store_load(ctx, store, _ptr(x), _ptr(z), _ptr(c), n, ld, _stream(stream)), ctx)
+    _, W = _nq(store)
+    px, n, ld = _planes(x, "x", W)
+    pz, nz, ldz = _planes(z, "z", W)
+    if nz != n or ldz != ld:
+        _bad("x and z must have the same shape and layout")
+    pc = _f64(c, "c", n, optional=(n == 0))
+    if c is not None and c.numel() != n:
+        _bad("c must have one coefficient per row")
+    _check(lib().iqcc_store_load(ctx, store, px, pz, pc, n, ld, _stream(stream)), ctx)
 
 
 def iqcc_store_count(ctx, store, stream=None) -> int:
@@ -207,10 +295,14 @@ def iqcc_store_stats(ctx, store, stream=None):
 def iqcc_store_lookup(ctx, store, qx, qz, stream=None):
     """qx, qz: int64 (W, n) device tensors -> (found bool, value float64) device tensors."""
     import torch
-    n = int(qx.shape[1])
+    _, W = _nq(store)
+    px, n, ld = _planes(qx, "qx", W)
+    pz, nz, ldz = _planes(qz, "qz", W)
+    if nz != n or ldz != ld:
+        _bad("qx and qz must have the same shape and layout")
     found = torch.empty((max(n, 1),), dtype=torch.int8, device="cuda")
     val = torch.empty((max(n, 1),), dtype=torch.float64, device="cuda")
-    _check(lib().iqcc_store_lookup(ctx, store, _ptr(qx), _ptr(qz), n, max(n, 1), _ptr(found), _ptr(val),
+    _check(lib().iqcc_store_lookup(ctx, store, px, pz, n, ld, _ptr(found), _ptr(val),
                                    _stream(stream)), ctx)
     return found[:n].bool(), val[:n]
 
@@ -233,27 +325,69 @@ def iqcc_store_export(ctx, store, stream=None):
 def iqcc_dress(ctx, store_in, px, pz, tau: float, eps: float, store_out, theta=None, phi=None,
                energy=None, stream=None):
     """One fused dressing step (store_in -> store_out); px, pz host uint64 words."""
-    ax, pxp = _words(px)
-    az, pzp = _words(pz)
-    _check(lib().iqcc_dress(ctx, store_in, pxp, pzp, float(tau), float(eps), _ptr(theta),
-                            _ptr(phi), _ptr(energy), store_out, _stream(stream)), ctx)
+    _, W = _nq(store_in)
+    ax, pxp = _words(px, W)
+    az, pzp = _words(pz, W)
+    opt = theta is None and phi is None and energy is None
+    th, ph = _angles(store_in, theta, phi, optional=opt)
+    pe = _f64(energy, "energy", 1, optional=opt)
+    _check(lib().iqcc_dress(ctx, store_in, pxp, pzp, float(tau), float(eps), th, ph, pe, store_out,
+                            _stream(stream)), ctx)
 
 
 def iqcc_dress_energy_update(ctx, store_in, px, pz, tau: float, eps: float, store_out, theta, phi,
                              energy_in, energy_out, stream=None):
     """Dressing step with the energy carried forward: energy_out = <out> given energy_in = <in>."""
-    ax, pxp = _words(px)
-    az, pzp = _words(pz)
-    _check(lib().iqcc_dress_energy_update(ctx, store_in, pxp, pzp, float(tau), float(eps),
-                                          _ptr(theta), _ptr(phi), _ptr(energy_in),
-                                          _ptr(energy_out), store_out, _stream(stream)), ctx)
+    _, W = _nq(store_in)
+    ax, pxp = _words(px, W)
+    az, pzp = _words(pz, W)
+    th, ph = _angles(store_in, theta, phi)
+    _check(lib().iqcc_dress_energy_update(ctx, store_in, pxp, pzp, float(tau), float(eps), th, ph,
+                                          _f64(energy_in, "energy_in"),
+                                          _f64(energy_out, "energy_out"), store_out,
+                                          _stream(stream)), ctx)
+
+
+def iqcc_dress_count(ctx, store_in, px, pz, stream=None) -> int:
+    """Synchronising: number of terms of store_in that anticommute with P."""
+    _, W = _nq(store_in)
+    ax, pxp = _words(px, W)
+    az, pzp = _words(pz, W)
+    n = ct.c_int64()
+    _check(lib().iqcc_dress_count(ctx, store_in, pxp, pzp, ct.byref(n), _stream(stream)), ctx)
+    return n.value
+
+
+def iqcc_pauli_products(ctx, n_qubits, x1, z1, x2, z2, stream=None):
+    """(x3, z3, e) device tensors with P1 P2 = i^e P3 row by row."""
+    import torch
+    W = (int(n_qubits) + 63) // 64
+    a, n, ld = _planes(x1, "x1", W)
+    args = [a]
+    for t, nm in ((z1, "z1"), (x2, "x2"), (z2, "z2")):
+        p_, n_, ld_ = _planes(t, nm, W)
+        if n_ != n or ld_ != ld:
+            _bad("all operand planes must have the same shape and layout")
+        args.append(p_)
+    x3 = torch.empty((W, max(ld, 1)), dtype=torch.int64, device="cuda")
+    z3 = torch.empty_like(x3)
+    e = torch.empty((max(n, 1),), dtype=torch.int8, device="cuda")
+    _check(lib().iqcc_pauli_products(ctx, int(n_qubits), *args, n, ld, _ptr(x3), _ptr(z3), _ptr(e),
+                                     _stream(stream)), ctx)
+    return x3[:, :n], z3[:, :n], e[:n]
 
 
 def iqcc_dress_raw(ctx, n_qubits, x, z, c, px, pz, tau, stream=None):
     """Raw dressing of flat rows; returns (ox, oz, oc, flag) device tensors."""
     import torch
-    n = int(c.numel())
-    W = int(x.shape[0])
+    W = (int(n_qubits) + 63) // 64
+    _, n, ld = _planes(x, "x", W)
+    _, nz, ldz = _planes(z, "z", W)
+    if nz != n or ldz != ld or ld != max(n, 1) or c.numel() != n:
+        _bad("x, z must be (W, n) contiguous planes and c (n,)")
+    _f64(c, "c", n, optional=(n == 0))
+    px, _ = _words(px, W)
+    pz, _ = _words(pz, W)
     ox = torch.empty((W, max(2 * n, 1)), dtype=torch.int64, device="cuda")
     oz = torch.empty_like(ox)
     oc = torch.empty((max(2 * n, 1),), dtype=torch.float64, device="cuda")
@@ -267,36 +401,49 @@ def iqcc_dress_raw(ctx, n_qubits, x, z, c, px, pz, tau, stream=None):
 
 
 def iqcc_merge_truncate(ctx, x, z, c, eps, store_out, stream=None):
-    n = int(c.numel())
-    _check(lib().iqcc_merge_truncate(ctx, _ptr(x), _ptr(z), _ptr(c), n, int(x.shape[1]), float(eps),
-                                     store_out, _stream(stream)), ctx)
+    _, W = _nq(store_out)
+    px, n, ld = _planes(x, "x", W)
+    pz, nz, ldz = _planes(z, "z", W)
+    if nz != n or ldz != ld or c.numel() != n:
+        _bad("x, z must be (W, n) planes with one coefficient per row")
+    _check(lib().iqcc_merge_truncate(ctx, px, pz, _f64(c, "c", n, optional=(n == 0)), n, ld,
+                                     float(eps), store_out, _stream(stream)), ctx)
 
 
 def iqcc_qmf_energy(ctx, store, theta, phi, energy=None, stream=None):
     import torch
     if energy is None:
         energy = torch.empty((), dtype=torch.float64, device="cuda")
-    _check(lib().iqcc_qmf_energy(ctx, store, _ptr(theta), _ptr(phi), _ptr(energy), _stream(stream)), ctx)
+    th, ph = _angles(store, theta, phi)
+    _check(lib().iqcc_qmf_energy(ctx, store, th, ph, _f64(energy, "energy"), _stream(stream)), ctx)
     return energy
 
 
 def iqcc_qmf_energy_backward(ctx, store, theta, phi, dE=None, lam=None, stream=None):
     """dE/dtheta, dE/dphi (scaled by dE); `lam`, if given, receives dE * <P_r> per row."""
     import torch
+    th, ph = _angles(store, theta, phi)
+    pdE = _f64(dE, "dE", 1, optional=True)
+    plam = _f64(lam, "lambda", iqcc_store_rows(store), optional=True)
     dtheta = torch.empty_like(theta)
     dphi = torch.empty_like(phi)
-    _check(lib().iqcc_qmf_energy_backward(ctx, store, _ptr(theta), _ptr(phi), _ptr(dE), _ptr(dtheta),
-                                          _ptr(dphi), _ptr(lam), _stream(stream)), ctx)
+    _check(lib().iqcc_qmf_energy_backward(ctx, store, th, ph, pdE, _ptr(dtheta), _ptr(dphi), plam,
+                                          _stream(stream)), ctx)
     return dtheta, dphi
 
 
 def iqcc_dis_gradients(ctx, store, theta, phi, cx, cz, mode=IQCC_DIS_BATCHED, stream=None):
     """cx, cz: int64 (W, n_cand) device tensors; returns g (n_cand,) float64."""
     import torch
-    n_cand = int(cx.shape[1])
+    _, W = _nq(store)
+    pcx, n_cand, ld = _planes(cx, "cx", W)
+    pcz, nz, ldz = _planes(cz, "cz", W)
+    if nz != n_cand or ldz != ld:
+        _bad("cx and cz must have the same shape and layout")
+    th, ph = _angles(store, theta, phi)
     g = torch.empty((max(n_cand, 1),), dtype=torch.float64, device="cuda")
-    _check(lib().iqcc_dis_gradients(ctx, store, _ptr(theta), _ptr(phi), _ptr(cx), _ptr(cz), n_cand,
-                                    n_cand, int(mode), _ptr(g), _stream(stream)), ctx)
+    _check(lib().iqcc_dis_gradients(ctx, store, th, ph, pcx, pcz, n_cand, ld, int(mode), _ptr(g),
+                                    _stream(stream)), ctx)
     return g[:n_cand]
 
 
@@ -319,35 +466,104 @@ def _check_tape(store_in, *tapes):
 def iqcc_dress_taped(ctx, store_in, px, pz, tau, eps, store_out, tape_self, tape_partner,
                      stream=None):
     _check_tape(store_in, tape_self, tape_partner)
-    ax, pxp = _words(px)
-    az, pzp = _words(pz)
+    _, W = _nq(store_in)
+    ax, pxp = _words(px, W)
+    az, pzp = _words(pz, W)
     _check(lib().iqcc_dress_taped(ctx, store_in, pxp, pzp, float(tau), float(eps), store_out,
                                   _ptr(tape_self), _ptr(tape_partner), _stream(stream)), ctx)
 
 
 def iqcc_dress_backward(ctx, store_in, px, pz, tau, tape_self, tape_partner, lambda_out,
-                        lambda_in, dtau, stream=None):
+                        lambda_in, dtau, stream=None, store_out=None):
+    """One reverse step; lambda_out has one entry per arena row of the step's
+    output store (checked when store_out is given), lambda_in one per row of
+    store_in."""
     _check_tape(store_in, tape_self, tape_partner)
-    ax, pxp = _words(px)
-    az, pzp = _words(pz)
+    _, W = _nq(store_in)
+    ax, pxp = _words(px, W)
+    az, pzp = _words(pz, W)
+    rows_out = iqcc_store_rows(store_out) if store_out is not None else 1
     _check(lib().iqcc_dress_backward(ctx, store_in, pxp, pzp, float(tau), _ptr(tape_self),
-                                     _ptr(tape_partner), _ptr(lambda_out), _ptr(lambda_in),
-                                     _ptr(dtau), _stream(stream)), ctx)
+                                     _ptr(tape_partner), _f64(lambda_out, "lambda_out", rows_out),
+                                     _f64(lambda_in, "lambda_in", iqcc_store_rows(store_in)),
+                                     _f64(dtau, "dtau"), _stream(stream)), ctx)
+
+
+def iqcc_chain_forward(ctx, h0, pxs, pzs, taus, eps, outs, tapes_self, tapes_partner, stream=None):
+    """Taped chain in one call: outs[j] (store handles) = step j; tapes per step."""
+    n = len(outs)
+    _, W = _nq(h0)
+    px = np.ascontiguousarray(np.asarray(pxs, np.uint64).reshape(n, -1))
+    pz = np.ascontiguousarray(np.asarray(pzs, np.uint64).reshape(n, -1))
+    if n and (px.shape[1] != W or pz.shape[1] != W):
+        _bad(f"entanglers must have {W} words")
+    tt = np.ascontiguousarray(np.asarray(taus, np.float64).reshape(-1))
+    if tt.size != n or len(tapes_self) != n or len(tapes_partner) != n:
+        _bad("one tau and one pair of tapes per step")
+    src = h0
+    for j in range(n):
+        _check_tape(src, tapes_self[j], tapes_partner[j])
+        src = outs[j]
+    a_out = (ct.c_void_p * max(n, 1))(*[o.value if hasattr(o, "value") else o for o in outs])
+    a_ts = (ct.c_void_p * max(n, 1))(*[t.data_ptr() for t in tapes_self])
+    a_tp = (ct.c_void_p * max(n, 1))(*[t.data_ptr() for t in tapes_partner])
+    _check(lib().iqcc_chain_forward(ctx, h0, n, px.ctypes.data_as(ct.c_void_p),
+                                    pz.ctypes.data_as(ct.c_void_p), tt.ctypes.data_as(ct.c_void_p),
+                                    float(eps), a_out, a_ts, a_tp, _stream(stream)), ctx)
+
+
+def iqcc_chain_backward(ctx, h0, pxs, pzs, taus, outs, tapes_self, tapes_partner, lambda_final,
+                        lambda_h0=None, stream=None):
+    """Reverse sweep of iqcc_chain_forward; returns dE/dtau (device, n_steps)."""
+    import torch
+    n = len(outs)
+    _, W = _nq(h0)
+    px = np.ascontiguousarray(np.asarray(pxs, np.uint64).reshape(n, -1))
+    pz = np.ascontiguousarray(np.asarray(pzs, np.uint64).reshape(n, -1))
+    tt = np.ascontiguousarray(np.asarray(taus, np.float64).reshape(-1))
+    if tt.size != n or len(tapes_self) != n or len(tapes_partner) != n:
+        _bad("one tau and one pair of tapes per step")
+    rows = max([iqcc_store_rows(h0)] + [iqcc_store_rows(o) for o in outs])
+    src = h0
+    for j in range(n):
+        _check_tape(src, tapes_self[j], tapes_partner[j])
+        src = outs[j]
+    plf = _f64(lambda_final, "lambda_final", iqcc_store_rows(outs[-1]) if n else 1)
+    ph0 = _f64(lambda_h0, "lambda_h0", iqcc_store_rows(h0), optional=True)
+    w0 = torch.empty(rows, dtype=torch.float64, device="cuda")
+    w1 = torch.empty(rows, dtype=torch.float64, device="cuda")
+    dtau = torch.zeros(max(n, 1), dtype=torch.float64, device="cuda")
+    a_out = (ct.c_void_p * max(n, 1))(*[o.value if hasattr(o, "value") else o for o in outs])
+    a_ts = (ct.c_void_p * max(n, 1))(*[t.data_ptr() for t in tapes_self])
+    a_tp = (ct.c_void_p * max(n, 1))(*[t.data_ptr() for t in tapes_partner])
+    _check(lib().iqcc_chain_backward(ctx, h0, n, px.ctypes.data_as(ct.c_void_p),
+                                     pz.ctypes.data_as(ct.c_void_p), tt.ctypes.data_as(ct.c_void_p),
+                                     a_out, a_ts, a_tp, plf, _ptr(w0), _ptr(w1), ph0, _ptr(dtau),
+                                     _stream(stream)), ctx)
+    return dtau[:n]
 
 
 def iqcc_expectations(ctx, store, theta, phi, out, scale=None, stream=None):
-    _check(lib().iqcc_expectations(ctx, store, _ptr(theta), _ptr(phi), _ptr(scale), _ptr(out),
-                                   _stream(stream)), ctx)
+    th, ph = _angles(store, theta, phi)
+    _check(lib().iqcc_expectations(ctx, store, th, ph, _f64(scale, "scale", 1, optional=True),
+                                   _f64(out, "out", iqcc_store_rows(store)), _stream(stream)), ctx)
     return out
 
 
 def _batch_args(ins, outs, pxs, pzs, taus):
     n = len(ins)
+    if n < 1 or len(outs) != n:
+        _bad("a batch needs one output store per input store")
+    W = _nq(ins[0])[1]
     a_in = (ct.c_void_p * n)(*[s.value if hasattr(s, "value") else s for s in ins])
     a_out = (ct.c_void_p * n)(*[s.value if hasattr(s, "value") else s for s in outs])
     px = np.ascontiguousarray(np.asarray(pxs, dtype=np.uint64).reshape(n, -1))
     pz = np.ascontiguousarray(np.asarray(pzs, dtype=np.uint64).reshape(n, -1))
-    tt = np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
+    if px.shape[1] != W or pz.shape[1] != W:
+        _bad(f"batch entanglers must have {W} words each")
+    tt = np.ascontiguousarray(np.asarray(taus, dtype=np.float64).reshape(-1))
+    if tt.size != n:
+        _bad("one tau per Hamiltonian")
     return n, a_in, a_out, px, pz, tt
 
 
@@ -415,9 +631,11 @@ def iqcc_qmf_energy_anti(ctx, store, px, pz, theta, phi, out=None, stream=None):
     import torch
     if out is None:
         out = torch.empty((), dtype=torch.float64, device="cuda")
-    ax, pxp = _words(px)
-    az, pzp = _words(pz)
-    _check(lib().iqcc_qmf_energy_anti(ctx, store, pxp, pzp, _ptr(theta), _ptr(phi), _ptr(out),
+    _, W = _nq(store)
+    ax, pxp = _words(px, W)
+    az, pzp = _words(pz, W)
+    th, ph = _angles(store, theta, phi)
+    _check(lib().iqcc_qmf_energy_anti(ctx, store, pxp, pzp, th, ph, _f64(out, "out"),
                                       _stream(stream)), ctx)
     return out
 
@@ -426,16 +644,20 @@ def iqcc_sortless_dress(ctx, n_qubits, x, z, c, px, pz, tau, eps, cap=None, stre
     """Sortless dressing of a canonically sorted flat Hamiltonian (device planes
     x, z of shape (W, n) int64, c (n,) float64); returns (ox, oz, oc) trimmed."""
     import torch
-    n = int(c.numel())
-    W = int(x.shape[0])
+    W = (int(n_qubits) + 63) // 64
+    _, n, ld = _planes(x, "x", W)
+    _, nz, ldz = _planes(z, "z", W)
+    if nz != n or ldz != ld or c.numel() != n:
+        _bad("x, z must be (W, n) planes with one coefficient per row")
+    _f64(c, "c", n, optional=(n == 0))
     cap = int(cap if cap is not None else max(2 * n, 1))
     ox = torch.empty((W, cap), dtype=torch.int64, device="cuda")
     oz = torch.empty((W, cap), dtype=torch.int64, device="cuda")
     oc = torch.empty((cap,), dtype=torch.float64, device="cuda")
-    ax, pxp = _words(px)
-    az, pzp = _words(pz)
+    ax, pxp = _words(px, W)
+    az, pzp = _words(pz, W)
     nout = ct.c_int64()
-    _check(lib().iqcc_sortless_dress(ctx, int(n_qubits), _ptr(x), _ptr(z), _ptr(c), n, int(x.stride(0)) if n else 0,
+    _check(lib().iqcc_sortless_dress(ctx, int(n_qubits), _ptr(x), _ptr(z), _ptr(c), n, ld if n else 0,
                                      pxp, pzp, float(tau), float(eps), _ptr(ox), _ptr(oz), _ptr(oc), cap, cap,
                                      ct.byref(nout), _stream(stream)), ctx)
     k = nout.value
@@ -444,7 +666,12 @@ def iqcc_sortless_dress(ctx, n_qubits, x, z, c, px, pz, tau, eps, cap=None, stre
 
 def iqcc_energy_trig_poly(ctx, store, pxs, pzs, theta, phi, work):
     """3^n coefficients of E(tau_1..tau_n); pxs, pzs (n, W) host words, work: n Stores."""
-    pxs = np.ascontiguousarray(pxs, np.uint64); pzs = np.ascontiguousarray(pzs, np.uint64)
+    _, W = _nq(store)
+    pxs = np.ascontiguousarray(np.asarray(pxs, np.uint64).reshape(len(work), -1))
+    pzs = np.ascontiguousarray(np.asarray(pzs, np.uint64).reshape(len(work), -1))
+    if pxs.shape[1] != W or pzs.shape[1] != W:
+        _bad(f"generators must have {W} words")
+    _angles(store, theta, phi)
     n = pxs.shape[0]
     coef = np.zeros(3 ** n)
     arr = (ct.c_void_p * n)(*[w.handle for w in work])
@@ -495,6 +722,7 @@ def iqcc_qcc_iteration(ctx, h: "Store", spare: "Store", theta, phi, w_max: int, 
     Returns dict(sel_x, sel_z (n_applied, W), sel_g, sel_tau, energy (n_applied + 1),
     n_candidates)."""
     W = iqcc_store_shape(h.handle)[1]
+    _angles(h.handle, theta, phi)
     k = max(int(n_select), 1)
     sx = np.zeros((k, W), np.uint64); sz = np.zeros((k, W), np.uint64)
     sg = np.zeros(k); st = np.zeros(k); en = np.zeros(k + 1)
@@ -513,12 +741,16 @@ def iqcc_qcc_iteration(ctx, h: "Store", spare: "Store", theta, phi, w_max: int, 
 
 
 class Store:
-    """Owning wrapper of a device term store."""
+    """A device term store whose memory is a torch tensor (iqcc_store_wrap)."""
 
-    def __init__(self, ctx: Context, n_qubits: int, max_terms: int):
+    def __init__(self, ctx: Context, n_qubits: int, max_terms: int, flags: int = 0):
+        import torch
         self.ctx = ctx
         self.n_qubits = n_qubits
-        self.handle = iqcc_store_create(ctx.handle, n_qubits, max_terms)
+        self.handle = None
+        nbytes = iqcc_store_bytes(n_qubits, max_terms, flags)
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.handle = iqcc_store_wrap(ctx.handle, n_qubits, max_terms, flags, self.mem)
 
     def load_numpy(self, x, z, c):
         import torch
@@ -538,6 +770,7 @@ class Store:
         if self.handle is not None and self.ctx.handle is not None:
             iqcc_store_destroy(self.ctx.handle, self.handle)
         self.handle = None
+        self.mem = None
 
     def __del__(self):
         try:

@@ -8,6 +8,7 @@ from oracle import oracle as O
 from paper_2603_08883_amd import inputs as I
 from paper_2603_08883_amd import iqcc
 from tests.gpu_util import assert_same_terms, describe
+from tests.golden.multiset_hash import multiset_hash_torch
 
 pytestmark = pytest.mark.gpu
 EPS = 1e-8
@@ -88,3 +89,35 @@ def test_batch_rejects_aliasing(ctx, hams):
     with pytest.raises(iqcc.IqccError):
         iqcc.iqcc_dress_batched(ctx.handle, [ins[0].handle, ins[1].handle], [outs[0].handle, ins[0].handle],
                                 pxs, pzs, taus, EPS)
+
+
+def test_full_batch_graph_against_oracle_digests(ctx):
+    """The 64-Hamiltonian batch of the benchmark (16-64 qubits, 1e3-1e6 terms),
+    captured once and replayed twice: each output's size and digest equal the
+    oracle's (tests/golden/c4b_batch.json)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "c4b_batch.json")))["items"]
+    hs = I.batch_hamiltonians(4)
+    assert [len(h["c"]) for h in hs] == [g["n_in"] for g in gold]
+    ins = [iqcc.Store(ctx, h["n_qubits"], max(2 * len(h["c"]), 64)).load_numpy(h["x"], h["z"], h["c"])
+           for h in hs]
+    outs = [iqcc.Store(ctx, h["n_qubits"], max(2 * len(h["c"]), 64)) for h in hs]
+    pxs, pzs, taus = _args(hs)
+    b = iqcc.iqcc_batch_create(ctx.handle, [s.handle for s in ins], [s.handle for s in outs], pxs, pzs,
+                               taus, EPS)
+    try:
+        for rep in range(2):
+            describe(rep, "full batch graph replay", n_ham=len(hs))
+            iqcc.iqcc_batch_launch(ctx.handle, b)
+            torch.cuda.synchronize()
+            for i, (o, g) in enumerate(zip(outs, gold)):
+                n_anti, _ = iqcc.iqcc_store_stats(ctx.handle, o.handle)
+                assert (o.count(), n_anti) == (g["n_out"], g["n_anti"]), (rep, i)
+                gx, gz, gc = iqcc.iqcc_store_export(ctx.handle, o.handle)
+                assert f"{multiset_hash_torch(gx, gz, gc):016x}" == g["digest"], (rep, i)
+    finally:
+        iqcc.iqcc_batch_destroy(ctx.handle, b)
+    for s_ in ins + outs:
+        s_.close()

@@ -1,0 +1,221 @@
+"""The C ABI beyond the core calls: caller-owned store memory, the sizing
+count, the product export, the debug validation of loads, the one-call taped
+chain, the batched-DIS tile and range knobs, and argument checks of the
+binding with device tensors."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2603_08883_amd import inputs as I
+from paper_2603_08883_amd import iqcc
+from paper_2603_08883_amd.autograd import DressingChain
+from tests.gpu_util import assert_same_terms, describe
+
+pytestmark = pytest.mark.gpu
+E_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = iqcc.Context(0)
+    yield c
+    c.close()
+
+
+def _angles(nq, seed):
+    th, ph = I.qmf_angles(nq, np.random.default_rng(seed))
+    return th, ph, torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()
+
+
+def test_store_lives_in_torch_memory(ctx):
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    s = iqcc.Store(ctx, nq, 2 * len(c))
+    assert isinstance(s.mem, torch.Tensor) and s.mem.is_cuda
+    assert s.mem.numel() == iqcc.iqcc_store_bytes(nq, 2 * len(c))
+    describe(0, "store in torch memory", n=len(c))
+    s.load_numpy(x, z, c)
+    assert_same_terms(s.to_numpy(), (x, z, c), "roundtrip")
+    s.close()
+    # too small, or not 256-byte aligned
+    need = iqcc.iqcc_store_bytes(nq, 1000)
+    mem = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(iqcc.IqccError) as e:
+        iqcc.iqcc_store_wrap(ctx.handle, nq, 1000, 0, mem[:need - 1])
+    assert e.value.code == iqcc.IQCC_ERR_CAPACITY
+    with pytest.raises(iqcc.IqccError) as e:
+        iqcc.iqcc_store_wrap(ctx.handle, nq, 1000, 0, mem[8:])
+    assert e.value.code == iqcc.IQCC_ERR_INVALID_ARG
+    h = iqcc.iqcc_store_wrap(ctx.handle, nq, 1000, 0, mem)
+    assert iqcc.iqcc_store_count(ctx.handle, h) == 0
+    iqcc.iqcc_store_destroy(ctx.handle, h)
+
+
+def test_dress_count_matches_oracle(ctx):
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    cx, cz = I.dis_candidates(x, nq, 4, 8, np.random.default_rng(7))
+    s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    for k in range(4):
+        describe(k, "dress_count", n=len(c))
+        n_anti = iqcc.iqcc_dress_count(ctx.handle, s.handle, cx[k], cz[k])
+        raw = O.dress_raw(nq, x, z, c, cx[k], cz[k], 0.3)
+        assert n_anti == len(raw[2]) - len(c)
+    assert iqcc.iqcc_dress_count(ctx.handle, s.handle, np.zeros(1, np.uint64), np.zeros(1, np.uint64)) == 0
+
+
+@pytest.mark.parametrize("nq", [7, 64, 124, 190])
+def test_pauli_products_match_oracle(ctx, nq):
+    W = (nq + 63) // 64
+    rng = np.random.default_rng(nq)
+    n = 300
+    mask = [(1 << max(0, min(64, nq - 64 * w))) - 1 for w in range(W)]
+    def words():
+        a = np.zeros((n, W), np.uint64)
+        for w in range(W):
+            a[:, w] = rng.integers(0, 2**63, size=n, dtype=np.uint64) * np.uint64(2) + \
+                rng.integers(0, 2, size=n, dtype=np.uint64)
+            a[:, w] &= np.uint64(mask[w])
+        return a
+    x1, z1, x2, z2 = words(), words(), words(), words()
+    x1[0] = z1[0] = 0                      # identity times anything
+    x2[1], z2[1] = x1[1], z1[1]            # P P = I
+    describe(0, "pauli_products", nq=nq, n=n)
+    gx, gz, ge = iqcc.iqcc_pauli_products(ctx.handle, nq, *(iqcc.to_device_words(a) for a in (x1, z1, x2, z2)))
+    gx, gz, ge = iqcc.from_device_words(gx), iqcc.from_device_words(gz), ge.cpu().numpy()
+    for i in range(n):
+        rx, rz, re_ = O.pauli_product(nq, x1[i], z1[i], x2[i], z2[i])
+        assert np.array_equal(gx[i], rx) and np.array_equal(gz[i], rz) and int(ge[i]) == re_, i
+    assert ge[0] == 0 and ge[1] == 0 and not gx[1].any() and not gz[1].any()
+
+
+def test_debug_validation_of_loads(ctx, monkeypatch):
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    x, z, c = x[:5000], z[:5000], c[:5000]
+    s = iqcc.Store(ctx, nq, 4 * len(c))
+    monkeypatch.setenv("IQCC_DEBUG_VALIDATE", "1")
+    describe(0, "debug validation", n=len(c))
+    s.load_numpy(x, z, c)                             # valid rows load
+    assert s.count() == len(c)
+    dx = np.concatenate([x, x[17:18]]); dz = np.concatenate([z, z[17:18]]); dc = np.concatenate([c, [1.0]])
+    with pytest.raises(iqcc.IqccError) as e:
+        s.load_numpy(dx, dz, dc)                      # a duplicate key
+    assert e.value.code == iqcc.IQCC_ERR_INVALID_ARG
+    assert s.count() == len(c)                        # store unchanged
+    px = x.copy(); px[3, 0] |= np.uint64(1) << np.uint64(45)   # qubit 45 of a 40-qubit word
+    with pytest.raises(iqcc.IqccError) as e:
+        s.load_numpy(px, z, c)
+    assert e.value.code == iqcc.IQCC_ERR_INVALID_ARG
+    monkeypatch.delenv("IQCC_DEBUG_VALIDATE")
+    s.load_numpy(dx, dz, dc)                          # unchecked without the variable
+    assert s.count() == len(dc)
+
+
+def test_chain_calls_match_python_chain_and_oracle(ctx):
+    nq, steps, eps = 40, 5, 1e-8
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    cx, cz = I.dis_candidates(x, nq, steps, 8, np.random.default_rng(71))
+    taus = I.taus(steps, np.random.default_rng(72))
+    th, ph, tht, pht = _angles(nq, 73)
+    ents = list(zip(cx, cz))
+    # Python-sequenced chain (autograd path) for the store sizes and dtau
+    chain = DressingChain(ctx, nq, x, z, c, ents, eps)
+    final = chain.run(list(taus))
+    lam = torch.empty(iqcc.iqcc_store_rows(final.handle), dtype=torch.float64, device="cuda")
+    iqcc.iqcc_qmf_energy_backward(ctx.handle, final.handle, tht, pht, None, lam)
+    d_py = chain.backward_taus(list(taus), lam).cpu().numpy()
+    # the same chain through the one-call C entry points, into fresh stores
+    h0 = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    outs = [iqcc.Store(ctx, nq, cap) for cap in chain.caps]
+    tapes_s, tapes_p = [], []
+    src = h0
+    for o in outs:
+        r = iqcc.iqcc_store_rows(src.handle)
+        tapes_s.append(torch.empty(r, dtype=torch.int32, device="cuda"))
+        tapes_p.append(torch.empty(r, dtype=torch.int32, device="cuda"))
+        src = o
+    describe(0, "chain_forward", steps=steps)
+    iqcc.iqcc_chain_forward(ctx.handle, h0.handle, cx, cz, taus, eps, [o.handle for o in outs], tapes_s, tapes_p)
+    assert_same_terms(outs[-1].to_numpy(), final.to_numpy(), "chain_forward vs Python chain")
+    lam2 = torch.empty(iqcc.iqcc_store_rows(outs[-1].handle), dtype=torch.float64, device="cuda")
+    iqcc.iqcc_qmf_energy_backward(ctx.handle, outs[-1].handle, tht, pht, None, lam2)
+    lam_h0 = torch.zeros(iqcc.iqcc_store_rows(h0.handle), dtype=torch.float64, device="cuda")
+    describe(0, "chain_backward", steps=steps)
+    d_c = iqcc.iqcc_chain_backward(ctx.handle, h0.handle, cx, cz, taus, [o.handle for o in outs],
+                                   tapes_s, tapes_p, lam2, lam_h0).cpu().numpy()
+    assert np.array_equal(d_c, d_py)
+    for k in (0, steps - 1):
+        g, _ = O.chain_tau_gradient(nq, x, z, c, ents, list(taus), eps, th, ph, k)
+        assert abs(d_c[k] - g) <= E_TOL * max(1.0, abs(g)), (k, d_c[k], g)
+    # dE/dc of the rows of H0: with the drop masks frozen every step is linear
+    # in the coefficients, so E = sum_r lambda_h0[r] c_r.  A load packs the
+    # rows bucket by bucket, so the export order is the row order.
+    n0 = len(c)
+    c_rows = h0.to_numpy()[2]
+    E = float(iqcc.iqcc_qmf_energy(ctx.handle, outs[-1].handle, tht, pht).item())
+    lin = float(np.dot(lam_h0.cpu().numpy()[:n0], c_rows))
+    assert abs(lin - E) <= E_TOL * max(1.0, abs(E)), (lin, E)
+    chain.close()
+
+
+def test_dis_tile_and_range_knobs(ctx):
+    """A single bucket range holds all 1024 buckets of the 40-qubit Hamiltonian
+    (two chunks of 512 with the prefix search), tiles of 1, 37 and 256
+    candidates: every setting matches the oracle, and at a fixed range count
+    the tile does not change a single bit."""
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    th, ph, tht, pht = _angles(nq, 81)
+    cx, cz = I.dis_candidates(x, nq, 300, 12, I.rng_for(1, I.PURPOSE_CANDIDATES))
+    s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    ref = O.dis_gradients(nq, x, z, c, th, ph, cx, cz)
+    dcx, dcz = iqcc.to_device_words(cx), iqcc.to_device_words(cz)
+    try:
+        for ranges in (1, 3, 0):
+            got = {}
+            for tile in (1, 37, 256):
+                iqcc.iqcc_set_param(ctx.handle, "dis_bucket_ranges", ranges)
+                iqcc.iqcc_set_param(ctx.handle, "dis_tile", tile)
+                describe(0, "dis knobs", ranges=ranges, tile=tile)
+                g = iqcc.iqcc_dis_gradients(ctx.handle, s.handle, tht, pht, dcx, dcz).cpu().numpy()
+                assert np.abs(g - ref).max() <= E_TOL, (ranges, tile)
+                got[tile] = g
+            assert np.array_equal(got[1], got[37]) and np.array_equal(got[1], got[256])
+    finally:
+        iqcc.iqcc_set_param(ctx.handle, "dis_bucket_ranges", 0)
+        iqcc.iqcc_set_param(ctx.handle, "dis_tile", 256)
+
+
+def test_binding_rejects_bad_device_arguments(ctx):
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    x, z, c = x[:2000], z[:2000], c[:2000]
+    s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    o = iqcc.Store(ctx, nq, 4 * len(c))
+    th, ph, tht, pht = _angles(nq, 91)
+    e = torch.zeros((), dtype=torch.float64, device="cuda")
+    px, pz = I.dis_candidates(x, nq, 1, 8, np.random.default_rng(92))
+    bad_angles = [tht.float(), tht[:nq - 1], torch.zeros(2 * nq, dtype=torch.float64, device="cuda")[::2],
+                  torch.from_numpy(th)]
+    for b in bad_angles:
+        with pytest.raises(iqcc.IqccError) as err:
+            iqcc.iqcc_qmf_energy(ctx.handle, s.handle, b, pht)
+        assert err.value.code == iqcc.IQCC_ERR_INVALID_ARG
+        with pytest.raises(iqcc.IqccError):
+            iqcc.iqcc_dress(ctx.handle, s.handle, px[0], pz[0], 0.1, 0.0, o.handle, tht, b, e)
+    with pytest.raises(iqcc.IqccError):      # a 2-word entangler for a 1-word store
+        iqcc.iqcc_dress(ctx.handle, s.handle, np.zeros(2, np.uint64), np.zeros(2, np.uint64), 0.1, 0.0, o.handle)
+    with pytest.raises(iqcc.IqccError):      # cotangent array shorter than the arena
+        iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht, None,
+                                      torch.empty(10, dtype=torch.float64, device="cuda"))
+    with pytest.raises(iqcc.IqccError):      # candidates with the wrong number of words
+        iqcc.iqcc_dis_gradients(ctx.handle, s.handle, tht, pht, torch.zeros((2, 5), dtype=torch.int64, device="cuda"),
+                                torch.zeros((2, 5), dtype=torch.int64, device="cuda"))
+    with pytest.raises(iqcc.IqccError):      # energy as float32
+        iqcc.iqcc_qmf_energy(ctx.handle, s.handle, tht, pht, torch.zeros((), dtype=torch.float32, device="cuda"))
+    # nothing above reached a kernel: the store still holds its terms
+    assert s.count() == len(c)
