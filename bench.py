@@ -45,25 +45,54 @@ def workload_chain():
     return x, z, c, list(zip(cx, cz)), taus, th, ph
 
 
-def cpu_baseline(x, z, c, ents, taus, th, ph, budget_s=12.0):
-    """The oracle as it stands, single thread, on the first steps of the chain."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(x, z, c, ents, taus, th, ph, budget_s=20.0, single_budget_s=8.0):
+    """The oracle as it stands on the host: its bucket-parallel form on every
+    core this process may use (the same terms and energies as the serial
+    oracle), over the chain's steps in order until about budget_s is spent,
+    and the serial oracle on one core over the first steps."""
     from oracle import oracle as O
     O.lib()
-    t0 = time.perf_counter()
-    n_out = 0
-    steps = 0
-    n0 = len(c)
-    for (px, pz), t in zip(ents, taus):
-        x, z, c = O.dress(N_QUBITS, x, z, c, px, pz, t, EPS)
-        O.qmf_energy(N_QUBITS, x, z, c, th, ph)
-        n_out += len(c)
-        steps += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n_out / dt, "unit": "dressed+merged terms/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {steps} of {N_STEPS_CHAIN} dressing steps (+energy) of the 124-qubit "
-                      f"chain, {n0} -> {len(c)} terms, {dt:.1f} s"}
+    cores = len(os.sched_getaffinity(0))
+
+    def run(step_fn, energy_fn, budget):
+        hx, hz, hc = x, z, c
+        t0 = time.perf_counter()
+        n_out = steps = 0
+        largest = 0
+        for (px, pz), t in zip(ents, taus):
+            largest = max(largest, len(hc))
+            hx, hz, hc = step_fn(hx, hz, hc, px, pz, t)
+            energy_fn(hx, hz, hc)
+            n_out += len(hc)
+            steps += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return n_out, steps, time.perf_counter() - t0, largest, len(hc)
+
+    n_out, steps, dt, largest, final = run(
+        lambda a, b, cc, px, pz, t: O.dress_par(N_QUBITS, a, b, cc, px, pz, t, EPS, cores),
+        lambda a, b, cc: O.qmf_energy_par(N_QUBITS, a, b, cc, th, ph, cores), budget_s)
+    s_out, s_steps, s_dt, _, s_final = run(
+        lambda a, b, cc, px, pz, t: O.dress(N_QUBITS, a, b, cc, px, pz, t, EPS),
+        lambda a, b, cc: O.qmf_energy(N_QUBITS, a, b, cc, th, ph), single_budget_s)
+    return {"value": n_out / dt, "unit": "dressed+merged terms/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {steps} of {N_STEPS_CHAIN} dressing steps (+energy) of the 124-qubit chain "
+                      f"on {cores} threads (bucket-parallel oracle: same terms and energies as the serial "
+                      f"one), {len(c)} -> {final} terms, largest step input {largest} terms, {dt:.1f} s",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"value": s_out / s_dt, "unit": "dressed+merged terms/s", "cores": 1,
+                              "sample": f"first {s_steps} steps, {len(c)} -> {s_final} terms, "
+                                        f"{s_dt:.1f} s"}}
 
 
 def profiled_traffic(ctx):
@@ -73,7 +102,7 @@ def profiled_traffic(ctx):
     import hashlib
     from paper_2603_08883_amd import iqcc
     here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", "k_dress_124q_chain_pmc.txt")
+    path = os.path.join(here, "profiles", "k_dress_inplace_124q_chain_pmc.txt")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -82,7 +111,7 @@ def profiled_traffic(ctx):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in ("kernels_dress.hip", "iqcc_internal.h"):
+    for f in ("kernels_inplace.hip", "iqcc_internal.h"):
         with open(os.path.join(here, "paper_2603_08883_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     knobs = " ".join(f"{k}={iqcc.iqcc_get_param(ctx.handle, k)}"
@@ -387,7 +416,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (scale for profiler byte counters)")
     ap.add_argument("--dis-plain-sample", type=int, default=256)
-    ap.add_argument("--max-terms", type=float, default=6e8)
+    ap.add_argument("--max-terms", type=float, default=1.3e8,
+                    help="max_terms of the in-place stores of the 124-qubit chain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -429,55 +459,56 @@ def main():
         x, z, c, ents, taus, th, ph = wl
         W = x.shape[1]
         bt = 16 * W + 8
-        h0 = iqcc.Store(ctx, N_QUBITS, 2 * len(c)).load_numpy(x, z, c)
-        s1 = iqcc.Store(ctx, N_QUBITS, int(args.max_terms))
-        s2 = iqcc.Store(ctx, N_QUBITS, int(args.max_terms))
+        INPLACE = iqcc.IQCC_STORE_INPLACE
+        max_ip = int(args.max_terms)
+        # resident H0 and the working store, both laid out in bucket regions
+        h0 = iqcc.Store(ctx, N_QUBITS, max_ip, INPLACE).load_numpy(x, z, c)
+        work = iqcc.Store(ctx, N_QUBITS, max_ip, INPLACE)
         tht = torch.from_numpy(th).cuda()
         pht = torch.from_numpy(ph).cuda()
         energies = torch.zeros(N_STEPS_CHAIN, dtype=torch.float64, device="cuda")
 
         def chain(events=None, carry=True):
-            """20 dressing steps; the energy of step 0 is summed in full, later
-            steps carry it forward (carry=False: every step sums in full)."""
-            src = h0
-            outs = (s1, s2)
+            """Copy H0 into the working store, then 20 in-place dressing steps;
+            the energy of step 0 is summed in full, later steps carry it
+            forward (carry=False: every step sums in full)."""
+            if events is not None:
+                events[0].record(stream)
+            iqcc.iqcc_store_copy(ctx.handle, h0.handle, work.handle)
             for j, ((px, pz), tau) in enumerate(zip(ents, taus)):
-                dst = outs[j % 2]
                 if events is not None:
-                    events[j].record(stream)
-                if carry and j > 0:
-                    iqcc.iqcc_dress_energy_update(ctx.handle, src.handle, px, pz, tau, EPS, dst.handle,
-                                                  tht, pht, energies[j - 1:j], energies[j:j + 1])
-                else:
-                    iqcc.iqcc_dress(ctx.handle, src.handle, px, pz, tau, EPS, dst.handle, tht, pht,
-                                    energies[j:j + 1])
-                src = dst
+                    events[j + 1].record(stream)
+                iqcc.iqcc_dress_inplace(ctx.handle, work.handle, px, pz, tau, EPS, tht, pht,
+                                        energies[j - 1:j] if (carry and j > 0) else None,
+                                        energies[j:j + 1])
             if events is not None:
                 events[-1].record(stream)
-            return src
+            return work
 
-        # untimed pass that records the per-step sizes (deterministic across replays)
-        sizes = []
-        src = h0
-        outs = (s1, s2)
+        # untimed pass that records the per-step sizes (the same on every replay)
+        sizes, relocated = [], 0
+        iqcc.iqcc_store_copy(ctx.handle, h0.handle, work.handle)
         n_in = len(c)
         for j, ((px, pz), tau) in enumerate(zip(ents, taus)):
-            dst = outs[j % 2]
-            iqcc.iqcc_dress(ctx.handle, src.handle, px, pz, tau, EPS, dst.handle, tht, pht,
-                            energies[j:j + 1])
-            n_out = dst.count()
-            n_anti, n_new = iqcc.iqcc_store_stats(ctx.handle, dst.handle)
+            iqcc.iqcc_dress_inplace(ctx.handle, work.handle, px, pz, tau, EPS, tht, pht, None,
+                                    energies[j:j + 1])
+            n_out = work.count()
+            n_anti, n_new = iqcc.iqcc_store_stats(ctx.handle, work.handle)
+            relocated += iqcc.iqcc_store_inplace_stats(ctx.handle, work.handle)["relocated"]
             sizes.append((n_in, n_anti, n_new, n_out))
             n_in = n_out
-            src = dst
-        log("step sizes (N_in, N_anti, N_new, N_out):", sizes[0], "...", sizes[-1])
+        ip_stats = iqcc.iqcc_store_inplace_stats(ctx.handle, work.handle)
+        log("step sizes (N_in, N_anti, N_new, N_out):", sizes[0], "...", sizes[-1],
+            f"relocated items {relocated}")
         e_full = energies.clone()
-        for _ in range(max(0, args.warmup - 1)):
+        for _ in range(max(0, args.warmup)):
             chain()
         torch.cuda.synchronize()
         per_step = np.zeros(N_STEPS_CHAIN)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(N_STEPS_CHAIN + 1)]
+        copy_s = 0.0
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(N_STEPS_CHAIN + 2)]
                for _ in range(args.steps)]
+        finals = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
@@ -485,11 +516,25 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         for k in range(args.steps):
+            copy_s += evs[k][0].elapsed_time(evs[k][1]) * 1e-3
             for j in range(N_STEPS_CHAIN):
-                per_step[j] += evs[k][j].elapsed_time(evs[k][j + 1]) * 1e-3
+                per_step[j] += evs[k][j + 1].elapsed_time(evs[k][j + 2]) * 1e-3
         per_step /= args.steps
+        copy_s /= args.steps
         chain_s = wall / args.steps
-        carry_err = float((energies - e_full).abs().max().item())
+        e_carry = energies.clone()
+        carry_err = float((e_carry - e_full).abs().max().item())
+        # bit-identical replays: the final store and energies of two more chains
+        digests = []
+        for _ in range(2):
+            chain()
+            ex, ez, ec = iqcc.iqcc_store_export(ctx.handle, work.handle)
+            digests.append((ex.cpu().numpy().tobytes(), ez.cpu().numpy().tobytes(),
+                            ec.cpu().numpy().tobytes(), energies.cpu().numpy().tobytes()))
+            del ex, ez, ec
+        identical = digests[0] == digests[1] and digests[0][3] == e_carry.cpu().numpy().tobytes()
+        del digests
+        torch.cuda.empty_cache()
         # the same chain with the energy summed in full after every step
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -497,10 +542,11 @@ def main():
             chain(carry=False)
         torch.cuda.synchronize()
         full_s = (time.perf_counter() - t0) / args.steps
-        total_out = sum(s[3] for s in sizes)
-        total_in = sum(s[0] for s in sizes)
-        alg_bytes = sum(bt * s[0] + 8 * s[1] + bt * s[2] for s in sizes)
-        stream_bytes = sum(bt * (s[0] + s[3]) for s in sizes)
+        total_out = sum(s_[3] for s_ in sizes)
+        total_in = sum(s_[0] for s_ in sizes)
+        alg = [bt * s_[0] + 8 * s_[1] + bt * s_[2] for s_ in sizes]
+        alg_bytes = sum(alg)
+        stream_bytes = sum(bt * (s_[0] + s_[3]) for s_ in sizes)
         kernel_s = per_step.sum()
         achieved = alg_bytes / kernel_s / 1e9
         traffic = profiled_traffic(ctx)
@@ -512,7 +558,8 @@ def main():
                 "workload": "124-qubit banded JW Hamiltonian (62 orbitals, band 6, decay 3), "
                             f"{len(c)} initial terms, 20 seeded DIS entanglers (weight 2-8), "
                             "tau~U(-0.2,0.2), |c|<1e-8 dropped after each step, QMF energy "
-                            "fused after each step; one step = the whole 20-entangler chain",
+                            "fused after each step; one step = the whole 20-entangler chain "
+                            "(copy of the resident H0 + 20 in-place dressings)",
                 "n_qubits": N_QUBITS, "initial_terms": len(c), "final_terms": sizes[-1][3],
                 "terms_processed": total_in, "terms_produced": total_out,
                 "parallelism": "1 GPU"},
@@ -523,7 +570,7 @@ def main():
                          "traffic": traffic,
                          "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                          "copy-calibrated)",
-                         "kernel": "k_dress (fused dress+merge+truncate+energy)",
+                         "kernel": "k_dress_inplace (in-place dress+merge+truncate+energy)",
                          "alg_bytes_per_chain": alg_bytes,
                          "alg_bytes_per_launch": alg_bytes / N_STEPS_CHAIN,
                          "traffic_over_alg_bytes": (traffic / (alg_bytes / N_STEPS_CHAIN)
@@ -531,16 +578,24 @@ def main():
                          "avg_launch_ms": kernel_s / N_STEPS_CHAIN * 1e3,
                          "measured_copy_gbps": copy_gbps,
                          "frac_of_measured_copy": achieved / copy_gbps},
-            "per_step_ms": [round(v * 1e3, 4) for v in per_step],
-            "final_energy": float(energies[-1].item()),
+            "per_step": [{"n_in": s_[0], "n_anti": s_[1], "n_new": s_[2], "n_out": s_[3],
+                          "energy": float(e_carry[j].item()), "ms": round(per_step[j] * 1e3, 4),
+                          "alg_gbps": alg[j] / per_step[j] / 1e9}
+                         for j, s_ in enumerate(sizes)],
+            "h0_copy_ms": copy_s * 1e3,
+            "final_energy": float(e_carry[-1].item()),
+            "bit_identical_replays": bool(identical),
+            "inplace": {"relocated_items": int(relocated), "region_rows": ip_stats["region_rows"],
+                        "pool_rows_used": ip_stats["pool_used"],
+                        "bucket_terms_at_max": iqcc.iqcc_get_param(ctx.handle, "inplace_bucket_terms"),
+                        "max_terms": max_ip},
             "energy": {"mode": "carried forward from step to step (only changed terms "
                                "evaluated); step 0 summed in full",
                        "max_abs_diff_vs_full_sum": carry_err,
                        "chain_ms_full_sum_every_step": full_s * 1e3},
         })
         log(f"chain {chain_s*1e3:.2f} ms, kernels {kernel_s*1e3:.2f} ms, {achieved:.0f} GB/s algorithmic")
-        # term-limit compression of the final Hamiltonian to 80 % of its terms
-        final = chain()
+        final = work
         # stand-alone QMF energy of the final Hamiltonian (HBM bound: 40 B per term)
         e1 = torch.zeros(1, dtype=torch.float64, device="cuda")
         iqcc.iqcc_qmf_energy(ctx.handle, final.handle, tht, pht, e1)
@@ -558,16 +613,51 @@ def main():
             "ms": t_e * 1e3, "hbm_gbps_algorithmic": bt * n_fin0 / t_e / 1e9,
             "roofline_frac": bt * n_fin0 / t_e / 1e9 / HBM_PEAK_GBPS,
             "frac_of_measured_copy": bt * n_fin0 / t_e / 1e9 / copy_gbps,
-            "matches_fused_energy": abs(float(e1.item()) - float(energies[-1].item())) <= 1e-10}
-        other = s1 if final is s2 else s2
+            "matches_fused_energy": abs(float(e1.item()) - float(e_carry[-1].item())) <= 1e-10}
+        # the out-of-place kernel on the same chain (every kept term rewritten
+        # into a fresh store), for comparison
+        s1 = iqcc.Store(ctx, N_QUBITS, max_ip)
+        s2 = iqcc.Store(ctx, N_QUBITS, max_ip)
+        h0p = iqcc.Store(ctx, N_QUBITS, 2 * len(c)).load_numpy(x, z, c)
+        e_oop = torch.zeros(N_STEPS_CHAIN, dtype=torch.float64, device="cuda")
+
+        def chain_oop():
+            src = h0p
+            for j, ((px, pz), tau) in enumerate(zip(ents, taus)):
+                dst = (s1, s2)[j % 2]
+                if j > 0:
+                    iqcc.iqcc_dress_energy_update(ctx.handle, src.handle, px, pz, tau, EPS, dst.handle,
+                                                  tht, pht, e_oop[j - 1:j], e_oop[j:j + 1])
+                else:
+                    iqcc.iqcc_dress(ctx.handle, src.handle, px, pz, tau, EPS, dst.handle, tht, pht,
+                                    e_oop[j:j + 1])
+                src = dst
+            return src
+
+        oop_final = chain_oop()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            oop_final = chain_oop()
+        torch.cuda.synchronize()
+        oop_s = (time.perf_counter() - t0) / args.steps
+        result["out_of_place_chain"] = {
+            "workload": "the same 20-step chain through the out-of-place kernel (k_dress: every kept "
+                        "term written to a fresh store)",
+            "chain_ms": oop_s * 1e3, "final_terms": oop_final.count(),
+            "energy_max_abs_diff_vs_inplace": float((e_oop - e_carry).abs().max().item()),
+            "inplace_speedup": oop_s / chain_s}
+        log(f"out-of-place chain {oop_s*1e3:.2f} ms")
+        # term-limit compression of the final Hamiltonian to 80 % of its terms
         n_fin = final.count()
         limit = int(0.8 * n_fin)
-        iqcc.iqcc_truncate_top(ctx.handle, final.handle, limit, other.handle)
+        other = s1 if oop_final is s2 else s2
+        iqcc.iqcc_truncate_top(ctx.handle, oop_final.handle, limit, other.handle)
         torch.cuda.synchronize()
         reps = 3
         t0 = time.perf_counter()
         for _ in range(reps):
-            iqcc.iqcc_truncate_top(ctx.handle, final.handle, limit, other.handle)
+            iqcc.iqcc_truncate_top(ctx.handle, oop_final.handle, limit, other.handle)
         torch.cuda.synchronize()
         t_lim = (time.perf_counter() - t0) / reps
         # two |c| digit passes over every term (the later ones read only the
@@ -588,7 +678,7 @@ def main():
             result["term_limit"]["cpu_oracle"] = {
                 "kind": "oracle", "cores": 1, "terms_per_s": len(c) / dt,
                 "sample": f"the initial Hamiltonian ({len(c)} terms) limited to 80 %, {dt:.2f} s"}
-        h0.close(); s1.close(); s2.close()
+        h0.close(); work.close(); s1.close(); s2.close(); h0p.close()
         if not args.no_cpu_baseline:
             log("CPU baseline (oracle)...")
             result["cpu_baseline"] = cpu_baseline(x, z, c, ents, taus, th, ph)

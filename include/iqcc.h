@@ -89,17 +89,33 @@ const char *iqcc_version(void);
  *   "dis_bucket_ranges"  bucket ranges (workgroups along the terms) of the
  *                        batched DIS launch; 0 = about 8 workgroups per CU
  *                        in total (0 .. 4096)
+ *   "inplace_bucket_terms" mean bucket size of an IQCC_STORE_INPLACE store
+ *                        when it holds max_terms terms (1 .. 65536)
+ *   "inplace_item_terms" input terms per work item of iqcc_dress_inplace
+ *                        while buckets are small; 0 = 1.5 x the stash
+ *   "inplace_cap"        anticommuting terms a wavefront of iqcc_dress_inplace
+ *                        stages in LDS; 0 = as many as fit (0 .. 512);
+ *                        larger sets go to the pool in hash rounds
+ *   "inplace_region_rows" smallest region of a bucket when an in-place store
+ *                        is loaded or copied (a bucket with c terms gets at
+ *                        least 2c rows); 0 = the arena minus the pool,
+ *                        divided evenly (0 .. 2^24)
  * Returns IQCC_ERR_INVALID_ARG for an unknown name or out-of-range value. */
 int iqcc_set_param(iqcc_ctx *ctx, const char *name, int64_t value);
 int iqcc_get_param(const iqcc_ctx *ctx, const char *name, int64_t *value);
 
 /* ---- term stores ---------------------------------------------------------- */
 
-/* Store flags.  IQCC_STORE_INPLACE: the arena has two halves, so the store can
- * be dressed in place (iqcc_dress_inplace): one half holds the live terms
- * with free rows after each bucket, the other receives a fresh layout when a
- * step doubles the bucket count or a bucket outgrows its free rows.  Device
- * memory about 10*max_terms*(16*W + 8) bytes instead of 2*max_terms*(16*W+8). */
+/* Store flags.  IQCC_STORE_INPLACE: a store that can be dressed in place
+ * (iqcc_dress_inplace).  Its contents, once written by iqcc_store_load,
+ * iqcc_store_copy or iqcc_dress_inplace, are laid out in bucket regions: about
+ * max_terms / "inplace_bucket_terms" buckets (fixed for the store's life),
+ * each owning a region of rows with free rows after its live ones, and a pool
+ * of max_terms / 2 rows for buckets that outgrow their region.  Device memory
+ * about 3.5*max_terms*(16*W + 8) bytes; rows below 2^31 (max_terms up to
+ * about 6e8).  Every other call accepts such a store like any other; when
+ * an out-of-place call writes it, the region layout is gone until the next
+ * load or copy. */
 #define IQCC_STORE_INPLACE 1u
 
 /* Create an empty store for `n_qubits` (1..256) qubits able to hold up to
@@ -126,6 +142,14 @@ int iqcc_store_wrap(iqcc_ctx *ctx, int n_qubits, int64_t max_terms, uint32_t fla
 /* Destroy a store (NULL is allowed); frees its memory only when the library
  * allocated it (iqcc_store_create*). */
 int iqcc_store_destroy(iqcc_ctx *ctx, iqcc_store *store);
+/* Copy the live terms of `src` into `dst`, an IQCC_STORE_INPLACE store of the
+ * same n_qubits, laid out in bucket regions (the previous contents of dst
+ * are discarded).  Each bucket of dst takes its terms in the order they have
+ * in src, so a copy of the same store gives the same rows every time.
+ * Asynchronous; IQCC_ERR_CAPACITY is reported by the next iqcc_store_count on
+ * dst if the regions do not fit its arena, and an invalid src makes dst
+ * invalid. */
+int iqcc_store_copy(iqcc_ctx *ctx, const iqcc_store *src, iqcc_store *dst, void *stream);
 /* Number of qubits / words of a store. */
 int iqcc_store_shape(const iqcc_store *store, int *n_qubits, int *n_words);
 
@@ -194,6 +218,34 @@ int iqcc_dress_energy_update(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t
                              const uint64_t *pz, double tau, double eps, const double *theta,
                              const double *phi, const double *energy_in, double *energy_out,
                              iqcc_store *out, void *stream);
+
+/* In-place form of iqcc_dress / iqcc_dress_energy_update (Sec. II Eq. 5,
+ * App. D merge, App. A compression): `store` becomes the dressed, merged and
+ * compressed Hamiltonian, with the same terms and coefficients bit for bit
+ * as iqcc_dress would write.  Terms that commute with P keep their rows and
+ * are not rewritten; an anticommuting term's new coefficient is written into
+ * its own row; new keys are appended after the live rows of their bucket;
+ * rows freed by compression are refilled from the end of the bucket.  A
+ * bucket that outgrows its region moves to the store's pool.
+ * `store` must be an IQCC_STORE_INPLACE store in the region layout
+ * (IQCC_ERR_INVALID_ARG otherwise).  theta, phi, energy_out (DEVICE) are
+ * optional, all NULL or all set: *energy_out receives <Omega|store|Omega>
+ * after the step.  energy_in (DEVICE, optional, needs the other three) holds
+ * the energy before the step; then only the change is evaluated, as in
+ * iqcc_dress_energy_update (energy_out may equal energy_in).  Row positions,
+ * coefficients and the energy are the same on every run for the same input
+ * layout (one wavefront per work item, items dealt out in a fixed order).
+ * Asynchronous; if the pool runs out the store becomes invalid, which the next
+ * iqcc_store_count reports as IQCC_ERR_CAPACITY. */
+int iqcc_dress_inplace(iqcc_ctx *ctx, iqcc_store *store, const uint64_t *px, const uint64_t *pz,
+                       double tau, double eps, const double *theta, const double *phi,
+                       const double *energy_in, double *energy_out, void *stream);
+
+/* Synchronising diagnostics of the last iqcc_dress_inplace on `store` (each
+ * pointer may be NULL): work items moved to the pool, rows freed by
+ * compression, rows per bucket region, pool rows in use. */
+int iqcc_store_inplace_stats(iqcc_ctx *ctx, const iqcc_store *store, int64_t *relocated, int64_t *freed,
+                             int64_t *region_rows, int64_t *pool_used, void *stream);
 
 /* Synchronising sizing call for a dressing step of `in` by P (HOST words px,
  * pz; Eq. 5): *n_anti = number of terms of `in` that anticommute with P.

@@ -29,7 +29,7 @@
 //  * tau tangents (iterated dressing, Eq. 6): forward-mode derivative of the chain
 //    with every step's truncation decision frozen at the forward pass.
 //
-// Build: g++ -O2 -std=c++17 -ffp-contract=off -fPIC -shared (no -ffast-math).
+// Build: g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -fPIC -shared (no -ffast-math).
 
 #include <algorithm>
 #include <map>
@@ -407,6 +407,115 @@ void oracle_chain_point(int nq, int W, int64_t n0, const uint64_t* x0, const uin
     found[i] = (int8_t)pc.value(K, qx + i * W, qz + i * W, &v);
     val[i] = v;
   }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The same step on several host threads (the CPU baseline on all cores).
+// Arithmetic and summation order are those of oracle_dress_raw,
+// oracle_merge_truncate and oracle_qmf_energy; only the work is split, so the
+// result does not depend on the thread count:
+//  * raw dressing of input slices, concatenated in input order;
+//  * the raw rows partitioned by a hash of the key (every copy of a key in one
+//    partition, in input order), each partition merged and compressed exactly
+//    as oracle_merge_truncate treats a whole list;
+//  * energy: per-term products in parallel, the Neumaier sum in input order.
+// Output rows come partition by partition, canonical inside a partition.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kParts = 256;
+
+inline uint32_t part_of(int W, const uint64_t* x, const uint64_t* z) {
+  uint64_t h = 0x9E3779B97F4A7C15ull;
+  for (int w = 0; w < W; ++w) {
+    h = (h ^ x[w]) * 0xBF58476D1CE4E5B9ull;
+    h = (h ^ z[w]) * 0x94D049BB133111EBull;
+  }
+  h ^= h >> 31;
+  return (uint32_t)(h % kParts);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t oracle_dress_step_par(int nq, int W, int64_t n, const uint64_t* x, const uint64_t* z,
+                              const double* c, const uint64_t* px, const uint64_t* pz, double tau,
+                              double eps, int nthreads, uint64_t* ox, uint64_t* oz, double* oc) {
+  const int T = nthreads > 0 ? nthreads : 1;
+  const int S = 4 * T;   // input slices
+  std::vector<std::vector<uint64_t>> sx(S), sz(S);
+  std::vector<std::vector<double>> sc(S);
+  std::vector<std::vector<int64_t>> cnt(S, std::vector<int64_t>(kParts, 0));
+#pragma omp parallel for schedule(dynamic) num_threads(T)
+  for (int s = 0; s < S; ++s) {
+    const int64_t lo = n * s / S, hi = n * (s + 1) / S;
+    sx[s].resize((size_t)(2 * (hi - lo)) * W);
+    sz[s].resize((size_t)(2 * (hi - lo)) * W);
+    sc[s].resize((size_t)(2 * (hi - lo)));
+    const int64_t m = oracle_dress_raw(nq, W, hi - lo, x + lo * W, z + lo * W, c + lo, px, pz, tau,
+                                       sx[s].data(), sz[s].data(), sc[s].data());
+    sc[s].resize((size_t)m);
+    for (int64_t i = 0; i < m; ++i) ++cnt[s][part_of(W, &sx[s][i * W], &sz[s][i * W])];
+  }
+  // partition-major layout; inside a partition the slices (input order) follow each other
+  std::vector<int64_t> poff(kParts + 1, 0);
+  std::vector<std::vector<int64_t>> at(S, std::vector<int64_t>(kParts, 0));
+  for (int p = 0; p < kParts; ++p) {
+    int64_t o = poff[p];
+    for (int s = 0; s < S; ++s) { at[s][p] = o; o += cnt[s][p]; }
+    poff[p + 1] = o;
+  }
+  const int64_t nraw = poff[kParts];
+  std::vector<uint64_t> qx((size_t)nraw * W), qz((size_t)nraw * W);
+  std::vector<double> qc((size_t)nraw);
+#pragma omp parallel for schedule(dynamic) num_threads(T)
+  for (int s = 0; s < S; ++s) {
+    std::vector<int64_t> pos = at[s];
+    for (int64_t i = 0; i < (int64_t)sc[s].size(); ++i) {
+      const uint32_t p = part_of(W, &sx[s][i * W], &sz[s][i * W]);
+      const int64_t r = pos[p]++;
+      std::memcpy(&qx[(size_t)r * W], &sx[s][i * W], W * 8);
+      std::memcpy(&qz[(size_t)r * W], &sz[s][i * W], W * 8);
+      qc[(size_t)r] = sc[s][i];
+    }
+    std::vector<uint64_t>().swap(sx[s]);
+    std::vector<uint64_t>().swap(sz[s]);
+    std::vector<double>().swap(sc[s]);
+  }
+  // merge + compression of each partition into its own slice of the output
+  std::vector<int64_t> kept(kParts, 0);
+#pragma omp parallel for schedule(dynamic) num_threads(T)
+  for (int p = 0; p < kParts; ++p) {
+    const int64_t b = poff[p], len = poff[p + 1] - poff[p];
+    kept[p] = oracle_merge_truncate(W, len, &qx[(size_t)b * W], &qz[(size_t)b * W], &qc[(size_t)b],
+                                    nullptr, eps, ox + b * W, oz + b * W, oc + b, nullptr);
+  }
+  int64_t m = 0;
+  for (int p = 0; p < kParts; ++p) {
+    const int64_t b = poff[p];
+    if (m != b) {
+      std::memmove(ox + m * W, ox + b * W, (size_t)kept[p] * W * 8);
+      std::memmove(oz + m * W, oz + b * W, (size_t)kept[p] * W * 8);
+      std::memmove(oc + m, oc + b, (size_t)kept[p] * 8);
+    }
+    m += kept[p];
+  }
+  return m;
+}
+
+double oracle_qmf_energy_par(int nq, int W, int64_t n, const uint64_t* x, const uint64_t* z,
+                             const double* c, const double* theta, const double* phi, int nthreads) {
+  const int T = nthreads > 0 ? nthreads : 1;
+  Bloch B(nq, theta, phi);
+  std::vector<double> t((size_t)n);
+#pragma omp parallel for schedule(static) num_threads(T)
+  for (int64_t i = 0; i < n; ++i) t[(size_t)i] = c[i] * B.expect(nq, x + i * W, z + i * W);
+  Neumaier acc;
+  for (int64_t i = 0; i < n; ++i) acc.add(t[(size_t)i]);
+  return acc.value();
 }
 
 }  // extern "C"

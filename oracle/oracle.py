@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, SRC])
+                               "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC])
         os.replace(tmp, LIB)
     return LIB
 
@@ -60,6 +60,11 @@ def lib():
         L.oracle_chain_point.restype = None
         L.oracle_chain_point.argtypes = [ct.c_int, ct.c_int, i64, P, P, P, ct.c_int, P, P, P,
                                          ct.c_double, i64, P, P, P, P]
+        L.oracle_dress_step_par.restype = i64
+        L.oracle_dress_step_par.argtypes = [ct.c_int, ct.c_int, i64, P, P, P, P, P, ct.c_double,
+                                            ct.c_double, ct.c_int, P, P, P]
+        L.oracle_qmf_energy_par.restype = ct.c_double
+        L.oracle_qmf_energy_par.argtypes = [ct.c_int, ct.c_int, i64, P, P, P, P, P, ct.c_int]
         L.oracle_qmf_grad_angles.restype = None
         L.oracle_qmf_grad_angles.argtypes = [ct.c_int, ct.c_int, i64, P, P, P, P, P, P, P]
         _lib = L
@@ -122,6 +127,27 @@ def merge_truncate(x, z, c, eps=0.0, dc=None):
 def dress(nq, x, z, c, px, pz, tau, eps=0.0):
     """One dressing step: raw dressing, merge, compression."""
     return merge_truncate(*dress_raw(nq, x, z, c, px, pz, tau), eps=eps)
+
+
+def dress_par(nq, x, z, c, px, pz, tau, eps=0.0, nthreads=1):
+    """dress() on `nthreads` host threads: the same terms and coefficients
+    (rows grouped by a key-hash partition, canonical inside each)."""
+    x, z, c = _rows(x, z, c)
+    n, W = x.shape
+    px = np.ascontiguousarray(px, np.uint64); pz = np.ascontiguousarray(pz, np.uint64)
+    ox = np.empty((max(2 * n, 1), W), np.uint64); oz = np.empty((max(2 * n, 1), W), np.uint64)
+    oc = np.empty(max(2 * n, 1), np.float64)
+    m = lib().oracle_dress_step_par(nq, W, n, _p(x), _p(z), _p(c), _p(px), _p(pz), float(tau),
+                                    float(eps), int(nthreads), _p(ox), _p(oz), _p(oc))
+    return ox[:m], oz[:m], oc[:m]
+
+
+def qmf_energy_par(nq, x, z, c, theta, phi, nthreads=1):
+    """qmf_energy() with the per-term products on `nthreads` threads (same value)."""
+    x, z, c = _rows(x, z, c)
+    n, W = x.shape
+    th = np.ascontiguousarray(theta, np.float64); ph = np.ascontiguousarray(phi, np.float64)
+    return lib().oracle_qmf_energy_par(nq, W, n, _p(x), _p(z), _p(c), _p(th), _p(ph), int(nthreads))
 
 
 def chain(nq, x, z, c, ents, taus, eps=0.0, callback=None):

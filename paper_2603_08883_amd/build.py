@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libiqcc.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "kernels_store.hip", "kernels_dress.hip", "kernels_energy.hip",
            "kernels_dis.hip", "kernels_merge.hip", "kernels_chain.hip", "kernels_qcc.hip",
-           "kernels_select.hip", "kernels_sortless.hip"]
+           "kernels_select.hip", "kernels_sortless.hip", "kernels_inplace.hip"]
 ARCH = os.environ.get("IQCC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

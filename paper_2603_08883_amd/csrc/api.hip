@@ -30,6 +30,10 @@ struct iqcc_ctx {
   int64_t fuse_energy = 1;
   int64_t dis_tile = 256;
   int64_t dis_bucket_ranges = 0;           // 0: about 8 workgroups per CU in total
+  int64_t inplace_bucket_terms = 128;      // mean bucket of an in-place store at max_terms
+  int64_t inplace_item_terms = 0;          // 0: from the stash capacity
+  int64_t inplace_cap = 0;                 // 0: as many stash entries as the LDS holds
+  int64_t inplace_region_rows = 0;         // 0: regions share the arena minus the pool
   // device scratch
   double* lut = nullptr;        // kMaxWords * 22 * 64
   double* partial = nullptr;    // n_partial
@@ -57,6 +61,7 @@ struct iqcc_store {
   void* mem = nullptr;    // the store's device memory (header, bucket table, arena)
   bool owned = false;     // true: allocated by iqcc_store_create*, freed by destroy
   double floor = 0.0;     // every live |c| is >= floor (0: unknown)
+  bool regions = false;   // contents laid out in bucket regions (in-place dressing allowed)
 };
 
 namespace {
@@ -227,8 +232,8 @@ namespace {
 // the bucket table (off, cnt, lim) and the arena planes x[W][cap], z[W][cap],
 // c[cap]; every array starts on a 256-byte boundary.
 struct StoreLayout {
-  int W = 0, mcap = 0, nhalves = 1;
-  int64_t half_rows = 0, cap = 0;
+  int W = 0, mcap = 0;
+  int64_t cap = 0;
   size_t off = 0, cnt = 0, lim = 0, x = 0, z = 0, c = 0, bytes = 0;
 };
 
@@ -244,16 +249,14 @@ bool store_layout(int n_qubits, int64_t max_terms, uint32_t flags, StoreLayout& 
   L.mcap = ilog2_ceil(max_terms / 16 + 1) + 1;
   if (L.mcap > kMaxBucketBits) L.mcap = kMaxBucketBits;
   if (flags & IQCC_STORE_INPLACE) {
-    // two halves: a relayout of up to max_terms input terms reserves at most
-    // 4 * max_terms rows (worst case with 2x slack), the rest of the live half
-    // is the pool for buckets that outgrow their region
-    L.nhalves = 2;
-    L.half_rows = 5 * max_terms + 1024;
+    // every bucket in a region of its own with room to grow (3 max_terms rows
+    // in all), plus a pool of max_terms / 2 rows for buckets that outgrow
+    // their region; rows are addressed with 32-bit offsets inside a step
+    L.cap = 3 * max_terms + max_terms / 2 + 4096;
+    if (L.cap >= (1ll << 31)) return false;
   } else {
-    L.nhalves = 1;
-    L.half_rows = 2 * max_terms + 1024;
+    L.cap = 2 * max_terms + 1024;
   }
-  L.cap = L.nhalves * L.half_rows;
   const size_t B = (size_t)1 << L.mcap;
   size_t o = kHeaderBytes;
   L.off = o; o = align256(o + 8 * B);
@@ -281,7 +284,7 @@ iqcc_store* store_from_memory(int n_qubits, int64_t max_terms, uint32_t flags, c
   st->d.m = (int*)(b + 16);
   st->d.err = (int*)(b + 20);
   st->d.stats = (int64_t*)(b + 24);
-  st->d.half = (int*)(b + 40);
+  st->d.aux = (int64_t*)(b + 40);
   st->d.off = (int64_t*)(b + L.off);
   st->d.cnt = (int64_t*)(b + L.cnt);
   st->d.lim = (int64_t*)(b + L.lim);
@@ -289,8 +292,6 @@ iqcc_store* store_from_memory(int n_qubits, int64_t max_terms, uint32_t flags, c
   st->d.z = (uint64_t*)(b + L.z);
   st->d.c = (double*)(b + L.c);
   st->d.cap = L.cap;
-  st->d.half_rows = L.half_rows;
-  st->d.nhalves = L.nhalves;
   st->d.mcap = L.mcap;
   return st;
 }
@@ -336,6 +337,21 @@ int store_open(iqcc_ctx* ctx, int n_qubits, int64_t max_terms, uint32_t flags, v
   }
   *out = st;
   return IQCC_OK;
+}
+
+// Bucket count and region rows of an in-place store: about
+// inplace_bucket_terms terms per bucket at max_terms, and regions that share
+// the arena minus a pool of max_terms / 2 rows.
+void inplace_geometry(const iqcc_ctx* ctx, const iqcc_store* st, int& m, int64_t& R) {
+  const double lg = std::log2((double)st->max_terms / (double)ctx->inplace_bucket_terms);
+  m = lg <= 0.0 ? 0 : (int)std::lround(lg);
+  if (m > st->d.mcap) m = st->d.mcap;
+  const int64_t pool = st->max_terms / 2 + 1024;
+  while (m > 0 && ((st->d.cap - pool) >> m) < 16) --m;   // regions of at least 16 rows
+  const int64_t B = 1ll << m;
+  R = ((st->d.cap - pool) / B) & ~(int64_t)15;
+  if (ctx->inplace_region_rows && ctx->inplace_region_rows < R) R = (ctx->inplace_region_rows + 15) & ~(int64_t)15;
+  if (R < 16) R = 16;
 }
 
 }  // namespace
@@ -400,6 +416,10 @@ int iqcc_set_param(iqcc_ctx* ctx, const char* name, int64_t v) {
       {"fuse_energy", &ctx->fuse_energy, 0, 1},
       {"dis_tile", &ctx->dis_tile, 1, 256},
       {"dis_bucket_ranges", &ctx->dis_bucket_ranges, 0, 4096},
+      {"inplace_bucket_terms", &ctx->inplace_bucket_terms, 1, 1 << 16},
+      {"inplace_item_terms", &ctx->inplace_item_terms, 0, 1 << 16},
+      {"inplace_cap", &ctx->inplace_cap, 0, 512},
+      {"inplace_region_rows", &ctx->inplace_region_rows, 0, 1 << 24},
   };
   for (auto& t : tab) {
     if (std::strcmp(t.n, name) == 0) {
@@ -421,6 +441,10 @@ int iqcc_get_param(const iqcc_ctx* ctx, const char* name, int64_t* v) {
       {"energy_grid_per_cu", ctx->energy_grid_per_cu},
       {"fuse_energy", ctx->fuse_energy}, {"dis_tile", ctx->dis_tile},
       {"dis_bucket_ranges", ctx->dis_bucket_ranges},
+      {"inplace_bucket_terms", ctx->inplace_bucket_terms},
+      {"inplace_item_terms", ctx->inplace_item_terms},
+      {"inplace_cap", ctx->inplace_cap},
+      {"inplace_region_rows", ctx->inplace_region_rows},
       {"n_cu", ctx->n_cu},
   };
   for (auto& t : tab)
@@ -488,11 +512,44 @@ int iqcc_store_load(iqcc_ctx* ctx, iqcc_store* st, const uint64_t* x, const uint
     rc = validate_rows(ctx, st->nq, st->W, x, z, n, ld, s);
     if (rc) return rc;
   }
+  st->floor = 0.0;
+  if (st->flags & IQCC_STORE_INPLACE) {
+    int64_t R = 0;
+    inplace_geometry(ctx, st, m, R);
+    const int64_t Bi = 1ll << m;
+    rc = ensure_scratch(ctx, 2 * Bi + Bi / 1024 + 16);
+    if (rc) return rc;
+    launch_store_load_regions(st->W, st->d, x, z, c, n, ld, m, R, ctx->scratch, s);
+    LAUNCH_CHECK(ctx);
+    st->regions = true;
+    return IQCC_OK;
+  }
   rc = ensure_scratch(ctx, B + B / 1024 + 16);
   if (rc) return rc;
-  st->floor = 0.0;
   launch_store_load(st->W, st->d, x, z, c, n, ld, m, ctx->scratch, s);
   LAUNCH_CHECK(ctx);
+  st->regions = false;
+  return IQCC_OK;
+}
+
+int iqcc_store_copy(iqcc_ctx* ctx, const iqcc_store* src, iqcc_store* dst, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!src || !dst) return fail(ctx, IQCC_ERR_INVALID_ARG, "store is null");
+  if (src == dst) return fail(ctx, IQCC_ERR_INVALID_ARG, "source and destination are the same store");
+  if (!(dst->flags & IQCC_STORE_INPLACE))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "destination is not an IQCC_STORE_INPLACE store");
+  if (src->nq != dst->nq) return fail(ctx, IQCC_ERR_INVALID_ARG, "qubit counts differ");
+  int m = 0;
+  int64_t R = 0;
+  inplace_geometry(ctx, dst, m, R);
+  const int64_t B = 1ll << m;
+  rc = ensure_scratch(ctx, B + B / 1024 + 16);
+  if (rc) return rc;
+  launch_store_copy_regions(dst->W, src->d, dst->d, m, R, ctx->scratch, as_stream(stream));
+  LAUNCH_CHECK(ctx);
+  dst->floor = src->floor;
+  dst->regions = true;
   return IQCC_OK;
 }
 
@@ -623,6 +680,7 @@ static int dress_impl(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px, c
   launch_dress(W, in->d, out->d, P, cfg, s);
   LAUNCH_CHECK(ctx);
   out->floor = eps;
+  out->regions = false;
   if (want_e) {
     if (!fused) launch_energy(W, out->d, grid, ctx->lut, ctx->partial, s);
     launch_finalize_sum(ctx->partial, grid, nullptr, energy, s, delta ? energy_in : nullptr);
@@ -646,6 +704,85 @@ int iqcc_dress_energy_update(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t
     return fail(ctx, IQCC_ERR_INVALID_ARG, "theta, phi, energy_in and energy_out are required");
   return dress_impl(ctx, in, px, pz, tau, eps, theta, phi, energy_in, energy_out, out, nullptr,
                     nullptr, stream);
+}
+
+int iqcc_dress_inplace(iqcc_ctx* ctx, iqcc_store* st, const uint64_t* px, const uint64_t* pz, double tau,
+                       double eps, const double* theta, const double* phi, const double* energy_in,
+                       double* energy_out, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!st || !px || !pz) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  if (!(st->flags & IQCC_STORE_INPLACE) || !st->regions)
+    return fail(ctx, IQCC_ERR_INVALID_ARG,
+                "store is not laid out in bucket regions (load or copy it into an IQCC_STORE_INPLACE store)");
+  if (!std::isfinite(tau)) return fail(ctx, IQCC_ERR_INVALID_ARG, "tau is not finite");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(ctx, IQCC_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  const bool want_e = theta || phi || energy_out;
+  if (want_e && !(theta && phi && energy_out))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "theta, phi and energy_out must be given together");
+  if (energy_in && !want_e) return fail(ctx, IQCC_ERR_INVALID_ARG, "energy_in without theta, phi, energy_out");
+  if (!padding_clear(st->nq, st->W, px, pz))
+    return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
+  const int W = st->W;
+  Entangler P = make_entangler(W, px, pz);
+  hipStream_t s = as_stream(stream);
+  const bool fused = want_e && ctx->fuse_energy;
+  const size_t budget = ctx->lds_per_block < ctx->lds_per_cu ? ctx->lds_per_block : ctx->lds_per_cu;
+  int cap = inplace_cap(W, fused, budget);
+  if (ctx->inplace_cap && ctx->inplace_cap < cap) cap = (int)ctx->inplace_cap;
+  if (cap < 16 || inplace_lds_bytes(W, cap, fused) > budget)
+    return fail(ctx, IQCC_ERR_UNSUPPORTED, "the in-place step does not fit the LDS of a workgroup");
+  const int grid = ctx->n_cu;
+  const int nparts = grid * inplace_waves_per_block();
+  rc = ensure_partial(ctx, nparts);
+  if (rc) return rc;
+  InplaceConfig cfg{};
+  cfg.C = std::cos(tau);
+  cfg.S = std::sin(tau);
+  cfg.eps = eps;
+  cfg.cap = cap;
+  cfg.item_terms = ctx->inplace_item_terms ? (int)ctx->inplace_item_terms : (3 * cap) / 2;
+  if (want_e) {
+    launch_build_lut(W, st->nq, theta, phi, ctx->lut, s);
+    LAUNCH_CHECK(ctx);
+  }
+  cfg.lut = fused ? ctx->lut : nullptr;
+  const bool delta = fused && energy_in;
+  cfg.delta = delta ? 1 : 0;
+  cfg.e_partial = ctx->partial;
+  launch_dress_inplace(W, st->d, P, cfg, grid, s);
+  LAUNCH_CHECK(ctx);
+  st->floor = eps;
+  if (want_e) {
+    if (fused) {
+      launch_finalize_sum(ctx->partial, nparts, nullptr, energy_out, s, delta ? energy_in : nullptr);
+    } else {
+      const int eg = (int)(ctx->n_cu * ctx->energy_grid_per_cu);
+      rc = ensure_partial(ctx, eg);
+      if (rc) return rc;
+      launch_energy(W, st->d, eg, ctx->lut, ctx->partial, s);
+      launch_finalize_sum(ctx->partial, eg, nullptr, energy_out, s);
+    }
+    LAUNCH_CHECK(ctx);
+  }
+  return IQCC_OK;
+}
+
+int iqcc_store_inplace_stats(iqcc_ctx* ctx, const iqcc_store* st, int64_t* relocated, int64_t* freed,
+                             int64_t* region_rows, int64_t* pool_used, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!st) return fail(ctx, IQCC_ERR_INVALID_ARG, "store is null");
+  int64_t buf[13];
+  hipStream_t s = as_stream(stream);
+  HIP_TRY(ctx, hipMemcpyAsync(buf, st->mem, sizeof buf, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  // header: total, top, m|err, stats[2], aux[8]
+  if (relocated) *relocated = buf[5 + 3];
+  if (freed) *freed = buf[5 + 4];
+  if (region_rows) *region_rows = buf[5 + 1];
+  if (pool_used) *pool_used = buf[1] - buf[5 + 2];
+  return IQCC_OK;
 }
 
 int iqcc_store_rows(const iqcc_store* st, int64_t* rows) {
@@ -801,6 +938,7 @@ static int batch_build(iqcc_ctx* ctx, int n_ham, const iqcc_store* const* ins,
     }
     h[i].in = a->d;
     h[i].out = o->d;
+    const_cast<iqcc_store*>(o)->regions = false;
     h[i].P = make_entangler(W, px + (size_t)i * W, pz + (size_t)i * W);
     h[i].C = std::cos(taus[i]);
     h[i].S = std::sin(taus[i]);
@@ -935,6 +1073,7 @@ int iqcc_merge_truncate(iqcc_ctx* ctx, const uint64_t* x, const uint64_t* z, con
   launch_merge_buckets(out->W, out->d, x, z, c, n, ld, m, eps, ctx->scratch, ctx->n_scratch,
                        as_stream(stream));
   LAUNCH_CHECK(ctx);
+  out->regions = false;
   return IQCC_OK;
 }
 
@@ -1295,6 +1434,7 @@ int iqcc_truncate_top(iqcc_ctx* ctx, const iqcc_store* in, int64_t max_terms, iq
     }
   }
   launch_select_compact(W, in->d, out->d, ss, keep_all, grid, s);
+  out->regions = false;
   LAUNCH_CHECK(ctx);
   HIP_TRY(ctx, hipStreamSynchronize(s));
   return IQCC_OK;

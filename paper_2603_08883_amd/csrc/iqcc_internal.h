@@ -268,10 +268,11 @@ struct StoreDev {
   int64_t* top;      // device scalar: arena rows reserved
   int* err;          // device scalar: 1 = arena overflow, 2 = bucket table overflow
   int64_t* stats;    // device [2]: anticommuting input terms, new terms of the last step
-  int* half;         // device scalar: arena half that holds the live rows (in-place stores)
-  int64_t half_rows; // rows per half (= cap for a store without the in-place layout)
+  int64_t* aux;      // device [8]: [0] change of `total` in an in-place step, [1] rows of
+                     //   a bucket region, [2] first pool row, [3] work items of the last
+                     //   in-place step that were relocated to the pool, [4] rows freed
+                     //   by compression in the last in-place step
   int mcap;          // bucket table holds 2^mcap buckets
-  int nhalves;       // 1, or 2 for a store that can be dressed in place
 };
 
 // Growth region of a bucket whose live rows are [off, off + cnt):
@@ -295,6 +296,162 @@ struct Entangler {
   uint8_t gstart[2 * kMaxWords + 1];                    // glist range of each half word
   uint8_t glist[2 * kMaxWords * kGroupsPerHalf];        // group index within its half word
 };
+
+// ---------------------------------------------------------------------------
+// Device helpers shared by the dressing kernels.
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ void load_key(const StoreDev& st, int64_t row, uint64_t* kx,
+                                         uint64_t* kz, double& c) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    kx[w] = st.x[w * st.cap + row];
+    kz[w] = st.z[w * st.cap + row];
+  }
+  c = st.c[row];
+}
+
+template <int W>
+__device__ __forceinline__ void store_key(const StoreDev& st, int64_t row, const uint64_t* kx,
+                                          const uint64_t* kz, double c) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    st.x[w * st.cap + row] = kx[w];
+    st.z[w * st.cap + row] = kz[w];
+  }
+  st.c[row] = c;
+}
+
+template <int W>
+__device__ __forceinline__ bool pivot_of(const Entangler& P, const uint64_t* kx,
+                                         const uint64_t* kz) {
+  uint64_t v = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    if (w == P.piv_word) v = P.piv_in_x ? kx[w] : kz[w];
+  return (v & P.piv_mask) != 0;
+}
+
+// residue classes use the high half of the representative hash; LDS table
+// slots use the low bits
+__device__ __forceinline__ uint32_t round_hash(uint32_t h) { return (h >> 16) | (h << 16); }
+
+template <int W>
+__device__ __forceinline__ uint32_t rep_hash(const Entangler& P, const uint64_t* kx,
+                                             const uint64_t* kz) {
+  uint64_t rx[W], rz[W];
+  const bool piv = pivot_of<W>(P, kx, kz);
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    rx[w] = piv ? kx[w] ^ P.px[w] : kx[w];
+    rz[w] = piv ? kz[w] ^ P.pz[w] : kz[w];
+  }
+  return table_hash<W>(rx, rz);
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ unsigned long long wave_bcast0(unsigned long long v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// <K> and <K^P> of the product state: A over the groups of K that P does not
+// touch, B and B' over P's groups for K and K^P (two of P's groups per LDS
+// round trip).
+template <int W>
+__device__ __forceinline__ void expect_split(const double* lut, const Entangler& P,
+                                             const uint64_t* x, const uint64_t* z, double& ek,
+                                             double& ekp) {
+  double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0, b = 1.0, b2 = 1.0, c1 = 1.0, c2 = 1.0;
+  if constexpr (W > 2) {
+    // A over the non-identity groups of K outside P's groups (fewer registers
+    // for wide keys)
+#pragma unroll
+    for (int h = 0; h < 2 * W; ++h) {
+      const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
+      const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
+      const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
+      uint32_t t = group_starts((xh | zh) & ~P.gbits[h]);
+      while (t) {
+        uint32_t e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = next_group_entry(t, xh, zh);
+        p0 *= lh[e[0]];
+        p1 *= lh[e[1]];
+        p2 *= lh[e[2]];
+        p3 *= lh[e[3]];
+      }
+    }
+  } else {
+    // A: every group of every half word with P's groups masked to the identity
+    // (table entry 0 = 1.0); each iteration issues 4 independent lookups per
+    // half word, so the whole product takes three LDS round trips
+    uint32_t xa[2 * W], za[2 * W];
+#pragma unroll
+    for (int h = 0; h < 2 * W; ++h) {
+      xa[h] = (uint32_t)(x[h >> 1] >> (32 * (h & 1))) & ~P.gbits[h];
+      za[h] = (uint32_t)(z[h >> 1] >> (32 * (h & 1))) & ~P.gbits[h];
+    }
+#pragma unroll 1
+    for (int g = 0; g < 12; g += 4) {
+      const uint32_t s0 = 3 * g;
+#pragma unroll
+      for (int h = 0; h < 2 * W; ++h) {
+        const double* lg = lut + (h * kGroupsPerHalf + g) * kLutEntries;
+        p0 *= lg[__builtin_amdgcn_ubfe(xa[h], s0, 3) | (__builtin_amdgcn_ubfe(za[h], s0, 3) << 3)];
+        p1 *= lg[kLutEntries + (__builtin_amdgcn_ubfe(xa[h], s0 + 3, 3) | (__builtin_amdgcn_ubfe(za[h], s0 + 3, 3) << 3))];
+        p2 *= lg[2 * kLutEntries + (__builtin_amdgcn_ubfe(xa[h], s0 + 6, 3) | (__builtin_amdgcn_ubfe(za[h], s0 + 6, 3) << 3))];
+        if (g + 3 < kGroupsPerHalf)
+          p3 *= lg[3 * kLutEntries + (__builtin_amdgcn_ubfe(xa[h], s0 + 9, 3) | (__builtin_amdgcn_ubfe(za[h], s0 + 9, 3) << 3))];
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2 * W; ++h) {
+    const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
+    const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
+    const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
+    const uint32_t pxh = (uint32_t)(P.px[h >> 1] >> (32 * (h & 1)));
+    const uint32_t pzh = (uint32_t)(P.pz[h >> 1] >> (32 * (h & 1)));
+    const int q1 = P.gstart[h + 1];
+    for (int q = P.gstart[h]; q < q1; q += 2) {   // two of P's groups per round trip
+      {
+        const uint32_t g = P.glist[q];
+        const uint32_t sh = 3 * g;
+        const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
+        const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
+        b *= lh[g * kLutEntries + code];
+        b2 *= lh[g * kLutEntries + (code ^ pcode)];
+      }
+      if (q + 1 < q1) {
+        const uint32_t g = P.glist[q + 1];
+        const uint32_t sh = 3 * g;
+        const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
+        const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
+        c1 *= lh[g * kLutEntries + code];
+        c2 *= lh[g * kLutEntries + (code ^ pcode)];
+      }
+    }
+  }
+  const double a = (p0 * p1) * (p2 * p3);
+  ek = a * (b * c1);
+  ekp = a * (b2 * c2);
+}
+
+__device__ __forceinline__ void pair_buckets(int64_t pi, uint32_t f, int thi, uint32_t& b0,
+                                             uint32_t& b1) {
+  if (f) {
+    const uint32_t lo = (uint32_t)pi & ((1u << thi) - 1);
+    b0 = (((uint32_t)pi >> thi) << (thi + 1)) | lo;
+    b1 = b0 ^ f;
+  } else {
+    b0 = b1 = (uint32_t)pi;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Host launchers (defined in the kernel files).
@@ -325,6 +482,29 @@ struct DressConfig {
 };
 void launch_dress(int W, const StoreDev& in, const StoreDev& out, const Entangler& P,
                   const DressConfig& cfg, hipStream_t s);
+
+// In-place dressing of a store laid out in bucket regions (kernels_inplace.hip).
+struct InplaceConfig {
+  double C, S, eps;
+  int cap;              // stash entries per wave (inplace_cap)
+  int item_terms;       // input terms per work item while buckets are small
+  const double* lut;    // null: no energy
+  int delta;            // 1: e_partial accumulates only the change of the energy
+  double* e_partial;    // [grid * inplace_waves_per_block()]
+};
+size_t inplace_lds_bytes(int W, int cap, bool energy);
+int inplace_cap(int W, bool energy, size_t lds_budget);
+int inplace_waves_per_block();
+void launch_dress_inplace(int W, const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, int grid,
+                          hipStream_t s);
+// Bucket regions: bucket b gets max(R, 2 cnt_b rounded up to 16) rows; the
+// pool starts after the last region.  Load of flat rows (as launch_store_load)
+// and copy of a store (deterministic: each destination bucket takes its rows
+// in source order).  Both set err = 1 when the regions do not fit the arena.
+int launch_store_load_regions(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
+                              int64_t n, int64_t ld, int m, int64_t R, int64_t* scratch, hipStream_t s);
+void launch_store_copy_regions(int W, const StoreDev& src, StoreDev dst, int m, int64_t R, int64_t* scratch,
+                               hipStream_t s);
 
 // One Hamiltonian of a batched dressing launch.
 struct BatchItem {

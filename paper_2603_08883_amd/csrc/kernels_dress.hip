@@ -109,65 +109,6 @@ struct PairState {
   }
 };
 
-template <int W>
-__device__ __forceinline__ void load_key(const StoreDev& st, int64_t row, uint64_t* kx,
-                                         uint64_t* kz, double& c) {
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    kx[w] = st.x[w * st.cap + row];
-    kz[w] = st.z[w * st.cap + row];
-  }
-  c = st.c[row];
-}
-
-template <int W>
-__device__ __forceinline__ void store_key(const StoreDev& st, int64_t row, const uint64_t* kx,
-                                          const uint64_t* kz, double c) {
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    st.x[w * st.cap + row] = kx[w];
-    st.z[w * st.cap + row] = kz[w];
-  }
-  st.c[row] = c;
-}
-
-template <int W>
-__device__ __forceinline__ bool pivot_of(const Entangler& P, const uint64_t* kx,
-                                         const uint64_t* kz) {
-  uint64_t v = 0;
-#pragma unroll
-  for (int w = 0; w < W; ++w)
-    if (w == P.piv_word) v = P.piv_in_x ? kx[w] : kz[w];
-  return (v & P.piv_mask) != 0;
-}
-
-// residue classes use the high half of the representative hash; LDS table
-// slots use the low bits
-__device__ __forceinline__ uint32_t round_hash(uint32_t h) { return (h >> 16) | (h << 16); }
-
-template <int W>
-__device__ __forceinline__ uint32_t rep_hash(const Entangler& P, const uint64_t* kx,
-                                             const uint64_t* kz) {
-  uint64_t rx[W], rz[W];
-  const bool piv = pivot_of<W>(P, kx, kz);
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    rx[w] = piv ? kx[w] ^ P.px[w] : kx[w];
-    rz[w] = piv ? kz[w] ^ P.pz[w] : kz[w];
-  }
-  return table_hash<W>(rx, rz);
-}
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-__device__ __forceinline__ unsigned long long wave_bcast0(unsigned long long v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-  return ((unsigned long long)hi << 32) | lo;
-}
-
 // Row positions for up to two entries per lane (categories a and b in
 // [0, 2 * NWORD), -1 for none) from the LDS counters ctr[0..NWORD), which hold
 // two 32-bit fields each (category 2k in the low field of word k, 2k + 1 in
@@ -204,89 +145,6 @@ __device__ __forceinline__ uint32_t wave_positions(unsigned long long* ctr, int 
     }
   }
   return nb;
-}
-
-// <K> and <K^P> of the product state: A over the groups of K that P does not
-// touch, B and B' over P's groups for K and K^P (two of P's groups per LDS
-// round trip).
-template <int W>
-__device__ __forceinline__ void expect_split(const double* lut, const Entangler& P,
-                                             const uint64_t* x, const uint64_t* z, double& ek,
-                                             double& ekp) {
-  double p0 = 1.0, p1 = 1.0, p2 = 1.0, p3 = 1.0, b = 1.0, b2 = 1.0, c1 = 1.0, c2 = 1.0;
-  if constexpr (W > 2) {
-    // A over the non-identity groups of K outside P's groups (fewer registers
-    // for wide keys)
-#pragma unroll
-    for (int h = 0; h < 2 * W; ++h) {
-      const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
-      const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
-      const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
-      uint32_t t = group_starts((xh | zh) & ~P.gbits[h]);
-      while (t) {
-        uint32_t e[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) e[k] = next_group_entry(t, xh, zh);
-        p0 *= lh[e[0]];
-        p1 *= lh[e[1]];
-        p2 *= lh[e[2]];
-        p3 *= lh[e[3]];
-      }
-    }
-  } else {
-    // A: every group of every half word with P's groups masked to the identity
-    // (table entry 0 = 1.0); each iteration issues 4 independent lookups per
-    // half word, so the whole product takes three LDS round trips
-    uint32_t xa[2 * W], za[2 * W];
-#pragma unroll
-    for (int h = 0; h < 2 * W; ++h) {
-      xa[h] = (uint32_t)(x[h >> 1] >> (32 * (h & 1))) & ~P.gbits[h];
-      za[h] = (uint32_t)(z[h >> 1] >> (32 * (h & 1))) & ~P.gbits[h];
-    }
-#pragma unroll 1
-    for (int g = 0; g < 12; g += 4) {
-      const uint32_t s0 = 3 * g;
-#pragma unroll
-      for (int h = 0; h < 2 * W; ++h) {
-        const double* lg = lut + (h * kGroupsPerHalf + g) * kLutEntries;
-        p0 *= lg[__builtin_amdgcn_ubfe(xa[h], s0, 3) | (__builtin_amdgcn_ubfe(za[h], s0, 3) << 3)];
-        p1 *= lg[kLutEntries + (__builtin_amdgcn_ubfe(xa[h], s0 + 3, 3) | (__builtin_amdgcn_ubfe(za[h], s0 + 3, 3) << 3))];
-        p2 *= lg[2 * kLutEntries + (__builtin_amdgcn_ubfe(xa[h], s0 + 6, 3) | (__builtin_amdgcn_ubfe(za[h], s0 + 6, 3) << 3))];
-        if (g + 3 < kGroupsPerHalf)
-          p3 *= lg[3 * kLutEntries + (__builtin_amdgcn_ubfe(xa[h], s0 + 9, 3) | (__builtin_amdgcn_ubfe(za[h], s0 + 9, 3) << 3))];
-      }
-    }
-  }
-#pragma unroll
-  for (int h = 0; h < 2 * W; ++h) {
-    const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
-    const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
-    const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
-    const uint32_t pxh = (uint32_t)(P.px[h >> 1] >> (32 * (h & 1)));
-    const uint32_t pzh = (uint32_t)(P.pz[h >> 1] >> (32 * (h & 1)));
-    const int q1 = P.gstart[h + 1];
-    for (int q = P.gstart[h]; q < q1; q += 2) {   // two of P's groups per round trip
-      {
-        const uint32_t g = P.glist[q];
-        const uint32_t sh = 3 * g;
-        const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
-        const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
-        b *= lh[g * kLutEntries + code];
-        b2 *= lh[g * kLutEntries + (code ^ pcode)];
-      }
-      if (q + 1 < q1) {
-        const uint32_t g = P.glist[q + 1];
-        const uint32_t sh = 3 * g;
-        const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
-        const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
-        c1 *= lh[g * kLutEntries + code];
-        c2 *= lh[g * kLutEntries + (code ^ pcode)];
-      }
-    }
-  }
-  const double a = (p0 * p1) * (p2 * p3);
-  ek = a * (b * c1);
-  ekp = a * (b2 * c2);
 }
 
 // One pass over the pair's input terms, each wave on its own 64-term slices
@@ -496,17 +354,6 @@ __device__ void emit_anti(const StoreDev& out, const Entangler& P, const Smem<W>
       if (j >= 0) tape_partner[sm.arow[i]] = (int32_t)(2 * (sm.orow[j] + 1) + ((sm.side[i] >> 1) & 1));
     }
     __syncthreads();
-  }
-}
-
-__device__ __forceinline__ void pair_buckets(int64_t pi, uint32_t f, int thi, uint32_t& b0,
-                                             uint32_t& b1) {
-  if (f) {
-    const uint32_t lo = (uint32_t)pi & ((1u << thi) - 1);
-    b0 = (((uint32_t)pi >> thi) << (thi + 1)) | lo;
-    b1 = b0 ^ f;
-  } else {
-    b0 = b1 = (uint32_t)pi;
   }
 }
 

@@ -1,0 +1,753 @@
+// In-place dressing step on gfx950 for stores laid out in bucket regions.
+//
+// The step computes what the out-of-place kernel computes (closed-form
+// dressing: Sec. II, Eq. 5; merge D = H + I: App. D; compression |c| < eps:
+// App. A, iterative procedure), but rewrites only what changes.  Every bucket
+// owns a region of rows with free rows after its live ones:
+//   - a term that commutes with P keeps its row, key and coefficient, so it is
+//     read (to classify it) and never written;
+//   - an anticommuting term K gets RN(cos tau c_K) + RN(s sin tau c_{K^P}) in
+//     its own row (8 bytes written);
+//   - a new key K^P (no partner in the input) is appended after the live rows
+//     of its bucket b ^ f;
+//   - rows freed by compression are refilled with the last live rows of the
+//     bucket, so the live rows stay contiguous.
+// A work item whose buckets would outgrow their regions (or whose
+// anticommuting terms do not fit the wave's LDS) is written to fresh regions
+// from the store's pool instead.
+//
+// Work split: one wavefront per work item, with no workgroup barrier after
+// the table load.  A work item is a bucket pair {b, b ^ f} (the single-device
+// form of the pairwise exchange between partitions, App. B/C), or several
+// consecutive pairs while buckets are small.  Wave g of the grid takes items
+// g, g + waves, g + 2 waves, ..., so every row position, every sum and the
+// energy partials are the same on every run.  Inside an item the anticommuting
+// terms are staged in the wave's LDS segment, joined on one member of each
+// {K, K^P} pair in an LDS hash table, and every output position comes from
+// ballots in stash order.
+#include "iqcc_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace iqcc {
+
+constexpr int kIPW = 16;          // waves per workgroup (one workgroup per CU)
+constexpr int kIPB = 64 * kIPW;
+constexpr int kIPSlots = 16;      // buckets per work item
+
+enum : uint8_t { kFComm = 1, kFHole = 2, kFNew = 4 };
+
+// Per-wave LDS segment: the stash of up to `cap` entries and the item's
+// bucket table.
+constexpr int kIPSlotArrays = 11;
+
+__host__ __device__ inline size_t seg_bytes(int W, int cap) {
+  size_t o = (size_t)W * cap * 16 + (size_t)cap * 8      // keys, coefficient
+           + (size_t)2 * cap * 4 + (size_t)cap * 4        // table (also the hole list), row
+           + (size_t)kIPSlotArrays * (kIPSlots + 1) * 4   // bucket table of the item
+           + (size_t)cap * 2 + (size_t)cap * 2;           // partner, slot + flag
+  return (o + 15) & ~(size_t)15;
+}
+
+size_t inplace_lds_bytes(int W, int cap, bool energy) {
+  return (energy ? (size_t)W * kGroupsPerWord * kLutEntries * 8 : 0) + kIPW * seg_bytes(W, cap);
+}
+
+int inplace_cap(int W, bool energy, size_t budget) {
+  int cap = 512;
+  while (cap > 8 && inplace_lds_bytes(W, cap, energy) > budget) cap -= 8;
+  return cap;
+}
+
+template <int W>
+struct Seg {
+  uint64_t* ax;      // [W][cap]
+  uint64_t* az;
+  double* ac;        // [cap]
+  int32_t* tab;      // [2 cap] join table, then the hole list
+  int32_t* arel;     // [cap] row of the entry relative to its bucket's first row
+  int32_t* s_off;    // bucket table of the item, one entry per slot:
+  int32_t* s_cnt;    //   first row, live rows, end of region (input)
+  int32_t* s_lim;
+  int32_t* s_pre;    //   [kIPSlots + 1] flat index of the slot's first term
+  int32_t* s_nnew;   //   new terms appended to the slot
+  int32_t* s_nhole;  //   rows freed by compression
+  int32_t* s_hfirst; //   first entry of the slot in the hole list
+  int32_t* s_ctr;    //   rows written so far (appends)
+  int32_t* s_noff;   //   first row / end of the fresh region (relocated items)
+  int32_t* s_nlim;
+  uint32_t* s_bkt;   //   bucket id
+  int16_t* partner;  // [cap]
+  uint8_t* aslot;    // [cap]
+  uint8_t* aflag;    // [cap]
+  int cap, tsize;
+};
+
+template <int W>
+__device__ __forceinline__ Seg<W> carve_seg(unsigned char* p, int cap) {
+  Seg<W> g;
+  size_t o = 0;
+  g.ax = (uint64_t*)(p + o); o += (size_t)W * cap * 8;
+  g.az = (uint64_t*)(p + o); o += (size_t)W * cap * 8;
+  g.ac = (double*)(p + o); o += (size_t)cap * 8;
+  g.tab = (int32_t*)(p + o); o += (size_t)2 * cap * 4;
+  g.arel = (int32_t*)(p + o); o += (size_t)cap * 4;
+  int32_t* sa = (int32_t*)(p + o); o += (size_t)kIPSlotArrays * (kIPSlots + 1) * 4;
+  g.s_off = sa;
+  g.s_cnt = sa + 1 * (kIPSlots + 1);
+  g.s_lim = sa + 2 * (kIPSlots + 1);
+  g.s_pre = sa + 3 * (kIPSlots + 1);
+  g.s_nnew = sa + 4 * (kIPSlots + 1);
+  g.s_nhole = sa + 5 * (kIPSlots + 1);
+  g.s_hfirst = sa + 6 * (kIPSlots + 1);
+  g.s_ctr = sa + 7 * (kIPSlots + 1);
+  g.s_noff = sa + 8 * (kIPSlots + 1);
+  g.s_nlim = sa + 9 * (kIPSlots + 1);
+  g.s_bkt = (uint32_t*)(sa + 10 * (kIPSlots + 1));
+  g.partner = (int16_t*)(p + o); o += (size_t)cap * 2;
+  g.aslot = (uint8_t*)(p + o); o += (size_t)cap;
+  g.aflag = (uint8_t*)(p + o);
+  g.cap = cap;
+  g.tsize = 2 * cap;
+  return g;
+}
+
+// LDS written by some lanes of this wave is read by others next: keep the
+// compiler from reordering across this point and wait for the LDS operations.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t table_slot(uint32_t h, int tsize) {
+  return (uint32_t)(((uint64_t)h * (uint32_t)tsize) >> 32);
+}
+
+// Largest slot s < nslots with pre[s] <= i (pre is non-decreasing, pre[0] = 0).
+__device__ __forceinline__ int slot_of(const int32_t* pre, int nslots, int i) {
+  int s = 0;
+#pragma unroll
+  for (int step = kIPSlots / 2; step; step >>= 1)
+    if (s + step < nslots && pre[s + step] <= i) s += step;
+  return s;
+}
+
+__device__ __forceinline__ bool sorted_contains(const int32_t* h, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (h[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo < n && h[lo] == v;
+}
+
+struct Geo {
+  uint32_t f;
+  int thi, selfp, ppi, nslots_max;
+  int64_t npairs, nitems;
+};
+
+struct WaveCounts {
+  int64_t anti = 0, fresh = 0, delta = 0, reloc = 0, freed = 0;
+};
+
+// Rows for the entries with `has` set, appended to their slot `d` in stash
+// order: at the tail of the live rows (tail) or in the slot's fresh region.
+template <int W>
+__device__ __forceinline__ void put_rows(const StoreDev& st, const Seg<W>& g, bool has, int d, bool tail,
+                                         const uint64_t* kx, const uint64_t* kz, double c) {
+  uint64_t todo = __ballot(has);
+  while (todo) {
+    const int lead = __builtin_ctzll(todo);
+    const int dd = __shfl(d, lead, 64);
+    const bool mine = has && d == dd;
+    const uint64_t mm = __ballot(mine);
+    const int base = g.s_ctr[dd];
+    if (mine) {
+      const int64_t row = (tail ? (int64_t)g.s_off[dd] + g.s_cnt[dd] : (int64_t)g.s_noff[dd]) + base +
+                          (int64_t)lanes_below(mm);
+      store_key<W>(st, row, kx, kz, c);
+    }
+    wave_sync();
+    if ((threadIdx.x & 63) == 0) g.s_ctr[dd] = base + __popcll(mm);
+    wave_sync();
+    todo &= ~mm;
+  }
+}
+
+// The item's buckets: slot s of pair k is bucket b0 (s = 2k) or b0 ^ f (s = 2k + 1),
+// or b0 alone when f = 0.  Returns the number of input terms of the item.
+template <int W>
+__device__ int item_setup(const StoreDev& st, const Geo& G, int64_t it, const Seg<W>& g, int& nslots) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q0 = it * G.ppi;
+  const int64_t left = G.npairs - q0;
+  const int np = (int)(left < G.ppi ? left : G.ppi);
+  nslots = G.selfp ? np : 2 * np;
+  int cnt = 0;
+  int64_t off = 0, lim = 0;
+  uint32_t b = 0;
+  if (lane < nslots) {
+    const int64_t q = q0 + (G.selfp ? lane : (lane >> 1));
+    uint32_t b0, b1;
+    pair_buckets(q, G.f, G.thi, b0, b1);
+    b = (!G.selfp && (lane & 1)) ? b1 : b0;
+    off = st.off[b];
+    cnt = (int)st.cnt[b];
+    lim = st.lim[b];
+  }
+  int incl = cnt;
+#pragma unroll
+  for (int d = 1; d < kIPSlots; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  const int n = __shfl(incl, nslots - 1, 64);
+  if (lane < nslots) {
+    g.s_off[lane] = (int32_t)off;
+    g.s_cnt[lane] = cnt;
+    g.s_lim[lane] = (int32_t)lim;
+    g.s_pre[lane] = incl - cnt;
+    g.s_bkt[lane] = b;
+    g.s_nnew[lane] = 0;
+    g.s_nhole[lane] = 0;
+    g.s_ctr[lane] = 0;
+  }
+  if (lane == 0) g.s_pre[nslots] = n;
+  wave_sync();
+  return n;
+}
+
+// One pass over the item's input terms, 128 per iteration (two loads in
+// flight per lane).
+//   mode 0: stash the anticommuting terms and the commuting terms that
+//           compression drops (flag kFComm); energy of the commuting terms;
+//   mode 1: append the kept commuting terms to the fresh regions, stash the
+//           anticommuting terms of residue class `rem` mod `mod`; energy of
+//           the commuting terms unless e_done;
+//   mode 2: stash the anticommuting terms of class `rem` only.
+// Returns the number of stash candidates (entries beyond cap are not
+// written); nanti receives the number of anticommuting terms.
+template <int W, bool ENERGY>
+__device__ int item_scan(const StoreDev& st, const Entangler& P, double eps, int delta,
+                         const double* lut, const Seg<W>& g, int nslots, int n, int mode, bool e_done,
+                         uint32_t mod, uint32_t rem, double& eacc, int& nanti) {
+  const int lane = threadIdx.x & 63;
+  int nst = 0;
+  nanti = 0;
+  for (int base = 0; base < n; base += 128) {
+    uint64_t kx[2][W], kz[2][W];
+    double kc[2];
+    int slot[2], rel[2];
+    bool valid[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = base + 64 * u + lane;
+      valid[u] = i < n;
+      slot[u] = valid[u] ? slot_of(g.s_pre, nslots, i) : 0;
+      rel[u] = valid[u] ? i - g.s_pre[slot[u]] : 0;
+      kc[u] = 0.0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) kx[u][w] = kz[u][w] = 0;
+      if (valid[u]) load_key<W>(st, (int64_t)g.s_off[slot[u]] + rel[u], kx[u], kz[u], kc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const bool anti = valid[u] && anticommutes<W>(kx[u], kz[u], P.px, P.pz);
+      nanti += (int)__popcll(__ballot(anti));
+      const bool comm_drop = valid[u] && !anti && fabs(kc[u]) < eps;
+      const bool comm_keep = valid[u] && !anti && !comm_drop;
+      bool stash = false;
+      if (anti && mode != 0 && mod > 1)
+        stash = (round_hash(rep_hash<W>(P, kx[u], kz[u])) & (mod - 1)) == rem;
+      else if (anti)
+        stash = true;
+      uint8_t flag = 0;
+      if (mode == 0 && comm_drop) {
+        stash = true;
+        flag = kFComm;
+      }
+      if (ENERGY && mode != 2 && !e_done) {
+        // commuting terms: every kept one, or (delta) only those compression drops
+        if (delta ? comm_drop : comm_keep) {
+          const double ek = expect_lut<W>(lut, kx[u], kz[u]);
+          eacc += comm_drop ? -(kc[u] * ek) : kc[u] * ek;
+        }
+      }
+      if (mode == 1) put_rows<W>(st, g, comm_keep, slot[u], false, kx[u], kz[u], kc[u]);
+      const uint64_t bm = __ballot(stash);
+      const int pos = nst + (int)lanes_below(bm);
+      if (stash && pos < g.cap) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          g.ax[w * g.cap + pos] = kx[u][w];
+          g.az[w * g.cap + pos] = kz[u][w];
+        }
+        g.ac[pos] = kc[u];
+        g.arel[pos] = rel[u];
+        g.aslot[pos] = (uint8_t)slot[u];
+        g.aflag[pos] = flag;
+      }
+      nst += (int)__popcll(bm);
+    }
+  }
+  wave_sync();
+  return nst;
+}
+
+template <int W>
+__device__ __forceinline__ void entry_key(const Seg<W>& g, int i, uint64_t* kx, uint64_t* kz) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    kx[w] = g.ax[w * g.cap + i];
+    kz[w] = g.az[w * g.cap + i];
+  }
+}
+
+// Pair each stashed anticommuting K with K^P: the members whose pivot bit is
+// 0 go into the table, the others look up K^P.
+template <int W>
+__device__ void item_join(const Entangler& P, const Seg<W>& g, int n) {
+  const int lane = threadIdx.x & 63;
+  for (int i = lane; i < g.tsize; i += 64) g.tab[i] = -1;
+  for (int i = lane; i < n; i += 64) g.partner[i] = -1;
+  wave_sync();
+  for (int i = lane; i < n; i += 64) {
+    if (g.aflag[i] & kFComm) continue;
+    uint64_t kx[W], kz[W];
+    entry_key<W>(g, i, kx, kz);
+    if (pivot_of<W>(P, kx, kz)) continue;
+    uint32_t h = table_slot(table_hash<W>(kx, kz), g.tsize);
+    while (atomicCAS(&g.tab[h], -1, i) != -1) h = (h + 1 == (uint32_t)g.tsize) ? 0 : h + 1;
+  }
+  wave_sync();
+  for (int i = lane; i < n; i += 64) {
+    if (g.aflag[i] & kFComm) continue;
+    uint64_t kx[W], kz[W];
+    entry_key<W>(g, i, kx, kz);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      kx[w] ^= P.px[w];
+      kz[w] ^= P.pz[w];
+    }
+    if (pivot_of<W>(P, kx, kz)) continue;   // the pivot bit of K is 0: K is in the table
+    uint32_t h = table_slot(table_hash<W>(kx, kz), g.tsize);
+    for (;;) {
+      const int j = g.tab[h];
+      if (j < 0) break;
+      bool eq = true;
+#pragma unroll
+      for (int w = 0; w < W; ++w) eq = eq && g.ax[w * g.cap + j] == kx[w] && g.az[w * g.cap + j] == kz[w];
+      if (eq) {
+        g.partner[i] = (int16_t)j;
+        g.partner[j] = (int16_t)i;
+        break;
+      }
+      h = (h + 1 == (uint32_t)g.tsize) ? 0 : h + 1;
+    }
+  }
+  wave_sync();
+}
+
+// Output values of stash entry i (an anticommuting term K with coefficient a):
+// own = RN(cos tau a) + RN(s_{K^P} sin tau a_{K^P}) when K^P is present, else
+// RN(cos tau a) together with the new term K^P of value s_K RN(sin tau a),
+// s = +1 for P K^.. = i^3 (..), -1 for i^1.
+template <int W>
+__device__ __forceinline__ void entry_values(const Entangler& P, double C, double S, const Seg<W>& g, int i,
+                                             const uint64_t* kx, const uint64_t* kz, double& a,
+                                             double& v_own, double& v_new, bool& paired) {
+  a = g.ac[i];
+  const int j = g.partner[i];
+  const double rot = __dmul_rn(C, a);
+  paired = j >= 0;
+  if (paired) {
+    uint64_t jx[W], jz[W];
+    entry_key<W>(g, j, jx, jz);
+    const int ej = product_phase<W>(P.px, P.pz, jx, jz);
+    const double sj = __dmul_rn(S, g.ac[j]);
+    v_own = __dadd_rn(rot, ej == 3 ? sj : -sj);
+    v_new = 0.0;
+  } else {
+    v_own = rot;
+    const int e = product_phase<W>(P.px, P.pz, kx, kz);
+    const double si = __dmul_rn(S, a);
+    v_new = e == 3 ? si : -si;
+  }
+}
+
+// In-place path, first emission pass: which entries free their row and which
+// add a new term, and how many per slot.
+template <int W>
+__device__ void count_outputs(const Entangler& P, double C, double S, double eps, const Seg<W>& g, int n,
+                              int selfp) {
+  const int lane = threadIdx.x & 63;
+  for (int i = lane; i < n; i += 64) {
+    uint8_t fl = g.aflag[i];
+    const int s = g.aslot[i];
+    if (fl & kFComm) {
+      fl |= kFHole;
+    } else {
+      uint64_t kx[W], kz[W];
+      entry_key<W>(g, i, kx, kz);
+      double a, vo, vn;
+      bool paired;
+      entry_values<W>(P, C, S, g, i, kx, kz, a, vo, vn, paired);
+      if (fabs(vo) < eps) fl |= kFHole;
+      if (!paired && !(fabs(vn) < eps)) {
+        fl |= kFNew;
+        atomicAdd(&g.s_nnew[selfp ? s : s ^ 1], 1);
+      }
+    }
+    if (fl & kFHole) atomicAdd(&g.s_nhole[s], 1);
+    g.aflag[i] = fl;
+  }
+  wave_sync();
+}
+
+// In-place path, second emission pass: rotated coefficients into their own
+// rows, new terms after the live rows of the partner bucket, energy.
+template <int W, bool ENERGY>
+__device__ void emit_inplace(const StoreDev& st, const Entangler& P, double C, double S, int delta,
+                             const double* lut, const Seg<W>& g, int n, int selfp, double& eacc) {
+  const int lane = threadIdx.x & 63;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    const bool valid = i < n;
+    const uint8_t fl = valid ? g.aflag[i] : (uint8_t)0;
+    const bool live = valid && !(fl & kFComm);
+    const int s = valid ? g.aslot[i] : 0;
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) kx[w] = kz[w] = 0;
+    double a = 0.0, vo = 0.0, vn = 0.0;
+    if (live) {
+      entry_key<W>(g, i, kx, kz);
+      bool paired;
+      entry_values<W>(P, C, S, g, i, kx, kz, a, vo, vn, paired);
+      if (!(fl & kFHole)) st.c[(int64_t)g.s_off[s] + g.arel[i]] = vo;
+      if (ENERGY) {
+        double ek, ekp;
+        expect_split<W>(lut, P, kx, kz, ek, ekp);
+        if (!(fl & kFHole)) eacc += vo * ek;
+        if (fl & kFNew) eacc += vn * ekp;
+        if (delta) eacc -= a * ek;
+      }
+    }
+    uint64_t qx[W], qz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      qx[w] = kx[w] ^ P.px[w];
+      qz[w] = kz[w] ^ P.pz[w];
+    }
+    put_rows<W>(st, g, live && (fl & kFNew), selfp ? s : s ^ 1, true, qx, qz, vn);
+  }
+  wave_sync();
+}
+
+// Relocation path emission: every kept output of the stash is appended to
+// the fresh region of its slot (own key to its own slot, K^P to the partner).
+template <int W, bool ENERGY>
+__device__ void emit_append(const StoreDev& st, const Entangler& P, double C, double S, double eps, int delta,
+                            const double* lut, const Seg<W>& g, int n, int selfp, double& eacc,
+                            int64_t& fresh) {
+  const int lane = threadIdx.x & 63;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    const bool valid = i < n;
+    const int s = valid ? g.aslot[i] : 0;
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) kx[w] = kz[w] = 0;
+    double a = 0.0, vo = 0.0, vn = 0.0;
+    bool paired = true;
+    if (valid) {
+      entry_key<W>(g, i, kx, kz);
+      entry_values<W>(P, C, S, g, i, kx, kz, a, vo, vn, paired);
+    }
+    const bool keep_own = valid && !(fabs(vo) < eps);
+    const bool keep_new = valid && !paired && !(fabs(vn) < eps);
+    if (ENERGY && valid) {
+      double ek, ekp;
+      expect_split<W>(lut, P, kx, kz, ek, ekp);
+      if (keep_own) eacc += vo * ek;
+      if (keep_new) eacc += vn * ekp;
+      if (delta) eacc -= a * ek;
+    }
+    fresh += __popcll(__ballot(keep_new));
+    put_rows<W>(st, g, keep_own, s, false, kx, kz, vo);
+    uint64_t qx[W], qz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      qx[w] = kx[w] ^ P.px[w];
+      qz[w] = kz[w] ^ P.pz[w];
+    }
+    put_rows<W>(st, g, keep_new, selfp ? s : s ^ 1, false, qx, qz, vn);
+  }
+  wave_sync();
+}
+
+// Refill the rows freed by compression with the last live rows of their
+// bucket (rows below the new count that are free take, in order, the live
+// rows at or above it).  The freed rows are the stash entries flagged kFHole,
+// in stash order, i.e. ascending within each slot.  Returns the rows freed.
+template <int W>
+__device__ int compact_holes(const StoreDev& st, const Seg<W>& g, int n, int nslots) {
+  const int lane = threadIdx.x & 63;
+  const int h = lane < nslots ? g.s_nhole[lane] : 0;
+  int incl = h;
+#pragma unroll
+  for (int d = 1; d < kIPSlots; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  const int total = __shfl(incl, nslots - 1, 64);
+  if (total == 0) return 0;
+  if (lane < nslots) g.s_hfirst[lane] = incl - h;
+  int32_t* holes = g.tab;   // the join table is no longer needed
+  int k = 0;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    const bool ho = i < n && (g.aflag[i] & kFHole);
+    const uint64_t bm = __ballot(ho);
+    if (ho) holes[k + (int)lanes_below(bm)] = g.arel[i];
+    k += (int)__popcll(bm);
+  }
+  wave_sync();
+  // this wave's row writes must be visible to its own loads below (the fence
+  // also drops stale lines from the CU's vector cache)
+  __threadfence();
+  for (int s = 0; s < nslots; ++s) {
+    const int nh = g.s_nhole[s];
+    if (nh == 0) continue;
+    const int end = g.s_cnt[s] + g.s_nnew[s];
+    const int fin = end - nh;
+    const int32_t* H = holes + g.s_hfirst[s];
+    const int64_t r0 = g.s_off[s];
+    int moved = 0;
+    for (int b = fin; b < end; b += 64) {
+      const int r = b + lane;
+      const bool lv = r < end && !sorted_contains(H, nh, r);
+      const uint64_t mm = __ballot(lv);
+      if (lv) {
+        const int dst = H[moved + (int)lanes_below(mm)];
+        uint64_t kx[W], kz[W];
+        double c;
+        load_key<W>(st, r0 + r, kx, kz, c);
+        store_key<W>(st, r0 + dst, kx, kz, c);
+      }
+      moved += (int)__popcll(mm);
+    }
+  }
+  return total;
+}
+
+template <int W, bool ENERGY>
+__device__ bool relocate_item(const StoreDev& st, const Entangler& P, const InplaceConfig& cfg,
+                              const double* lut, const Seg<W>& g, int nslots, int n, int selfp,
+                              bool e_done, int nanti, double& eacc, WaveCounts& wc) {
+  const int lane = threadIdx.x & 63;
+  // fresh regions from the pool: own rows + the partner's (worst case output)
+  int need = 0;
+  if (lane < nslots) {
+    const int c0 = g.s_cnt[lane];
+    const int cp = selfp ? c0 : g.s_cnt[lane ^ 1];
+    need = (c0 + cp + 15) & ~15;
+  }
+  int incl = need;
+#pragma unroll
+  for (int d = 1; d < kIPSlots; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  const int total = __shfl(incl, nslots - 1, 64);
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd((unsigned long long*)st.top, (unsigned long long)total);
+  base = wave_bcast0(base);
+  if ((int64_t)base + total > st.cap) {
+    if (lane == 0) atomicOr(st.err, 1);
+    return false;
+  }
+  if (lane < nslots) {
+    g.s_noff[lane] = (int32_t)(base + (incl - need));
+    g.s_nlim[lane] = (int32_t)(base + incl);
+    g.s_ctr[lane] = 0;
+  }
+  wave_sync();
+  // residue classes of a hash of the pair representative (both members of a
+  // {K, K^P} pair share the class), about cap/4 terms each; if a class still
+  // overflows the stash, the item is redone with twice as many classes (the
+  // fresh regions are rewritten from their start)
+  uint32_t R = 1;
+  while ((int64_t)R * (g.cap / 4) < nanti && R < (1u << 20)) R <<= 1;
+  for (;;) {
+    double e_try = 0.0;
+    int64_t fresh_try = 0;
+    if (lane < nslots) g.s_ctr[lane] = 0;
+    wave_sync();
+    bool ok = true;
+    for (uint32_t r = 0; r < R; ++r) {
+      int na;
+      const int nst = item_scan<W, ENERGY>(st, P, cfg.eps, cfg.delta, lut, g, nslots, n, r == 0 ? 1 : 2,
+                                           e_done, R, r, e_try, na);
+      if (nst > g.cap) {
+        ok = false;
+        break;
+      }
+      item_join<W>(P, g, nst);
+      emit_append<W, ENERGY>(st, P, cfg.C, cfg.S, cfg.eps, cfg.delta, lut, g, nst, selfp, e_try, fresh_try);
+    }
+    if (ok) {
+      eacc += e_try;
+      wc.fresh += fresh_try;
+      break;
+    }
+    if (R >= (1u << 20)) {
+      if (lane == 0) atomicOr(st.err, 4);
+      return false;
+    }
+    R <<= 1;
+  }
+  int dl = 0;
+  if (lane < nslots) {
+    const uint32_t b = g.s_bkt[lane];
+    st.off[b] = g.s_noff[lane];
+    st.lim[b] = g.s_nlim[lane];
+    st.cnt[b] = g.s_ctr[lane];
+    dl = g.s_ctr[lane] - g.s_cnt[lane];
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) dl += __shfl_down(dl, d, 64);
+  wc.delta += __shfl(dl, 0, 64);
+  wc.reloc += 1;
+  return true;
+}
+
+template <int W, bool ENERGY>
+__device__ void process_item(const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, const Geo& G,
+                             const double* lut, const Seg<W>& g, int64_t it, double& eacc, WaveCounts& wc) {
+  const int lane = threadIdx.x & 63;
+  int nslots;
+  const int n = item_setup<W>(st, G, it, g, nslots);
+  if (n == 0) return;
+  int nanti;
+  const int nst = item_scan<W, ENERGY>(st, P, cfg.eps, cfg.delta, lut, g, nslots, n, 0, false, 1, 0, eacc, nanti);
+  wc.anti += nanti;
+  if (nst > g.cap) {
+    relocate_item<W, ENERGY>(st, P, cfg, lut, g, nslots, n, G.selfp, true, nanti, eacc, wc);
+    return;
+  }
+  item_join<W>(P, g, nst);
+  count_outputs<W>(P, cfg.C, cfg.S, cfg.eps, g, nst, G.selfp);
+  // room for the appended rows before the freed ones are refilled
+  bool fits = true;
+  if (lane < nslots) fits = g.s_cnt[lane] + g.s_nnew[lane] <= g.s_lim[lane] - g.s_off[lane];
+  if (__ballot(!fits)) {
+    relocate_item<W, ENERGY>(st, P, cfg, lut, g, nslots, n, G.selfp, true, nanti, eacc, wc);
+    return;
+  }
+  emit_inplace<W, ENERGY>(st, P, cfg.C, cfg.S, cfg.delta, lut, g, nst, G.selfp, eacc);
+  const int freed = compact_holes<W>(st, g, nst, nslots);
+  int dl = 0, nw = 0;
+  if (lane < nslots) {
+    nw = g.s_nnew[lane];
+    dl = nw - g.s_nhole[lane];
+    st.cnt[g.s_bkt[lane]] = g.s_cnt[lane] + dl;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    dl += __shfl_down(dl, d, 64);
+    nw += __shfl_down(nw, d, 64);
+  }
+  wc.delta += __shfl(dl, 0, 64);
+  wc.fresh += __shfl(nw, 0, 64);
+  wc.freed += freed;
+}
+
+template <int W, bool ENERGY>
+__global__ __launch_bounds__(kIPB) void k_dress_inplace(StoreDev st, Entangler P, InplaceConfig cfg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const size_t lut_bytes = ENERGY ? (size_t)W * kGroupsPerWord * kLutEntries * 8 : 0;
+  double* lut = (double*)smem;
+  if (ENERGY) {
+    for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kIPB) lut[i] = cfg.lut[i];
+  }
+  __syncthreads();
+  const Seg<W> g = carve_seg<W>(smem + lut_bytes + (size_t)wave * seg_bytes(W, cfg.cap), cfg.cap);
+  const int64_t gw = (int64_t)blockIdx.x * kIPW + wave;
+  double eacc = 0.0;
+  WaveCounts wc;
+  if (*st.err == 0) {
+    const int m = *st.m;
+    const int64_t n_in = *st.total;
+    Geo G;
+    const uint32_t mask = (uint32_t)((1ull << m) - 1);
+    G.f = P.hp & mask;
+    G.selfp = G.f == 0;
+    G.thi = G.f ? 31 - __clz(G.f) : 0;
+    G.npairs = G.f ? (1ll << (m - 1)) : (1ll << m);
+    const int64_t mean = (n_in >> m) > 0 ? (n_in >> m) : 1;
+    const int64_t pair_terms = G.selfp ? mean : 2 * mean;
+    const int maxp = G.selfp ? kIPSlots : kIPSlots / 2;
+    int ppi = 1;
+    while (ppi * 2 <= maxp && (int64_t)ppi * 2 * pair_terms <= cfg.item_terms) ppi *= 2;
+    G.ppi = ppi;
+    G.nitems = (G.npairs + ppi - 1) / ppi;
+    const int64_t nw = (int64_t)gridDim.x * kIPW;
+    for (int64_t it = gw; it < G.nitems; it += nw)
+      process_item<W, ENERGY>(st, P, cfg, G, lut, g, it, eacc, wc);
+  }
+  if (lane == 0) {
+    if (wc.anti) atomicAdd((unsigned long long*)&st.stats[0], (unsigned long long)wc.anti);
+    if (wc.fresh) atomicAdd((unsigned long long*)&st.stats[1], (unsigned long long)wc.fresh);
+    if (wc.delta) atomicAdd((unsigned long long*)&st.aux[0], (unsigned long long)wc.delta);
+    if (wc.reloc) atomicAdd((unsigned long long*)&st.aux[3], (unsigned long long)wc.reloc);
+    if (wc.freed) atomicAdd((unsigned long long*)&st.aux[4], (unsigned long long)wc.freed);
+  }
+  if (ENERGY) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) eacc += __shfl_down(eacc, d, 64);
+    if (lane == 0) cfg.e_partial[gw] = eacc;
+  }
+}
+
+__global__ void k_inplace_begin(StoreDev st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st.stats[0] = 0;
+    st.stats[1] = 0;
+    st.aux[0] = 0;
+    st.aux[3] = 0;
+    st.aux[4] = 0;
+  }
+}
+
+__global__ void k_inplace_end(StoreDev st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *st.total += st.aux[0];
+}
+
+template <int W, bool E>
+static void launch_inplace_t(const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, int grid,
+                             hipStream_t s) {
+  const size_t lds = inplace_lds_bytes(W, cfg.cap, E);
+  (void)hipFuncSetAttribute((const void*)k_dress_inplace<W, E>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_dress_inplace<W, E>), dim3(grid), dim3(kIPB), lds, s, st, P, cfg);
+}
+
+void launch_dress_inplace(int W, const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, int grid,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_inplace_begin, dim3(1), dim3(64), 0, s, st);
+  const bool e = cfg.lut != nullptr;
+  switch (W) {
+    case 1: e ? launch_inplace_t<1, true>(st, P, cfg, grid, s) : launch_inplace_t<1, false>(st, P, cfg, grid, s); break;
+    case 2: e ? launch_inplace_t<2, true>(st, P, cfg, grid, s) : launch_inplace_t<2, false>(st, P, cfg, grid, s); break;
+    case 3: e ? launch_inplace_t<3, true>(st, P, cfg, grid, s) : launch_inplace_t<3, false>(st, P, cfg, grid, s); break;
+    default: e ? launch_inplace_t<4, true>(st, P, cfg, grid, s) : launch_inplace_t<4, false>(st, P, cfg, grid, s); break;
+  }
+  hipLaunchKernelGGL(k_inplace_end, dim3(1), dim3(64), 0, s, st);
+}
+
+int inplace_waves_per_block() { return kIPW; }
+
+}  // namespace iqcc

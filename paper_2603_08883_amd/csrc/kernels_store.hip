@@ -8,7 +8,6 @@ namespace iqcc {
 
 __global__ void k_zero_counters(StoreDev st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *st.half = 0;
     *st.total = 0;
     *st.top = 0;
     *st.err = 0;
@@ -151,7 +150,6 @@ __global__ void k_set_packed_lim(StoreDev st, int64_t B) {
 
 __global__ void k_load_finish(StoreDev st, int m, int64_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *st.half = 0;
     *st.m = m;
     *st.total = n;
     *st.top = n;
@@ -196,6 +194,171 @@ int launch_store_load(int W, StoreDev st, const uint64_t* x, const uint64_t* z, 
   }
   hipLaunchKernelGGL(k_load_finish, dim3(1), dim3(64), 0, s, st, m, n);
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Bucket regions (stores dressed in place): bucket b owns rows
+// [off_b, off_b + reg_b) with reg_b = max(R, 2 cnt_b rounded up to 16), so it
+// can grow after its live rows; the pool for buckets that outgrow their
+// region starts after the last region.
+// ---------------------------------------------------------------------------
+__global__ void k_region_sizes(const int64_t* cnt, int64_t B, int64_t R, int64_t* reg) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < B;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = (2 * cnt[b] + 15) & ~(int64_t)15;
+    reg[b] = r > R ? r : R;
+  }
+}
+
+__global__ void k_region_lim(StoreDev st, const int64_t* reg, int64_t B) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < B;
+       b += (int64_t)gridDim.x * blockDim.x)
+    st.lim[b] = st.off[b] + reg[b];
+}
+
+// n >= 0: the live terms; n < 0: take them (and an error flag) from src.
+__global__ void k_regions_finish(StoreDev st, const int64_t* reg, int64_t B, int m, int64_t R, int64_t n,
+                                 StoreDev src) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int64_t end = st.off[B - 1] + reg[B - 1];
+    const int serr = n < 0 ? *src.err : 0;
+    *st.m = m;
+    *st.total = n < 0 ? *src.total : n;
+    *st.top = end;
+    *st.err = serr ? serr : (end > st.cap ? 1 : 0);
+    st.stats[0] = 0;
+    st.stats[1] = 0;
+    st.aux[0] = 0;
+    st.aux[1] = R;
+    st.aux[2] = end;
+    st.aux[3] = 0;
+    st.aux[4] = 0;
+  }
+}
+
+template <int W>
+__global__ void k_load_scatter_guarded(const uint64_t* __restrict__ x, const uint64_t* __restrict__ z,
+                                       const double* __restrict__ c, int64_t n, int64_t ld, uint32_t mask,
+                                       int64_t* fill, StoreDev st) {
+  if (*st.err) return;   // the regions do not fit the arena: write nothing
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t kx[W], kz[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      kx[w] = x[w * ld + i];
+      kz[w] = z[w * ld + i];
+    }
+    const uint32_t b = bucket_hash<W>(kx, kz) & mask;
+    const int64_t pos = st.off[b] + (int64_t)atomicAdd((unsigned long long*)&fill[b], 1ull);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      st.x[w * st.cap + pos] = kx[w];
+      st.z[w * st.cap + pos] = kz[w];
+    }
+    st.c[pos] = c[i];
+  }
+}
+
+static void regions_from_counts(StoreDev st, int64_t B, int m, int64_t R, int64_t n, const StoreDev& src,
+                                int64_t* reg, int64_t* scan_tmp, hipStream_t s) {
+  int64_t lb = (B + kBlock - 1) / kBlock;
+  if (lb > 4096) lb = 4096;
+  hipLaunchKernelGGL(k_region_sizes, dim3((unsigned)lb), dim3(kBlock), 0, s, st.cnt, B, R, reg);
+  launch_scan_i64(reg, st.off, B, scan_tmp, s);
+  hipLaunchKernelGGL(k_region_lim, dim3((unsigned)lb), dim3(kBlock), 0, s, st, reg, B);
+  hipLaunchKernelGGL(k_regions_finish, dim3(1), dim3(64), 0, s, st, reg, B, m, R, n, src);
+}
+
+int launch_store_load_regions(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
+                              int64_t n, int64_t ld, int m, int64_t R, int64_t* scratch, hipStream_t s) {
+  const int64_t B = 1ll << m;
+  const uint32_t mask = (uint32_t)(B - 1);
+  int64_t* fill = scratch;              // B
+  int64_t* reg = scratch + B;           // B
+  int64_t* scan_tmp = scratch + 2 * B;  // ceil(B/1024)+1
+  fill_i64(st.cnt, B, 0, s);
+  fill_i64(fill, B, 0, s);
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  if (n > 0) {
+    switch (W) {
+      case 1: hipLaunchKernelGGL(k_load_hist<1>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, st.cnt); break;
+      case 2: hipLaunchKernelGGL(k_load_hist<2>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, st.cnt); break;
+      case 3: hipLaunchKernelGGL(k_load_hist<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, st.cnt); break;
+      default: hipLaunchKernelGGL(k_load_hist<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, st.cnt); break;
+    }
+  }
+  regions_from_counts(st, B, m, R, n, st, reg, scan_tmp, s);
+  if (n > 0) {
+    switch (W) {
+      case 1: hipLaunchKernelGGL(k_load_scatter_guarded<1>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, fill, st); break;
+      case 2: hipLaunchKernelGGL(k_load_scatter_guarded<2>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, fill, st); break;
+      case 3: hipLaunchKernelGGL(k_load_scatter_guarded<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, fill, st); break;
+      default: hipLaunchKernelGGL(k_load_scatter_guarded<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, fill, st); break;
+    }
+  }
+  return 0;
+}
+
+// One wave per destination bucket d (m bits): its terms are those of source
+// bucket d mod 2^ms whose hash has low bits d (m >= ms), or every term of the
+// source buckets d + k 2^m in order (m < ms).  COUNT: live rows only; else the
+// rows, in source order (ballot ranks).
+template <int W, bool COUNT>
+__global__ void k_copy_regions(StoreDev src, StoreDev dst, int m) {
+  if (*src.err || (!COUNT && *dst.err)) return;   // an invalid source is not read
+  const int lane = threadIdx.x & 63;
+  const int ms = *src.m;
+  const int64_t B = 1ll << m;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const uint32_t mask = (uint32_t)(B - 1);
+  const int64_t nsrc = m >= ms ? 1 : (1ll << (ms - m));
+  for (int64_t d = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); d < B; d += waves) {
+    int64_t k = 0;
+    const int64_t base = COUNT ? 0 : dst.off[d];
+    for (int64_t t = 0; t < nsrc; ++t) {
+      const int64_t sb = m >= ms ? (d & ((1ll << ms) - 1)) : d + (t << m);
+      const int64_t n = src.cnt[sb], off = src.off[sb];
+      for (int64_t i0 = 0; i0 < n; i0 += 64) {
+        const int64_t i = i0 + lane;
+        uint64_t kx[W], kz[W];
+        double c = 0.0;
+        bool sel = false;
+        if (i < n) {
+          load_key<W>(src, off + i, kx, kz, c);
+          sel = m < ms || (bucket_hash<W>(kx, kz) & mask) == (uint32_t)d;
+        }
+        const uint64_t bm = __ballot(sel);
+        if (!COUNT && sel) store_key<W>(dst, base + k + (int64_t)lanes_below(bm), kx, kz, c);
+        k += __popcll(bm);
+      }
+    }
+    if (COUNT && lane == 0) dst.cnt[d] = k;
+  }
+}
+
+void launch_store_copy_regions(int W, const StoreDev& src, StoreDev dst, int m, int64_t R, int64_t* scratch,
+                               hipStream_t s) {
+  const int64_t B = 1ll << m;
+  int64_t* reg = scratch;               // B
+  int64_t* scan_tmp = scratch + B;      // ceil(B/1024)+1
+  int64_t blocks = (B + kWaves - 1) / kWaves;
+  if (blocks > 16384) blocks = 16384;
+  switch (W) {
+    case 1: hipLaunchKernelGGL((k_copy_regions<1, true>), dim3(blocks), dim3(kBlock), 0, s, src, dst, m); break;
+    case 2: hipLaunchKernelGGL((k_copy_regions<2, true>), dim3(blocks), dim3(kBlock), 0, s, src, dst, m); break;
+    case 3: hipLaunchKernelGGL((k_copy_regions<3, true>), dim3(blocks), dim3(kBlock), 0, s, src, dst, m); break;
+    default: hipLaunchKernelGGL((k_copy_regions<4, true>), dim3(blocks), dim3(kBlock), 0, s, src, dst, m); break;
+  }
+  regions_from_counts(dst, B, m, R, -1, src, reg, scan_tmp, s);
+  switch (W) {
+    case 1: hipLaunchKernelGGL((k_copy_regions<1, false>), dim3(blocks), dim3(kBlock), 0, s, src, dst, m); break;
+    case 2: hipLaunchKernelGGL((k_copy_regions<2, false>), dim3(blocks), dim3(kBlock), 0, s, src, dst, m); break;
+    case 3: hipLaunchKernelGGL((k_copy_regions<3, false>), dim3(blocks), dim3(kBlock), 0, s, src, dst, m); break;
+    default: hipLaunchKernelGGL((k_copy_regions<4, false>), dim3(blocks), dim3(kBlock), 0, s, src, dst, m); break;
+  }
 }
 
 // ---------------------------------------------------------------------------

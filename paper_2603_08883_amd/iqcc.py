@@ -75,6 +75,10 @@ def lib():
         "iqcc_store_lookup": (i32, [P, P, P, P, i64, i64, P, P, P]),
         "iqcc_dress": (i32, [P, P, P, P, d, d, P, P, P, P, P]),
         "iqcc_dress_energy_update": (i32, [P, P, P, P, d, d, P, P, P, P, P, P]),
+        "iqcc_dress_inplace": (i32, [P, P, P, P, d, d, P, P, P, P, P]),
+        "iqcc_store_copy": (i32, [P, P, P, P]),
+        "iqcc_store_inplace_stats": (i32, [P, P, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64),
+                                           ct.POINTER(i64), P]),
         "iqcc_dress_raw": (i32, [P, i32, P, P, P, i64, i64, P, P, d, P, P, P, P, i64, P]),
         "iqcc_merge_truncate": (i32, [P, P, P, P, i64, i64, d, P, P]),
         "iqcc_qmf_energy": (i32, [P, P, P, P, P, P]),
@@ -115,7 +119,8 @@ def exported_symbols():
         "iqcc_pauli_products", "iqcc_chain_forward", "iqcc_chain_backward",
         "iqcc_store_shape", "iqcc_store_load", "iqcc_store_count", "iqcc_store_export",
         "iqcc_store_stats", "iqcc_store_lookup",
-        "iqcc_dress", "iqcc_dress_energy_update", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
+        "iqcc_dress", "iqcc_dress_energy_update", "iqcc_dress_inplace", "iqcc_store_copy",
+        "iqcc_store_inplace_stats", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
         "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
         "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
         "iqcc_dress_batched", "iqcc_batch_create", "iqcc_batch_launch", "iqcc_batch_destroy",
@@ -346,6 +351,36 @@ def iqcc_dress_energy_update(ctx, store_in, px, pz, tau: float, eps: float, stor
                                           _f64(energy_in, "energy_in"),
                                           _f64(energy_out, "energy_out"), store_out,
                                           _stream(stream)), ctx)
+
+
+def iqcc_dress_inplace(ctx, store, px, pz, tau: float, eps: float, theta=None, phi=None,
+                       energy_in=None, energy_out=None, stream=None):
+    """In-place dressing step of an IQCC_STORE_INPLACE store; px, pz host uint64
+    words.  energy_out (with theta, phi) receives the energy after the step;
+    energy_in, if given, is the energy before it (only the change is evaluated)."""
+    _, W = _nq(store)
+    ax, pxp = _words(px, W)
+    az, pzp = _words(pz, W)
+    opt = theta is None and phi is None and energy_out is None
+    if opt and energy_in is not None:
+        _bad("energy_in needs theta, phi and energy_out")
+    th, ph = _angles(store, theta, phi, optional=opt)
+    _check(lib().iqcc_dress_inplace(ctx, store, pxp, pzp, float(tau), float(eps), th, ph,
+                                    _f64(energy_in, "energy_in", 1, optional=True),
+                                    _f64(energy_out, "energy_out", 1, optional=opt),
+                                    _stream(stream)), ctx)
+
+
+def iqcc_store_copy(ctx, src, dst, stream=None):
+    """Copy the terms of src into the IQCC_STORE_INPLACE store dst (bucket regions)."""
+    _check(lib().iqcc_store_copy(ctx, src, dst, _stream(stream)), ctx)
+
+
+def iqcc_store_inplace_stats(ctx, store, stream=None):
+    """Synchronising: {relocated, freed, region_rows, pool_used} of the last in-place step."""
+    v = [ct.c_int64() for _ in range(4)]
+    _check(lib().iqcc_store_inplace_stats(ctx, store, *[ct.byref(a) for a in v], _stream(stream)), ctx)
+    return dict(zip(("relocated", "freed", "region_rows", "pool_used"), (a.value for a in v)))
 
 
 def iqcc_dress_count(ctx, store_in, px, pz, stream=None) -> int:

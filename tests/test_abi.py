@@ -98,6 +98,9 @@ def test_new_entry_points_reject_null_context(lib):
     assert lib.iqcc_store_create_ex(None, 8, 100, 0, ct.byref(h)) == bad
     assert lib.iqcc_store_wrap(None, 8, 100, 0, None, 0, ct.byref(h), None) == bad
     assert lib.iqcc_dress_count(None, None, None, None, ct.byref(n), None) == bad
+    assert lib.iqcc_dress_inplace(None, None, None, None, 0.1, 0.0, None, None, None, None, None) == bad
+    assert lib.iqcc_store_copy(None, None, None, None) == bad
+    assert lib.iqcc_store_inplace_stats(None, None, None, None, None, None, None) == bad
     assert lib.iqcc_pauli_products(None, 8, None, None, None, None, 0, 0, None, None, None, None) == bad
     assert lib.iqcc_chain_forward(None, None, 0, None, None, None, 0.0, None, None, None, None) == bad
     assert lib.iqcc_chain_backward(None, None, 0, None, None, None, None, None, None, None,
@@ -111,7 +114,11 @@ def test_store_bytes_host_only(lib):
     assert 0 < small < big
     # the arena dominates: 2 * max_terms rows of (16 W + 8) bytes for W = 2
     assert big >= 2 * 100000 * 40
-    assert b(124, 100000, iqcc.IQCC_STORE_INPLACE) >= 4.5 * big
+    # an in-place store: 3.5 * max_terms rows (regions + pool), below 2^31 rows
+    assert b(124, 100000, iqcc.IQCC_STORE_INPLACE) >= 1.7 * big
+    with pytest.raises(iqcc.IqccError) as e:
+        b(124, 1 << 30, iqcc.IQCC_STORE_INPLACE)
+    assert e.value.code == iqcc.IQCC_ERR_INVALID_ARG
     assert b(64, 1000) < b(65, 1000)               # one more word per key
     for args in ((0, 100), (8, 0), (8, -5), (8, 1 << 40), (8, 100, 2)):
         with pytest.raises(iqcc.IqccError) as e:

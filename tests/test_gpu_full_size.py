@@ -1,91 +1,135 @@
-"""Parity at the full 124-qubit workload, in the launch configuration bench.py
-times (default knobs, fused energy, ping-pong stores).
+"""Parity at the full 124-qubit workload (banded JW H0 of 62 orbitals, band 6,
+decay 3; 20 DIS entanglers, tau ~ U(-0.2, 0.2), eps = 1e-8), in the launch
+configuration bench.py times, against expected values that the oracle alone
+wrote (tests/golden/c3_chain.json, from tests/golden/make_goldens.py):
 
-* The first 6 steps are compared with the oracle's full chain term by term
-  (bit-exact) and energy by energy (1e-10).
-* After all 20 steps (~1.5e8 terms) 4000 sampled output terms are recomputed
-  one by one by the oracle's point query of the chain (bit-exact), and keys
-  K ^ P_j around them are checked both ways (present/absent and value) through
-  the device lookup.
-* The energy fused into every dressing step (computed in full on even steps,
-  carried forward from the previous step on odd ones) equals the stand-alone
-  energy kernel on that step's output (property that holds at any size).
+* every one of the 20 steps: the live term count, the number of
+  anticommuting input terms, the order-independent 64-bit digest of the
+  (key, coefficient bits) multiset -- so keys and coefficients are compared
+  bit for bit -- and the QMF energy within 1e-10 (Sec. II Eqs. 3 and 5,
+  App. D merge, App. A compression);
+* the same for the out-of-place kernel chain;
+* the 248 angle gradients of the final Hamiltonian within 1e-10 and
+  dE/dtau_k for k in {0, 9, 19} (compression masks frozen, Eq. 6) within
+  1e-10 relative, through the taped chain and its reverse sweep.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
 
-from oracle import oracle as O
 from paper_2603_08883_amd import inputs as I
 from paper_2603_08883_amd import iqcc
-from tests.gpu_util import assert_same_terms, describe
+from paper_2603_08883_amd.autograd import DressingChain
+from tests.gpu_util import describe
+from tests.golden.multiset_hash import multiset_hash, multiset_hash_torch
 
 pytestmark = pytest.mark.gpu
 
 NQ, STEPS, EPS, CONFIG = 124, 20, 1e-8, 2
-PREFIX = 6
+MAX_TERMS = int(1.3e8)          # the in-place stores of bench.py
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_chain.json")
 
 
 @pytest.fixture(scope="module")
-def workload():
+def gold():
+    return json.load(open(GOLDEN))
+
+
+@pytest.fixture(scope="module")
+def workload(gold):
     x, z, c = I.hamiltonian_banded(NQ, CONFIG, band=6, decay=3.0)
+    assert f"{multiset_hash(x, z, c):016x}" == gold["initial_digest"], "input generator changed"
     cx, cz = I.dis_candidates(x, NQ, STEPS, 8, I.rng_for(CONFIG, I.PURPOSE_ENTANGLERS))
     taus = I.taus(STEPS, I.rng_for(CONFIG, I.PURPOSE_TAUS))
     th, ph = I.qmf_angles(NQ, I.rng_for(CONFIG, I.PURPOSE_ANGLES))
     return x, z, c, list(zip(cx, cz)), taus, th, ph
 
 
-def test_full_size_chain(workload):
+@pytest.fixture(scope="module")
+def ctx():
+    c = iqcc.Context(0)
+    yield c
+    c.close()
+
+
+def _digest(ctx, store):
+    x, z, c = iqcc.iqcc_store_export(ctx.handle, store.handle)
+    d = multiset_hash_torch(x, z, c)
+    del x, z, c
+    torch.cuda.empty_cache()
+    return f"{d:016x}"
+
+
+def _check_step(ctx, j, store, energy, ref):
+    n = store.count()
+    assert n == ref["n_out"], (j, n, ref["n_out"])
+    n_anti, _ = iqcc.iqcc_store_stats(ctx.handle, store.handle)
+    assert n_anti == ref["n_anti"], (j, n_anti, ref["n_anti"])
+    assert _digest(ctx, store) == ref["digest"], f"step {j}: terms or coefficient bits differ"
+    e_ref = ref["energy"]["value"]
+    assert abs(energy - e_ref) <= 1e-10, (j, energy, e_ref)
+
+
+def test_full_size_inplace_chain_against_goldens(ctx, gold, workload):
     x, z, c, ents, taus, th, ph = workload
-    ctx = iqcc.Context(0)
-    h0 = iqcc.Store(ctx, NQ, 2 * len(c)).load_numpy(x, z, c)
-    s1 = iqcc.Store(ctx, NQ, int(6e8))
-    s2 = iqcc.Store(ctx, NQ, int(6e8))
+    INPLACE = iqcc.IQCC_STORE_INPLACE
+    h0 = iqcc.Store(ctx, NQ, MAX_TERMS, INPLACE).load_numpy(x, z, c)
+    work = iqcc.Store(ctx, NQ, MAX_TERMS, INPLACE)
     tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
     e = torch.zeros(STEPS, dtype=torch.float64, device="cuda")
-    src, outs = h0, (s1, s2)
-    ox, oz, oc = x, z, c
+    iqcc.iqcc_store_copy(ctx.handle, h0.handle, work.handle)
     for j, ((px, pz), t) in enumerate(zip(ents, taus)):
-        dst = outs[j % 2]
-        describe(j, "full-size dress", n=src.count(), update=j % 2)
+        describe(j, "full-size in-place dress", carry=j > 0)
+        iqcc.iqcc_dress_inplace(ctx.handle, work.handle, px, pz, t, EPS, tht, pht,
+                                e[j - 1:j] if j else None, e[j:j + 1])
+        _check_step(ctx, j, work, float(e[j].item()), gold["steps"][j])
+    h0.close(); work.close()
+    torch.cuda.empty_cache()
+
+
+def test_full_size_out_of_place_chain_against_goldens(ctx, gold, workload):
+    x, z, c, ents, taus, th, ph = workload
+    h0 = iqcc.Store(ctx, NQ, 2 * len(c)).load_numpy(x, z, c)
+    s1 = iqcc.Store(ctx, NQ, MAX_TERMS)
+    s2 = iqcc.Store(ctx, NQ, MAX_TERMS)
+    tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
+    e = torch.zeros(STEPS, dtype=torch.float64, device="cuda")
+    src = h0
+    for j, ((px, pz), t) in enumerate(zip(ents, taus)):
+        dst = (s1, s2)[j % 2]
+        describe(j, "full-size out-of-place dress", carry=j % 2)
         if j % 2:
-            # odd steps carry the energy forward from the previous step's result
             iqcc.iqcc_dress_energy_update(ctx.handle, src.handle, px, pz, t, EPS, dst.handle, tht, pht,
                                           e[j - 1:j], e[j:j + 1])
         else:
             iqcc.iqcc_dress(ctx.handle, src.handle, px, pz, t, EPS, dst.handle, tht, pht, e[j:j + 1])
-        n = dst.count()
-        # fused energy == stand-alone energy kernel on the same output
-        e2 = iqcc.iqcc_qmf_energy(ctx.handle, dst.handle, tht, pht)
-        assert abs(e[j].item() - e2.item()) <= 1e-10, (j, e[j].item(), e2.item())
-        if j < PREFIX:
-            ox, oz, oc = O.dress(NQ, ox, oz, oc, px, pz, t, EPS)
-            assert_same_terms(dst.to_numpy(), (ox, oz, oc), f"step {j}")
-            assert abs(e[j].item() - O.qmf_energy(NQ, ox, oz, oc, th, ph)) <= 1e-10
+        _check_step(ctx, j, dst, float(e[j].item()), gold["steps"][j])
         src = dst
-    final = src
-    n_final = final.count()
-    assert n_final > 5e7
-    # sampled output rows, recomputed one by one by the oracle
-    fx, fz, fc = iqcc.iqcc_store_export(ctx.handle, final.handle)
-    g = torch.Generator(device="cuda").manual_seed(5)
-    idx = torch.randint(0, n_final, (4000,), device="cuda", generator=g)
-    sx = iqcc.from_device_words(fx[:, idx]); sz = iqcc.from_device_words(fz[:, idx])
-    sc = fc[idx].cpu().numpy()
-    del fx, fz, fc
+    h0.close(); s1.close(); s2.close()
     torch.cuda.empty_cache()
-    describe(STEPS, "point queries", n=len(sc))
-    found, val = O.chain_point(NQ, x, z, c, ents, taus, EPS, sx, sz)
-    assert found.all()
-    assert np.array_equal(val, sc)
-    # neighbours K ^ P_j: presence and value must agree both ways
-    for j in (STEPS - 1, STEPS - 2, 3):
-        qx = sx[:1000] ^ np.asarray(ents[j][0], np.uint64)
-        qz = sz[:1000] ^ np.asarray(ents[j][1], np.uint64)
-        f_o, v_o = O.chain_point(NQ, x, z, c, ents, taus, EPS, qx, qz)
-        f_g, v_g = iqcc.iqcc_store_lookup(ctx.handle, final.handle, iqcc.to_device_words(qx),
-                                          iqcc.to_device_words(qz))
-        f_g = f_g.cpu().numpy(); v_g = v_g.cpu().numpy()
-        assert np.array_equal(f_o, f_g), (j, f_o.sum(), f_g.sum())
-        assert np.array_equal(v_o[f_o], v_g[f_g])
-    h0.close(); s1.close(); s2.close(); ctx.close()
+
+
+def test_full_size_gradients_against_goldens(ctx, gold, workload):
+    x, z, c, ents, taus, th, ph = workload
+    tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
+    chain = DressingChain(ctx, NQ, x, z, c, ents, EPS)
+    describe(0, "full-size taped chain")
+    final = chain.run(list(taus))
+    assert _digest(ctx, final) == gold["steps"][-1]["digest"]
+    lam = torch.empty(iqcc.iqcc_store_rows(final.handle), dtype=torch.float64, device="cuda")
+    describe(STEPS, "full-size angle backward")
+    dth, dph = iqcc.iqcc_qmf_energy_backward(ctx.handle, final.handle, tht, pht, None, lam)
+    ref_t = np.array([v["value"] for v in gold["grad_theta"]])
+    ref_p = np.array([v["value"] for v in gold["grad_phi"]])
+    assert np.abs(dth.cpu().numpy() - ref_t).max() <= 1e-10
+    assert np.abs(dph.cpu().numpy() - ref_p).max() <= 1e-10
+    describe(STEPS, "full-size tau backward")
+    dtau = chain.backward_taus(list(taus), lam).cpu().numpy()
+    for k, v in gold["grad_tau"].items():
+        g = v["value"]
+        assert abs(dtau[int(k)] - g) <= 1e-10 * max(1.0, abs(g)), (k, dtau[int(k)], g)
+    chain.close()
+    torch.cuda.empty_cache()
