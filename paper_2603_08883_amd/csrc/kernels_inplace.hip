@@ -8,44 +8,52 @@
 //     read (to classify it) and never written;
 //   - an anticommuting term K gets RN(cos tau c_K) + RN(s sin tau c_{K^P}) in
 //     its own row (8 bytes written);
-//   - a new key K^P (no partner in the input) is appended after the live rows
-//     of its bucket b ^ f;
-//   - rows freed by compression are refilled with the last live rows of the
-//     bucket, so the live rows stay contiguous.
+//   - a new key K^P (no partner in the input) goes to its bucket b ^ f: first
+//     into rows freed by compression, then after the live rows;
+//   - when compression frees more rows of a bucket than new keys arrive, the
+//     last live rows of the bucket move down into the remaining free rows, so
+//     the live rows stay contiguous.
 // A work item whose buckets would outgrow their regions (or whose
-// anticommuting terms do not fit the wave's LDS) is written to fresh regions
-// from the store's pool instead.
+// anticommuting terms do not fit the wave's LDS stash) is written to fresh
+// regions from the store's pool instead.
 //
 // Work split: one wavefront per work item, with no workgroup barrier after
 // the table load.  A work item is a bucket pair {b, b ^ f} (the single-device
-// form of the pairwise exchange between partitions, App. B/C), or several
+// form of the pairwise exchange between partitions, App. B/C), or up to 32
 // consecutive pairs while buckets are small.  Wave g of the grid takes items
-// g, g + waves, g + 2 waves, ..., so every row position, every sum and the
-// energy partials are the same on every run.  Inside an item the anticommuting
-// terms are staged in the wave's LDS segment, joined on one member of each
-// {K, K^P} pair in an LDS hash table, and every output position comes from
-// ballots in stash order.
+// g, g + waves, g + 2 waves, ..., and loads the bucket table of its next item
+// while it works on the current one.  Every row position, every sum and the
+// energy partials are the same on every run.  Inside an item the
+// anticommuting terms are staged in the wave's LDS segment, joined on one
+// member of each {K, K^P} pair in an LDS hash table, and every output
+// position comes from ballots in stash order.  Lane s of the wave holds the
+// bucket table entry of the item's slot s.
 #include "iqcc_internal.h"
 
 #pragma clang fp contract(off)
 
 namespace iqcc {
 
-constexpr int kIPW = 16;          // waves per workgroup (one workgroup per CU)
+#ifndef IQCC_INPLACE_WAVES
+#define IQCC_INPLACE_WAVES 16
+#endif
+constexpr int kIPW = IQCC_INPLACE_WAVES;   // waves per workgroup (one workgroup per CU)
 constexpr int kIPB = 64 * kIPW;
-constexpr int kIPSlots = 16;      // buckets per work item
+constexpr int kIPSlots = 64;      // buckets per work item (one per lane)
 
 enum : uint8_t { kFComm = 1, kFHole = 2, kFNew = 4 };
 
-// Per-wave LDS segment: the stash of up to `cap` entries and the item's
-// bucket table.
-constexpr int kIPSlotArrays = 11;
+// Per-wave LDS segment: the stash of up to `cap` entries, its join table and
+// per-slot counters of the item.
+constexpr int kIPSlotArrays = 5;
+
+__host__ __device__ inline int ip_tsize(int cap) { return (3 * cap / 2 + 7) & ~7; }
 
 __host__ __device__ inline size_t seg_bytes(int W, int cap) {
-  size_t o = (size_t)W * cap * 16 + (size_t)cap * 8      // keys, coefficient
-           + (size_t)2 * cap * 4 + (size_t)cap * 4        // table (also the hole list), row
-           + (size_t)kIPSlotArrays * (kIPSlots + 1) * 4   // bucket table of the item
-           + (size_t)cap * 2 + (size_t)cap * 2;           // partner, slot + flag
+  size_t o = (size_t)W * cap * 16 + (size_t)cap * 8       // keys, coefficient
+           + (size_t)ip_tsize(cap) * 4 + (size_t)cap * 4   // join table (later the freed rows), row
+           + (size_t)kIPSlotArrays * (kIPSlots + 1) * 4    // per-slot counters
+           + (size_t)cap * 2 + (size_t)cap * 2;            // partner, slot + flag
   return (o + 15) & ~(size_t)15;
 }
 
@@ -64,19 +72,13 @@ struct Seg {
   uint64_t* ax;      // [W][cap]
   uint64_t* az;
   double* ac;        // [cap]
-  int32_t* tab;      // [2 cap] join table, then the hole list
+  int32_t* tab;      // [tsize] join table; afterwards the freed rows of every slot
   int32_t* arel;     // [cap] row of the entry relative to its bucket's first row
-  int32_t* s_off;    // bucket table of the item, one entry per slot:
-  int32_t* s_cnt;    //   first row, live rows, end of region (input)
-  int32_t* s_lim;
-  int32_t* s_pre;    //   [kIPSlots + 1] flat index of the slot's first term
-  int32_t* s_nnew;   //   new terms appended to the slot
-  int32_t* s_nhole;  //   rows freed by compression
-  int32_t* s_hfirst; //   first entry of the slot in the hole list
-  int32_t* s_ctr;    //   rows written so far (appends)
-  int32_t* s_noff;   //   first row / end of the fresh region (relocated items)
-  int32_t* s_nlim;
-  uint32_t* s_bkt;   //   bucket id
+  int32_t* s_pre;    // [kIPSlots + 1] flat index of the slot's first input term
+  int32_t* s_nnew;   // new keys arriving in the slot
+  int32_t* s_nhole;  // rows of the slot freed by compression
+  int32_t* s_hfirst; // first freed row of the slot in the list
+  int32_t* s_ctr;    // rows placed so far
   int16_t* partner;  // [cap]
   uint8_t* aslot;    // [cap]
   uint8_t* aflag;    // [cap]
@@ -90,46 +92,34 @@ __device__ __forceinline__ Seg<W> carve_seg(unsigned char* p, int cap) {
   g.ax = (uint64_t*)(p + o); o += (size_t)W * cap * 8;
   g.az = (uint64_t*)(p + o); o += (size_t)W * cap * 8;
   g.ac = (double*)(p + o); o += (size_t)cap * 8;
-  g.tab = (int32_t*)(p + o); o += (size_t)2 * cap * 4;
+  g.tsize = ip_tsize(cap);
+  g.tab = (int32_t*)(p + o); o += (size_t)g.tsize * 4;
   g.arel = (int32_t*)(p + o); o += (size_t)cap * 4;
   int32_t* sa = (int32_t*)(p + o); o += (size_t)kIPSlotArrays * (kIPSlots + 1) * 4;
-  g.s_off = sa;
-  g.s_cnt = sa + 1 * (kIPSlots + 1);
-  g.s_lim = sa + 2 * (kIPSlots + 1);
-  g.s_pre = sa + 3 * (kIPSlots + 1);
-  g.s_nnew = sa + 4 * (kIPSlots + 1);
-  g.s_nhole = sa + 5 * (kIPSlots + 1);
-  g.s_hfirst = sa + 6 * (kIPSlots + 1);
-  g.s_ctr = sa + 7 * (kIPSlots + 1);
-  g.s_noff = sa + 8 * (kIPSlots + 1);
-  g.s_nlim = sa + 9 * (kIPSlots + 1);
-  g.s_bkt = (uint32_t*)(sa + 10 * (kIPSlots + 1));
+  g.s_pre = sa;
+  g.s_nnew = sa + 1 * (kIPSlots + 1);
+  g.s_nhole = sa + 2 * (kIPSlots + 1);
+  g.s_hfirst = sa + 3 * (kIPSlots + 1);
+  g.s_ctr = sa + 4 * (kIPSlots + 1);
   g.partner = (int16_t*)(p + o); o += (size_t)cap * 2;
   g.aslot = (uint8_t*)(p + o); o += (size_t)cap;
   g.aflag = (uint8_t*)(p + o);
   g.cap = cap;
-  g.tsize = 2 * cap;
   return g;
 }
 
-// LDS written by some lanes of this wave is read by others next: keep the
-// compiler from reordering across this point and wait for the LDS operations.
+// LDS written by some lanes of this wave is read by others next.  The LDS
+// unit executes one wave's operations in issue order, so only the compiler
+// must not move LDS accesses across this point: a wavefront-scope fence (no
+// wait instruction; a workgroup-scope fence would also wait for every
+// outstanding global store of the wave).
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ uint32_t table_slot(uint32_t h, int tsize) {
   return (uint32_t)(((uint64_t)h * (uint32_t)tsize) >> 32);
-}
-
-// Largest slot s < nslots with pre[s] <= i (pre is non-decreasing, pre[0] = 0).
-__device__ __forceinline__ int slot_of(const int32_t* pre, int nslots, int i) {
-  int s = 0;
-#pragma unroll
-  for (int step = kIPSlots / 2; step; step >>= 1)
-    if (s + step < nslots && pre[s + step] <= i) s += step;
-  return s;
 }
 
 __device__ __forceinline__ bool sorted_contains(const int32_t* h, int n, int v) {
@@ -141,20 +131,86 @@ __device__ __forceinline__ bool sorted_contains(const int32_t* h, int n, int v) 
   return lo < n && h[lo] == v;
 }
 
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(v, d, 64);
+    if (lane >= d) v += y;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
 struct Geo {
   uint32_t f;
-  int thi, selfp, ppi, nslots_max;
+  int thi, selfp, ppi;
   int64_t npairs, nitems;
 };
+
+// Bucket table entry of slot `lane` of a work item (lanes >= nslots: empty).
+struct SlotDesc {
+  int off = 0, cnt = 0, lim = 0;   // rows of an in-place store are below 2^31
+  uint32_t b = 0;
+  int nslots = 0;
+};
+
+// The item's buckets: slot s of pair k is bucket b0 (s = 2k) or b0 ^ f (s = 2k + 1),
+// or b0 alone when f = 0.
+__device__ __forceinline__ SlotDesc load_desc(const StoreDev& st, const Geo& G, int64_t it) {
+  const int lane = threadIdx.x & 63;
+  SlotDesc d;
+  const int64_t q0 = it * G.ppi;
+  const int64_t left = G.npairs - q0;
+  const int np = (int)(left < G.ppi ? left : G.ppi);
+  d.nslots = G.selfp ? np : 2 * np;
+  if (lane < d.nslots) {
+    const int64_t q = q0 + (G.selfp ? lane : (lane >> 1));
+    uint32_t b0, b1;
+    pair_buckets(q, G.f, G.thi, b0, b1);
+    d.b = (!G.selfp && (lane & 1)) ? b1 : b0;
+    d.off = (int)st.off[d.b];
+    d.cnt = (int)st.cnt[d.b];
+    d.lim = (int)st.lim[d.b];
+  }
+  return d;
+}
+
+// Per-lane (slot = lane) state of the item being processed.
+struct Item {
+  int off, cnt, room;   // first row, live rows, rows of the region (input layout)
+  int noff;             // first row of the fresh region (relocated items)
+  uint32_t b;
+  int pre;              // flat index of the slot's first term
+  int pre1;             // flat index of slot 1 (wave-uniform)
+  int nslots, n;
+};
+
+// Slot of flat index i: the largest s < nslots with pre[s] <= i.
+template <int W>
+__device__ __forceinline__ int slot_of(const Seg<W>& g, const Item& I, int i) {
+  if (I.nslots <= 2) return (I.nslots == 2 && i >= I.pre1) ? 1 : 0;
+  int s = 0;
+#pragma unroll
+  for (int step = kIPSlots / 2; step; step >>= 1)
+    if (s + step < I.nslots && g.s_pre[s + step] <= i) s += step;
+  return s;
+}
 
 struct WaveCounts {
   int64_t anti = 0, fresh = 0, delta = 0, reloc = 0, freed = 0;
 };
 
-// Rows for the entries with `has` set, appended to their slot `d` in stash
-// order: at the tail of the live rows (tail) or in the slot's fresh region.
-template <int W>
-__device__ __forceinline__ void put_rows(const StoreDev& st, const Seg<W>& g, bool has, int d, bool tail,
+// Rows for the entries with `has` set, placed in their slot `d` in stash
+// order.  MODE 0 (in place): first the slot's freed rows, in ascending order,
+// then the rows after its live ones; MODE 1: the slot's fresh region.
+template <int W, int MODE>
+__device__ __forceinline__ void put_rows(const StoreDev& st, const Seg<W>& g, const Item& I, bool has, int d,
                                          const uint64_t* kx, const uint64_t* kz, double c) {
   uint64_t todo = __ballot(has);
   while (todo) {
@@ -163,9 +219,17 @@ __device__ __forceinline__ void put_rows(const StoreDev& st, const Seg<W>& g, bo
     const bool mine = has && d == dd;
     const uint64_t mm = __ballot(mine);
     const int base = g.s_ctr[dd];
+    const int o = __shfl(MODE == 0 ? I.off : I.noff, dd, 64);
+    const int ct = __shfl(I.cnt, dd, 64);
     if (mine) {
-      const int64_t row = (tail ? (int64_t)g.s_off[dd] + g.s_cnt[dd] : (int64_t)g.s_noff[dd]) + base +
-                          (int64_t)lanes_below(mm);
+      const int rank = base + (int)lanes_below(mm);
+      int64_t row;
+      if (MODE == 0) {
+        const int nh = g.s_nhole[dd];
+        row = rank < nh ? (int64_t)o + g.tab[g.s_hfirst[dd] + rank] : (int64_t)o + ct + (rank - nh);
+      } else {
+        row = (int64_t)o + rank;
+      }
       store_key<W>(st, row, kx, kz, c);
     }
     wave_sync();
@@ -175,67 +239,23 @@ __device__ __forceinline__ void put_rows(const StoreDev& st, const Seg<W>& g, bo
   }
 }
 
-// The item's buckets: slot s of pair k is bucket b0 (s = 2k) or b0 ^ f (s = 2k + 1),
-// or b0 alone when f = 0.  Returns the number of input terms of the item.
-template <int W>
-__device__ int item_setup(const StoreDev& st, const Geo& G, int64_t it, const Seg<W>& g, int& nslots) {
-  const int lane = threadIdx.x & 63;
-  const int64_t q0 = it * G.ppi;
-  const int64_t left = G.npairs - q0;
-  const int np = (int)(left < G.ppi ? left : G.ppi);
-  nslots = G.selfp ? np : 2 * np;
-  int cnt = 0;
-  int64_t off = 0, lim = 0;
-  uint32_t b = 0;
-  if (lane < nslots) {
-    const int64_t q = q0 + (G.selfp ? lane : (lane >> 1));
-    uint32_t b0, b1;
-    pair_buckets(q, G.f, G.thi, b0, b1);
-    b = (!G.selfp && (lane & 1)) ? b1 : b0;
-    off = st.off[b];
-    cnt = (int)st.cnt[b];
-    lim = st.lim[b];
-  }
-  int incl = cnt;
-#pragma unroll
-  for (int d = 1; d < kIPSlots; d <<= 1) {
-    const int y = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += y;
-  }
-  const int n = __shfl(incl, nslots - 1, 64);
-  if (lane < nslots) {
-    g.s_off[lane] = (int32_t)off;
-    g.s_cnt[lane] = cnt;
-    g.s_lim[lane] = (int32_t)lim;
-    g.s_pre[lane] = incl - cnt;
-    g.s_bkt[lane] = b;
-    g.s_nnew[lane] = 0;
-    g.s_nhole[lane] = 0;
-    g.s_ctr[lane] = 0;
-  }
-  if (lane == 0) g.s_pre[nslots] = n;
-  wave_sync();
-  return n;
-}
-
 // One pass over the item's input terms, 128 per iteration (two loads in
 // flight per lane).
 //   mode 0: stash the anticommuting terms and the commuting terms that
 //           compression drops (flag kFComm); energy of the commuting terms;
-//   mode 1: append the kept commuting terms to the fresh regions, stash the
-//           anticommuting terms of residue class `rem` mod `mod`; energy of
-//           the commuting terms unless e_done;
+//   mode 1: put the kept commuting terms into the fresh regions, stash the
+//           anticommuting terms of residue class `rem` mod `mod`;
 //   mode 2: stash the anticommuting terms of class `rem` only.
 // Returns the number of stash candidates (entries beyond cap are not
 // written); nanti receives the number of anticommuting terms.
 template <int W, bool ENERGY>
-__device__ int item_scan(const StoreDev& st, const Entangler& P, double eps, int delta,
-                         const double* lut, const Seg<W>& g, int nslots, int n, int mode, bool e_done,
-                         uint32_t mod, uint32_t rem, double& eacc, int& nanti) {
+__device__ int item_scan(const StoreDev& st, const Entangler& P, double eps, int delta, const double* lut,
+                         const Seg<W>& g, const Item& I, int mode, uint32_t mod, uint32_t rem, double& eacc,
+                         int& nanti) {
   const int lane = threadIdx.x & 63;
   int nst = 0;
   nanti = 0;
-  for (int base = 0; base < n; base += 128) {
+  for (int base = 0; base < I.n; base += 128) {
     uint64_t kx[2][W], kz[2][W];
     double kc[2];
     int slot[2], rel[2];
@@ -243,13 +263,15 @@ __device__ int item_scan(const StoreDev& st, const Entangler& P, double eps, int
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int i = base + 64 * u + lane;
-      valid[u] = i < n;
-      slot[u] = valid[u] ? slot_of(g.s_pre, nslots, i) : 0;
-      rel[u] = valid[u] ? i - g.s_pre[slot[u]] : 0;
+      valid[u] = i < I.n;
+      slot[u] = valid[u] ? slot_of<W>(g, I, i) : 0;
+      const int pre = __shfl(I.pre, slot[u], 64);
+      const int off = __shfl(I.off, slot[u], 64);
+      rel[u] = i - pre;
       kc[u] = 0.0;
 #pragma unroll
       for (int w = 0; w < W; ++w) kx[u][w] = kz[u][w] = 0;
-      if (valid[u]) load_key<W>(st, (int64_t)g.s_off[slot[u]] + rel[u], kx[u], kz[u], kc[u]);
+      if (valid[u]) load_key<W>(st, (int64_t)off + rel[u], kx[u], kz[u], kc[u]);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -257,24 +279,22 @@ __device__ int item_scan(const StoreDev& st, const Entangler& P, double eps, int
       nanti += (int)__popcll(__ballot(anti));
       const bool comm_drop = valid[u] && !anti && fabs(kc[u]) < eps;
       const bool comm_keep = valid[u] && !anti && !comm_drop;
-      bool stash = false;
+      bool stash = anti;
       if (anti && mode != 0 && mod > 1)
         stash = (round_hash(rep_hash<W>(P, kx[u], kz[u])) & (mod - 1)) == rem;
-      else if (anti)
-        stash = true;
       uint8_t flag = 0;
       if (mode == 0 && comm_drop) {
         stash = true;
         flag = kFComm;
       }
-      if (ENERGY && mode != 2 && !e_done) {
+      if (ENERGY && mode == 0) {
         // commuting terms: every kept one, or (delta) only those compression drops
         if (delta ? comm_drop : comm_keep) {
           const double ek = expect_lut<W>(lut, kx[u], kz[u]);
           eacc += comm_drop ? -(kc[u] * ek) : kc[u] * ek;
         }
       }
-      if (mode == 1) put_rows<W>(st, g, comm_keep, slot[u], false, kx[u], kz[u], kc[u]);
+      if (mode == 1) put_rows<W, 1>(st, g, I, comm_keep, slot[u], kx[u], kz[u], kc[u]);
       const uint64_t bm = __ballot(stash);
       const int pos = nst + (int)lanes_below(bm);
       if (stash && pos < g.cap) {
@@ -352,7 +372,7 @@ __device__ void item_join(const Entangler& P, const Seg<W>& g, int n) {
 // Output values of stash entry i (an anticommuting term K with coefficient a):
 // own = RN(cos tau a) + RN(s_{K^P} sin tau a_{K^P}) when K^P is present, else
 // RN(cos tau a) together with the new term K^P of value s_K RN(sin tau a),
-// s = +1 for P K^.. = i^3 (..), -1 for i^1.
+// where s_A = +1 when P A = i^3 (A^P) and -1 when P A = i^1 (A^P).
 template <int W>
 __device__ __forceinline__ void entry_values(const Entangler& P, double C, double S, const Seg<W>& g, int i,
                                              const uint64_t* kx, const uint64_t* kz, double& a,
@@ -377,7 +397,7 @@ __device__ __forceinline__ void entry_values(const Entangler& P, double C, doubl
 }
 
 // In-place path, first emission pass: which entries free their row and which
-// add a new term, and how many per slot.
+// add a new key, and how many per slot.
 template <int W>
 __device__ void count_outputs(const Entangler& P, double C, double S, double eps, const Seg<W>& g, int n,
                               int selfp) {
@@ -405,11 +425,34 @@ __device__ void count_outputs(const Entangler& P, double C, double S, double eps
   wave_sync();
 }
 
+// The freed rows of every slot, ascending within the slot (the stash is in
+// flat order: slot-major, rows ascending), into g.tab; returns their number.
+template <int W>
+__device__ int list_holes(const Seg<W>& g, const Item& I, int n) {
+  const int lane = threadIdx.x & 63;
+  const int h = lane < I.nslots ? g.s_nhole[lane] : 0;
+  const int incl = wave_incl_scan(h);
+  const int total = __shfl(incl, 63, 64);
+  if (total == 0) return 0;
+  if (lane < I.nslots) g.s_hfirst[lane] = incl - h;
+  int k = 0;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    const bool ho = i < n && (g.aflag[i] & kFHole);
+    const uint64_t bm = __ballot(ho);
+    if (ho) g.tab[k + (int)lanes_below(bm)] = g.arel[i];
+    k += (int)__popcll(bm);
+  }
+  wave_sync();
+  return total;
+}
+
 // In-place path, second emission pass: rotated coefficients into their own
-// rows, new terms after the live rows of the partner bucket, energy.
+// rows, new keys into the partner slot (freed rows first), energy.
 template <int W, bool ENERGY>
 __device__ void emit_inplace(const StoreDev& st, const Entangler& P, double C, double S, int delta,
-                             const double* lut, const Seg<W>& g, int n, int selfp, double& eacc) {
+                             const double* lut, const Seg<W>& g, const Item& I, int n, int selfp,
+                             double& eacc) {
   const int lane = threadIdx.x & 63;
   for (int i0 = 0; i0 < n; i0 += 64) {
     const int i = i0 + lane;
@@ -417,6 +460,7 @@ __device__ void emit_inplace(const StoreDev& st, const Entangler& P, double C, d
     const uint8_t fl = valid ? g.aflag[i] : (uint8_t)0;
     const bool live = valid && !(fl & kFComm);
     const int s = valid ? g.aslot[i] : 0;
+    const int off = __shfl(I.off, s, 64);
     uint64_t kx[W], kz[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) kx[w] = kz[w] = 0;
@@ -425,7 +469,7 @@ __device__ void emit_inplace(const StoreDev& st, const Entangler& P, double C, d
       entry_key<W>(g, i, kx, kz);
       bool paired;
       entry_values<W>(P, C, S, g, i, kx, kz, a, vo, vn, paired);
-      if (!(fl & kFHole)) st.c[(int64_t)g.s_off[s] + g.arel[i]] = vo;
+      if (!(fl & kFHole)) st.c[(int64_t)off + g.arel[i]] = vo;
       if (ENERGY) {
         double ek, ekp;
         expect_split<W>(lut, P, kx, kz, ek, ekp);
@@ -440,127 +484,70 @@ __device__ void emit_inplace(const StoreDev& st, const Entangler& P, double C, d
       qx[w] = kx[w] ^ P.px[w];
       qz[w] = kz[w] ^ P.pz[w];
     }
-    put_rows<W>(st, g, live && (fl & kFNew), selfp ? s : s ^ 1, true, qx, qz, vn);
+    put_rows<W, 0>(st, g, I, live && (fl & kFNew), selfp ? s : s ^ 1, qx, qz, vn);
   }
   wave_sync();
 }
 
-// Relocation path emission: every kept output of the stash is appended to
-// the fresh region of its slot (own key to its own slot, K^P to the partner).
-template <int W, bool ENERGY>
-__device__ void emit_append(const StoreDev& st, const Entangler& P, double C, double S, double eps, int delta,
-                            const double* lut, const Seg<W>& g, int n, int selfp, double& eacc,
-                            int64_t& fresh) {
-  const int lane = threadIdx.x & 63;
-  for (int i0 = 0; i0 < n; i0 += 64) {
-    const int i = i0 + lane;
-    const bool valid = i < n;
-    const int s = valid ? g.aslot[i] : 0;
-    uint64_t kx[W], kz[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) kx[w] = kz[w] = 0;
-    double a = 0.0, vo = 0.0, vn = 0.0;
-    bool paired = true;
-    if (valid) {
-      entry_key<W>(g, i, kx, kz);
-      entry_values<W>(P, C, S, g, i, kx, kz, a, vo, vn, paired);
-    }
-    const bool keep_own = valid && !(fabs(vo) < eps);
-    const bool keep_new = valid && !paired && !(fabs(vn) < eps);
-    if (ENERGY && valid) {
-      double ek, ekp;
-      expect_split<W>(lut, P, kx, kz, ek, ekp);
-      if (keep_own) eacc += vo * ek;
-      if (keep_new) eacc += vn * ekp;
-      if (delta) eacc -= a * ek;
-    }
-    fresh += __popcll(__ballot(keep_new));
-    put_rows<W>(st, g, keep_own, s, false, kx, kz, vo);
-    uint64_t qx[W], qz[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      qx[w] = kx[w] ^ P.px[w];
-      qz[w] = kz[w] ^ P.pz[w];
-    }
-    put_rows<W>(st, g, keep_new, selfp ? s : s ^ 1, false, qx, qz, vn);
-  }
-  wave_sync();
-}
-
-// Refill the rows freed by compression with the last live rows of their
-// bucket (rows below the new count that are free take, in order, the live
-// rows at or above it).  The freed rows are the stash entries flagged kFHole,
-// in stash order, i.e. ascending within each slot.  Returns the rows freed.
+// Slots that lost more rows than new keys arrived: the live rows at or above
+// the slot's new count move, in order, into the freed rows below it that no
+// new key took.  A moved row is either an anticommuting term of the stash
+// (its new coefficient is recomputed from the stash) or a commuting term that
+// this step has not written (read from the store).
 template <int W>
-__device__ int compact_holes(const StoreDev& st, const Seg<W>& g, int n, int nslots) {
+__device__ void refill(const StoreDev& st, const Entangler& P, double C, double S, const Seg<W>& g,
+                       const Item& I, int n) {
   const int lane = threadIdx.x & 63;
-  const int h = lane < nslots ? g.s_nhole[lane] : 0;
-  int incl = h;
-#pragma unroll
-  for (int d = 1; d < kIPSlots; d <<= 1) {
-    const int y = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += y;
-  }
-  const int total = __shfl(incl, nslots - 1, 64);
-  if (total == 0) return 0;
-  if (lane < nslots) g.s_hfirst[lane] = incl - h;
-  int32_t* holes = g.tab;   // the join table is no longer needed
-  int k = 0;
-  for (int i0 = 0; i0 < n; i0 += 64) {
-    const int i = i0 + lane;
-    const bool ho = i < n && (g.aflag[i] & kFHole);
-    const uint64_t bm = __ballot(ho);
-    if (ho) holes[k + (int)lanes_below(bm)] = g.arel[i];
-    k += (int)__popcll(bm);
-  }
-  wave_sync();
-  // this wave's row writes must be visible to its own loads below (the fence
-  // also drops stale lines from the CU's vector cache)
-  __threadfence();
-  for (int s = 0; s < nslots; ++s) {
-    const int nh = g.s_nhole[s];
-    if (nh == 0) continue;
-    const int end = g.s_cnt[s] + g.s_nnew[s];
-    const int fin = end - nh;
-    const int32_t* H = holes + g.s_hfirst[s];
-    const int64_t r0 = g.s_off[s];
+  for (int s = 0; s < I.nslots; ++s) {
+    const int nh = g.s_nhole[s], nn = g.s_nnew[s];
+    const int cnt = __shfl(I.cnt, s, 64);
+    const int off = __shfl(I.off, s, 64);
+    if (nh <= nn) continue;
+    const int fin = cnt - (nh - nn);
+    const int32_t* H = g.tab + g.s_hfirst[s];
+    // the slot's stash entries: aslot is non-decreasing
+    int lo = 0, hi = n;
+    while (lo < hi) { const int m = (lo + hi) >> 1; if (g.aslot[m] < s) lo = m + 1; else hi = m; }
+    const int e0 = lo;
+    hi = n;
+    while (lo < hi) { const int m = (lo + hi) >> 1; if (g.aslot[m] <= s) lo = m + 1; else hi = m; }
+    const int e1 = lo;
     int moved = 0;
-    for (int b = fin; b < end; b += 64) {
+    for (int b = fin; b < cnt; b += 64) {
       const int r = b + lane;
-      const bool lv = r < end && !sorted_contains(H, nh, r);
+      const bool lv = r < cnt && !sorted_contains(H, nh, r);
       const uint64_t mm = __ballot(lv);
       if (lv) {
-        const int dst = H[moved + (int)lanes_below(mm)];
+        const int dst = H[nn + moved + (int)lanes_below(mm)];
+        int a0 = e0, a1 = e1;   // stash entry with row r (rows ascend within the slot)
+        while (a0 < a1) { const int m = (a0 + a1) >> 1; if (g.arel[m] < r) a0 = m + 1; else a1 = m; }
         uint64_t kx[W], kz[W];
         double c;
-        load_key<W>(st, r0 + r, kx, kz, c);
-        store_key<W>(st, r0 + dst, kx, kz, c);
+        if (a0 < e1 && g.arel[a0] == r) {
+          entry_key<W>(g, a0, kx, kz);
+          double a, vn;
+          bool paired;
+          entry_values<W>(P, C, S, g, a0, kx, kz, a, c, vn, paired);
+        } else {
+          load_key<W>(st, (int64_t)off + r, kx, kz, c);
+        }
+        store_key<W>(st, (int64_t)off + dst, kx, kz, c);
       }
       moved += (int)__popcll(mm);
     }
   }
-  return total;
 }
 
 template <int W, bool ENERGY>
 __device__ bool relocate_item(const StoreDev& st, const Entangler& P, const InplaceConfig& cfg,
-                              const double* lut, const Seg<W>& g, int nslots, int n, int selfp,
-                              bool e_done, int nanti, double& eacc, WaveCounts& wc) {
+                              const double* lut, const Seg<W>& g, Item& I, int selfp, int nanti,
+                              double& eacc, WaveCounts& wc) {
   const int lane = threadIdx.x & 63;
   // fresh regions from the pool: own rows + the partner's (worst case output)
-  int need = 0;
-  if (lane < nslots) {
-    const int c0 = g.s_cnt[lane];
-    const int cp = selfp ? c0 : g.s_cnt[lane ^ 1];
-    need = (c0 + cp + 15) & ~15;
-  }
-  int incl = need;
-#pragma unroll
-  for (int d = 1; d < kIPSlots; d <<= 1) {
-    const int y = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += y;
-  }
-  const int total = __shfl(incl, nslots - 1, 64);
+  const int cp = __shfl(I.cnt, selfp ? lane : (lane ^ 1), 64);
+  const int need = lane < I.nslots ? ((I.cnt + cp + 15) & ~15) : 0;
+  const int incl = wave_incl_scan(need);
+  const int total = __shfl(incl, 63, 64);
   unsigned long long base = 0;
   if (lane == 0) base = atomicAdd((unsigned long long*)st.top, (unsigned long long)total);
   base = wave_bcast0(base);
@@ -568,12 +555,7 @@ __device__ bool relocate_item(const StoreDev& st, const Entangler& P, const Inpl
     if (lane == 0) atomicOr(st.err, 1);
     return false;
   }
-  if (lane < nslots) {
-    g.s_noff[lane] = (int32_t)(base + (incl - need));
-    g.s_nlim[lane] = (int32_t)(base + incl);
-    g.s_ctr[lane] = 0;
-  }
-  wave_sync();
+  I.noff = (int)(base + (incl - need));
   // residue classes of a hash of the pair representative (both members of a
   // {K, K^P} pair share the class), about cap/4 terms each; if a class still
   // overflows the stash, the item is redone with twice as many classes (the
@@ -583,19 +565,52 @@ __device__ bool relocate_item(const StoreDev& st, const Entangler& P, const Inpl
   for (;;) {
     double e_try = 0.0;
     int64_t fresh_try = 0;
-    if (lane < nslots) g.s_ctr[lane] = 0;
+    if (lane < I.nslots) g.s_ctr[lane] = 0;
     wave_sync();
     bool ok = true;
     for (uint32_t r = 0; r < R; ++r) {
       int na;
-      const int nst = item_scan<W, ENERGY>(st, P, cfg.eps, cfg.delta, lut, g, nslots, n, r == 0 ? 1 : 2,
-                                           e_done, R, r, e_try, na);
+      const int nst = item_scan<W, ENERGY>(st, P, cfg.eps, cfg.delta, lut, g, I, r == 0 ? 1 : 2, R, r,
+                                           e_try, na);
       if (nst > g.cap) {
         ok = false;
         break;
       }
       item_join<W>(P, g, nst);
-      emit_append<W, ENERGY>(st, P, cfg.C, cfg.S, cfg.eps, cfg.delta, lut, g, nst, selfp, e_try, fresh_try);
+      // every kept output into the fresh region of its slot
+      for (int i0 = 0; i0 < nst; i0 += 64) {
+        const int i = i0 + lane;
+        const bool valid = i < nst;
+        const int s = valid ? g.aslot[i] : 0;
+        uint64_t kx[W], kz[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) kx[w] = kz[w] = 0;
+        double a = 0.0, vo = 0.0, vn = 0.0;
+        bool paired = true;
+        if (valid) {
+          entry_key<W>(g, i, kx, kz);
+          entry_values<W>(P, cfg.C, cfg.S, g, i, kx, kz, a, vo, vn, paired);
+        }
+        const bool keep_own = valid && !(fabs(vo) < cfg.eps);
+        const bool keep_new = valid && !paired && !(fabs(vn) < cfg.eps);
+        if (ENERGY && valid) {
+          double ek, ekp;
+          expect_split<W>(lut, P, kx, kz, ek, ekp);
+          if (keep_own) e_try += vo * ek;
+          if (keep_new) e_try += vn * ekp;
+          if (cfg.delta) e_try -= a * ek;
+        }
+        fresh_try += __popcll(__ballot(keep_new));
+        put_rows<W, 1>(st, g, I, keep_own, s, kx, kz, vo);
+        uint64_t qx[W], qz[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          qx[w] = kx[w] ^ P.px[w];
+          qz[w] = kz[w] ^ P.pz[w];
+        }
+        put_rows<W, 1>(st, g, I, keep_new, selfp ? s : s ^ 1, qx, qz, vn);
+      }
+      wave_sync();
     }
     if (ok) {
       eacc += e_try;
@@ -609,58 +624,68 @@ __device__ bool relocate_item(const StoreDev& st, const Entangler& P, const Inpl
     R <<= 1;
   }
   int dl = 0;
-  if (lane < nslots) {
-    const uint32_t b = g.s_bkt[lane];
-    st.off[b] = g.s_noff[lane];
-    st.lim[b] = g.s_nlim[lane];
-    st.cnt[b] = g.s_ctr[lane];
-    dl = g.s_ctr[lane] - g.s_cnt[lane];
+  if (lane < I.nslots) {
+    const int cnt_new = g.s_ctr[lane];
+    st.off[I.b] = I.noff;
+    st.lim[I.b] = (int64_t)I.noff + need;
+    st.cnt[I.b] = cnt_new;
+    dl = cnt_new - I.cnt;
   }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) dl += __shfl_down(dl, d, 64);
-  wc.delta += __shfl(dl, 0, 64);
+  wc.delta += wave_sum(dl);
   wc.reloc += 1;
   return true;
 }
 
 template <int W, bool ENERGY>
 __device__ void process_item(const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, const Geo& G,
-                             const double* lut, const Seg<W>& g, int64_t it, double& eacc, WaveCounts& wc) {
+                             const double* lut, const Seg<W>& g, const SlotDesc& d, double& eacc,
+                             WaveCounts& wc) {
   const int lane = threadIdx.x & 63;
-  int nslots;
-  const int n = item_setup<W>(st, G, it, g, nslots);
-  if (n == 0) return;
+  Item I;
+  I.nslots = d.nslots;
+  I.off = d.off;
+  I.cnt = d.cnt;
+  I.room = d.lim - d.off;
+  I.b = d.b;
+  I.noff = 0;
+  const int incl = wave_incl_scan(I.cnt);
+  I.pre = incl - I.cnt;
+  I.n = __shfl(incl, 63, 64);
+  I.pre1 = __shfl(I.pre, 1, 64);
+  if (I.n == 0) return;
+  if (lane <= I.nslots) g.s_pre[lane] = lane < I.nslots ? I.pre : I.n;
+  if (lane < I.nslots) {
+    g.s_nnew[lane] = 0;
+    g.s_nhole[lane] = 0;
+    g.s_ctr[lane] = 0;
+  }
+  wave_sync();
   int nanti;
-  const int nst = item_scan<W, ENERGY>(st, P, cfg.eps, cfg.delta, lut, g, nslots, n, 0, false, 1, 0, eacc, nanti);
+  const int nst = item_scan<W, ENERGY>(st, P, cfg.eps, cfg.delta, lut, g, I, 0, 1, 0, eacc, nanti);
   wc.anti += nanti;
   if (nst > g.cap) {
-    relocate_item<W, ENERGY>(st, P, cfg, lut, g, nslots, n, G.selfp, true, nanti, eacc, wc);
+    relocate_item<W, ENERGY>(st, P, cfg, lut, g, I, G.selfp, nanti, eacc, wc);
     return;
   }
   item_join<W>(P, g, nst);
   count_outputs<W>(P, cfg.C, cfg.S, cfg.eps, g, nst, G.selfp);
-  // room for the appended rows before the freed ones are refilled
+  int nn = 0, nh = 0;
   bool fits = true;
-  if (lane < nslots) fits = g.s_cnt[lane] + g.s_nnew[lane] <= g.s_lim[lane] - g.s_off[lane];
+  if (lane < I.nslots) {
+    nn = g.s_nnew[lane];
+    nh = g.s_nhole[lane];
+    fits = I.cnt + (nn > nh ? nn - nh : 0) <= I.room;
+  }
   if (__ballot(!fits)) {
-    relocate_item<W, ENERGY>(st, P, cfg, lut, g, nslots, n, G.selfp, true, nanti, eacc, wc);
+    relocate_item<W, ENERGY>(st, P, cfg, lut, g, I, G.selfp, nanti, eacc, wc);
     return;
   }
-  emit_inplace<W, ENERGY>(st, P, cfg.C, cfg.S, cfg.delta, lut, g, nst, G.selfp, eacc);
-  const int freed = compact_holes<W>(st, g, nst, nslots);
-  int dl = 0, nw = 0;
-  if (lane < nslots) {
-    nw = g.s_nnew[lane];
-    dl = nw - g.s_nhole[lane];
-    st.cnt[g.s_bkt[lane]] = g.s_cnt[lane] + dl;
-  }
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    dl += __shfl_down(dl, d, 64);
-    nw += __shfl_down(nw, d, 64);
-  }
-  wc.delta += __shfl(dl, 0, 64);
-  wc.fresh += __shfl(nw, 0, 64);
+  const int freed = list_holes<W>(g, I, nst);
+  emit_inplace<W, ENERGY>(st, P, cfg.C, cfg.S, cfg.delta, lut, g, I, nst, G.selfp, eacc);
+  if (__ballot(nh > nn)) refill<W>(st, P, cfg.C, cfg.S, g, I, nst);
+  if (lane < I.nslots) st.cnt[I.b] = I.cnt + nn - nh;
+  wc.delta += wave_sum(nn - nh);
+  wc.fresh += wave_sum(nn);
   wc.freed += freed;
 }
 
@@ -696,8 +721,14 @@ __global__ __launch_bounds__(kIPB) void k_dress_inplace(StoreDev st, Entangler P
     G.ppi = ppi;
     G.nitems = (G.npairs + ppi - 1) / ppi;
     const int64_t nw = (int64_t)gridDim.x * kIPW;
-    for (int64_t it = gw; it < G.nitems; it += nw)
-      process_item<W, ENERGY>(st, P, cfg, G, lut, g, it, eacc, wc);
+    SlotDesc next;
+    if (gw < G.nitems) next = load_desc(st, G, gw);
+    for (int64_t it = gw; it < G.nitems; it += nw) {
+      const SlotDesc cur = next;
+      // the next item's bucket table is in flight while this item is processed
+      if (it + nw < G.nitems) next = load_desc(st, G, it + nw);
+      process_item<W, ENERGY>(st, P, cfg, G, lut, g, cur, eacc, wc);
+    }
   }
   if (lane == 0) {
     if (wc.anti) atomicAdd((unsigned long long*)&st.stats[0], (unsigned long long)wc.anti);
@@ -731,7 +762,8 @@ template <int W, bool E>
 static void launch_inplace_t(const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, int grid,
                              hipStream_t s) {
   const size_t lds = inplace_lds_bytes(W, cfg.cap, E);
-  (void)hipFuncSetAttribute((const void*)k_dress_inplace<W, E>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)k_dress_inplace<W, E>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
   hipLaunchKernelGGL((k_dress_inplace<W, E>), dim3(grid), dim3(kIPB), lds, s, st, P, cfg);
 }
 
