@@ -374,6 +374,20 @@ int iqcc_expectations(iqcc_ctx *ctx, const iqcc_store *h, const double *theta, c
 int iqcc_qmf_energy(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
                     const double *phi, double *energy, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * energy as iqcc_qmf_energy, from the same kernels, with no allocation of any
+ * kind.  Its scratch (the QMF group table and the per-workgroup partial sums)
+ * is a fixed array of device memory inside the library, about 110 KB per
+ * device, held until the process ends.  The grid (n_cu * energy_grid_per_cu
+ * workgroups) may use at most 8192 partial sums; a larger one is refused with
+ * IQCC_ERR_CAPACITY before any launch.  All calls on one device share that
+ * scratch, so calls that overlap on a device (other streams, other contexts
+ * or threads) race; calls in one stream are ordered.  Each call rewrites all
+ * the scratch it reads. */
+int iqcc_qmf_energy_noalloc(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
+                            const double *phi, double *energy, void *stream);
+
 /* Backward of iqcc_qmf_energy: dtheta[j] = dE_scale * dE/dtheta_j and
  * dphi[j] = dE_scale * dE/dphi_j (DEVICE arrays of n_qubits), where dE_scale
  * is the DEVICE scalar upstream gradient (NULL means 1).  lambda (NULL, or a

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/iqcc.h"
@@ -354,6 +355,31 @@ void inplace_geometry(const iqcc_ctx* ctx, const iqcc_store* st, int& m, int64_t
   if (R < 16) R = 16;
 }
 
+// ---- allocation-free QMF energy ----------------------------------------------
+// Device scratch of iqcc_qmf_energy_noalloc: the 3-qubit group table of the
+// QMF state (kMaxWords * 22 * 64 doubles) followed by the per-workgroup
+// partial sums (at most kNoAllocPartials).  Every device the library runs on
+// holds its own copy until the process ends; host code reaches it only
+// through the per-device address from hipGetSymbolAddress.
+constexpr int kNoAllocLut = kMaxWords * kGroupsPerWord * kLutEntries;
+constexpr int kNoAllocPartials = 8192;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocLut + kNoAllocPartials];
+double* g_scratch[kNoAllocDevices] = {};
+std::mutex g_scratch_mu;
+
+// Called once per device by iqcc_ctx_create with that device current.  A
+// failure is not fatal for the context: only the allocation-free entry point
+// then reports it.
+void noalloc_setup(int device) {
+  if (device < 0 || device >= kNoAllocDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[device] = (double*)p;
+  else (void)hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" {
@@ -384,6 +410,7 @@ int iqcc_ctx_create(iqcc_ctx** out, int device) {
         (size_t)v > ctx->lds_per_cu)
       ctx->lds_per_cu = (size_t)v;
   }
+  noalloc_setup(device);
   if (hipMalloc(&ctx->lut, sizeof(double) * kMaxWords * kGroupsPerWord * kLutEntries) != hipSuccess) {
     delete ctx;
     return IQCC_ERR_HIP;
@@ -1091,6 +1118,26 @@ int iqcc_qmf_energy(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, con
   launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
   launch_energy(h->W, h->d, grid, ctx->lut, ctx->partial, s);
   launch_finalize_sum(ctx->partial, grid, nullptr, energy, s);
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
+int iqcc_qmf_energy_noalloc(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, const double* phi,
+                            double* energy, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!h || !theta || !phi || !energy) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  double* base = (ctx->device >= 0 && ctx->device < kNoAllocDevices) ? g_scratch[ctx->device] : nullptr;
+  if (!base) return fail(ctx, IQCC_ERR_HIP, "the device scratch of the allocation-free entry point is unavailable");
+  const int64_t grid = ctx->n_cu * ctx->energy_grid_per_cu;
+  if (grid > kNoAllocPartials)
+    return fail(ctx, IQCC_ERR_CAPACITY,
+                "allocation-free energy holds %d workgroup partials, the grid needs %lld "
+                "(lower energy_grid_per_cu)", kNoAllocPartials, (long long)grid);
+  hipStream_t s = as_stream(stream);
+  launch_build_lut(h->W, h->nq, theta, phi, base, s);
+  launch_energy(h->W, h->d, (int)grid, base, base + kNoAllocLut, s);
+  launch_finalize_sum(base + kNoAllocLut, (int)grid, nullptr, energy, s);
   LAUNCH_CHECK(ctx);
   return IQCC_OK;
 }

@@ -28,6 +28,7 @@ IQCC_ERR_UNSUPPORTED = -4
 IQCC_DIS_BATCHED = 0
 IQCC_DIS_PLAIN = 1
 IQCC_STORE_INPLACE = 1
+NOALLOC_MAX_PARTIALS = 8192   # workgroup partials the allocation-free energy holds
 
 _lib = None
 
@@ -82,6 +83,7 @@ def lib():
         "iqcc_dress_raw": (i32, [P, i32, P, P, P, i64, i64, P, P, d, P, P, P, P, i64, P]),
         "iqcc_merge_truncate": (i32, [P, P, P, P, i64, i64, d, P, P]),
         "iqcc_qmf_energy": (i32, [P, P, P, P, P, P]),
+        "iqcc_qmf_energy_noalloc": (i32, [P, P, P, P, P, P]),
         "iqcc_qmf_energy_backward": (i32, [P, P, P, P, P, P, P, P, P]),
         "iqcc_dis_gradients": (i32, [P, P, P, P, P, P, i64, i64, i32, P, P]),
         "iqcc_store_rows": (i32, [P, ct.POINTER(i64)]),
@@ -121,7 +123,7 @@ def exported_symbols():
         "iqcc_store_stats", "iqcc_store_lookup",
         "iqcc_dress", "iqcc_dress_energy_update", "iqcc_dress_inplace", "iqcc_store_copy",
         "iqcc_store_inplace_stats", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
-        "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
+        "iqcc_qmf_energy_noalloc", "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
         "iqcc_dress_taped", "iqcc_dress_backward", "iqcc_expectations",
         "iqcc_dress_batched", "iqcc_batch_create", "iqcc_batch_launch", "iqcc_batch_destroy",
         "iqcc_qmf_energy_anti", "iqcc_flip_sets", "iqcc_qcc_iteration", "iqcc_truncate_top",
@@ -443,6 +445,18 @@ def iqcc_merge_truncate(ctx, x, z, c, eps, store_out, stream=None):
         _bad("x, z must be (W, n) planes with one coefficient per row")
     _check(lib().iqcc_merge_truncate(ctx, px, pz, _f64(c, "c", n, optional=(n == 0)), n, ld,
                                      float(eps), store_out, _stream(stream)), ctx)
+
+
+def iqcc_qmf_energy_noalloc(ctx, store, theta, phi, energy=None, stream=None):
+    """iqcc_qmf_energy without any device allocation by the library (its scratch
+    is a fixed device array); `energy` must be given when the caller cannot
+    allocate either."""
+    import torch
+    if energy is None:
+        energy = torch.empty((), dtype=torch.float64, device="cuda")
+    th, ph = _angles(store, theta, phi)
+    _check(lib().iqcc_qmf_energy_noalloc(ctx, store, th, ph, _f64(energy, "energy"), _stream(stream)), ctx)
+    return energy
 
 
 def iqcc_qmf_energy(ctx, store, theta, phi, energy=None, stream=None):
