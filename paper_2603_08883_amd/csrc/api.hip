@@ -31,7 +31,7 @@ struct iqcc_ctx {
   int64_t fuse_energy = 1;
   int64_t dis_tile = 256;
   int64_t dis_bucket_ranges = 0;           // 0: about 8 workgroups per CU in total
-  int64_t inplace_bucket_terms = 128;      // mean bucket of an in-place store at max_terms
+  int64_t inplace_bucket_terms = 256;      // mean bucket of an in-place store at max_terms
   int64_t inplace_item_terms = 0;          // 0: from the stash capacity
   int64_t inplace_cap = 0;                 // 0: as many stash entries as the LDS holds
   int64_t inplace_region_rows = 0;         // 0: regions share the arena minus the pool
@@ -63,6 +63,7 @@ struct iqcc_store {
   bool owned = false;     // true: allocated by iqcc_store_create*, freed by destroy
   double floor = 0.0;     // every live |c| is >= floor (0: unknown)
   bool regions = false;   // contents laid out in bucket regions (in-place dressing allowed)
+  int region_m = -1;      // their bucket bits (fixed while the layout lasts)
 };
 
 namespace {
@@ -201,21 +202,15 @@ Entangler make_entangler(int W, const uint64_t* px, const uint64_t* pz) {
     if (P.pz[w]) { P.piv_word = w; P.piv_in_x = 0; P.piv_mask = P.pz[w] & (~P.pz[w] + 1); break; }
   }
   // 3-qubit groups (per 32-bit half word) that P touches
-  int t = 0;
   for (int h = 0; h < 2 * W; ++h) {
-    P.gstart[h] = (uint8_t)t;
     const uint32_t v = (uint32_t)((P.px[h >> 1] | P.pz[h >> 1]) >> (32 * (h & 1)));
     uint32_t bits = 0;
     for (int g = 0; g < kGroupsPerHalf; ++g) {
       const uint32_t m = (7u << (3 * g));
-      if (v & m) {
-        P.glist[t++] = (uint8_t)g;
-        bits |= m;
-      }
+      if (v & m) bits |= m;
     }
     P.gbits[h] = bits;
   }
-  P.gstart[2 * W] = (uint8_t)t;
   return P;
 }
 
@@ -549,6 +544,7 @@ int iqcc_store_load(iqcc_ctx* ctx, iqcc_store* st, const uint64_t* x, const uint
     launch_store_load_regions(st->W, st->d, x, z, c, n, ld, m, R, ctx->scratch, s);
     LAUNCH_CHECK(ctx);
     st->regions = true;
+    st->region_m = m;
     return IQCC_OK;
   }
   rc = ensure_scratch(ctx, B + B / 1024 + 16);
@@ -573,10 +569,12 @@ int iqcc_store_copy(iqcc_ctx* ctx, const iqcc_store* src, iqcc_store* dst, void*
   const int64_t B = 1ll << m;
   rc = ensure_scratch(ctx, B + B / 1024 + 16);
   if (rc) return rc;
-  launch_store_copy_regions(dst->W, src->d, dst->d, m, R, ctx->scratch, as_stream(stream));
+  launch_store_copy_regions(dst->W, src->d, dst->d, m, R, ctx->scratch, as_stream(stream),
+                            src->regions && src->region_m == m);
   LAUNCH_CHECK(ctx);
   dst->floor = src->floor;
   dst->regions = true;
+  dst->region_m = m;
   return IQCC_OK;
 }
 

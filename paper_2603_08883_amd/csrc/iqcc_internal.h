@@ -293,8 +293,6 @@ struct Entangler {
   // the 3-qubit groups P touches, for the split expectation product
   // <K> = A * B and <K^P> = A * B' (A over the other groups of K)
   uint32_t gbits[2 * kMaxWords];                        // per half word: bits of those groups
-  uint8_t gstart[2 * kMaxWords + 1];                    // glist range of each half word
-  uint8_t glist[2 * kMaxWords * kGroupsPerHalf];        // group index within its half word
 };
 
 // ---------------------------------------------------------------------------
@@ -410,6 +408,10 @@ __device__ __forceinline__ void expect_split(const double* lut, const Entangler&
       }
     }
   }
+  // B and B' over P's groups, two per LDS round trip.  The groups come from
+  // the uniform bit mask gbits (scalar registers): indexing an array of the
+  // by-value kernel argument with a loop counter makes the compiler read it
+  // from memory, and that wait would also wait for every store in flight.
 #pragma unroll
   for (int h = 0; h < 2 * W; ++h) {
     const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
@@ -417,19 +419,21 @@ __device__ __forceinline__ void expect_split(const double* lut, const Entangler&
     const double* lh = lut + h * kGroupsPerHalf * kLutEntries;
     const uint32_t pxh = (uint32_t)(P.px[h >> 1] >> (32 * (h & 1)));
     const uint32_t pzh = (uint32_t)(P.pz[h >> 1] >> (32 * (h & 1)));
-    const int q1 = P.gstart[h + 1];
-    for (int q = P.gstart[h]; q < q1; q += 2) {   // two of P's groups per round trip
+    uint32_t t = P.gbits[h] & 0x49249249u;   // the first bit of each of P's groups
+    while (t) {
       {
-        const uint32_t g = P.glist[q];
-        const uint32_t sh = 3 * g;
+        const uint32_t sh = (uint32_t)__builtin_ctz(t);
+        t &= t - 1;
+        const uint32_t g = div3_small(sh);
         const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
         const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
         b *= lh[g * kLutEntries + code];
         b2 *= lh[g * kLutEntries + (code ^ pcode)];
       }
-      if (q + 1 < q1) {
-        const uint32_t g = P.glist[q + 1];
-        const uint32_t sh = 3 * g;
+      if (t) {
+        const uint32_t sh = (uint32_t)__builtin_ctz(t);
+        t &= t - 1;
+        const uint32_t g = div3_small(sh);
         const uint32_t code = __builtin_amdgcn_ubfe(xh, sh, 3) | (__builtin_amdgcn_ubfe(zh, sh, 3) << 3);
         const uint32_t pcode = __builtin_amdgcn_ubfe(pxh, sh, 3) | (__builtin_amdgcn_ubfe(pzh, sh, 3) << 3);
         c1 *= lh[g * kLutEntries + code];
@@ -503,8 +507,10 @@ void launch_dress_inplace(int W, const StoreDev& st, const Entangler& P, const I
 // in source order).  Both set err = 1 when the regions do not fit the arena.
 int launch_store_load_regions(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
                               int64_t n, int64_t ld, int m, int64_t R, int64_t* scratch, hipStream_t s);
+// same_m: the source has the same bucket count m (its current m is known on
+// the host), so every bucket keeps its terms.
 void launch_store_copy_regions(int W, const StoreDev& src, StoreDev dst, int m, int64_t R, int64_t* scratch,
-                               hipStream_t s);
+                               hipStream_t s, bool same_m);
 
 // One Hamiltonian of a batched dressing launch.
 struct BatchItem {

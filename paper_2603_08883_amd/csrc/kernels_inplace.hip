@@ -35,17 +35,21 @@
 namespace iqcc {
 
 #ifndef IQCC_INPLACE_WAVES
-#define IQCC_INPLACE_WAVES 16
+#define IQCC_INPLACE_WAVES 12
 #endif
 constexpr int kIPW = IQCC_INPLACE_WAVES;   // waves per workgroup (one workgroup per CU)
 constexpr int kIPB = 64 * kIPW;
 constexpr int kIPSlots = 64;      // buckets per work item (one per lane)
+#ifndef IQCC_INPLACE_UNROLL
+#define IQCC_INPLACE_UNROLL 2
+#endif
+constexpr int kIPU = IQCC_INPLACE_UNROLL;   // 64-term slices of the scan in flight per wave
 
 enum : uint8_t { kFComm = 1, kFHole = 2, kFNew = 4 };
 
 // Per-wave LDS segment: the stash of up to `cap` entries, its join table and
 // per-slot counters of the item.
-constexpr int kIPSlotArrays = 5;
+constexpr int kIPSlotArrays = 4;
 
 __host__ __device__ inline int ip_tsize(int cap) { return (3 * cap / 2 + 7) & ~7; }
 
@@ -74,8 +78,7 @@ struct Seg {
   double* ac;        // [cap]
   int32_t* tab;      // [tsize] join table; afterwards the freed rows of every slot
   int32_t* arel;     // [cap] row of the entry relative to its bucket's first row
-  int32_t* s_pre;    // [kIPSlots + 1] flat index of the slot's first input term
-  int32_t* s_nnew;   // new keys arriving in the slot
+  int32_t* s_nnew;   // [kIPSlots + 1] new keys arriving in the slot
   int32_t* s_nhole;  // rows of the slot freed by compression
   int32_t* s_hfirst; // first freed row of the slot in the list
   int32_t* s_ctr;    // rows placed so far
@@ -96,11 +99,10 @@ __device__ __forceinline__ Seg<W> carve_seg(unsigned char* p, int cap) {
   g.tab = (int32_t*)(p + o); o += (size_t)g.tsize * 4;
   g.arel = (int32_t*)(p + o); o += (size_t)cap * 4;
   int32_t* sa = (int32_t*)(p + o); o += (size_t)kIPSlotArrays * (kIPSlots + 1) * 4;
-  g.s_pre = sa;
-  g.s_nnew = sa + 1 * (kIPSlots + 1);
-  g.s_nhole = sa + 2 * (kIPSlots + 1);
-  g.s_hfirst = sa + 3 * (kIPSlots + 1);
-  g.s_ctr = sa + 4 * (kIPSlots + 1);
+  g.s_nnew = sa;
+  g.s_nhole = sa + 1 * (kIPSlots + 1);
+  g.s_hfirst = sa + 2 * (kIPSlots + 1);
+  g.s_ctr = sa + 3 * (kIPSlots + 1);
   g.partner = (int16_t*)(p + o); o += (size_t)cap * 2;
   g.aslot = (uint8_t*)(p + o); o += (size_t)cap;
   g.aflag = (uint8_t*)(p + o);
@@ -191,15 +193,62 @@ struct Item {
   int nslots, n;
 };
 
-// Slot of flat index i: the largest s < nslots with pre[s] <= i.
-template <int W>
-__device__ __forceinline__ int slot_of(const Seg<W>& g, const Item& I, int i) {
+// Slot of flat index i: the largest s < nslots with pre_s <= i, where lane s
+// holds pre_s (non-decreasing, pre_0 = 0).  Called by the whole wave.
+__device__ __forceinline__ int slot_of(const Item& I, int i) {
   if (I.nslots <= 2) return (I.nslots == 2 && i >= I.pre1) ? 1 : 0;
   int s = 0;
 #pragma unroll
-  for (int step = kIPSlots / 2; step; step >>= 1)
-    if (s + step < I.nslots && g.s_pre[s + step] <= i) s += step;
+  for (int step = kIPSlots / 2; step; step >>= 1) {
+    const int c = s + step;
+    const int pc = __shfl(I.pre, c < kIPSlots ? c : kIPSlots - 1, 64);
+    if (c < I.nslots && pc <= i) s = c;
+  }
   return s;
+}
+
+// The item's per-lane state from its bucket table entries.
+__device__ __forceinline__ Item make_item(const SlotDesc& d) {
+  Item I;
+  I.nslots = d.nslots;
+  I.off = d.off;
+  I.cnt = d.cnt;
+  I.room = d.lim - d.off;
+  I.b = d.b;
+  I.noff = 0;
+  const int incl = wave_incl_scan(I.cnt);
+  I.pre = incl - I.cnt;
+  I.n = __shfl(incl, 63, 64);
+  I.pre1 = __shfl(I.pre, 1, 64);
+  return I;
+}
+
+// U slices of 64 input terms of an item, loaded ahead of their use.
+template <int W, int U>
+struct Slices {
+  uint64_t kx[U][W], kz[U][W];
+  double kc[U];
+  int slot[U], rel[U];
+};
+
+// Issue the loads of flat indices [base, base + 64 U) of item I.
+template <int W, int U>
+__device__ __forceinline__ void issue_slices(const StoreDev& st, const Item& I, int base, Slices<W, U>& S) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = base + 64 * u + lane;
+    const bool valid = i < I.n;
+    const int sl = slot_of(I, i);
+    const int pre = __shfl(I.pre, sl, 64);
+    const int off = __shfl(I.off, sl, 64);
+    S.slot[u] = sl;
+    S.rel[u] = i - pre;
+    S.kc[u] = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) S.kx[u][w] = S.kz[u][w] = 0;
+    if (valid) load_key<W>(st, (int64_t)off + S.rel[u], S.kx[u], S.kz[u], S.kc[u]);
+  }
 }
 
 struct WaveCounts {
@@ -209,110 +258,109 @@ struct WaveCounts {
 // Rows for the entries with `has` set, placed in their slot `d` in stash
 // order.  MODE 0 (in place): first the slot's freed rows, in ascending order,
 // then the rows after its live ones; MODE 1: the slot's fresh region.
+// Lanes with the same d are consecutive (the stash and the scan are in
+// slot-major order, and a new key goes to slot s ^ 1 or s), so a lane's rank
+// is the slot's count so far plus the `has` lanes between the start of its
+// run of equal d and itself; the last lane of each run advances the count.
+// Lanes past the end of the data pass d = -1.
 template <int W, int MODE>
 __device__ __forceinline__ void put_rows(const StoreDev& st, const Seg<W>& g, const Item& I, bool has, int d,
                                          const uint64_t* kx, const uint64_t* kz, double c) {
-  uint64_t todo = __ballot(has);
-  while (todo) {
-    const int lead = __builtin_ctzll(todo);
-    const int dd = __shfl(d, lead, 64);
-    const bool mine = has && d == dd;
-    const uint64_t mm = __ballot(mine);
-    const int base = g.s_ctr[dd];
-    const int o = __shfl(MODE == 0 ? I.off : I.noff, dd, 64);
-    const int ct = __shfl(I.cnt, dd, 64);
-    if (mine) {
-      const int rank = base + (int)lanes_below(mm);
-      int64_t row;
-      if (MODE == 0) {
-        const int nh = g.s_nhole[dd];
-        row = rank < nh ? (int64_t)o + g.tab[g.s_hfirst[dd] + rank] : (int64_t)o + ct + (rank - nh);
-      } else {
-        row = (int64_t)o + rank;
-      }
-      store_key<W>(st, row, kx, kz, c);
+  const int lane = threadIdx.x & 63;
+  const uint64_t hm = __ballot(has);
+  if (hm == 0) return;
+  const int dprev = __shfl_up(d, 1, 64);
+  const uint64_t heads = __ballot(lane == 0 || d != dprev);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);   // lanes <= this one
+  const int start = 63 - __clzll(heads & upto);
+  const uint64_t run_below = ((1ull << lane) - 1) & ~((1ull << start) - 1);
+  const int before = __popcll(hm & run_below);
+  const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1);
+  const int dd = d < 0 ? 0 : d;
+  const int base = d >= 0 ? g.s_ctr[dd] : 0;
+  const int o = __shfl(MODE == 0 ? I.off : I.noff, dd, 64);
+  const int ct = __shfl(I.cnt, dd, 64);
+  if (has) {
+    const int rank = base + before;
+    int64_t row;
+    if (MODE == 0) {
+      const int nh = g.s_nhole[dd];
+      row = rank < nh ? (int64_t)o + g.tab[g.s_hfirst[dd] + rank] : (int64_t)o + ct + (rank - nh);
+    } else {
+      row = (int64_t)o + rank;
     }
-    wave_sync();
-    if ((threadIdx.x & 63) == 0) g.s_ctr[dd] = base + __popcll(mm);
-    wave_sync();
-    todo &= ~mm;
+    store_key<W>(st, row, kx, kz, c);
   }
+  wave_sync();
+  if (tail && d >= 0) g.s_ctr[dd] = base + before + (has ? 1 : 0);
+  wave_sync();
 }
 
-// One pass over the item's input terms, 128 per iteration (two loads in
-// flight per lane).
+// Classify U loaded slices (flat indices base + 64 u + lane):
 //   mode 0: stash the anticommuting terms and the commuting terms that
 //           compression drops (flag kFComm); energy of the commuting terms;
 //   mode 1: put the kept commuting terms into the fresh regions, stash the
 //           anticommuting terms of residue class `rem` mod `mod`;
 //   mode 2: stash the anticommuting terms of class `rem` only.
-// Returns the number of stash candidates (entries beyond cap are not
-// written); nanti receives the number of anticommuting terms.
-template <int W, bool ENERGY>
-__device__ int item_scan(const StoreDev& st, const Entangler& P, double eps, int delta, const double* lut,
-                         const Seg<W>& g, const Item& I, int mode, uint32_t mod, uint32_t rem, double& eacc,
-                         int& nanti) {
+// nst counts the stash candidates (entries beyond cap are not written); nanti
+// the anticommuting terms.
+template <int W, bool ENERGY, int U>
+__device__ __forceinline__ void classify_slices(const StoreDev& st, const Entangler& P, double eps, int delta,
+                                                const double* lut, const Seg<W>& g, const Item& I, int base,
+                                                const Slices<W, U>& S, int mode, uint32_t mod, uint32_t rem,
+                                                double& eacc, int& nst, int& nanti) {
   const int lane = threadIdx.x & 63;
-  int nst = 0;
-  nanti = 0;
-  for (int base = 0; base < I.n; base += 128) {
-    uint64_t kx[2][W], kz[2][W];
-    double kc[2];
-    int slot[2], rel[2];
-    bool valid[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int i = base + 64 * u + lane;
-      valid[u] = i < I.n;
-      slot[u] = valid[u] ? slot_of<W>(g, I, i) : 0;
-      const int pre = __shfl(I.pre, slot[u], 64);
-      const int off = __shfl(I.off, slot[u], 64);
-      rel[u] = i - pre;
-      kc[u] = 0.0;
-#pragma unroll
-      for (int w = 0; w < W; ++w) kx[u][w] = kz[u][w] = 0;
-      if (valid[u]) load_key<W>(st, (int64_t)off + rel[u], kx[u], kz[u], kc[u]);
+  for (int u = 0; u < U; ++u) {
+    const bool valid = base + 64 * u + lane < I.n;
+    const bool anti = valid && anticommutes<W>(S.kx[u], S.kz[u], P.px, P.pz);
+    nanti += (int)__popcll(__ballot(anti));
+    const bool comm_drop = valid && !anti && fabs(S.kc[u]) < eps;
+    const bool comm_keep = valid && !anti && !comm_drop;
+    bool stash = anti;
+    if (anti && mode != 0 && mod > 1)
+      stash = (round_hash(rep_hash<W>(P, S.kx[u], S.kz[u])) & (mod - 1)) == rem;
+    uint8_t flag = 0;
+    if (mode == 0 && comm_drop) {
+      stash = true;
+      flag = kFComm;
     }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const bool anti = valid[u] && anticommutes<W>(kx[u], kz[u], P.px, P.pz);
-      nanti += (int)__popcll(__ballot(anti));
-      const bool comm_drop = valid[u] && !anti && fabs(kc[u]) < eps;
-      const bool comm_keep = valid[u] && !anti && !comm_drop;
-      bool stash = anti;
-      if (anti && mode != 0 && mod > 1)
-        stash = (round_hash(rep_hash<W>(P, kx[u], kz[u])) & (mod - 1)) == rem;
-      uint8_t flag = 0;
-      if (mode == 0 && comm_drop) {
-        stash = true;
-        flag = kFComm;
+    if (ENERGY && mode == 0) {
+      // commuting terms: every kept one, or (delta) only those compression drops
+      if (delta ? comm_drop : comm_keep) {
+        const double ek = expect_lut<W>(lut, S.kx[u], S.kz[u]);
+        eacc += comm_drop ? -(S.kc[u] * ek) : S.kc[u] * ek;
       }
-      if (ENERGY && mode == 0) {
-        // commuting terms: every kept one, or (delta) only those compression drops
-        if (delta ? comm_drop : comm_keep) {
-          const double ek = expect_lut<W>(lut, kx[u], kz[u]);
-          eacc += comm_drop ? -(kc[u] * ek) : kc[u] * ek;
-        }
-      }
-      if (mode == 1) put_rows<W, 1>(st, g, I, comm_keep, slot[u], kx[u], kz[u], kc[u]);
-      const uint64_t bm = __ballot(stash);
-      const int pos = nst + (int)lanes_below(bm);
-      if (stash && pos < g.cap) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          g.ax[w * g.cap + pos] = kx[u][w];
-          g.az[w * g.cap + pos] = kz[u][w];
-        }
-        g.ac[pos] = kc[u];
-        g.arel[pos] = rel[u];
-        g.aslot[pos] = (uint8_t)slot[u];
-        g.aflag[pos] = flag;
-      }
-      nst += (int)__popcll(bm);
     }
+    if (mode == 1) put_rows<W, 1>(st, g, I, comm_keep, valid ? S.slot[u] : -1, S.kx[u], S.kz[u], S.kc[u]);
+    const uint64_t bm = __ballot(stash);
+    const int pos = nst + (int)lanes_below(bm);
+    if (stash && pos < g.cap) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        g.ax[w * g.cap + pos] = S.kx[u][w];
+        g.az[w * g.cap + pos] = S.kz[u][w];
+      }
+      g.ac[pos] = S.kc[u];
+      g.arel[pos] = S.rel[u];
+      g.aslot[pos] = (uint8_t)S.slot[u];
+      g.aflag[pos] = flag;
+    }
+    nst += (int)__popcll(bm);
   }
-  wave_sync();
-  return nst;
+}
+
+// One pass over the item's input terms from flat index `from` on, U slices
+// per iteration (their loads in flight before any is classified).
+template <int W, bool ENERGY, int U>
+__device__ void item_scan(const StoreDev& st, const Entangler& P, double eps, int delta, const double* lut,
+                          const Seg<W>& g, const Item& I, int from, int mode, uint32_t mod, uint32_t rem,
+                          double& eacc, int& nst, int& nanti) {
+  for (int base = from; base < I.n; base += 64 * U) {
+    Slices<W, U> S;
+    issue_slices<W, U>(st, I, base, S);
+    classify_slices<W, ENERGY, U>(st, P, eps, delta, lut, g, I, base, S, mode, mod, rem, eacc, nst, nanti);
+  }
 }
 
 template <int W>
@@ -484,7 +532,7 @@ __device__ void emit_inplace(const StoreDev& st, const Entangler& P, double C, d
       qx[w] = kx[w] ^ P.px[w];
       qz[w] = kz[w] ^ P.pz[w];
     }
-    put_rows<W, 0>(st, g, I, live && (fl & kFNew), selfp ? s : s ^ 1, qx, qz, vn);
+    put_rows<W, 0>(st, g, I, live && (fl & kFNew), valid ? (selfp ? s : s ^ 1) : -1, qx, qz, vn);
   }
   wave_sync();
 }
@@ -569,9 +617,10 @@ __device__ bool relocate_item(const StoreDev& st, const Entangler& P, const Inpl
     wave_sync();
     bool ok = true;
     for (uint32_t r = 0; r < R; ++r) {
-      int na;
-      const int nst = item_scan<W, ENERGY>(st, P, cfg.eps, cfg.delta, lut, g, I, r == 0 ? 1 : 2, R, r,
-                                           e_try, na);
+      // one slice at a time: the next item's slices may be in flight
+      int nst = 0, na = 0;
+      item_scan<W, ENERGY, 1>(st, P, cfg.eps, cfg.delta, lut, g, I, 0, r == 0 ? 1 : 2, R, r, e_try, nst, na);
+      wave_sync();
       if (nst > g.cap) {
         ok = false;
         break;
@@ -601,14 +650,14 @@ __device__ bool relocate_item(const StoreDev& st, const Entangler& P, const Inpl
           if (cfg.delta) e_try -= a * ek;
         }
         fresh_try += __popcll(__ballot(keep_new));
-        put_rows<W, 1>(st, g, I, keep_own, s, kx, kz, vo);
+        put_rows<W, 1>(st, g, I, keep_own, valid ? s : -1, kx, kz, vo);
         uint64_t qx[W], qz[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
           qx[w] = kx[w] ^ P.px[w];
           qz[w] = kz[w] ^ P.pz[w];
         }
-        put_rows<W, 1>(st, g, I, keep_new, selfp ? s : s ^ 1, qx, qz, vn);
+        put_rows<W, 1>(st, g, I, keep_new, valid ? (selfp ? s : s ^ 1) : -1, qx, qz, vn);
       }
       wave_sync();
     }
@@ -636,32 +685,36 @@ __device__ bool relocate_item(const StoreDev& st, const Entangler& P, const Inpl
   return true;
 }
 
+// One work item.  S holds the loads of its first kIPU slices, issued while
+// the previous item was processed; once this item's input is stashed, the
+// loads of the next item's first slices (item In, from descriptor dn) are
+// issued into S, so they are in flight while this item is joined and emitted.
 template <int W, bool ENERGY>
 __device__ void process_item(const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, const Geo& G,
-                             const double* lut, const Seg<W>& g, const SlotDesc& d, double& eacc,
-                             WaveCounts& wc) {
+                             const double* lut, const Seg<W>& g, Item& I, Slices<W, kIPU>& S, bool have_next,
+                             const SlotDesc& dn, Item& In, double& eacc, WaveCounts& wc) {
   const int lane = threadIdx.x & 63;
-  Item I;
-  I.nslots = d.nslots;
-  I.off = d.off;
-  I.cnt = d.cnt;
-  I.room = d.lim - d.off;
-  I.b = d.b;
-  I.noff = 0;
-  const int incl = wave_incl_scan(I.cnt);
-  I.pre = incl - I.cnt;
-  I.n = __shfl(incl, 63, 64);
-  I.pre1 = __shfl(I.pre, 1, 64);
-  if (I.n == 0) return;
-  if (lane <= I.nslots) g.s_pre[lane] = lane < I.nslots ? I.pre : I.n;
+  if (I.n == 0) {
+    if (have_next) {
+      In = make_item(dn);
+      issue_slices<W, kIPU>(st, In, 0, S);
+    }
+    return;
+  }
   if (lane < I.nslots) {
     g.s_nnew[lane] = 0;
     g.s_nhole[lane] = 0;
     g.s_ctr[lane] = 0;
   }
   wave_sync();
-  int nanti;
-  const int nst = item_scan<W, ENERGY>(st, P, cfg.eps, cfg.delta, lut, g, I, 0, 1, 0, eacc, nanti);
+  int nst = 0, nanti = 0;
+  classify_slices<W, ENERGY, kIPU>(st, P, cfg.eps, cfg.delta, lut, g, I, 0, S, 0, 1, 0, eacc, nst, nanti);
+  item_scan<W, ENERGY, kIPU>(st, P, cfg.eps, cfg.delta, lut, g, I, 64 * kIPU, 0, 1, 0, eacc, nst, nanti);
+  wave_sync();
+  if (have_next) {
+    In = make_item(dn);
+    issue_slices<W, kIPU>(st, In, 0, S);
+  }
   wc.anti += nanti;
   if (nst > g.cap) {
     relocate_item<W, ENERGY>(st, P, cfg, lut, g, I, G.selfp, nanti, eacc, wc);
@@ -721,13 +774,22 @@ __global__ __launch_bounds__(kIPB) void k_dress_inplace(StoreDev st, Entangler P
     G.ppi = ppi;
     G.nitems = (G.npairs + ppi - 1) / ppi;
     const int64_t nw = (int64_t)gridDim.x * kIPW;
-    SlotDesc next;
-    if (gw < G.nitems) next = load_desc(st, G, gw);
+    // bucket tables two items ahead, term slices one item ahead
+    SlotDesc d_next;
+    if (gw + nw < G.nitems) d_next = load_desc(st, G, gw + nw);
+    Item I;
+    Slices<W, kIPU> S;
+    if (gw < G.nitems) {
+      I = make_item(load_desc(st, G, gw));
+      issue_slices<W, kIPU>(st, I, 0, S);
+    }
     for (int64_t it = gw; it < G.nitems; it += nw) {
-      const SlotDesc cur = next;
-      // the next item's bucket table is in flight while this item is processed
-      if (it + nw < G.nitems) next = load_desc(st, G, it + nw);
-      process_item<W, ENERGY>(st, P, cfg, G, lut, g, cur, eacc, wc);
+      const bool have_next = it + nw < G.nitems;
+      const SlotDesc dn = d_next;
+      if (it + 2 * nw < G.nitems) d_next = load_desc(st, G, it + 2 * nw);
+      Item In;
+      process_item<W, ENERGY>(st, P, cfg, G, lut, g, I, S, have_next, dn, In, eacc, wc);
+      I = In;
     }
   }
   if (lane == 0) {

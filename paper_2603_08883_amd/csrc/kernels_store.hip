@@ -339,11 +339,74 @@ __global__ void k_copy_regions(StoreDev src, StoreDev dst, int m) {
   }
 }
 
+// Same bucket count on both sides: bucket b keeps its terms.  Counts first,
+// then the rows: one wave per 64 consecutive buckets, lanes over the flat
+// index of their rows (coalesced for large buckets, dense for small ones).
+__global__ void k_copy_counts_same(StoreDev src, StoreDev dst, int64_t B) {
+  if (*src.err) return;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < B;
+       b += (int64_t)gridDim.x * blockDim.x)
+    dst.cnt[b] = src.cnt[b];
+}
+
+template <int W>
+__global__ void k_copy_rows_same(StoreDev src, StoreDev dst, int64_t B) {
+  if (*src.err || *dst.err) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t g = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); g * 64 < B; g += waves) {
+    const int64_t b = g * 64 + lane;
+    const int64_t cnt = b < B ? src.cnt[b] : 0;
+    const int64_t soff = b < B ? src.off[b] : 0;
+    const int64_t doff = b < B ? dst.off[b] : 0;
+    int64_t incl = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    const int64_t pre = incl - cnt;
+    const int64_t n = __shfl(incl, 63, 64);
+    for (int64_t i0 = 0; i0 < n; i0 += 64) {
+      const int64_t i = i0 + lane;
+      int s = 0;   // the last lane whose first row is <= i
+#pragma unroll
+      for (int step = 32; step; step >>= 1) {
+        const int64_t pc = __shfl(pre, s + step, 64);
+        if (s + step < 64 && pc <= i) s += step;
+      }
+      const int64_t ps = __shfl(pre, s, 64), so = __shfl(soff, s, 64), dof = __shfl(doff, s, 64);
+      if (i < n) {
+        uint64_t kx[W], kz[W];
+        double c;
+        load_key<W>(src, so + (i - ps), kx, kz, c);
+        store_key<W>(dst, dof + (i - ps), kx, kz, c);
+      }
+    }
+  }
+}
+
 void launch_store_copy_regions(int W, const StoreDev& src, StoreDev dst, int m, int64_t R, int64_t* scratch,
-                               hipStream_t s) {
+                               hipStream_t s, bool same_m) {
   const int64_t B = 1ll << m;
   int64_t* reg = scratch;               // B
   int64_t* scan_tmp = scratch + B;      // ceil(B/1024)+1
+  if (same_m) {
+    int64_t lb = (B + kBlock - 1) / kBlock;
+    if (lb > 4096) lb = 4096;
+    hipLaunchKernelGGL(k_copy_counts_same, dim3((unsigned)lb), dim3(kBlock), 0, s, src, dst, B);
+    regions_from_counts(dst, B, m, R, -1, src, reg, scan_tmp, s);
+    int64_t wb = (B / 64 + kWaves - 1) / kWaves;
+    if (wb < 1) wb = 1;
+    if (wb > 8192) wb = 8192;
+    switch (W) {
+      case 1: hipLaunchKernelGGL(k_copy_rows_same<1>, dim3((unsigned)wb), dim3(kBlock), 0, s, src, dst, B); break;
+      case 2: hipLaunchKernelGGL(k_copy_rows_same<2>, dim3((unsigned)wb), dim3(kBlock), 0, s, src, dst, B); break;
+      case 3: hipLaunchKernelGGL(k_copy_rows_same<3>, dim3((unsigned)wb), dim3(kBlock), 0, s, src, dst, B); break;
+      default: hipLaunchKernelGGL(k_copy_rows_same<4>, dim3((unsigned)wb), dim3(kBlock), 0, s, src, dst, B); break;
+    }
+    return;
+  }
   int64_t blocks = (B + kWaves - 1) / kWaves;
   if (blocks > 16384) blocks = 16384;
   switch (W) {
