@@ -332,7 +332,10 @@ int iqcc_dress_taped(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px, co
  *   lambda_in[A] = lambda_out[A]                                      (commuting A)
  *   dtau = sum_A -sin(t) c_A lambda_out[A] + s_A cos(t) c_A lambda_out[A^P].
  * The rows of A^P and the signs s_A come from the tape of iqcc_dress_taped;
- * px, pz name the step's entangler and are only checked against n_qubits. */
+ * px, pz name the step's entangler and are only checked against n_qubits.
+ * dtau is an exact fixed-point sum (resolution 2^-60) of the per-row terms, so
+ * it has the same bits for any order of the rows; it is NaN if a term is not
+ * finite or the terms' magnitudes add up to 2^31 or more. */
 int iqcc_dress_backward(iqcc_ctx *ctx, const iqcc_store *in, const uint64_t *px,
                         const uint64_t *pz, double tau, const int32_t *tape_self,
                         const int32_t *tape_partner, const double *lambda_out,
@@ -394,7 +397,13 @@ int iqcc_qmf_energy_noalloc(iqcc_ctx *ctx, const iqcc_store *h, const double *th
  * DEVICE array of iqcc_store_rows entries) receives, for every live row r,
  * dE_scale * <Omega| P_r |Omega>: the cotangent of each coefficient, as
  * iqcc_expectations computes it (same values up to the rounding of the
- * product; rows that hold no term are left untouched). */
+ * product; rows that hold no term are left untouched).  dtheta and dphi are
+ * the same bits on every run and for any order of the rows within the
+ * buckets: every per-term contribution is added as an exact 120-bit fixed-
+ * point integer (resolution 2^-60), and the per-workgroup sums are reduced
+ * in a fixed order.  The exact sums need every |c| < 2^31 and, per workgroup,
+ * (largest |c|) * (terms) < 2^42; past those bounds, or with a non-finite
+ * coefficient or angle, dtheta and dphi come out NaN. */
 int iqcc_qmf_energy_backward(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
                              const double *phi, const double *dE_scale, double *dtheta,
                              double *dphi, double *lambda, void *stream);

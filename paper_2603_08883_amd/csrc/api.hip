@@ -837,11 +837,11 @@ int iqcc_dress_backward(iqcc_ctx* ctx, const iqcc_store* in, const uint64_t* px,
     return fail(ctx, IQCC_ERR_INVALID_ARG, "entangler has bits beyond n_qubits");
   hipStream_t s = as_stream(stream);
   const int grid = (int)(ctx->n_cu * 4);
-  rc = ensure_partial(ctx, grid);
+  rc = ensure_partial(ctx, 3 * (int64_t)grid);   // exact fixed-point parts
   if (rc) return rc;
   launch_dress_backward(in->W, in->d, std::cos(tau), std::sin(tau), tape_self, tape_partner,
                         lambda_out, lambda_in, ctx->partial, grid, s);
-  launch_finalize_sum(ctx->partial, grid, nullptr, dtau, s);
+  launch_finalize_fixed(ctx->partial, grid, dtau, s);
   LAUNCH_CHECK(ctx);
   return IQCC_OK;
 }

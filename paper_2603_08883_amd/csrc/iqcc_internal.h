@@ -125,6 +125,83 @@ __device__ __forceinline__ double block_sum_n(double v, double* tmp) {
   return s;  // valid in thread 0
 }
 
+// Exact sums of doubles whose result does not depend on the order of the
+// additions.  A value v with |v| < 2^31 is taken as the pair of integers
+//   n1 = round(v * 2^20),  n0 = round((v - n1 * 2^-20) * 2^60),
+// so v = n1 * 2^-20 + n0 * 2^-60 to within 2^-61; integer sums of the pairs
+// are exact.  Adding 1.5 * 2^32 (resp. 1.5 * 2^-8) rounds to a multiple of
+// 2^-20 (2^-60), and the difference of the bit patterns is that multiple as an
+// integer (both sums stay in the binade of the constant).
+struct FixedSum {
+  long long hi = 0;    // units of 2^-20
+  long long lo = 0;    // units of 2^-60
+  double mag = 0.0;    // sum of |v| in any order: range check only
+};
+
+__device__ __forceinline__ void fixed_split(double v, long long& n1, long long& n0) {
+  const double k1 = 0x1.8p32, k0 = 0x1.8p-8;
+  const double a1 = v + k1;
+  const double r = v - (a1 - k1);
+  const double a0 = r + k0;
+  n1 = __double_as_longlong(a1) - __double_as_longlong(k1);
+  n0 = __double_as_longlong(a0) - __double_as_longlong(k0);
+}
+
+__device__ __forceinline__ void fixed_add(FixedSum& f, double v) {
+  long long n1, n0;
+  fixed_split(v, n1, n0);
+  f.hi += n1;
+  f.lo += n0;
+  f.mag += fabs(v);
+}
+
+// Moves whole units of 2^-20 out of lo (|lo| < 2^40 afterwards).
+__device__ __forceinline__ void fixed_normalize(FixedSum& f) {
+  const long long carry = f.lo >> 40;
+  f.hi += carry;
+  f.lo -= carry * (1ll << 40);
+}
+
+// The value of a sum of at most 2^23 normalized parts whose values were
+// finite and summed to magnitude below 2^31 (NaN otherwise).
+__device__ __forceinline__ double fixed_value(long long hi, long long lo, double mag) {
+  if (!(mag < 0x1p31)) return __builtin_nan("");
+  return (double)hi * 0x1p-20 + (double)lo * 0x1p-60;
+}
+
+// Block sum of FixedSum parts (exact in hi and lo), valid in thread 0; the
+// parts are normalized first.
+template <int NW>
+__device__ __forceinline__ FixedSum block_fixed_sum(FixedSum f, long long* tmp_hi, long long* tmp_lo,
+                                                    double* tmp_mag) {
+  fixed_normalize(f);
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    f.hi += __shfl_down(f.hi, d, 64);
+    f.lo += __shfl_down(f.lo, d, 64);
+    f.mag += __shfl_down(f.mag, d, 64);
+  }
+  if (lane == 0) {
+    tmp_hi[wid] = f.hi;
+    tmp_lo[wid] = f.lo;
+    tmp_mag[wid] = f.mag;
+  }
+  __syncthreads();
+  FixedSum t;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NW; ++i) {
+      t.hi += tmp_hi[i];
+      t.lo += tmp_lo[i];
+      t.mag += tmp_mag[i];
+    }
+    fixed_normalize(t);
+  }
+  __syncthreads();
+  return t;
+}
+
 // Block-wide sum of doubles in a fixed order (lane tree, then waves in order).
 __device__ __forceinline__ double block_sum(double v, double* tmp) {
   const int lane = threadIdx.x & 63;
@@ -540,6 +617,9 @@ void launch_dress_raw(int W, const uint64_t* x, const uint64_t* z, const double*
 // *out = (base ? *base : 0) + (scale ? *scale : 1) * sum(partial[0..n)); out may alias base.
 void launch_finalize_sum(const double* partial, int n, const double* scale, double* out,
                          hipStream_t s, const double* base = nullptr);
+// *out = exact sum of n FixedSum parts stored as three 8-byte words each
+// (hi, lo, mag), NaN when the values were out of range.
+void launch_finalize_fixed(const double* parts, int n, double* out, hipStream_t s);
 
 // Device state of the term-limit selection (kernels_select.hip).
 struct SelState {

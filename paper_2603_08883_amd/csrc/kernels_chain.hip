@@ -13,7 +13,8 @@
 //   dE/dt += sum_A  -sin(t) c[A] lambda'[A] + s_A cos(t) c[A] lambda'[A^P].
 // The tape recorded by the forward kernel gives, for every input row, the
 // output rows of A and A^P and the sign s_A, so no key is read or looked up
-// here.
+// here.  The step's dE/dt is an exact fixed-point sum, so it has the same
+// bits for any order of the rows.
 #include "iqcc_internal.h"
 
 #pragma clang fp contract(off)
@@ -26,9 +27,11 @@ __global__ __launch_bounds__(kBlock) void k_dress_backward(StoreDev in, double C
                                                            const int32_t* tape_partner,
                                                            const double* lam_out, double* lam_in,
                                                            double* partial) {
-  __shared__ double red[kWaves];
+  __shared__ long long red_hi[kWaves], red_lo[kWaves];
+  __shared__ double red_mag[kWaves];
   const int64_t B = 1ll << *in.m;
-  double acc = 0.0;
+  // dE/dt as an exact fixed-point sum: the same bits for any row order
+  FixedSum acc;
   for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
     const int64_t n = in.cnt[b], off = in.off[b];
     for (int64_t i = threadIdx.x; i < n; i += kBlock) {
@@ -45,11 +48,15 @@ __global__ __launch_bounds__(kBlock) void k_dress_backward(StoreDev in, double C
       const double s = (enc & 1) ? 1.0 : -1.0;
       const double c = in.c[row];
       lam_in[row] = __dadd_rn(__dmul_rn(C, la), s * __dmul_rn(S, lp));
-      acc += __dadd_rn(-__dmul_rn(__dmul_rn(S, c), la), s * __dmul_rn(__dmul_rn(C, c), lp));
+      fixed_add(acc, __dadd_rn(-__dmul_rn(__dmul_rn(S, c), la), s * __dmul_rn(__dmul_rn(C, c), lp)));
     }
   }
-  const double t = block_sum(acc, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  const FixedSum t = block_fixed_sum<kWaves>(acc, red_hi, red_lo, red_mag);
+  if (threadIdx.x == 0) {
+    partial[3 * blockIdx.x] = __longlong_as_double(t.hi);
+    partial[3 * blockIdx.x + 1] = __longlong_as_double(t.lo);
+    partial[3 * blockIdx.x + 2] = t.mag;
+  }
 }
 
 void launch_dress_backward(int W, const StoreDev& in, double C, double S,

@@ -5,6 +5,8 @@
 // b(X) = sin t cos f, b(Y) = sin t sin f, b(Z) = cos t.  Terms are streamed
 // once; the product uses a 3-qubit-group table in LDS and skips identity
 // groups.  Partial sums are per workgroup and reduced in a fixed order.
+#include <cfloat>
+
 #include "iqcc_internal.h"
 
 #pragma clang fp contract(off)
@@ -64,6 +66,24 @@ void launch_finalize_sum(const double* partial, int n, const double* scale, doub
   hipLaunchKernelGGL(k_finalize_sum, dim3(1), dim3(kBlock), 0, s, partial, n, scale, base, out);
 }
 
+// Exact sum of FixedSum parts (hi, lo, mag as three 8-byte words each).
+__global__ void k_finalize_fixed(const double* parts, int n, double* out) {
+  __shared__ long long red_hi[kWaves], red_lo[kWaves];
+  __shared__ double red_mag[kWaves];
+  FixedSum f;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    f.hi += __double_as_longlong(parts[3 * i]);
+    f.lo += __double_as_longlong(parts[3 * i + 1]);
+    f.mag += parts[3 * i + 2];
+  }
+  const FixedSum t = block_fixed_sum<kWaves>(f, red_hi, red_lo, red_mag);
+  if (threadIdx.x == 0) *out = fixed_value(t.hi, t.lo, t.mag);
+}
+
+void launch_finalize_fixed(const double* parts, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_fixed, dim3(1), dim3(kBlock), 0, s, parts, n, out);
+}
+
 // <K> from every 3-qubit group of every half word, identity groups included
 // (their table entry 0 is 1.0): a fixed, branch-free sequence of independent
 // lookups whose addresses take two VALU operations each.
@@ -86,21 +106,39 @@ __device__ __forceinline__ double expect_dense(const double* lut, const uint64_t
 }
 
 // ---------------------------------------------------------------------------
-// Energy of a store: workgroup g takes buckets g, g + grid, ...
+// Energy of a store.  Workgroup g takes the groups of G consecutive buckets
+// g, g + grid, ... (G = 1 .. 256 so that every workgroup has a group); the
+// rows of a group's buckets are streamed as one flat range, kEItems terms per
+// thread and pass, so small buckets do not each cost a round trip.
 // ---------------------------------------------------------------------------
 constexpr int kEItems = 4;
 
 template <int W>
-__global__ __launch_bounds__(kBlock) void k_energy(StoreDev st, const double* lut_g,
-                                                   double* partial) {
+__global__ __launch_bounds__(kBlock) void k_energy(StoreDev st, const double* lut_g, double* partial) {
   __shared__ double lut[W * kGroupsPerWord * kLutEntries];
   __shared__ double red[kWaves];
+  __shared__ uint64_t scan_tmp[kWaves];
+  __shared__ int64_t s_pre[kBlock + 1];
+  __shared__ int64_t s_off[kBlock];
   for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
-  __syncthreads();
   const int64_t B = 1ll << *st.m;
+  int64_t G = B / gridDim.x;
+  G = G < 1 ? 1 : (G > kBlock ? kBlock : G);
+  const int64_t ngroups = (B + G - 1) / G;
   double acc = 0.0;
-  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
-    const int64_t n = st.cnt[b], off = st.off[b];
+  __syncthreads();
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t b = grp * G + threadIdx.x;
+    const bool mine = threadIdx.x < G && b < B;
+    const int64_t cnt = mine ? st.cnt[b] : 0;
+    const int64_t off = mine ? st.off[b] : 0;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan((uint64_t)cnt, scan_tmp, total);
+    s_pre[threadIdx.x] = (int64_t)ex;
+    s_off[threadIdx.x] = off;
+    if (threadIdx.x == 0) s_pre[kBlock] = (int64_t)total;
+    __syncthreads();
+    const int64_t n = (int64_t)total;
     for (int64_t i0 = 0; i0 < n; i0 += kBlock * kEItems) {
       uint64_t kx[kEItems][W], kz[kEItems][W];
       double kc[kEItems];
@@ -108,21 +146,26 @@ __global__ __launch_bounds__(kBlock) void k_energy(StoreDev st, const double* lu
       for (int r = 0; r < kEItems; ++r) {
         const int64_t i = i0 + r * kBlock + threadIdx.x;
         kc[r] = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) kx[r][w] = kz[r][w] = 0;
         if (i < n) {
+          int lo = 0;   // the last bucket of the group whose first row is <= i
+#pragma unroll
+          for (int step = kBlock / 2; step; step >>= 1)
+            if (s_pre[lo + step] <= i) lo += step;
+          const int64_t row = s_off[lo] + (i - s_pre[lo]);
 #pragma unroll
           for (int w = 0; w < W; ++w) {
-            kx[r][w] = __builtin_nontemporal_load(&st.x[w * st.cap + off + i]);
-            kz[r][w] = __builtin_nontemporal_load(&st.z[w * st.cap + off + i]);
+            kx[r][w] = __builtin_nontemporal_load(&st.x[w * st.cap + row]);
+            kz[r][w] = __builtin_nontemporal_load(&st.z[w * st.cap + row]);
           }
-          kc[r] = __builtin_nontemporal_load(&st.c[off + i]);
-        } else {
-#pragma unroll
-          for (int w = 0; w < W; ++w) kx[r][w] = kz[r][w] = 0;
+          kc[r] = __builtin_nontemporal_load(&st.c[row]);
         }
       }
 #pragma unroll
       for (int r = 0; r < kEItems; ++r) acc += kc[r] * expect_dense<W>(lut, kx[r], kz[r]);
     }
+    __syncthreads();
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -139,64 +182,309 @@ void launch_energy(int W, const StoreDev& st, int grid, const double* lut, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Backward w.r.t. the Bloch angles.
+// Backward w.r.t. the Bloch angles (derivative of the Eq. 3 energy).
 // dE/dtheta_q = sum_sigma S[q][sigma] db_sigma/dtheta (likewise phi), where
 // S[q][sigma] adds, over the terms with sigma on qubit q, c times the product
 // of the term's other factors.
 //
-// The product of a term is taken over its 3-qubit groups (the energy table),
-// so the derivative is first formed per group table entry:
-//   T[e] = sum over the terms whose group g has code e of c * prod_{g' != g} L_g',
-// then, once per workgroup, S[q][sigma] = sum over the codes e of q's group
-// with sigma at q's position of T[e] * (product of the other qubits' factors
-// of that code).  Per term: ZK, the number of zero group factors, and PK, the
-// product of the non-zero ones, formed as one division by the product of
-// their tabulated reciprocals (the term's <K> is PK when ZK = 0, else 0; it
-// is written per row when the caller asks for the coefficient cotangents).  The other groups of group g then multiply to
-// PK * (1 / L_g) when L_g != 0 and ZK = 0, to PK when L_g = 0 and ZK = 1, and
-// to 0 otherwise (exact zeros never divide).  Only the term's non-identity
-// groups are visited for T.  T lives in LDS and takes FP64 atomics (one per
-// non-identity group of a term); per-workgroup S are reduced in a fixed
-// order.  acc layout per workgroup: [3 * nq] with sigma order X, Z, Y.
+// The product of a term runs over its 3-qubit groups (the energy table L), so
+// the derivative is first formed per group table entry:
+//   T[g][e] = sum over the terms whose group g has code e != 0 of
+//             c * prod_{g' != g} L_g',
+// and once per workgroup S[q][sigma] = sum over the codes e of q's group with
+// sigma at q's position of T[g][e] * (product of the group's other qubit
+// factors of that code).  The product of a term's other groups comes from
+// prefix and suffix products -- inside each 32-bit half word over its 11
+// groups, and across the half words over their products -- with no division,
+// so vanishing factors need no special case.
+//
+// Summation order does not change the result.  Each value is split into two
+// integers, round(v * 2^20) and round((v - that * 2^-20) * 2^60), and added
+// to two 64-bit integer tables with LDS atomics, which are exact; per
+// workgroup the two sums turn into one double, and the per-workgroup S are
+// reduced in a fixed order, so dE/dtheta and dE/dphi are the same on every
+// run.  The split is exact for |v| < 2^31 and the sums cannot overflow while
+// (largest |c| of the workgroup's terms) * (its term count) < 2^42 and the
+// count is below 2^23; a workgroup past these bounds, or one that meets a
+// non-finite coefficient or angle, writes NaN instead of its S.  Resolution:
+// 2^-61 per added value.
+// acc layout per workgroup: [3 * nq] with sigma order X, Z, Y.
 // ---------------------------------------------------------------------------
-constexpr int kBwdBlock = 512;
-
-// LDS tables of the backward hold one pad entry after every group's 64
-// entries, so that the same code of different groups falls in different
-// banks (entry e sits at e + e / 64).
-__host__ __device__ constexpr int bwd_padded(int n) { return n + n / kLutEntries; }
+#ifndef IQCC_BWD_GROT
+#define IQCC_BWD_GROT 1
+#endif
+#ifndef IQCC_BWD_BLOCK
+#define IQCC_BWD_BLOCK 512
+#endif
+#ifndef IQCC_BWD_COPIES
+#define IQCC_BWD_COPIES 1
+#endif
+constexpr int kBwdBlock = IQCC_BWD_BLOCK;
+// copies of the integer tables; lane l adds into copy l % kBwdCopies
+constexpr int kBwdCopies = IQCC_BWD_COPIES;
+constexpr int kBwdGroup = 256;   // most buckets per group of one flat range
+// LDS tables of the backward hold each 3-qubit group's 64 entries at a stride
+// of 65, so that equal codes of different groups fall in different banks.
+constexpr int kBwdStride = kLutEntries + 1;
 
 size_t energy_bwd_lds_bytes(int W) {
-  return (size_t)2 * bwd_padded(W * kGroupsPerWord * kLutEntries) * 8 + (size_t)W * 64 * 4 * 8;
+  // energy table, the two integer tables (the per-qubit factors of the
+  // epilogue reuse the first), bucket-group scan
+  return (size_t)(1 + 2 * kBwdCopies) * W * kGroupsPerWord * kBwdStride * 8 + (size_t)(2 * kBwdGroup + 1) * 8;
 }
 
-// Workgroups per CU that the LDS of one CU holds (160 KiB), at most four
-// 512-thread workgroups (32 waves).
+// Workgroups per CU that the LDS of one CU holds (160 KiB), at most 2048
+// threads (32 waves) in all.
 int energy_bwd_blocks_per_cu(int W) {
-  const int k = (int)((size_t)160 * 1024 / energy_bwd_lds_bytes(W));
-  return k < 1 ? 1 : k > 4 ? 4 : k;
+  const int k = (int)((size_t)160 * 1024 / (energy_bwd_lds_bytes(W) + 512));
+  const int kmax = 2048 / kBwdBlock;
+  return k < 1 ? 1 : k > kmax ? kmax : k;
+}
+
+// v as round(v * 2^20) * 2^-20 + round(r * 2^60) * 2^-60 (r the remainder),
+// both added to their integer tables.  Adding 1.5 * 2^32 (resp. 1.5 * 2^-8)
+// rounds to a multiple of 2^-20 (2^-60), and the difference of the bit
+// patterns is that multiple as an integer (both sums stay in the binade of the
+// constant, whose low 32 bits are zero).
+__device__ __forceinline__ void add_fixed(unsigned long long* hi, unsigned long long* lo, int e, double v) {
+  const double k1 = 0x1.8p32, k0 = 0x1.8p-8;
+  const double a1 = v + k1;
+  const double r = v - (a1 - k1);
+  const double a0 = r + k0;
+  atomicAdd(&hi[e], (unsigned long long)(__double_as_longlong(a1) - __double_as_longlong(k1)));
+  atomicAdd(&lo[e], (unsigned long long)(__double_as_longlong(a0) - __double_as_longlong(k0)));
+}
+
+// One term of the backward: T contributions of its non-identity groups and,
+// when lam is given, its cotangent.
+template <int W>
+__device__ __forceinline__ void bwd_term(const double* lut, unsigned long long* thi,
+                                         unsigned long long* tlo, const uint64_t* kx,
+                                         const uint64_t* kz, double c, double* lam_row,
+                                         double scale) {
+  constexpr int NH = kGroupsPerHalf * kBwdStride;
+  // products of the 2W half words (identity groups read entry 0 = 1.0)
+  double hp[2 * W];
+#pragma unroll
+  for (int h = 0; h < 2 * W; ++h) {
+    const uint32_t xh = (uint32_t)(kx[h >> 1] >> (32 * (h & 1)));
+    const uint32_t zh = (uint32_t)(kz[h >> 1] >> (32 * (h & 1)));
+    const double* lh = lut + h * NH;
+    double p0 = 1.0, p1 = 1.0;
+#pragma unroll
+    for (int g = 0; g < kGroupsPerHalf; ++g) {
+      const uint32_t code = __builtin_amdgcn_ubfe(xh, 3 * g, 3) | (__builtin_amdgcn_ubfe(zh, 3 * g, 3) << 3);
+      if (g & 1) p1 *= lh[g * kBwdStride + code]; else p0 *= lh[g * kBwdStride + code];
+    }
+    hp[h] = p0 * p1;
+  }
+  // <K> for the coefficient cotangent
+  if (lam_row) {
+    double all = hp[0];
+#pragma unroll
+    for (int h = 1; h < 2 * W; ++h) all *= hp[h];
+    *lam_row = scale * all;
+  }
+  // c times the product of the other half words, per half word
+  double ho[2 * W];
+  double pre = c;
+#pragma unroll
+  for (int h = 0; h < 2 * W; ++h) { ho[h] = pre; pre *= hp[h]; }
+  double suf = 1.0;
+#pragma unroll
+  for (int h = 2 * W - 1; h >= 0; --h) { ho[h] *= suf; suf *= hp[h]; }
+  // each half word: prefix and suffix over its groups.  A term visits its
+  // half words starting at one picked from its own key bits, so that the
+  // lanes of a wave add into different half words' tables at a time (fewer
+  // lanes on one LDS address); the values do not depend on where the term
+  // sits in the store.
+  const uint32_t mix = ((uint32_t)kx[0] ^ (uint32_t)(kz[0] >> 29) ^ (uint32_t)(kx[W - 1] >> 35)) * 0x9E3779B1u;
+  const int rot = (int)__umulhi(mix, 2u * W);
+#pragma unroll 1
+  for (int j = 0; j < 2 * W; ++j) {
+    int h = rot + j;
+    h = h >= 2 * W ? h - 2 * W : h;
+    uint64_t xw = kx[0], zw = kz[0];
+    double oh = ho[0];
+#pragma unroll
+    for (int u = 1; u < 2 * W; ++u) {
+      if (u == h) oh = ho[u];
+      if ((u & 1) == 0 && u == (h & ~1)) { xw = kx[u >> 1]; zw = kz[u >> 1]; }
+    }
+    const uint32_t xh = (uint32_t)(xw >> (32 * (h & 1)));
+    const uint32_t zh = (uint32_t)(zw >> (32 * (h & 1)));
+#if IQCC_BWD_GROT
+    // groups visited from one picked from the term's key bits as well
+    const int rg = (int)__umulhi(mix * 0x85EBCA6Bu, (uint32_t)kGroupsPerHalf);
+    const uint64_t xr = ((uint64_t)xh | ((uint64_t)xh << 33)) >> (3 * rg);
+    const uint64_t zr = ((uint64_t)zh | ((uint64_t)zh << 33)) >> (3 * rg);
+    double L[kGroupsPerHalf];
+    uint32_t code[kGroupsPerHalf];
+    int idx[kGroupsPerHalf];
+    // group rg + g of the half, wrapped: the base before and after the wrap
+    const int base_lo = h * NH + rg * kBwdStride;
+    const int base_hi = base_lo - kGroupsPerHalf * kBwdStride;
+#pragma unroll
+    for (int g = 0; g < kGroupsPerHalf; ++g) {
+      code[g] = (uint32_t)((xr >> (3 * g)) & 7) | ((uint32_t)((zr >> (3 * g)) & 7) << 3);
+      idx[g] = (rg < kGroupsPerHalf - g ? base_lo : base_hi) + g * kBwdStride + (int)code[g];
+      L[g] = lut[idx[g]];
+    }
+#else
+    const double* lh = lut + h * NH;
+    double L[kGroupsPerHalf];
+    uint32_t code[kGroupsPerHalf];
+    int idx[kGroupsPerHalf];
+#pragma unroll
+    for (int g = 0; g < kGroupsPerHalf; ++g) {
+      code[g] = __builtin_amdgcn_ubfe(xh, 3 * g, 3) | (__builtin_amdgcn_ubfe(zh, 3 * g, 3) << 3);
+      idx[g] = h * NH + g * kBwdStride + (int)code[g];
+      L[g] = lh[g * kBwdStride + code[g]];
+    }
+#endif
+    double sf[kGroupsPerHalf];
+    sf[kGroupsPerHalf - 1] = 1.0;
+#pragma unroll
+    for (int g = kGroupsPerHalf - 1; g > 0; --g) sf[g - 1] = sf[g] * L[g];
+    double pg = oh;
+#pragma unroll
+    for (int g = 0; g < kGroupsPerHalf; ++g) {
+      if (code[g] != 0) add_fixed(thi, tlo, idx[g], pg * sf[g]);
+      pg *= L[g];
+    }
+  }
 }
 
 template <int W>
-__global__ __launch_bounds__(kBwdBlock) void k_energy_bwd(StoreDev st, int nq, const double* theta,
-                                                          const double* phi, const double* lut_g,
-                                                          const double* dE, double* lam,
-                                                          double* acc_g) {
-  constexpr int NE = W * kGroupsPerWord * kLutEntries;
-  constexpr int NP = bwd_padded(NE);
-  constexpr int HP = bwd_padded(kGroupsPerHalf * kLutEntries);   // padded entries per half word
+__global__ __launch_bounds__(kBwdBlock, 4) void k_energy_bwd(StoreDev st, int nq, const double* theta,
+                                                             const double* phi, const double* lut_g,
+                                                             const double* dE, double* lam,
+                                                             double* acc_g) {
+  constexpr int NE = W * kGroupsPerWord * kBwdStride;
+  constexpr int NH = kGroupsPerHalf * kBwdStride;   // entries per half word
   extern __shared__ __align__(16) unsigned char smem_bwd[];
-  double* rec = (double*)smem_bwd;     // 1 / L per table entry (0 where L is 0)
-  double* tg = rec + NP;               // T per table entry
-  double* fac = tg + NP;               // per qubit: factor of I, X, Z, Y
-  for (int i = threadIdx.x; i < NP; i += kBwdBlock) {
-    const int g = i / (kLutEntries + 1), k = i % (kLutEntries + 1);
-    const double l = k < kLutEntries ? lut_g[g * kLutEntries + k] : 1.0;
-    const double r = 1.0 / l;
-    // a factor whose reciprocal overflows (|L| below 2^-1024) counts as a zero
-    rec[i] = (l != 0.0 && r - r == 0.0) ? r : 0.0;
-    tg[i] = 0.0;
+  double* lut = (double*)smem_bwd;                                     // [NE] L per group entry
+  unsigned long long* thi = (unsigned long long*)(lut + NE);           // [NE] sums of round(v 2^20)
+  unsigned long long* tlo = thi + NE;                                  // [NE] sums of the remainders
+  double* fac = (double*)thi;   // epilogue: per qubit, factor of I, X, Z, Y (4 * 64W <= NE)
+  int64_t* s_pre = (int64_t*)(thi + 2 * kBwdCopies * NE);              // [kBwdGroup + 1] group scan
+  int64_t* s_off = s_pre + kBwdGroup + 1;                              // [kBwdGroup] first rows
+  __shared__ double s_cmax[kBwdBlock / 64];
+  __shared__ long long s_cnt[kBwdBlock / 64];
+  __shared__ uint64_t scan_tmp[kBwdBlock / 64];
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < NE; i += kBwdBlock) {
+    const int k = i % kBwdStride;
+    lut[i] = k < kLutEntries ? lut_g[i / kBwdStride * kLutEntries + k] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kBwdCopies; ++k) thi[2 * k * NE + i] = tlo[2 * k * NE + i] = 0ull;
   }
+  for (int q = threadIdx.x; q < nq; q += kBwdBlock)
+    if (!(fabs(theta[q]) <= DBL_MAX && fabs(phi[q]) <= DBL_MAX)) s_bad = 1;
+  const int my_copy = (int)(threadIdx.x % kBwdCopies) * 2 * NE;
+  const double scale = dE ? *dE : 1.0;
+  bool ok = true;   // every coefficient finite and below 2^31 in magnitude
+  double cmax = 0.0;
+  long long nmine = 0;
+  // Workgroup g takes the groups of G consecutive buckets g, g + grid, ...;
+  // a group's rows are one flat range, one term per thread and pass, the next
+  // pass's term loaded while this one is processed.
+  const int64_t B = 1ll << *st.m;
+  int64_t G = B / gridDim.x;
+  G = G < 1 ? 1 : (G > kBwdGroup ? kBwdGroup : G);
+  const int64_t ngroups = (B + G - 1) / G;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t b = grp * G + threadIdx.x;
+    const bool mine = threadIdx.x < G && b < B;
+    const int64_t cnt = mine ? st.cnt[b] : 0;
+    const int64_t off = mine ? st.off[b] : 0;
+    uint64_t total;
+    // (the scan's barriers also order the previous group's reads of s_pre)
+    const uint64_t ex = block_exclusive_scan_n<kBwdBlock / 64>((uint64_t)cnt, scan_tmp, total);
+    if (threadIdx.x < kBwdGroup) {
+      s_pre[threadIdx.x] = (int64_t)ex;
+      s_off[threadIdx.x] = off;
+    }
+    if (threadIdx.x == 0) s_pre[kBwdGroup] = (int64_t)total;
+    __syncthreads();
+    const int64_t n = (int64_t)total;
+    auto row_of = [&](int64_t i) {
+      int lo = 0;   // the last bucket of the group whose first row is <= i
+#pragma unroll
+      for (int step = kBwdGroup / 2; step; step >>= 1)
+        if (s_pre[lo + step] <= i) lo += step;
+      return s_off[lo] + (i - s_pre[lo]);
+    };
+    uint64_t cx[W], cz[W], nx[W], nz[W];
+    double cc = 0.0, nc = 0.0;
+    int64_t crow = 0, nrow = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) cx[w] = cz[w] = 0;
+    if (threadIdx.x < n) {
+      crow = row_of(threadIdx.x);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        cx[w] = __builtin_nontemporal_load(&st.x[w * st.cap + crow]);
+        cz[w] = __builtin_nontemporal_load(&st.z[w * st.cap + crow]);
+      }
+      cc = __builtin_nontemporal_load(&st.c[crow]);
+    }
+    for (int64_t i0 = 0; i0 < n; i0 += kBwdBlock) {
+      const int64_t in = i0 + kBwdBlock + threadIdx.x;
+#pragma unroll
+      for (int w = 0; w < W; ++w) nx[w] = nz[w] = 0;
+      nc = 0.0;
+      if (in < n) {
+        nrow = row_of(in);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          nx[w] = __builtin_nontemporal_load(&st.x[w * st.cap + nrow]);
+          nz[w] = __builtin_nontemporal_load(&st.z[w * st.cap + nrow]);
+        }
+        nc = __builtin_nontemporal_load(&st.c[nrow]);
+      }
+      if (i0 + threadIdx.x < n) {
+        ++nmine;
+        ok = ok && fabs(cc) < 0x1p31;
+        cmax = fmax(cmax, fabs(cc));
+        bwd_term<W>(lut, thi + my_copy, tlo + my_copy, cx, cz, cc, lam ? lam + crow : nullptr, scale);
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w) { cx[w] = nx[w]; cz[w] = nz[w]; }
+      cc = nc;
+      crow = nrow;
+    }
+  }
+  // bounds of the exact integer sums (see above), over the workgroup
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    cmax = fmax(cmax, __shfl_xor(cmax, d, 64));
+    nmine += __shfl_xor(nmine, d, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_cmax[threadIdx.x >> 6] = cmax;
+    s_cnt[threadIdx.x >> 6] = nmine;
+  }
+  if (!ok) s_bad = 1;
+  __syncthreads();
+  double cm = 0.0;
+  long long nwg = 0;
+  for (int k = 0; k < kBwdBlock / 64; ++k) {
+    cm = fmax(cm, s_cmax[k]);
+    nwg += s_cnt[k];
+  }
+  const bool in_range = s_bad == 0 && nwg < (1ll << 23) && cm * (double)nwg < 0x1p42;
+  // the sums as doubles, over the energy table (no longer needed), then the
+  // per-qubit factors over the first integer table
+  for (int i = threadIdx.x; i < NE; i += kBwdBlock) {
+    unsigned long long a = thi[i], b = tlo[i];
+#pragma unroll
+    for (int k = 1; k < kBwdCopies; ++k) { a += thi[2 * k * NE + i]; b += tlo[2 * k * NE + i]; }
+    lut[i] = (double)(long long)a * 0x1p-20 + (double)(long long)b * 0x1p-60;
+  }
+  __syncthreads();
   for (int q = threadIdx.x; q < 64 * W; q += kBwdBlock) {
     double st_ = 0, ct = 1, sp = 0, cp = 1;
     if (q < nq) {
@@ -206,82 +494,13 @@ __global__ __launch_bounds__(kBwdBlock) void k_energy_bwd(StoreDev st, int nq, c
     for (int op = 0; op < 4; ++op) fac[4 * q + op] = bloch_factor(op, st_, ct, sp, cp);
   }
   __syncthreads();
-  const double scale = dE ? *dE : 1.0;
-  const int64_t B = 1ll << *st.m;
-  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
-    const int64_t n = st.cnt[b], off = st.off[b];
-    for (int64_t i = threadIdx.x; i < n; i += kBwdBlock) {
-      uint64_t kx[W], kz[W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        kx[w] = __builtin_nontemporal_load(&st.x[w * st.cap + off + i]);
-        kz[w] = __builtin_nontemporal_load(&st.z[w * st.cap + off + i]);
-      }
-      const double c = __builtin_nontemporal_load(&st.c[off + i]);
-      // ZK, the number of zero group factors, and R, the product of the
-      // reciprocals of the others: every group of every half word in a fixed
-      // order (identity groups read 1.0), the same group in every lane at a time
-      double r[4] = {1.0, 1.0, 1.0, 1.0};
-      int zk = 0;
-#pragma unroll 1
-      for (int w = 0; w < W; ++w) {
-        uint64_t xw = kx[0], zw = kz[0];
-#pragma unroll
-        for (int u = 1; u < W; ++u) {
-          xw = u == w ? kx[u] : xw;
-          zw = u == w ? kz[u] : zw;
-        }
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-          const uint32_t xh = (uint32_t)(xw >> (32 * hh));
-          const uint32_t zh = (uint32_t)(zw >> (32 * hh));
-          const double* rh = rec + (2 * w + hh) * HP;
-#pragma unroll
-          for (int g = 0; g < kGroupsPerHalf; ++g) {
-            const uint32_t code = __builtin_amdgcn_ubfe(xh, 3 * g, 3) | (__builtin_amdgcn_ubfe(zh, 3 * g, 3) << 3);
-            const double v = rh[g * (kLutEntries + 1) + code];
-            zk += v == 0.0;
-            r[g & 3] *= v == 0.0 ? 1.0 : v;
-          }
-        }
-      }
-      const double pk = 1.0 / ((r[0] * r[1]) * (r[2] * r[3]));   // PK
-      // dE/dc of the term: <K> = PK without zero factors, else 0
-      if (lam) lam[off + i] = zk == 0 ? scale * pk : 0.0;
-      if (zk > 1) continue;   // every group's other factors include a zero
-      const double cpk = c * pk;
-      const bool one_zero = zk == 1;
-      // T over the term's non-identity groups only
-#pragma unroll
-      for (int h = 0; h < 2 * W; ++h) {
-        const uint32_t xh = (uint32_t)(kx[h >> 1] >> (32 * (h & 1)));
-        const uint32_t zh = (uint32_t)(kz[h >> 1] >> (32 * (h & 1)));
-        const double* rh = rec + h * HP;
-        double* th = tg + h * HP;
-        uint32_t t = group_starts(xh | zh);
-        while (t) {
-          // entry 0 (code 0 of group 0) only comes from an exhausted t
-          const uint32_t e0 = next_group_entry(t, xh, zh);
-          const uint32_t e1 = next_group_entry(t, xh, zh);
-          const uint32_t p0 = e0 + (e0 >> 6), p1 = e1 + (e1 >> 6);
-          const double v0 = rh[p0], v1 = rh[p1];
-          const bool z0 = v0 == 0.0, z1 = v1 == 0.0;
-          const double o0 = z0 ? cpk : cpk * v0;
-          const double o1 = z1 ? cpk : cpk * v1;
-          if (e0 != 0 && z0 == one_zero) atomicAdd(&th[p0], o0);
-          if (e1 != 0 && z1 == one_zero) atomicAdd(&th[p1], o1);
-        }
-      }
-    }
-  }
-  __syncthreads();
   // S[q][sigma] from T: the codes of q's group with sigma at q's position,
   // each weighted by the product of the group's other factors of that code
   for (int k = threadIdx.x; k < 3 * nq; k += kBwdBlock) {
     const int q = k / 3, op = k % 3 + 1;   // op: 1 = X, 2 = Z, 3 = Y
     const int h = q >> 5, bit = q & 31;
     const int g = (int)div3_small((uint32_t)bit), r = bit - 3 * g;
-    const double* th = tg + h * HP + g * (kLutEntries + 1);
+    const double* tg = lut + h * NH + g * kBwdStride;
     double s = 0.0;
     for (int code = 1; code < kLutEntries; ++code) {
       if ((((code >> r) & 1) | (((code >> (3 + r)) & 1) << 1)) != op) continue;
@@ -296,9 +515,9 @@ __global__ __launch_bounds__(kBwdBlock) void k_energy_bwd(StoreDev st, int nq, c
         }
         other *= fac[4 * (32 * h + 3 * g + r2) + o2];
       }
-      if (valid) s += th[code] * other;
+      if (valid) s += tg[code] * other;
     }
-    acc_g[(int64_t)blockIdx.x * 3 * nq + k] = s;
+    acc_g[(int64_t)blockIdx.x * 3 * nq + k] = in_range ? s : __builtin_nan("");
   }
 }
 
@@ -307,8 +526,8 @@ static void launch_bwd_w(int nq, const StoreDev& st, int grid, const double* the
                          const double* phi, const double* lut, const double* dE, double* lam,
                          double* acc, hipStream_t s) {
   const size_t lds = energy_bwd_lds_bytes(W);
-  hipFuncSetAttribute((const void*)k_energy_bwd<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds);
+  (void)hipFuncSetAttribute((const void*)k_energy_bwd<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
   hipLaunchKernelGGL(k_energy_bwd<W>, dim3(grid), dim3(kBwdBlock), lds, s, st, nq, theta, phi,
                      lut, dE, lam, acc);
 }

@@ -277,6 +277,46 @@ def test_energy_backward_degenerate(ctx):
         assert live.numel() == n and (n == 0 or live.item() == 1.0)
 
 
+def test_energy_backward_bit_identical(ctx):
+    """dE/dtheta and dE/dphi are the same bits on repeated calls and for any
+    row order of the same terms (the sums are exact integer sums), and match
+    the oracle."""
+    nq = 124
+    x, z, c = I.hamiltonian_banded(nq, 7, band=3)
+    th, ph, tht, pht = _angles(nq, 21)
+    perm = np.random.default_rng(22).permutation(len(c))
+    s1 = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    s2 = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x[perm], z[perm], c[perm])
+    describe(0, "energy_backward bit-identical", nq=nq, n=len(c))
+    runs = [iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht, None, None) for s in (s1, s1, s2)]
+    for dt, dp in runs[1:]:
+        assert torch.equal(dt, runs[0][0]) and torch.equal(dp, runs[0][1])
+    rt, rp = O.qmf_grad_angles(nq, x, z, c, th, ph)
+    assert np.abs(runs[0][0].cpu().numpy() - rt).max() <= E_TOL
+    assert np.abs(runs[0][1].cpu().numpy() - rp).max() <= E_TOL
+
+
+def test_energy_backward_out_of_range(ctx):
+    """A coefficient beyond the exact fixed-point range, or a non-finite angle,
+    gives NaN angle gradients rather than wrong finite ones."""
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    th, ph, tht, pht = _angles(nq, 23)
+    big = c.copy()
+    big[5] = 2.0 ** 32
+    s = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, big)
+    describe(0, "energy_backward out of range", nq=nq)
+    dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s.handle, tht, pht, None, None)
+    assert torch.isnan(dt).all() and torch.isnan(dp).all()
+    s2 = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+    th_bad = tht.clone()
+    th_bad[3] = float("nan")
+    dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s2.handle, th_bad, pht, None, None)
+    assert torch.isnan(dt).all() and torch.isnan(dp).all()
+    dt, dp = iqcc.iqcc_qmf_energy_backward(ctx.handle, s2.handle, tht, pht, None, None)
+    assert torch.isfinite(dt).all() and torch.isfinite(dp).all()
+
+
 @pytest.mark.parametrize("nq,angles", [(40, "z-eigen"), (40, "mixed"), (124, "z-eigen"), (124, "mixed"),
                                        (150, "mixed"), (200, "mixed")])
 def test_energy_backward_special_angles(ctx, nq, angles):
