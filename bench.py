@@ -24,6 +24,8 @@ import numpy as np
 
 METRIC = "dressed+merged Pauli terms/s & HBM GB/s @124q; DIS grads/s batched vs plain"
 HBM_PEAK_GBPS = 8000.0
+# VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 N_QUBITS = 124
 N_STEPS_CHAIN = 20
 EPS = 1e-8
@@ -96,7 +98,7 @@ def cpu_baseline(x, z, c, ents, taus, th, ph, budget_s=20.0, single_budget_s=8.0
 
 
 def profiled_traffic(ctx):
-    """HBM bytes per k_dress launch from the committed hardware-counter summary
+    """HBM bytes per k_dress_inplace launch from the committed hardware-counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a kernel of known traffic), or None
     when the kernel source or the launch knobs differ from the profiled ones."""
     import hashlib
@@ -115,11 +117,36 @@ def profiled_traffic(ctx):
         with open(os.path.join(here, "paper_2603_08883_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     knobs = " ".join(f"{k}={iqcc.iqcc_get_param(ctx.handle, k)}"
-                     for k in ("split_bucket_terms", "anti_cap", "grid_per_cu"))
+                     for k in ("inplace_bucket_terms", "inplace_item_terms", "inplace_cap",
+                               "inplace_region_rows"))
     if fields.get("kernel_source_sha256") != h.hexdigest() or fields.get("knobs") != knobs:
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def dis_ops_per_pair():
+    """VALU lane-operations per (term, candidate) pair of k_dis_batched from the
+    committed counter summary (SQ_INSTS_VALU * 64 / pairs), or None when the
+    kernel source differs from the profiled one."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "k_dis_batched_100q_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    with open(os.path.join(here, "paper_2603_08883_amd", "csrc", "kernels_dis.hip"), "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(fields["valu_lane_ops_per_pair"])
     except (KeyError, ValueError):
         return None
 
@@ -144,6 +171,39 @@ def measured_copy_gbps():
     del src, dst
     torch.cuda.empty_cache()
     return nbytes / (ms * 1e-3) / 1e9
+
+
+def angle_backward_leg(ctx, stream, final, tht, pht, bt, reps=5):
+    """dE/dtheta, dE/dphi and the per-term cotangents of the final 124-qubit
+    Hamiltonian (in-place store) in one call, timed with HIP events on the
+    library's stream; checks that two calls give the same bits."""
+    import torch
+    from paper_2603_08883_amd import iqcc
+    n = final.count()
+    lam = torch.empty(iqcc.iqcc_store_rows(final.handle), dtype=torch.float64, device="cuda")
+    d1 = iqcc.iqcc_qmf_energy_backward(ctx.handle, final.handle, tht, pht, None, lam)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        d2 = iqcc.iqcc_qmf_energy_backward(ctx.handle, final.handle, tht, pht, None, lam)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    same = bool(torch.equal(d1[0], d2[0]) and torch.equal(d1[1], d2[1]))
+    del lam
+    torch.cuda.empty_cache()
+    nbytes = (bt + 8) * n   # read each term, write its cotangent
+    log(f"angle backward {ms:.3f} ms over {n} terms")
+    return {"workload": f"final 124-qubit Hamiltonian ({n} terms, in-place store): dE/dtheta, "
+                        "dE/dphi and the per-term cotangents in one call",
+            "ms": ms, "alg_bytes": int(nbytes),
+            "hbm_gbps_algorithmic": nbytes / (ms * 1e-3) / 1e9,
+            "roofline_frac_hbm": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "bit_identical_calls": same,
+            "bound": "VALU and LDS: 44 group lookups, prefix/suffix products and an exact "
+                     "fixed-point add per 3-qubit group of every term"}
 
 
 def autograd_leg(ctx, stream, wl):
@@ -261,6 +321,39 @@ def autograd_leg(ctx, stream, wl):
             "roofline_frac_hbm": bwd_bytes / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
             "bound": "valu (counters: VALU issue about 70% of SIMD time)"},
     }
+
+
+def c5_leg(ctx, wl, steps=50, lr=0.1):
+    """Joint gradient-based optimisation of the 248 Bloch angles and 20 tau of
+    the 124-qubit chain (App. A iterative procedure): gradient descent with
+    Armijo backtracking, each trial a full taped forward, each accepted point
+    differentiated by the reverse sweep."""
+    import torch
+    from paper_2603_08883_amd.autograd import DressingChain, optimize
+    x, z, c, ents, taus, th, ph = wl
+    chain = DressingChain(ctx, N_QUBITS, x, z, c, ents, EPS)
+    stats = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    energies, params = optimize(chain, torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda(),
+                                torch.tensor(taus, dtype=torch.float64, device="cuda"),
+                                steps=steps, lr=lr, stats=stats)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_final = chain.stores[-1].count()
+    chain.close()
+    torch.cuda.empty_cache()
+    taken = len(energies) - 1
+    log(f"C5 optimisation: {taken} steps, E {energies[0]:.10f} -> {energies[-1]:.10f}, "
+        f"{dt / max(taken, 1) * 1e3:.1f} ms/step")
+    return {"workload": "124-qubit 20-step chain (eps 1e-8): gradient descent with Armijo "
+                        "backtracking on (theta, phi, tau) jointly, lr 0.1",
+            "steps_requested": steps, "steps_taken": taken,
+            "energy_first": energies[0], "energy_last": energies[-1],
+            "energies": energies,
+            "non_increasing": all(b <= a for a, b in zip(energies, energies[1:])),
+            "seconds": dt, "ms_per_step": dt / max(taken, 1) * 1e3,
+            "final_terms": int(n_final), **stats}
 
 
 def sortless_leg(ctx, wl, fused_chain_ms, fused_final_terms):
@@ -409,16 +502,29 @@ def main():
     ap.add_argument("--no-chain", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autograd", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 50-step joint optimisation")
     ap.add_argument("--no-qcc", action="store_true")
     ap.add_argument("--no-sortless", action="store_true")
     ap.add_argument("--no-poly", action="store_true")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (batch and DIS knobs; in-place chain knobs reported)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (scale for profiler byte counters)")
-    ap.add_argument("--dis-plain-sample", type=int, default=256)
+    ap.add_argument("--dis-plain-sample", type=int, default=1024)
+    ap.add_argument("--only", choices=("chain", "angle-backward", "dis", "batch"),
+                    help="run one leg alone (for profiling): the timed in-place chain; the "
+                         "angle backward on the chain's final Hamiltonian; DIS; the batch")
     ap.add_argument("--max-terms", type=float, default=1.3e8,
                     help="max_terms of the in-place stores of the 124-qubit chain")
     args = ap.parse_args()
+    if args.only is not None:
+        for leg in ("cpu_baseline", "dis", "chain", "batch", "autograd", "c5", "qcc", "sortless",
+                    "poly"):
+            setattr(args, "no_" + leg, True)
+        if args.only in ("chain", "angle-backward"):
+            args.no_chain = False
+        else:
+            setattr(args, "no_" + args.only, False)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design, not a built path)", file=sys.stderr)
@@ -501,6 +607,10 @@ def main():
         log("step sizes (N_in, N_anti, N_new, N_out):", sizes[0], "...", sizes[-1],
             f"relocated items {relocated}")
         e_full = energies.clone()
+        if args.only == "angle-backward":
+            result["angle_backward"] = angle_backward_leg(ctx, stream, work, tht, pht, bt)
+            print(json.dumps(result), flush=True)
+            return
         for _ in range(max(0, args.warmup)):
             chain()
         torch.cuda.synchronize()
@@ -595,7 +705,22 @@ def main():
                        "chain_ms_full_sum_every_step": full_s * 1e3},
         })
         log(f"chain {chain_s*1e3:.2f} ms, kernels {kernel_s*1e3:.2f} ms, {achieved:.0f} GB/s algorithmic")
+        if args.only == "chain":
+            print(json.dumps(result), flush=True)
+            return
+        if not args.no_autotune:
+            # the tuner's pick for this chain is reported; the headline above
+            # keeps the default knobs, which the committed counter profile names
+            from paper_2603_08883_amd import autotune
+            before = {k: iqcc.iqcc_get_param(ctx.handle, k) for k in autotune.INPLACE_SPACE}
+            tp_, ts_ = autotune.tune_inplace(ctx, h0, work, ents, taus, EPS, tht, pht, W, len(c))
+            result["inplace_autotune"] = {"params": tp_, "chain_ms_at_tuning": ts_ * 1e3,
+                                          "default_params": before,
+                                          "headline_chain_ms_default_params": chain_s * 1e3}
+            autotune.apply(ctx, before)
+            chain()   # the final store again under the default knobs
         final = work
+        result["angle_backward"] = angle_backward_leg(ctx, stream, work, tht, pht, bt)
         # stand-alone QMF energy of the final Hamiltonian (HBM bound: 40 B per term)
         e1 = torch.zeros(1, dtype=torch.float64, device="cuda")
         iqcc.iqcc_qmf_energy(ctx.handle, final.handle, tht, pht, e1)
@@ -694,6 +819,8 @@ def main():
     if not args.no_autograd:
         result["autograd"] = autograd_leg(ctx, stream, wl)
         torch.cuda.empty_cache()
+    if not args.no_c5:
+        result["c5_optimisation"] = c5_leg(ctx, wl)
     del wl
 
     if not args.no_dis:
@@ -706,6 +833,13 @@ def main():
         h = iqcc.Store(ctx, nq, len(c)).load_numpy(x, z, c)
         tht = torch.from_numpy(th).cuda(); pht = torch.from_numpy(ph).cuda()
         dcx = iqcc.to_device_words(cx); dcz = iqcc.to_device_words(cz)
+        dis_tuned = None
+        if not args.no_autotune:
+            from paper_2603_08883_amd import autotune
+            ns_t = min(2048, cx.shape[0])
+            tp_, ts_ = autotune.tune_dis(ctx, h, tht, pht, dcx[:, :ns_t].contiguous(),
+                                         dcz[:, :ns_t].contiguous(), x.shape[1], len(c))
+            dis_tuned = {"params": tp_, "sample_candidates": ns_t, "sample_s_at_tuning": ts_}
         g = iqcc.iqcc_dis_gradients(ctx.handle, h.handle, tht, pht, dcx, dcz, iqcc.IQCC_DIS_BATCHED)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
@@ -727,15 +861,27 @@ def main():
         tp = e0.elapsed_time(e1) * 1e-3
         agree = float((g[:ns] - gp).abs().max().item())
         pairs = float(len(c)) * cx.shape[0]
+        plain_bytes = (16 * x.shape[1] + 8) * len(c)   # every term read once per candidate
+        plain_gbps = plain_bytes / (tp / ns) / 1e9
+        ops = dis_ops_per_pair()
         result["dis"] = {
             "workload": "1e7-term 100-qubit Hamiltonian (banded JW, expanded by XOR with DIS-form "
                         "generators), 1e4 seeded DIS candidates of weight 2-12",
             "n_terms": len(c), "n_candidates": int(cx.shape[0]),
             "batched_grads_per_s": cx.shape[0] / tb, "batched_s": tb,
             "batched_pairs_per_s": pairs / tb,
+            "batched_roofline": {"bound": "alu", "valu_lane_ops_per_pair": ops,
+                                 "achieved": pairs / tb * ops if ops else None,
+                                 "peak": VALU_LANE_OPS_PEAK, "unit": "VALU lane-ops/s",
+                                 "frac": pairs / tb * ops / VALU_LANE_OPS_PEAK if ops else None},
             "plain_grads_per_s": ns / tp, "plain_sample": ns,
+            "plain_ms_per_candidate": tp / ns * 1e3,
+            "plain_hbm_gbps_algorithmic": plain_gbps,
+            "plain_roofline_frac_hbm": plain_gbps / HBM_PEAK_GBPS,
             "speedup_batched_vs_plain": (cx.shape[0] / tb) / (ns / tp),
             "max_abs_diff_batched_vs_plain": agree,
+            "knobs": {k: iqcc.iqcc_get_param(ctx.handle, k) for k in ("dis_tile", "dis_bucket_ranges")},
+            "autotuned": dis_tuned,
         }
         log(f"DIS batched {cx.shape[0]/tb:.0f} grads/s, plain {ns/tp:.0f} grads/s")
         h.close()
@@ -758,9 +904,10 @@ def main():
         hout = [s.handle for s in outs]
         n_terms = sum(len(h["c"]) for h in hs)
         tuned = None
-        if args.autotune:
+        if not args.no_autotune:
             from paper_2603_08883_amd import autotune
-            tuned = autotune.tune_batch(ctx, hin, hout, pxs, pzs, btaus, EPS, 1, n_terms)[0]
+            tp_, ts_ = autotune.tune_batch(ctx, hin, hout, pxs, pzs, btaus, EPS, 1, n_terms)
+            tuned = {"params": tp_, "graph_ms_at_tuning": ts_ * 1e3}
 
         def plain():
             for i in range(len(hs)):
@@ -783,11 +930,19 @@ def main():
         tg = timed(lambda: iqcc.iqcc_batch_launch(ctx.handle, b))
         n_out = sum(o.count() for o in outs)
         iqcc.iqcc_batch_destroy(ctx.handle, b)
+        # every input term read once and every output term written once (24 B each, W = 1)
+        b_bytes = 24 * (n_terms + n_out)
         result["batch"] = {
             "workload": f"{len(hs)} Hamiltonians, 16-64 qubits, {n_terms} terms (log-uniform "
                         "1e3-1e6 each), one entangler each, eps=1e-8",
             "graph_ms": tg * 1e3, "plain_calls_ms": tp * 1e3, "speedup_graph_vs_plain": tp / tg,
-            "terms_per_s_graph": n_out / tg, "autotuned": tuned}
+            "terms_per_s_graph": n_out / tg, "output_terms": int(n_out),
+            "alg_bytes": int(b_bytes), "hbm_gbps_algorithmic": b_bytes / tg / 1e9,
+            "roofline_frac_hbm": b_bytes / tg / 1e9 / HBM_PEAK_GBPS,
+            "knobs": {k: iqcc.iqcc_get_param(ctx.handle, k)
+                      for k in ("batch_anti_cap", "batch_split_bucket_terms", "batch_unit_pairs",
+                                "grid_per_cu")},
+            "autotuned": tuned}
         log(f"batch: graph {tg*1e3:.3f} ms vs {len(hs)} plain calls {tp*1e3:.3f} ms")
         for s_ in ins + outs:
             s_.close()

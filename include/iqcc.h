@@ -81,6 +81,9 @@ const char *iqcc_version(void);
  *   "batch_split_bucket_terms", "batch_anti_cap"
  *                        the same two settings for batched dressing of many
  *                        small Hamiltonians (iqcc_dress_batched, iqcc_batch_*)
+ *   "batch_unit_pairs"   consecutive bucket pairs of one Hamiltonian per work
+ *                        unit of a batch (1 .. 65536); read when the batch is
+ *                        created
  *   "energy_grid_per_cu" workgroups per compute unit of the stand-alone energy
  *                        kernel (1 .. 32)
  *   "fuse_energy"        1: dressing evaluates the energy of its output in the

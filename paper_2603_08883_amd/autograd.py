@@ -123,20 +123,33 @@ def qmf_chain_energy(theta, phi, taus, chain: DressingChain):
 
 
 def optimize(chain: DressingChain, theta, phi, taus, steps: int = 50, lr: float = 0.1,
-             shrink: float = 0.5, c1: float = 1e-4, max_backtracks: int = 30):
-    """Gradient descent with Armijo backtracking on (theta, phi, tau) jointly.
+             shrink: float = 0.5, c1: float = 1e-4, max_backtracks: int = 30, stats=None):
+    """Gradient descent with Armijo backtracking on (theta, phi, tau) jointly
+    (the joint optimisation of amplitudes and QMF parameters, App. A).
 
-    Returns the list of accepted energies (non-increasing)."""
+    Every trial point runs the taped forward once; an accepted trial is
+    differentiated from that same forward.  Returns the list of accepted
+    energies (non-increasing) and the final parameters; `stats`, if a dict,
+    receives the number of forward and backward passes."""
     params = [theta.detach().clone(), phi.detach().clone(), taus.detach().clone()]
     energies = []
+    n_fwd = n_bwd = 0
 
-    def energy_and_grad(p):
+    def forward(p):
+        nonlocal n_fwd
+        n_fwd += 1
         q = [t.detach().clone().requires_grad_(True) for t in p]
-        E = qmf_chain_energy(q[0], q[1], q[2], chain)
-        E.backward()
-        return float(E.item()), [t.grad.detach() for t in q]
+        return qmf_chain_energy(q[0], q[1], q[2], chain), q
 
-    E, grads = energy_and_grad(params)
+    def gradient(E_t, q):
+        nonlocal n_bwd
+        n_bwd += 1
+        E_t.backward()
+        return [t.grad.detach() for t in q]
+
+    E_t, q = forward(params)
+    E = float(E_t.item())
+    grads = gradient(E_t, q)
     energies.append(E)
     for _ in range(steps):
         gnorm2 = sum(float((g * g).sum().item()) for g in grads)
@@ -145,14 +158,17 @@ def optimize(chain: DressingChain, theta, phi, taus, steps: int = 50, lr: float 
         step = lr
         for _ in range(max_backtracks):
             trial = [p - step * g for p, g in zip(params, grads)]
-            with torch.no_grad():
-                Et = float(qmf_chain_energy(trial[0], trial[1], trial[2], chain).item())
+            Et_t, qt = forward(trial)
+            Et = float(Et_t.item())
             if Et <= E - c1 * step * gnorm2:
                 break
             step *= shrink
         else:
             break
         params = trial
-        E, grads = energy_and_grad(params)
+        E = Et
+        grads = gradient(Et_t, qt)
         energies.append(E)
+    if isinstance(stats, dict):
+        stats.update({"forward_passes": n_fwd, "backward_passes": n_bwd})
     return energies, params

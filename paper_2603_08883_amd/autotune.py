@@ -1,8 +1,8 @@
 """Autotuner for bucket and tile sizes of the dressing kernels.
 
 Times candidate settings of the library's knobs ("anti_cap", "grid_per_cu",
-"split_bucket_terms", their batched-dressing counterparts "batch_anti_cap" and
-"batch_split_bucket_terms") on the caller's own workload through
+"split_bucket_terms", their batched-dressing counterparts "batch_anti_cap",
+"batch_split_bucket_terms" and "batch_unit_pairs", and the DIS tile "dis_tile") on the caller's own workload through
 the C ABI, keeps the fastest, and caches the choice in a JSON file keyed by
 (device architecture, words per key, log2 of the term count, workload kind).
 Only timing and bookkeeping happen here; every measured call runs in libiqcc.
@@ -21,10 +21,12 @@ from . import iqcc
 CACHE = os.environ.get("IQCC_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "iqcc", "autotune.json"))
 
-BATCH_SPACE = {"batch_anti_cap": [256, 512, 1024], "grid_per_cu": [1, 2, 4],
-               "batch_split_bucket_terms": [256, 384, 768]}
+BATCH_SPACE = {"batch_anti_cap": [512, 1024], "grid_per_cu": [1, 2, 4],
+               "batch_split_bucket_terms": [384, 768], "batch_unit_pairs": [4, 8, 32]}
 CHAIN_SPACE = {"anti_cap": [512, 1024], "grid_per_cu": [1, 2, 4],
                "split_bucket_terms": [256, 384, 768]}
+INPLACE_SPACE = {"inplace_item_terms": [0, 192, 384], "inplace_cap": [0, 256]}
+DIS_SPACE = {"dis_tile": [64, 128, 256], "dis_bucket_ranges": [0, 512, 1024]}
 
 
 def _arch():
@@ -91,6 +93,10 @@ def tune_batch(ctx, ins, outs, pxs, pzs, taus, eps, W, n_terms, space=None, use_
             continue
         try:
             t = _time(lambda: iqcc.iqcc_batch_launch(ctx.handle, b))
+            for o in outs:   # a setting whose outputs overflowed does not count
+                iqcc.iqcc_store_count(ctx.handle, o)
+        except iqcc.IqccError:
+            continue
         finally:
             iqcc.iqcc_batch_destroy(ctx.handle, b)
         if best is None or t < best[1]:
@@ -137,3 +143,66 @@ def tune_chain(ctx, h0, stores, entanglers, taus, eps, W, n_terms, steps=4, spac
     cache[key] = {"params": best[0], "seconds": best[1]}
     _save(cache)
     return best
+
+
+def _search(ctx, space, key, run, use_cache, check=None):
+    """Time `run` under every setting of `space` (cached under `key`); a
+    setting for which `check()` raises (e.g. a capacity error of the last
+    run) is skipped.  The best setting is applied and run once more, so the
+    caller's outputs come from it."""
+    cache = _load()
+    if use_cache and key in cache:
+        apply(ctx, cache[key]["params"])
+        return cache[key]["params"], cache[key]["seconds"]
+    before = {k: iqcc.iqcc_get_param(ctx.handle, k) for k in space}
+    best = None
+    names = sorted(space)
+    for vals in itertools.product(*[space[k] for k in names]):
+        params = dict(zip(names, vals))
+        try:
+            apply(ctx, params)
+            t = _time(run)
+            if check is not None:
+                check()
+        except iqcc.IqccError:
+            continue
+        if best is None or t < best[1]:
+            best = (params, t)
+    if best is None:
+        apply(ctx, before)
+        raise RuntimeError("no setting of the search space ran")
+    apply(ctx, best[0])
+    run()
+    if check is not None:
+        check()
+    cache[key] = {"params": best[0], "seconds": best[1]}
+    _save(cache)
+    return best
+
+
+def tune_inplace(ctx, h0, work, entanglers, taus, eps, theta, phi, W, n_terms, space=None,
+                 use_cache=True):
+    """Pick the in-place dressing knobs for a chain (copy of H0 + every step with
+    the fused energy); returns (params, seconds)."""
+    space = space or INPLACE_SPACE
+    e = torch.zeros(max(len(entanglers), 1), dtype=torch.float64, device="cuda")
+
+    def run():
+        iqcc.iqcc_store_copy(ctx.handle, h0.handle, work.handle)
+        for j, ((px, pz), t) in enumerate(zip(entanglers, taus)):
+            iqcc.iqcc_dress_inplace(ctx.handle, work.handle, px, pz, float(t), eps, theta, phi,
+                                    e[j - 1:j] if j else None, e[j:j + 1])
+
+    return _search(ctx, space, _key("inplace", W, n_terms, f"s{len(entanglers)}"), run, use_cache,
+                   check=lambda: iqcc.iqcc_store_count(ctx.handle, work.handle))
+
+
+def tune_dis(ctx, store, theta, phi, cx, cz, W, n_terms, space=None, use_cache=True):
+    """Pick the batched DIS tile and bucket ranges on the caller's candidates
+    (cx, cz device words, a sample is enough); returns (params, seconds)."""
+    space = space or DIS_SPACE
+
+    def run():
+        iqcc.iqcc_dis_gradients(ctx.handle, store.handle, theta, phi, cx, cz, iqcc.IQCC_DIS_BATCHED)
+
+    return _search(ctx, space, _key("dis", W, n_terms, f"c{cx.shape[1]}"), run, use_cache)

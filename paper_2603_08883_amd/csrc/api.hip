@@ -27,6 +27,7 @@ struct iqcc_ctx {
   int64_t grid_per_cu = 2;
   int64_t batch_split_bucket_terms = 384;   // many small Hamiltonians: more, smaller pairs
   int64_t batch_anti_cap = 512;
+  int64_t batch_unit_pairs = 8;             // bucket pairs per work unit of a batch
   int64_t energy_grid_per_cu = 16;         // stand-alone energy kernel
   int64_t fuse_energy = 1;
   int64_t dis_tile = 256;
@@ -434,6 +435,7 @@ int iqcc_set_param(iqcc_ctx* ctx, const char* name, int64_t v) {
       {"grid_per_cu", &ctx->grid_per_cu, 1, 16},
       {"batch_split_bucket_terms", &ctx->batch_split_bucket_terms, 1, 1 << 20},
       {"batch_anti_cap", &ctx->batch_anti_cap, 16, 8192},
+      {"batch_unit_pairs", &ctx->batch_unit_pairs, 1, 1 << 16},
       {"energy_grid_per_cu", &ctx->energy_grid_per_cu, 1, 32},
       {"fuse_energy", &ctx->fuse_energy, 0, 1},
       {"dis_tile", &ctx->dis_tile, 1, 256},
@@ -459,7 +461,7 @@ int iqcc_get_param(const iqcc_ctx* ctx, const char* name, int64_t* v) {
       {"load_bucket_terms", ctx->load_bucket_terms}, {"split_bucket_terms", ctx->split_bucket_terms},
       {"anti_cap", ctx->anti_cap}, {"grid_per_cu", ctx->grid_per_cu},
       {"batch_split_bucket_terms", ctx->batch_split_bucket_terms},
-      {"batch_anti_cap", ctx->batch_anti_cap},
+      {"batch_anti_cap", ctx->batch_anti_cap}, {"batch_unit_pairs", ctx->batch_unit_pairs},
       {"energy_grid_per_cu", ctx->energy_grid_per_cu},
       {"fuse_energy", ctx->fuse_energy}, {"dis_tile", ctx->dis_tile},
       {"dis_bucket_ranges", ctx->dis_bucket_ranges},
@@ -986,6 +988,7 @@ static int batch_build(iqcc_ctx* ctx, int n_ham, const iqcc_store* const* ins,
   b->cfg.eps = eps;
   b->cfg.split_thr = ctx->batch_split_bucket_terms;
   b->cfg.anti_cap = (int)ctx->batch_anti_cap;
+  b->cfg.unit_pairs = (int)ctx->batch_unit_pairs;
   const size_t lds = dress_lds_bytes(W, b->cfg.anti_cap, false, false);
   if (lds > ctx->lds_per_block)
     return fail(ctx, IQCC_ERR_INVALID_ARG, "anti_cap needs more LDS than a workgroup has");
@@ -1185,7 +1188,7 @@ int iqcc_dis_gradients(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, 
                ctx->partial, (int)gt, g, s, theta, phi, h->nq, ctx->partial + n_part);
   } else {
     const int grid = (int)(ctx->n_cu * 4);
-    rc = ensure_partial(ctx, grid);
+    rc = ensure_partial(ctx, grid + 1);   // per-workgroup sums and a finish counter
     if (rc) return rc;
     launch_dis(h->W, h->d, ctx->lut, cx, cz, n_cand, ld_cand, 1, 1, grid, ctx->partial, 0, g, s,
                theta, phi, h->nq, nullptr);

@@ -560,6 +560,7 @@ struct DressConfig {
   int32_t* tape_partner;  //   and -1 for a commuting row; for an anticommuting row
                           //   2 * (output row of K^P + 1) + [s_K = +1], where the
                           //   output row is -1 when K^P is absent or dropped
+  int unit_pairs;         // batched dressing: consecutive bucket pairs per work unit
 };
 void launch_dress(int W, const StoreDev& in, const StoreDev& out, const Entangler& P,
                   const DressConfig& cfg, hipStream_t s);
@@ -597,7 +598,7 @@ struct BatchItem {
 };
 // Device-side sizing of one Hamiltonian's step (written by the plan kernel).
 struct BatchPlan {
-  int64_t item_start;   // first work item (bucket pair) of this Hamiltonian
+  int64_t item_start;   // first work unit (up to unit_pairs bucket pairs) of this Hamiltonian
   int64_t npairs;
   uint32_t f;
   int m, split, thi;

@@ -264,16 +264,25 @@ __global__ void k_dis_reduce(const double* partial, int rows, int64_t n_cand, do
   }
 }
 
-// Plain form: one candidate per launch.  Each wave streams whole buckets
-// (64 consecutive rows per load, four loads in flight per lane), so short
-// buckets keep every lane busy.
+// Plain form: one candidate per launch.  Workgroup g takes the groups of G
+// consecutive buckets g, g + grid, ... and streams each group's rows as one
+// flat range, four terms per thread and pass, so short buckets keep every lane
+// busy.  The last workgroup to finish sums the per-workgroup partials in a
+// fixed order and writes g[a], so a candidate costs one launch.
+constexpr int kDisOneR = 4;
+
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* lut_g,
                                                     const uint64_t* cx, const uint64_t* cz,
-                                                    int64_t ld_cand, int64_t a, double* partial) {
-  constexpr int R = 4;   // rows per lane per round
+                                                    int64_t ld_cand, int64_t a, double* partial,
+                                                    unsigned int* done, double* g) {
+  constexpr int R = kDisOneR;
   __shared__ double lut[W * kGroupsPerWord * kLutEntries];
   __shared__ double red[kWaves];
+  __shared__ uint64_t scan_tmp[kWaves];
+  __shared__ int64_t s_pre[kBlock + 1];
+  __shared__ int64_t s_off[kBlock];
+  __shared__ int s_last;
   for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
   uint64_t px[W], pz[W];
 #pragma unroll
@@ -281,30 +290,51 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
     px[w] = cx[w * ld_cand + a];
     pz[w] = cz[w * ld_cand + a];
   }
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
   const int64_t B = 1ll << *st.m;
-  const int64_t waves = (int64_t)gridDim.x * kWaves;
+  int64_t G = B / gridDim.x;
+  G = G < 1 ? 1 : (G > kBlock ? kBlock : G);
+  const int64_t ngroups = (B + G - 1) / G;
   double acc = 0.0;
-  for (int64_t b = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); b < B; b += waves) {
-    const int64_t n = st.cnt[b], off = st.off[b];
-    for (int64_t i0 = 0; i0 < n; i0 += 64 * R) {
+  __syncthreads();
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t b = grp * G + threadIdx.x;
+    const bool mine = threadIdx.x < G && b < B;
+    const int64_t cnt = mine ? st.cnt[b] : 0;
+    const int64_t off = mine ? st.off[b] : 0;
+    uint64_t total;
+    // (the scan's barriers also order the previous group's reads of s_pre)
+    const uint64_t ex = block_exclusive_scan((uint64_t)cnt, scan_tmp, total);
+    s_pre[threadIdx.x] = (int64_t)ex;
+    s_off[threadIdx.x] = off;
+    if (threadIdx.x == 0) s_pre[kBlock] = (int64_t)total;
+    __syncthreads();
+    const int64_t n = (int64_t)total;
+    for (int64_t i0 = 0; i0 < n; i0 += kBlock * R) {
       uint64_t kx[R][W], kz[R][W];
       double kc[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int64_t i = i0 + r * 64 + lane;
-        const bool ok = i < n;
+        const int64_t i = i0 + r * kBlock + threadIdx.x;
+        kc[r] = 0.0;
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-          kx[r][w] = ok ? st.x[w * st.cap + off + i] : 0;
-          kz[r][w] = ok ? st.z[w * st.cap + off + i] : 0;
+        for (int w = 0; w < W; ++w) kx[r][w] = kz[r][w] = 0;
+        if (i < n) {
+          int lo = 0;   // the last bucket of the group whose first row is <= i
+#pragma unroll
+          for (int step = kBlock / 2; step; step >>= 1)
+            if (s_pre[lo + step] <= i) lo += step;
+          const int64_t row = s_off[lo] + (i - s_pre[lo]);
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            kx[r][w] = __builtin_nontemporal_load(&st.x[w * st.cap + row]);
+            kz[r][w] = __builtin_nontemporal_load(&st.z[w * st.cap + row]);
+          }
+          kc[r] = __builtin_nontemporal_load(&st.c[row]);
         }
-        kc[r] = ok ? st.c[off + i] : 0.0;
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (anticommutes<W>(kx[r], kz[r], px, pz)) {   // padding rows (key 0) commute
+        if (anticommutes<W>(kx[r], kz[r], px, pz)) {   // padding (key 0) commutes
           const int e = product_phase<W>(kx[r], kz[r], px, pz);
           uint64_t qx[W], qz[W];
 #pragma unroll
@@ -319,8 +349,26 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
     }
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s;
+    __threadfence();
+    s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last) {   // every partial is written: sum them in a fixed order
+    __threadfence();
+    const volatile double* vp = partial;
+    double t = 0.0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += kBlock) t += vp[k];
+    t = block_sum(t, red);
+    if (threadIdx.x == 0) {
+      g[a] = t;
+      *done = 0u;   // ready for the next candidate
+    }
+  }
 }
+
+__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx,
                 const uint64_t* cz, int64_t n_cand, int64_t ld_cand, int mode, int tile,
@@ -344,14 +392,16 @@ void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx
     int64_t blocks = (n_cand + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_dis_reduce, dim3((unsigned)blocks), dim3(kBlock), 0, s, partial, grid_terms, n_cand, g);
   } else {
+    // partial[0, grid) per-workgroup sums, then the finish counter
+    unsigned int* done = reinterpret_cast<unsigned int*>(partial + grid);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, done);
     for (int64_t a = 0; a < n_cand; ++a) {
       switch (W) {
-        case 1: hipLaunchKernelGGL(k_dis_one<1>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial); break;
-        case 2: hipLaunchKernelGGL(k_dis_one<2>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial); break;
-        case 3: hipLaunchKernelGGL(k_dis_one<3>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial); break;
-        default: hipLaunchKernelGGL(k_dis_one<4>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial); break;
+        case 1: hipLaunchKernelGGL(k_dis_one<1>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial, done, g); break;
+        case 2: hipLaunchKernelGGL(k_dis_one<2>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial, done, g); break;
+        case 3: hipLaunchKernelGGL(k_dis_one<3>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial, done, g); break;
+        default: hipLaunchKernelGGL(k_dis_one<4>, dim3(grid), dim3(kBlock), 0, s, st, lut, cx, cz, ld_cand, a, partial, done, g); break;
       }
-      launch_finalize_sum(partial, grid, nullptr, g + a, s);
     }
   }
 }

@@ -562,44 +562,59 @@ __global__ __launch_bounds__(kDB) __attribute__((amdgpu_waves_per_eu(4))) void k
 // ---------------------------------------------------------------------------
 // Batched dressing of many independent Hamiltonians (one entangler each) in
 // one persistent launch.  A plan kernel sizes every Hamiltonian's step on the
-// device (no host synchronisation, so the pair of launches can be captured in
-// a HIP graph); workgroups then take (Hamiltonian, bucket pair) items from an
-// atomic queue, so uneven sizes balance across the chip.
+// device, one thread per Hamiltonian and a scan (no host synchronisation, so
+// the pair of launches can be captured in a HIP graph); workgroups then take
+// work units -- up to unit_pairs consecutive bucket pairs of one Hamiltonian --
+// from an atomic queue, so uneven sizes balance across the chip while the
+// queue, the Hamiltonian lookup, the row reservation and the counter flush
+// are paid once per unit.
 // ---------------------------------------------------------------------------
-__global__ void k_batch_plan(int n_ham, const BatchItem* items, BatchPlan* plan,
-                             int64_t split_thr, int64_t* queue) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(kBlock) void k_batch_plan(int n_ham, const BatchItem* items,
+                                                       BatchPlan* plan, int64_t split_thr,
+                                                       int unit_pairs, int64_t* queue) {
+  __shared__ uint64_t scan_tmp[kWaves];
   int64_t start = 0;
-  for (int i = 0; i < n_ham; ++i) {
-    const BatchItem& it = items[i];
+  for (int base = 0; base < n_ham; base += kBlock) {
+    const int i = base + threadIdx.x;
     BatchPlan p{};
-    p.item_start = start;
-    *it.out.total = 0;
-    *it.out.top = 0;
-    *it.out.err = 0;
-    it.out.stats[0] = 0;
-    it.out.stats[1] = 0;
-    const int ierr = *it.in.err;
-    const int m = *it.in.m;
-    const int64_t n_in = *it.in.total;
-    const int split = (m < it.out.mcap) && (n_in > (split_thr << m)) ? 1 : 0;
-    if (ierr || m + split > it.out.mcap) {
-      *it.out.err = ierr ? ierr : 2;
-      p.npairs = 0;
-    } else {
-      const uint32_t f = it.P.hp & (uint32_t)((1ull << m) - 1);
-      p.m = m;
-      p.split = split;
-      p.f = f;
-      p.thi = f ? 31 - __clz(f) : 0;
-      p.npairs = f ? (1ll << (m - 1)) : (1ll << m);
-      *it.out.m = m + split;
+    int64_t units = 0;
+    if (i < n_ham) {
+      const BatchItem& it = items[i];
+      *it.out.total = 0;
+      *it.out.top = 0;
+      *it.out.err = 0;
+      it.out.stats[0] = 0;
+      it.out.stats[1] = 0;
+      const int ierr = *it.in.err;
+      const int m = *it.in.m;
+      const int64_t n_in = *it.in.total;
+      const int split = (m < it.out.mcap) && (n_in > (split_thr << m)) ? 1 : 0;
+      if (ierr || m + split > it.out.mcap) {
+        *it.out.err = ierr ? ierr : 2;
+        p.npairs = 0;
+      } else {
+        const uint32_t f = it.P.hp & (uint32_t)((1ull << m) - 1);
+        p.m = m;
+        p.split = split;
+        p.f = f;
+        p.thi = f ? 31 - __clz(f) : 0;
+        p.npairs = f ? (1ll << (m - 1)) : (1ll << m);
+        *it.out.m = m + split;
+      }
+      units = (p.npairs + unit_pairs - 1) / unit_pairs;
     }
-    start += p.npairs;
-    plan[i] = p;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan((uint64_t)units, scan_tmp, total);
+    if (i < n_ham) {
+      p.item_start = start + (int64_t)ex;
+      plan[i] = p;
+    }
+    start += (int64_t)total;
   }
-  plan[n_ham].item_start = start;
-  *queue = 0;
+  if (threadIdx.x == 0) {
+    plan[n_ham].item_start = start;
+    *queue = 0;
+  }
 }
 
 template <int W>
@@ -610,46 +625,38 @@ __global__ __launch_bounds__(kDB) __attribute__((amdgpu_waves_per_eu(4))) void k
   const Smem<W> sm = carve<W, false>(smem, cfg.anti_cap, false);
   const int64_t total = plan[n_ham].item_start;
   double eacc = 0.0;
-  constexpr int64_t kGrab = 4;   // items taken per queue atomic
-  int64_t item = 0, left = 0;
   for (;;) {
-    if (left == 0) {
-      if (threadIdx.x == 0) sm.misc[4] = (int64_t)atomicAdd((unsigned long long*)queue, (unsigned long long)kGrab);
-      __syncthreads();
-      item = sm.misc[4];
-      __syncthreads();
-      left = kGrab;
+    if (threadIdx.x == 0) {
+      const int64_t unit = (int64_t)atomicAdd((unsigned long long*)queue, 1ull);
+      int lo = 0, hi = n_ham - 1;   // last Hamiltonian whose first unit is <= unit
+      if (unit < total) {
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (plan[mid].item_start <= unit) lo = mid; else hi = mid - 1;
+        }
+      }
+      sm.misc[4] = unit;
+      sm.misc[6] = lo;
     }
-    if (item >= total) break;
-    int lo = 0, hi = n_ham - 1;   // last i with item_start <= item
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (plan[mid].item_start <= item) lo = mid; else hi = mid - 1;
-    }
-    const BatchItem& it = items[lo];
-    const BatchPlan p = plan[lo];
+    __syncthreads();
+    const int64_t unit = sm.misc[4];
+    const int h = (int)sm.misc[6];
+    __syncthreads();
+    if (unit >= total) break;
+    const BatchItem& it = items[h];
+    const BatchPlan p = plan[h];
     DressConfig c = cfg;
     c.C = it.C;
     c.S = it.S;
-    // items come from a dynamic queue: reserve per pair
-    const int64_t pi = item - p.item_start;
-    const int64_t need = pair_need(it.in, pi, p.f, p.thi);
-    if (threadIdx.x == 0) {
-      int64_t b = need ? (int64_t)atomicAdd((unsigned long long*)it.out.top, (unsigned long long)need) : 0;
-      if (b + need > it.out.cap) {
-        atomicOr(it.out.err, 1);
-        b = -1;
-      }
-      sm.misc[5] = b;
-    }
-    __syncthreads();
-    const int64_t base = sm.misc[5];
-    __syncthreads();
+    const int64_t p0 = (unit - p.item_start) * cfg.unit_pairs;
+    const int64_t p1 = p0 + cfg.unit_pairs < p.npairs ? p0 + cfg.unit_pairs : p.npairs;
+    int64_t base = reserve_rows(it.in, it.out, p0, 1, p1, p.f, p.thi, sm.scan, sm.misc);
     StepCounts counts;
-    process_pair<W, false>(it.in, it.out, it.P, c, sm, pi, p.m, p.split, p.f, p.thi, base, eacc, counts);
+    for (int64_t pi = p0; pi < p1; ++pi) {
+      process_pair<W, false>(it.in, it.out, it.P, c, sm, pi, p.m, p.split, p.f, p.thi, base, eacc, counts);
+      if (base >= 0) base += pair_need(it.in, pi, p.f, p.thi);
+    }
     flush_counts(it.out, counts);
-    ++item;
-    --left;
   }
 }
 
@@ -667,7 +674,8 @@ void set_dress_batch_attributes(int W, int anti_cap) {
 void launch_dress_batch(int W, int n_ham, const BatchItem* items, BatchPlan* plan,
                         const DressConfig& cfg, int64_t* queue, hipStream_t s) {
   const size_t lds = dress_lds_bytes(W, cfg.anti_cap, false, false);
-  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(64), 0, s, n_ham, items, plan, cfg.split_thr, queue);
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kBlock), 0, s, n_ham, items, plan, cfg.split_thr,
+                     cfg.unit_pairs, queue);
   const BatchPlan* cp = plan;
   switch (W) {
     case 1: hipLaunchKernelGGL(k_dress_batch<1>, dim3(cfg.grid), dim3(kDB), lds, s, n_ham, items, cp, cfg, queue); break;

@@ -121,3 +121,54 @@ def test_full_batch_graph_against_oracle_digests(ctx):
         iqcc.iqcc_batch_destroy(ctx.handle, b)
     for s_ in ins + outs:
         s_.close()
+
+
+@pytest.mark.parametrize("unit_pairs", [1, 3, 1000])
+def test_batch_work_units(ctx, hams, unit_pairs):
+    """Work units of one bucket pair, of an odd count that splits Hamiltonians
+    unevenly, and of more pairs than any Hamiltonian has: the same terms as the
+    oracle."""
+    old = iqcc.iqcc_get_param(ctx.handle, "batch_unit_pairs")
+    iqcc.iqcc_set_param(ctx.handle, "batch_unit_pairs", unit_pairs)
+    try:
+        ins, outs = _stores(ctx, hams)
+        pxs, pzs, taus = _args(hams)
+        describe(0, "dress_batched work units", unit_pairs=unit_pairs)
+        iqcc.iqcc_dress_batched(ctx.handle, [s.handle for s in ins], [s.handle for s in outs], pxs, pzs,
+                                taus, EPS)
+        for i, (o, r) in enumerate(zip(outs, _refs(hams))):
+            assert_same_terms(o.to_numpy(), r, f"unit_pairs {unit_pairs} item {i}")
+    finally:
+        iqcc.iqcc_set_param(ctx.handle, "batch_unit_pairs", old)
+
+
+def test_autotuned_batch_bit_identical(ctx, hams, tmp_path, monkeypatch):
+    """The autotuner's pick for the batch changes timing only: every output has
+    the same (key, coefficient bits) multiset as under the default knobs."""
+    from paper_2603_08883_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "autotune.json"))
+    pxs, pzs, taus = _args(hams)
+    defaults = {k: iqcc.iqcc_get_param(ctx.handle, k) for k in autotune.BATCH_SPACE}
+    ins, outs = _stores(ctx, hams)
+    hin, hout = [s.handle for s in ins], [s.handle for s in outs]
+    describe(0, "batch under default knobs")
+    iqcc.iqcc_dress_batched(ctx.handle, hin, hout, pxs, pzs, taus, EPS)
+    ref = [f"{multiset_hash_torch(*iqcc.iqcc_store_export(ctx.handle, o.handle)):016x}" for o in outs]
+    try:
+        describe(0, "batch autotune")
+        params, secs = autotune.tune_batch(ctx, hin, hout, pxs, pzs, taus, EPS, 1,
+                                           sum(len(h["c"]) for h in hams), use_cache=False)
+        assert secs > 0 and set(params) == set(autotune.BATCH_SPACE)
+        assert all(iqcc.iqcc_get_param(ctx.handle, k) == v for k, v in params.items())
+        ins2, outs2 = _stores(ctx, hams)
+        iqcc.iqcc_dress_batched(ctx.handle, [s.handle for s in ins2], [s.handle for s in outs2], pxs, pzs,
+                                taus, EPS)
+        got = [f"{multiset_hash_torch(*iqcc.iqcc_store_export(ctx.handle, o.handle)):016x}" for o in outs2]
+        assert got == ref
+        # the choice is cached and re-applied without timing
+        autotune.apply(ctx, defaults)
+        again, _ = autotune.tune_batch(ctx, hin, hout, pxs, pzs, taus, EPS, 1,
+                                       sum(len(h["c"]) for h in hams))
+        assert again == params
+    finally:
+        autotune.apply(ctx, defaults)

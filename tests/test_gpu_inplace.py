@@ -246,3 +246,42 @@ def test_inplace_argument_checks(ctx):
     with pytest.raises(iqcc.IqccError):
         iqcc.iqcc_store_copy(ctx.handle, ip.handle, plain.handle)          # not an in-place store
     plain.close(); ip.close()
+
+
+def test_autotuned_inplace_chain_bit_identical(ctx, tmp_path, monkeypatch):
+    """The autotuner's pick for the in-place chain changes timing only: the
+    final store holds the same (key, coefficient bits) multiset and the same
+    energies bit for bit as under the default knobs."""
+    from paper_2603_08883_amd import autotune
+    from tests.golden.multiset_hash import multiset_hash_torch
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "autotune.json"))
+    nq, steps = 40, 5
+    x, z, c = I.hamiltonian_dense(nq, 3)
+    cx, cz = I.dis_candidates(x, nq, steps, 8, I.rng_for(3, I.PURPOSE_ENTANGLERS))
+    ents = list(zip(cx, cz))
+    taus = I.taus(steps, I.rng_for(3, I.PURPOSE_TAUS))
+    th, ph, tht, pht = _angles(nq, 13)
+    defaults = {k: iqcc.iqcc_get_param(ctx.handle, k) for k in autotune.INPLACE_SPACE}
+    h0 = iqcc.Store(ctx, nq, 8 * len(c), INPLACE).load_numpy(x, z, c)
+    work = iqcc.Store(ctx, nq, 8 * len(c), INPLACE)
+
+    def run():
+        e = torch.zeros(steps, dtype=torch.float64, device="cuda")
+        iqcc.iqcc_store_copy(ctx.handle, h0.handle, work.handle)
+        for j, ((px, pz), t) in enumerate(zip(ents, taus)):
+            iqcc.iqcc_dress_inplace(ctx.handle, work.handle, px, pz, t, 1e-8, tht, pht,
+                                    e[j - 1:j] if j else None, e[j:j + 1])
+        return (f"{multiset_hash_torch(*iqcc.iqcc_store_export(ctx.handle, work.handle)):016x}",
+                e.cpu().numpy().tobytes())
+
+    describe(0, "in-place chain under default knobs", nq=nq)
+    ref = run()
+    try:
+        describe(0, "in-place autotune", nq=nq)
+        params, secs = autotune.tune_inplace(ctx, h0, work, ents, taus, 1e-8, tht, pht, 1, len(c),
+                                             use_cache=False)
+        assert secs > 0 and set(params) == set(autotune.INPLACE_SPACE)
+        assert run() == ref
+    finally:
+        autotune.apply(ctx, defaults)
+    h0.close(); work.close()
