@@ -623,6 +623,8 @@ __global__ __launch_bounds__(kDB) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                      int64_t* queue) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Smem<W> sm = carve<W, false>(smem, cfg.anti_cap, false);
+  __shared__ __align__(16) BatchItem s_item;
+  static_assert(sizeof(BatchItem) % 8 == 0, "BatchItem is copied as 64-bit words");
   const int64_t total = plan[n_ham].item_start;
   double eacc = 0.0;
   for (;;) {
@@ -641,22 +643,30 @@ __global__ __launch_bounds__(kDB) __attribute__((amdgpu_waves_per_eu(4))) void k
     __syncthreads();
     const int64_t unit = sm.misc[4];
     const int h = (int)sm.misc[6];
-    __syncthreads();
     if (unit >= total) break;
-    const BatchItem& it = items[h];
+    // the unit's Hamiltonian descriptors, copied once into LDS (read there
+    // by every pair of the unit instead of from global memory)
+    constexpr int kItemWords = (int)(sizeof(BatchItem) / 8);
+    for (int k = threadIdx.x; k < kItemWords; k += kDB)
+      reinterpret_cast<uint64_t*>(&s_item)[k] = reinterpret_cast<const uint64_t*>(items + h)[k];
+    __syncthreads();
+    const StoreDev& in = s_item.in;
+    const StoreDev& out = s_item.out;
+    const Entangler& P = s_item.P;
     const BatchPlan p = plan[h];
     DressConfig c = cfg;
-    c.C = it.C;
-    c.S = it.S;
+    c.C = s_item.C;
+    c.S = s_item.S;
     const int64_t p0 = (unit - p.item_start) * cfg.unit_pairs;
     const int64_t p1 = p0 + cfg.unit_pairs < p.npairs ? p0 + cfg.unit_pairs : p.npairs;
-    int64_t base = reserve_rows(it.in, it.out, p0, 1, p1, p.f, p.thi, sm.scan, sm.misc);
+    int64_t base = reserve_rows(in, out, p0, 1, p1, p.f, p.thi, sm.scan, sm.misc);
     StepCounts counts;
     for (int64_t pi = p0; pi < p1; ++pi) {
-      process_pair<W, false>(it.in, it.out, it.P, c, sm, pi, p.m, p.split, p.f, p.thi, base, eacc, counts);
-      if (base >= 0) base += pair_need(it.in, pi, p.f, p.thi);
+      process_pair<W, false>(in, out, P, c, sm, pi, p.m, p.split, p.f, p.thi, base, eacc, counts);
+      if (base >= 0) base += pair_need(in, pi, p.f, p.thi);
     }
-    flush_counts(it.out, counts);
+    flush_counts(out, counts);
+    __syncthreads();   // every thread is done with s_item before the next copy
   }
 }
 
