@@ -761,7 +761,8 @@ int iqcc_dress_inplace(iqcc_ctx* ctx, iqcc_store* st, const uint64_t* px, const 
     return fail(ctx, IQCC_ERR_UNSUPPORTED, "the in-place step does not fit the LDS of a workgroup");
   const int grid = ctx->n_cu;
   const int nparts = grid * inplace_waves_per_block();
-  rc = ensure_partial(ctx, nparts);
+  // energy partials, then five counts per wavefront
+  rc = ensure_partial(ctx, 6 * (int64_t)nparts);
   if (rc) return rc;
   InplaceConfig cfg{};
   cfg.C = std::cos(tau);
@@ -769,27 +770,23 @@ int iqcc_dress_inplace(iqcc_ctx* ctx, iqcc_store* st, const uint64_t* px, const 
   cfg.eps = eps;
   cfg.cap = cap;
   cfg.item_terms = ctx->inplace_item_terms ? (int)ctx->inplace_item_terms : (3 * cap) / 2;
-  if (want_e) {
-    launch_build_lut(W, st->nq, theta, phi, ctx->lut, s);
-    LAUNCH_CHECK(ctx);
-  }
-  cfg.lut = fused ? ctx->lut : nullptr;
+  cfg.theta = fused ? theta : nullptr;
+  cfg.phi = fused ? phi : nullptr;
+  cfg.nq = st->nq;
   const bool delta = fused && energy_in;
   cfg.delta = delta ? 1 : 0;
   cfg.e_partial = ctx->partial;
-  launch_dress_inplace(W, st->d, P, cfg, grid, s);
+  cfg.counts = reinterpret_cast<int64_t*>(ctx->partial + nparts);
+  launch_dress_inplace(W, st->d, P, cfg, grid, delta ? energy_in : nullptr, fused ? energy_out : nullptr, s);
   LAUNCH_CHECK(ctx);
   st->floor = eps;
-  if (want_e) {
-    if (fused) {
-      launch_finalize_sum(ctx->partial, nparts, nullptr, energy_out, s, delta ? energy_in : nullptr);
-    } else {
-      const int eg = (int)(ctx->n_cu * ctx->energy_grid_per_cu);
-      rc = ensure_partial(ctx, eg);
-      if (rc) return rc;
-      launch_energy(W, st->d, eg, ctx->lut, ctx->partial, s);
-      launch_finalize_sum(ctx->partial, eg, nullptr, energy_out, s);
-    }
+  if (want_e && !fused) {
+    const int eg = (int)(ctx->n_cu * ctx->energy_grid_per_cu);
+    rc = ensure_partial(ctx, eg);
+    if (rc) return rc;
+    launch_build_lut(W, st->nq, theta, phi, ctx->lut, s);
+    launch_energy(W, st->d, eg, ctx->lut, ctx->partial, s);
+    launch_finalize_sum(ctx->partial, eg, nullptr, energy_out, s);
     LAUNCH_CHECK(ctx);
   }
   return IQCC_OK;

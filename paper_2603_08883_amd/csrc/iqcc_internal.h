@@ -305,6 +305,13 @@ __device__ __forceinline__ double expect_lut(const double* lut, const uint64_t* 
   }
 }
 
+// <sigma> of one qubit of the QMF product state (Eq. 3) from sin/cos of its
+// Bloch angles; op: 0 = I, 1 = X, 2 = Z, 3 = Y (bit0 = x, bit1 = z).
+__device__ __forceinline__ double bloch_factor(int op, double st, double ct, double sp,
+                                               double cp) {
+  return op == 0 ? 1.0 : op == 1 ? st * cp : op == 2 ? ct : st * sp;
+}
+
 // Anticommutation of K with P: parity of |xK & zP| + |zK & xP|.
 template <int W>
 __device__ __forceinline__ bool anticommutes(const uint64_t* x, const uint64_t* z,
@@ -570,15 +577,22 @@ struct InplaceConfig {
   double C, S, eps;
   int cap;              // stash entries per wave (inplace_cap)
   int item_terms;       // input terms per work item while buckets are small
-  const double* lut;    // null: no energy
+  const double* theta;  // null: no energy; else the QMF angles (the group
+  const double* phi;    //   table is built in each workgroup's LDS)
+  int nq;
   int delta;            // 1: e_partial accumulates only the change of the energy
   double* e_partial;    // [grid * inplace_waves_per_block()]
+  int64_t* counts;      // [grid * inplace_waves_per_block()][5]: anticommuting
+                        //   inputs, new keys, change of the term count,
+                        //   relocated items, freed rows, per wavefront
 };
 size_t inplace_lds_bytes(int W, int cap, bool energy);
 int inplace_cap(int W, bool energy, size_t lds_budget);
 int inplace_waves_per_block();
+// The step and its finishing kernel (counters of the store, and the energy
+// into energy_out, plus *energy_in when given, if energy_out is not null).
 void launch_dress_inplace(int W, const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, int grid,
-                          hipStream_t s);
+                          const double* energy_in, double* energy_out, hipStream_t s);
 // Bucket regions: bucket b gets max(R, 2 cnt_b rounded up to 16) rows; the
 // pool starts after the last region.  Load of flat rows (as launch_store_load)
 // and copy of a store (deterministic: each destination bucket takes its rows

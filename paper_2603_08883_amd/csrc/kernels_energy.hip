@@ -13,12 +13,6 @@
 
 namespace iqcc {
 
-__device__ __forceinline__ double bloch_factor(int op, double st, double ct, double sp,
-                                               double cp) {
-  // op: 0 = I, 1 = X, 2 = Z, 3 = Y (bit0 = x, bit1 = z)
-  return op == 0 ? 1.0 : op == 1 ? st * cp : op == 2 ? ct : st * sp;
-}
-
 __global__ void k_build_lut(int W, int nq, const double* theta, const double* phi, double* lut) {
   const int n = W * kGroupsPerWord * kLutEntries;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {

@@ -750,7 +750,31 @@ __global__ __launch_bounds__(kIPB) void k_dress_inplace(StoreDev st, Entangler P
   const size_t lut_bytes = ENERGY ? (size_t)W * kGroupsPerWord * kLutEntries * 8 : 0;
   double* lut = (double*)smem;
   if (ENERGY) {
-    for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kIPB) lut[i] = cfg.lut[i];
+    // the 3-qubit group table of the QMF state, built in LDS from the angles;
+    // the per-qubit factors sit in the (not yet used) wave segments
+    double* fq = (double*)(smem + lut_bytes);
+    for (int q = threadIdx.x; q < 64 * W; q += kIPB) {
+      double st_ = 0.0, ct = 1.0, sp = 0.0, cp = 1.0;
+      if (q < cfg.nq) {
+        sincos(cfg.theta[q], &st_, &ct);
+        sincos(cfg.phi[q], &sp, &cp);
+      }
+#pragma unroll
+      for (int op = 0; op < 4; ++op) fq[4 * q + op] = bloch_factor(op, st_, ct, sp, cp);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kIPB) {
+      const int code = i % kLutEntries, gi = i / kLutEntries;
+      const int h = gi / kGroupsPerHalf, gg = gi % kGroupsPerHalf;
+      double p = 1.0;
+      for (int r = 0; r < 3; ++r) {
+        const int bit = 3 * gg + r, q = 32 * h + bit;
+        if (bit >= 32 || q >= cfg.nq) continue;
+        const int op = ((code >> r) & 1) | (((code >> (3 + r)) & 1) << 1);
+        if (op != 0) p *= fq[4 * q + op];
+      }
+      lut[i] = p;
+    }
   }
   __syncthreads();
   const Seg<W> g = carve_seg<W>(smem + lut_bytes + (size_t)wave * seg_bytes(W, cfg.cap), cfg.cap);
@@ -792,12 +816,14 @@ __global__ __launch_bounds__(kIPB) void k_dress_inplace(StoreDev st, Entangler P
       I = In;
     }
   }
+  // per-wavefront counts (summed by k_inplace_end, no atomics)
   if (lane == 0) {
-    if (wc.anti) atomicAdd((unsigned long long*)&st.stats[0], (unsigned long long)wc.anti);
-    if (wc.fresh) atomicAdd((unsigned long long*)&st.stats[1], (unsigned long long)wc.fresh);
-    if (wc.delta) atomicAdd((unsigned long long*)&st.aux[0], (unsigned long long)wc.delta);
-    if (wc.reloc) atomicAdd((unsigned long long*)&st.aux[3], (unsigned long long)wc.reloc);
-    if (wc.freed) atomicAdd((unsigned long long*)&st.aux[4], (unsigned long long)wc.freed);
+    int64_t* c = cfg.counts + 5 * gw;
+    c[0] = wc.anti;
+    c[1] = wc.fresh;
+    c[2] = wc.delta;
+    c[3] = wc.reloc;
+    c[4] = wc.freed;
   }
   if (ENERGY) {
 #pragma unroll
@@ -806,18 +832,36 @@ __global__ __launch_bounds__(kIPB) void k_dress_inplace(StoreDev st, Entangler P
   }
 }
 
-__global__ void k_inplace_begin(StoreDev st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st.stats[0] = 0;
-    st.stats[1] = 0;
-    st.aux[0] = 0;
-    st.aux[3] = 0;
-    st.aux[4] = 0;
+// Finishes a step in one workgroup: sums the per-wavefront counts into the
+// store's counters (integer sums) and the energy partials in a fixed order
+// (each thread a strided share, then the lane tree and the waves in order).
+__global__ __launch_bounds__(kBlock) void k_inplace_end(StoreDev st, const int64_t* counts,
+                                                        const double* e_partial, int nparts,
+                                                        const double* energy_in, double* energy_out) {
+  __shared__ double red[kWaves];
+  __shared__ unsigned long long s_cnt[5];
+  if (threadIdx.x < 5) s_cnt[threadIdx.x] = 0ull;
+  __syncthreads();
+  unsigned long long mine[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
+  double e = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) mine[k] += (unsigned long long)counts[5 * i + k];
+    if (energy_out) e += e_partial[i];
   }
-}
-
-__global__ void k_inplace_end(StoreDev st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *st.total += st.aux[0];
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    if (mine[k]) atomicAdd(&s_cnt[k], mine[k]);
+  const double es = block_sum(e, red);   // also orders the LDS adds above
+  if (threadIdx.x == 0) {
+    st.stats[0] = (int64_t)s_cnt[0];
+    st.stats[1] = (int64_t)s_cnt[1];
+    st.aux[0] = (int64_t)s_cnt[2];
+    st.aux[3] = (int64_t)s_cnt[3];
+    st.aux[4] = (int64_t)s_cnt[4];
+    *st.total += (int64_t)s_cnt[2];
+    if (energy_out) *energy_out = energy_in ? *energy_in + es : es;
+  }
 }
 
 template <int W, bool E>
@@ -830,16 +874,16 @@ static void launch_inplace_t(const StoreDev& st, const Entangler& P, const Inpla
 }
 
 void launch_dress_inplace(int W, const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, int grid,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_inplace_begin, dim3(1), dim3(64), 0, s, st);
-  const bool e = cfg.lut != nullptr;
+                          const double* energy_in, double* energy_out, hipStream_t s) {
+  const bool e = cfg.theta != nullptr;
   switch (W) {
     case 1: e ? launch_inplace_t<1, true>(st, P, cfg, grid, s) : launch_inplace_t<1, false>(st, P, cfg, grid, s); break;
     case 2: e ? launch_inplace_t<2, true>(st, P, cfg, grid, s) : launch_inplace_t<2, false>(st, P, cfg, grid, s); break;
     case 3: e ? launch_inplace_t<3, true>(st, P, cfg, grid, s) : launch_inplace_t<3, false>(st, P, cfg, grid, s); break;
     default: e ? launch_inplace_t<4, true>(st, P, cfg, grid, s) : launch_inplace_t<4, false>(st, P, cfg, grid, s); break;
   }
-  hipLaunchKernelGGL(k_inplace_end, dim3(1), dim3(64), 0, s, st);
+  hipLaunchKernelGGL(k_inplace_end, dim3(1), dim3(kBlock), 0, s, st, cfg.counts, cfg.e_partial,
+                     grid * kIPW, energy_in, energy_out);
 }
 
 int inplace_waves_per_block() { return kIPW; }

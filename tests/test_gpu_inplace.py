@@ -250,8 +250,9 @@ def test_inplace_argument_checks(ctx):
 
 def test_autotuned_inplace_chain_bit_identical(ctx, tmp_path, monkeypatch):
     """The autotuner's pick for the in-place chain changes timing only: the
-    final store holds the same (key, coefficient bits) multiset and the same
-    energies bit for bit as under the default knobs."""
+    final store holds the same (key, coefficient bits) multiset as under the
+    default knobs.  The energies are sums whose order follows the work items,
+    which the knobs resize, so they agree to rounding."""
     from paper_2603_08883_amd import autotune
     from tests.golden.multiset_hash import multiset_hash_torch
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "autotune.json"))
@@ -272,7 +273,7 @@ def test_autotuned_inplace_chain_bit_identical(ctx, tmp_path, monkeypatch):
             iqcc.iqcc_dress_inplace(ctx.handle, work.handle, px, pz, t, 1e-8, tht, pht,
                                     e[j - 1:j] if j else None, e[j:j + 1])
         return (f"{multiset_hash_torch(*iqcc.iqcc_store_export(ctx.handle, work.handle)):016x}",
-                e.cpu().numpy().tobytes())
+                e.cpu().numpy())
 
     describe(0, "in-place chain under default knobs", nq=nq)
     ref = run()
@@ -281,7 +282,9 @@ def test_autotuned_inplace_chain_bit_identical(ctx, tmp_path, monkeypatch):
         params, secs = autotune.tune_inplace(ctx, h0, work, ents, taus, 1e-8, tht, pht, 1, len(c),
                                              use_cache=False)
         assert secs > 0 and set(params) == set(autotune.INPLACE_SPACE)
-        assert run() == ref
+        got = run()
+        assert got[0] == ref[0]
+        assert np.abs(got[1] - ref[1]).max() <= 1e-12 * np.abs(ref[1]).max()
     finally:
         autotune.apply(ctx, defaults)
     h0.close(); work.close()
