@@ -267,9 +267,20 @@ __global__ void k_dis_reduce(const double* partial, int rows, int64_t n_cand, do
 // Plain form: one candidate per launch.  Workgroup g takes the groups of G
 // consecutive buckets g, g + grid, ... and streams each group's rows as one
 // flat range, four terms per thread and pass, so short buckets keep every lane
-// busy.  The last workgroup to finish sums the per-workgroup partials in a
-// fixed order and writes g[a], so a candidate costs one launch.
+// busy.  About half the terms anticommute with a candidate; their products
+// Q = K P_a go to a per-wavefront ring in LDS, and the expectation of Q is
+// formed on full wavefronts of 64 ring entries, so the 44-lookup product is
+// not issued for lanes whose term commutes.  The last workgroup to finish
+// sums the per-workgroup partials in a fixed order and writes g[a], so a
+// candidate costs one launch.
 constexpr int kDisOneR = 4;
+constexpr int kDisRing = 128;   // ring entries per wavefront (< 64 left + 64 added)
+
+template <int W>
+struct DisRing {
+  uint64_t x[W][kDisRing], z[W][kDisRing];
+  double v[kDisRing];   // +-c: the sign of Im(i^e) for the product phase e
+};
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* lut_g,
@@ -282,6 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
   __shared__ uint64_t scan_tmp[kWaves];
   __shared__ int64_t s_pre[kBlock + 1];
   __shared__ int64_t s_off[kBlock];
+  __shared__ DisRing<W> ring_all[kWaves];
   __shared__ int s_last;
   for (int i = threadIdx.x; i < W * kGroupsPerWord * kLutEntries; i += kBlock) lut[i] = lut_g[i];
   uint64_t px[W], pz[W];
@@ -290,11 +302,37 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
     px[w] = cx[w * ld_cand + a];
     pz[w] = cz[w * ld_cand + a];
   }
+  const int lane = threadIdx.x & 63;
+  DisRing<W>& ring = ring_all[threadIdx.x >> 6];
+  int head = 0, fill = 0;   // wave-uniform ring state
+  double acc = 0.0;
+  // <Q> of 64 ring entries from the head (lanes past `count` add nothing)
+  auto drain = [&](int count) {
+    // the ring entries were written by other lanes of this wavefront
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int k = (head + lane) & (kDisRing - 1);
+    if (lane < count) {
+      uint64_t qx[W], qz[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        qx[w] = ring.x[w][k];
+        qz[w] = ring.z[w][k];
+      }
+      acc += ring.v[k] * expect_lut<W>(lut, qx, qz);
+    }
+    head = (head + count) & (kDisRing - 1);
+    fill -= count;
+    // the drained entries are read before later entries overwrite them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
   const int64_t B = 1ll << *st.m;
   int64_t G = B / gridDim.x;
   G = G < 1 ? 1 : (G > kBlock ? kBlock : G);
   const int64_t ngroups = (B + G - 1) / G;
-  double acc = 0.0;
   __syncthreads();
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const int64_t b = grp * G + threadIdx.x;
@@ -334,20 +372,25 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (anticommutes<W>(kx[r], kz[r], px, pz)) {   // padding (key 0) commutes
+        // padding lanes (key 0) commute
+        const bool anti = anticommutes<W>(kx[r], kz[r], px, pz);
+        const uint64_t mask = __ballot(anti);
+        if (anti) {
           const int e = product_phase<W>(kx[r], kz[r], px, pz);
-          uint64_t qx[W], qz[W];
+          const int k = (head + fill + lanes_below(mask)) & (kDisRing - 1);
 #pragma unroll
           for (int w = 0; w < W; ++w) {
-            qx[w] = kx[r][w] ^ px[w];
-            qz[w] = kz[r][w] ^ pz[w];
+            ring.x[w][k] = kx[r][w] ^ px[w];
+            ring.z[w][k] = kz[r][w] ^ pz[w];
           }
-          const double v = kc[r] * expect_lut<W>(lut, qx, qz);
-          acc += (e == 1) ? v : -v;
+          ring.v[k] = (e == 1) ? kc[r] : -kc[r];
         }
+        fill += __popcll(mask);
+        if (fill >= 64) drain(64);   // LDS operations of one wavefront complete in order
       }
     }
   }
+  if (fill > 0) drain(fill);
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) {
     partial[blockIdx.x] = s;
