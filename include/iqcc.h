@@ -384,7 +384,7 @@ int iqcc_qmf_energy(iqcc_ctx *ctx, const iqcc_store *h, const double *theta,
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * energy as iqcc_qmf_energy, from the same kernels, with no allocation of any
  * kind.  Its scratch (the QMF group table and the per-workgroup partial sums)
- * is a fixed array of device memory inside the library, about 110 KB per
+ * is a fixed array of device memory inside the library, 128 KB per
  * device, held until the process ends.  The grid (n_cu * energy_grid_per_cu
  * workgroups) may use at most 8192 partial sums; a larger one is refused with
  * IQCC_ERR_CAPACITY before any launch.  All calls on one device share that

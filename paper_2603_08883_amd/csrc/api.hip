@@ -37,7 +37,7 @@ struct iqcc_ctx {
   int64_t inplace_cap = 0;                 // 0: as many stash entries as the LDS holds
   int64_t inplace_region_rows = 0;         // 0: regions share the arena minus the pool
   // device scratch
-  double* lut = nullptr;        // kMaxWords * 22 * 64
+  double* lut = nullptr;        // 8192: 3-qubit (4 x 22 x 64) or 4-qubit (2 x 16 x 256) tables
   double* partial = nullptr;    // n_partial
   int64_t n_partial = 0;
   int64_t* scratch = nullptr;   // n_scratch
@@ -357,7 +357,9 @@ void inplace_geometry(const iqcc_ctx* ctx, const iqcc_store* st, int& m, int64_t
 // partial sums (at most kNoAllocPartials).  Every device the library runs on
 // holds its own copy until the process ends; host code reaches it only
 // through the per-device address from hipGetSymbolAddress.
-constexpr int kNoAllocLut = kMaxWords * kGroupsPerWord * kLutEntries;
+constexpr int kNoAllocLut = 8192;   // energy table: 2 words x 16 nibbles x 256, or 4 x 22 x 64
+static_assert(kNoAllocLut >= 2 * 16 * 256 && kNoAllocLut >= kMaxWords * kGroupsPerWord * kLutEntries,
+              "the allocation-free energy table holds every table layout");
 constexpr int kNoAllocPartials = 8192;
 constexpr int kNoAllocDevices = 64;
 static __device__ __align__(256) double scratch[kNoAllocLut + kNoAllocPartials];
@@ -407,7 +409,7 @@ int iqcc_ctx_create(iqcc_ctx** out, int device) {
       ctx->lds_per_cu = (size_t)v;
   }
   noalloc_setup(device);
-  if (hipMalloc(&ctx->lut, sizeof(double) * kMaxWords * kGroupsPerWord * kLutEntries) != hipSuccess) {
+  if (hipMalloc(&ctx->lut, sizeof(double) * 8192) != hipSuccess) {   // every energy table layout
     delete ctx;
     return IQCC_ERR_HIP;
   }
@@ -1113,8 +1115,7 @@ int iqcc_qmf_energy(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, con
   const int grid = (int)(ctx->n_cu * ctx->energy_grid_per_cu);
   rc = ensure_partial(ctx, grid);
   if (rc) return rc;
-  launch_build_lut(h->W, h->nq, theta, phi, ctx->lut, s);
-  launch_energy(h->W, h->d, grid, ctx->lut, ctx->partial, s);
+  launch_energy_table(h->W, h->nq, h->d, grid, theta, phi, ctx->lut, ctx->partial, s);
   launch_finalize_sum(ctx->partial, grid, nullptr, energy, s);
   LAUNCH_CHECK(ctx);
   return IQCC_OK;
@@ -1133,8 +1134,7 @@ int iqcc_qmf_energy_noalloc(iqcc_ctx* ctx, const iqcc_store* h, const double* th
                 "allocation-free energy holds %d workgroup partials, the grid needs %lld "
                 "(lower energy_grid_per_cu)", kNoAllocPartials, (long long)grid);
   hipStream_t s = as_stream(stream);
-  launch_build_lut(h->W, h->nq, theta, phi, base, s);
-  launch_energy(h->W, h->d, (int)grid, base, base + kNoAllocLut, s);
+  launch_energy_table(h->W, h->nq, h->d, (int)grid, theta, phi, base, base + kNoAllocLut, s);
   launch_finalize_sum(base + kNoAllocLut, (int)grid, nullptr, energy, s);
   LAUNCH_CHECK(ctx);
   return IQCC_OK;

@@ -679,6 +679,12 @@ void launch_flip_rows(int W, const StoreDev& st, int w_max, uint64_t* ox, uint64
                       int64_t ld, unsigned long long* count, int grid, hipStream_t s);
 void launch_energy_anti(int W, const StoreDev& st, const PauliKey& P, int grid, const double* lut,
                         double* partial, hipStream_t s);
+// Stand-alone energy: builds the table (4-qubit groups for keys of up to two
+// words, else 3-qubit groups) into `lut` (energy_lut_doubles(W) doubles) and
+// writes grid partial sums.
+int energy_lut_doubles(int W);
+void launch_energy_table(int W, int nq, const StoreDev& st, int grid, const double* theta,
+                         const double* phi, double* lut, double* partial, hipStream_t s);
 void launch_energy(int W, const StoreDev& st, int grid, const double* lut, double* e_partial,
                    hipStream_t s);
 int energy_bwd_blocks_per_cu(int W);

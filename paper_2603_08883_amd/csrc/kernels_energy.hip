@@ -176,6 +176,141 @@ void launch_energy(int W, const StoreDev& st, int grid, const double* lut, doubl
 }
 
 // ---------------------------------------------------------------------------
+// Stand-alone energy with a table per 4-qubit group ("nibble"): 16 groups per
+// key word, 256 entries each (4 x bits, 4 z bits), 32 KB per word in LDS, so
+// keys of up to two words.  A byte of x and the same byte of z hold two
+// nibbles; two bit-field inserts per 32-bit half word put the codes of its
+// eight groups into the bytes of two registers, and each lookup takes one byte
+// extraction: 32 lookups per two-word term instead of 44, at about a third of
+// the address arithmetic.
+// ---------------------------------------------------------------------------
+constexpr int kNibbleEntries = 256;
+constexpr int kNibblesPerWord = 16;
+constexpr int kE4Block = 512;
+
+__global__ void k_build_lut4(int W, int nq, const double* theta, const double* phi, double* lut) {
+  const int n = W * kNibblesPerWord * kNibbleEntries;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int code = e % kNibbleEntries;
+    const int gi = e / kNibbleEntries;   // qubits 4 gi .. 4 gi + 3
+    double p = 1.0;
+    for (int r = 0; r < 4; ++r) {
+      const int q = 4 * gi + r;
+      if (q >= nq) continue;
+      const int op = ((code >> r) & 1) | (((code >> (4 + r)) & 1) << 1);
+      if (op == 0) continue;
+      double st, ct, sp, cp;
+      sincos(theta[q], &st, &ct);
+      sincos(phi[q], &sp, &cp);
+      p *= bloch_factor(op, st, ct, sp, cp);
+    }
+    lut[e] = p;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ double expect_nibble(const double* lut, const uint64_t* x, const uint64_t* z) {
+  double p[4] = {1.0, 1.0, 1.0, 1.0};
+#pragma unroll
+  for (int h = 0; h < 2 * W; ++h) {
+    const uint32_t xh = (uint32_t)(x[h >> 1] >> (32 * (h & 1)));
+    const uint32_t zh = (uint32_t)(z[h >> 1] >> (32 * (h & 1)));
+    // byte k: code of nibble 2k (lo) and of nibble 2k + 1 (hi), x bits low
+    const uint32_t lo = ((zh << 4) & 0xF0F0F0F0u) | (xh & 0x0F0F0F0Fu);
+    const uint32_t hi = ((xh >> 4) & 0x0F0F0F0Fu) | (zh & 0xF0F0F0F0u);
+    const double* lh = lut + 8 * h * kNibbleEntries;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      p[k] *= lh[(2 * k) * kNibbleEntries + ((lo >> (8 * k)) & 0xFFu)];
+      p[k] *= lh[(2 * k + 1) * kNibbleEntries + ((hi >> (8 * k)) & 0xFFu)];
+    }
+  }
+  return (p[0] * p[1]) * (p[2] * p[3]);
+}
+
+template <int W>
+__global__ __launch_bounds__(kE4Block) void k_energy4(StoreDev st, const double* lut_g, double* partial) {
+  constexpr int NE = W * kNibblesPerWord * kNibbleEntries;
+  extern __shared__ __align__(16) unsigned char smem_e4[];
+  double* lut = (double*)smem_e4;
+  int64_t* s_pre = (int64_t*)(lut + NE);     // [kE4Block + 1]
+  int64_t* s_off = s_pre + kE4Block + 1;     // [kE4Block]
+  __shared__ double red[kE4Block / 64];
+  __shared__ uint64_t scan_tmp[kE4Block / 64];
+  for (int i = threadIdx.x; i < NE; i += kE4Block) lut[i] = lut_g[i];
+  const int64_t B = 1ll << *st.m;
+  int64_t G = B / gridDim.x;
+  G = G < 1 ? 1 : (G > kE4Block ? kE4Block : G);
+  const int64_t ngroups = (B + G - 1) / G;
+  double acc = 0.0;
+  __syncthreads();
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t b = grp * G + threadIdx.x;
+    const bool mine = threadIdx.x < G && b < B;
+    const int64_t cnt = mine ? st.cnt[b] : 0;
+    const int64_t off = mine ? st.off[b] : 0;
+    uint64_t total;
+    // (the scan's barriers also order the previous group's reads of s_pre)
+    const uint64_t ex = block_exclusive_scan_n<kE4Block / 64>((uint64_t)cnt, scan_tmp, total);
+    s_pre[threadIdx.x] = (int64_t)ex;
+    s_off[threadIdx.x] = off;
+    if (threadIdx.x == 0) s_pre[kE4Block] = (int64_t)total;
+    __syncthreads();
+    const int64_t n = (int64_t)total;
+    for (int64_t i0 = 0; i0 < n; i0 += kE4Block * kEItems) {
+      uint64_t kx[kEItems][W], kz[kEItems][W];
+      double kc[kEItems];
+#pragma unroll
+      for (int r = 0; r < kEItems; ++r) {
+        const int64_t i = i0 + r * kE4Block + threadIdx.x;
+        kc[r] = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) kx[r][w] = kz[r][w] = 0;
+        if (i < n) {
+          int lo = 0;   // the last bucket of the group whose first row is <= i
+#pragma unroll
+          for (int step = kE4Block / 2; step; step >>= 1)
+            if (s_pre[lo + step] <= i) lo += step;
+          const int64_t row = s_off[lo] + (i - s_pre[lo]);
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            kx[r][w] = __builtin_nontemporal_load(&st.x[w * st.cap + row]);
+            kz[r][w] = __builtin_nontemporal_load(&st.z[w * st.cap + row]);
+          }
+          kc[r] = __builtin_nontemporal_load(&st.c[row]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kEItems; ++r) acc += kc[r] * expect_nibble<W>(lut, kx[r], kz[r]);
+    }
+  }
+  const double s = block_sum_n<kE4Block / 64>(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+int energy_lut_doubles(int W) {
+  return W <= 2 ? W * kNibblesPerWord * kNibbleEntries : W * kGroupsPerWord * kLutEntries;
+}
+
+void launch_energy_table(int W, int nq, const StoreDev& st, int grid, const double* theta,
+                         const double* phi, double* lut, double* partial, hipStream_t s) {
+  if (W > 2) {
+    launch_build_lut(W, nq, theta, phi, lut, s);
+    launch_energy(W, st, grid, lut, partial, s);
+    return;
+  }
+  hipLaunchKernelGGL(k_build_lut4, dim3(16), dim3(kBlock), 0, s, W, nq, theta, phi, lut);
+  const size_t lds = (size_t)W * kNibblesPerWord * kNibbleEntries * 8 + (size_t)(2 * kE4Block + 1) * 8;
+  if (W == 1) {
+    (void)hipFuncSetAttribute((const void*)k_energy4<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_energy4<1>, dim3(grid), dim3(kE4Block), lds, s, st, lut, partial);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_energy4<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_energy4<2>, dim3(grid), dim3(kE4Block), lds, s, st, lut, partial);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Backward w.r.t. the Bloch angles (derivative of the Eq. 3 energy).
 // dE/dtheta_q = sum_sigma S[q][sigma] db_sigma/dtheta (likewise phi), where
 // S[q][sigma] adds, over the terms with sigma on qubit q, c times the product
