@@ -594,8 +594,9 @@ def main():
             return work
 
         # untimed pass that records the per-step sizes (the same on every replay)
-        sizes, relocated = [], 0
+        sizes, relocated, sum_c2 = [], 0, []
         iqcc.iqcc_store_copy(ctx.handle, h0.handle, work.handle)
+        sum_c2_h0 = float(iqcc.iqcc_store_sum_squares(ctx.handle, work.handle).item())
         n_in = len(c)
         for j, ((px, pz), tau) in enumerate(zip(ents, taus)):
             iqcc.iqcc_dress_inplace(ctx.handle, work.handle, px, pz, tau, EPS, tht, pht, None,
@@ -604,6 +605,7 @@ def main():
             n_anti, n_new = iqcc.iqcc_store_stats(ctx.handle, work.handle)
             relocated += iqcc.iqcc_store_inplace_stats(ctx.handle, work.handle)["relocated"]
             sizes.append((n_in, n_anti, n_new, n_out))
+            sum_c2.append(float(iqcc.iqcc_store_sum_squares(ctx.handle, work.handle).item()))
             n_in = n_out
         ip_stats = iqcc.iqcc_store_inplace_stats(ctx.handle, work.handle)
         log("step sizes (N_in, N_anti, N_new, N_out):", sizes[0], "...", sizes[-1],
@@ -691,9 +693,11 @@ def main():
                          "measured_copy_gbps": copy_gbps,
                          "frac_of_measured_copy": achieved / copy_gbps},
             "per_step": [{"n_in": s_[0], "n_anti": s_[1], "n_new": s_[2], "n_out": s_[3],
+                          "sum_c2": sum_c2[j],
                           "energy": float(e_carry[j].item()), "ms": round(per_step[j] * 1e3, 4),
                           "alg_gbps": alg[j] / per_step[j] / 1e9}
                          for j, s_ in enumerate(sizes)],
+            "sum_c2_h0": sum_c2_h0,
             "h0_copy_ms": copy_s * 1e3,
             "final_energy": float(e_carry[-1].item()),
             "bit_identical_replays": bool(identical),

@@ -170,6 +170,13 @@ int iqcc_store_load(iqcc_ctx *ctx, iqcc_store *store, const uint64_t *x, const u
  * table (its contents are then undefined). */
 int iqcc_store_count(iqcc_ctx *ctx, const iqcc_store *store, int64_t *n, void *stream);
 
+/* *out (DEVICE scalar) = sum of c^2 over the live terms of the store.  By
+ * Eq. 5 a dressing step keeps this sum (cos^2 + sin^2 = 1 on every rotated
+ * pair) and compression (App. A) lowers it by the squares it drops, so it is a
+ * per-step check of a chain.  Asynchronous; the per-workgroup sums are reduced
+ * in a fixed order. */
+int iqcc_store_sum_squares(iqcc_ctx *ctx, const iqcc_store *store, double *out, void *stream);
+
 /* Synchronising: counters of the dressing step that produced `store`:
  * *n_anti = input terms that anticommuted with the entangler, *n_new = output
  * terms whose key was not in the input (both 0 after iqcc_store_load). */

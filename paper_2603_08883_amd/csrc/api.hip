@@ -615,6 +615,20 @@ int iqcc_store_stats(iqcc_ctx* ctx, const iqcc_store* st, int64_t* n_anti, int64
   return IQCC_OK;
 }
 
+int iqcc_store_sum_squares(iqcc_ctx* ctx, const iqcc_store* st, double* out, void* stream) {
+  int rc = check_ctx(ctx);
+  if (rc) return rc;
+  if (!st || !out) return fail(ctx, IQCC_ERR_INVALID_ARG, "null argument");
+  const int grid = (int)(ctx->n_cu * 4);
+  rc = ensure_partial(ctx, grid);
+  if (rc) return rc;
+  hipStream_t s = as_stream(stream);
+  launch_sum_squares(st->d, grid, ctx->partial, s);
+  launch_finalize_sum(ctx->partial, grid, nullptr, out, s);
+  LAUNCH_CHECK(ctx);
+  return IQCC_OK;
+}
+
 int iqcc_store_lookup(iqcc_ctx* ctx, const iqcc_store* st, const uint64_t* qx, const uint64_t* qz,
                       int64_t n, int64_t ld, int8_t* found, double* val, void* stream) {
   int rc = check_ctx(ctx);

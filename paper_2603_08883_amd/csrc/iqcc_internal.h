@@ -551,6 +551,7 @@ int launch_store_load(int W, StoreDev st, const uint64_t* x, const uint64_t* z, 
                       int64_t n, int64_t ld, int m, int64_t* scratch, hipStream_t s);
 void launch_store_export(int W, StoreDev st, int m, uint64_t* x, uint64_t* z, double* c, int64_t ld,
                          int64_t* dest_off, int64_t* scratch, hipStream_t s);
+void launch_sum_squares(const StoreDev& st, int grid, double* partial, hipStream_t s);
 void launch_lookup(int W, const StoreDev& st, const uint64_t* qx, const uint64_t* qz, int64_t n,
                    int64_t ld, int8_t* found, double* val, hipStream_t s);
 void launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s);

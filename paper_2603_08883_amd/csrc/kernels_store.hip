@@ -507,4 +507,27 @@ void launch_lookup(int W, const StoreDev& st, const uint64_t* qx, const uint64_t
   }
 }
 
+// Sum of c^2 over the live rows (the squared Frobenius norm of the Pauli sum
+// up to 2^n, which a dressing step keeps and compression lowers).  Workgroup g
+// takes buckets g, g + grid, ...; per-workgroup sums are reduced in a fixed
+// order by launch_finalize_sum.
+__global__ void k_sum_squares(StoreDev st, double* partial) {
+  __shared__ double red[kWaves];
+  const int64_t B = 1ll << *st.m;
+  double acc = 0.0;
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t n = st.cnt[b], off = st.off[b];
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      const double c = st.c[off + i];
+      acc += c * c;
+    }
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+void launch_sum_squares(const StoreDev& st, int grid, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_squares, dim3(grid), dim3(kBlock), 0, s, st, partial);
+}
+
 }  // namespace iqcc

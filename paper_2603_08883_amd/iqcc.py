@@ -73,6 +73,7 @@ def lib():
         "iqcc_store_count": (i32, [P, P, ct.POINTER(i64), P]),
         "iqcc_store_export": (i32, [P, P, P, P, P, i64, i64, ct.POINTER(i64), P]),
         "iqcc_store_stats": (i32, [P, P, ct.POINTER(i64), ct.POINTER(i64), P]),
+        "iqcc_store_sum_squares": (i32, [P, P, P, P]),
         "iqcc_store_lookup": (i32, [P, P, P, P, i64, i64, P, P, P]),
         "iqcc_dress": (i32, [P, P, P, P, d, d, P, P, P, P, P]),
         "iqcc_dress_energy_update": (i32, [P, P, P, P, d, d, P, P, P, P, P, P]),
@@ -120,7 +121,7 @@ def exported_symbols():
         "iqcc_store_create_ex", "iqcc_store_bytes", "iqcc_store_wrap", "iqcc_dress_count",
         "iqcc_pauli_products", "iqcc_chain_forward", "iqcc_chain_backward",
         "iqcc_store_shape", "iqcc_store_load", "iqcc_store_count", "iqcc_store_export",
-        "iqcc_store_stats", "iqcc_store_lookup",
+        "iqcc_store_stats", "iqcc_store_sum_squares", "iqcc_store_lookup",
         "iqcc_dress", "iqcc_dress_energy_update", "iqcc_dress_inplace", "iqcc_store_copy",
         "iqcc_store_inplace_stats", "iqcc_dress_raw", "iqcc_merge_truncate", "iqcc_qmf_energy",
         "iqcc_qmf_energy_noalloc", "iqcc_qmf_energy_backward", "iqcc_dis_gradients", "iqcc_store_rows",
@@ -290,6 +291,15 @@ def iqcc_store_count(ctx, store, stream=None) -> int:
     n = ct.c_int64()
     _check(lib().iqcc_store_count(ctx, store, ct.byref(n), _stream(stream)), ctx)
     return n.value
+
+
+def iqcc_store_sum_squares(ctx, store, out=None, stream=None):
+    """Sum of c^2 over the live terms (float64 device scalar; `out` optional)."""
+    import torch
+    if out is None:
+        out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    _check(lib().iqcc_store_sum_squares(ctx, store, _f64(out, "out", 1), _stream(stream)), ctx)
+    return out
 
 
 def iqcc_store_stats(ctx, store, stream=None):

@@ -288,3 +288,25 @@ def test_autotuned_inplace_chain_bit_identical(ctx, tmp_path, monkeypatch):
     finally:
         autotune.apply(ctx, defaults)
     h0.close(); work.close()
+
+
+def test_sum_squares_per_step(ctx):
+    """iqcc_store_sum_squares equals the sum of the exported coefficients'
+    squares, and across in-place steps at eps = 0 it stays at the H0 value to
+    rounding (a dressing step keeps sum c^2, Eq. 5)."""
+    nq, steps = 40, 4
+    x, z, c = I.hamiltonian_dense(nq, 5)
+    cx, cz = I.dis_candidates(x, nq, steps, 8, I.rng_for(5, I.PURPOSE_ENTANGLERS))
+    taus = I.taus(steps, I.rng_for(5, I.PURPOSE_TAUS))
+    s = iqcc.Store(ctx, nq, 8 * len(c), INPLACE).load_numpy(x, z, c)
+    ref0 = float(np.sum(c * c))
+    describe(0, "sum of squares", nq=nq)
+    got0 = float(iqcc.iqcc_store_sum_squares(ctx.handle, s.handle).item())
+    assert abs(got0 - ref0) <= 1e-12 * ref0
+    for j, ((px, pz), t) in enumerate(zip(zip(cx, cz), taus)):
+        iqcc.iqcc_dress_inplace(ctx.handle, s.handle, px, pz, t, 0.0)
+        got = float(iqcc.iqcc_store_sum_squares(ctx.handle, s.handle).item())
+        ex = s.to_numpy()[2]
+        assert abs(got - float(np.sum(ex * ex))) <= 1e-12 * ref0, j
+        assert abs(got - ref0) <= 1e-11 * ref0, (j, got, ref0)
+    s.close()
