@@ -173,6 +173,74 @@ def measured_copy_gbps():
     return nbytes / (ms * 1e-3) / 1e9
 
 
+def extended_chain_leg(ctx, stream, wl, steps=4, max_terms=4.0e8):
+    """The chain carried past its 20 steps, to the 12-GB-class footprint of the
+    largest workloads: H0 loaded into an in-place store sized for 4e8 terms
+    (2^21 buckets), the 20 steps of the chain (untimed), then `steps` more
+    seeded DIS entanglers timed with HIP events; per step sizes, time and
+    algorithmic bandwidth, energy carried.  Run last: its 58 GB store is
+    allocated after every other leg."""
+    import torch
+    from paper_2603_08883_amd import inputs as I
+    from paper_2603_08883_amd import iqcc
+    x, z, c, ents, taus, th, ph = wl
+    cx, cz = I.dis_candidates(x, N_QUBITS, steps, 8, I.rng_for(CONFIG + 50, I.PURPOSE_ENTANGLERS))
+    taus2 = I.taus(steps, I.rng_for(CONFIG + 50, I.PURPOSE_TAUS))
+    tht = torch.from_numpy(th).cuda()
+    pht = torch.from_numpy(ph).cuda()
+    big = iqcc.Store(ctx, N_QUBITS, int(max_terms), iqcc.IQCC_STORE_INPLACE)
+    K = len(ents)
+    e = torch.zeros(K + steps, dtype=torch.float64, device="cuda")
+
+    def chain20():
+        big.load_numpy(x, z, c)
+        for j, ((px, pz), t) in enumerate(zip(ents, taus)):
+            iqcc.iqcc_dress_inplace(ctx.handle, big.handle, px, pz, t, EPS, tht, pht,
+                                    e[j - 1:j] if j else None, e[j:j + 1])
+
+    def step(j):
+        k = K + j
+        iqcc.iqcc_dress_inplace(ctx.handle, big.handle, cx[j], cz[j], taus2[j], EPS, tht, pht,
+                                e[k - 1:k], e[k:k + 1])
+
+    sizes = []   # untimed pass: sizes of every extra step
+    chain20()
+    n_in = big.count()
+    for j in range(steps):
+        step(j)
+        n_out = big.count()
+        n_anti, n_new = iqcc.iqcc_store_stats(ctx.handle, big.handle)
+        sizes.append((n_in, n_anti, n_new, n_out))
+        n_in = n_out
+    chain20()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    for j in range(steps):
+        evs[j].record(stream)
+        step(j)
+    evs[steps].record(stream)
+    torch.cuda.synchronize()
+    ms = [evs[j].elapsed_time(evs[j + 1]) for j in range(steps)]
+    bt = 16 * x.shape[1] + 8
+    alg = [bt * s_[0] + 8 * s_[1] + bt * s_[2] for s_ in sizes]
+    st = iqcc.iqcc_store_inplace_stats(ctx.handle, big.handle)
+    out = {"workload": f"the 124-qubit chain continued by {steps} more seeded DIS entanglers past its "
+                       f"20 steps, in an in-place store for {max_terms:.1e} terms",
+           "arena_gb": iqcc.iqcc_store_bytes(N_QUBITS, int(max_terms), iqcc.IQCC_STORE_INPLACE) / 1e9,
+           "final_terms": sizes[-1][3], "final_term_bytes_gb": sizes[-1][3] * bt / 1e9,
+           "steps_ms": sum(ms), "alg_gbps": sum(alg) / (sum(ms) * 1e-3) / 1e9,
+           "roofline_frac": sum(alg) / (sum(ms) * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+           "relocated_items_last_step": st["relocated"],
+           "per_step": [{"n_in": s_[0], "n_anti": s_[1], "n_new": s_[2], "n_out": s_[3],
+                         "energy": float(e[K + j].item()), "ms": round(ms[j], 4),
+                         "alg_gbps": alg[j] / (ms[j] * 1e-3) / 1e9} for j, s_ in enumerate(sizes)]}
+    big.close()
+    torch.cuda.empty_cache()
+    log(f"extended chain: {sizes[0][0]} -> {sizes[-1][3]} terms in {sum(ms):.2f} ms, "
+        f"{out['alg_gbps']:.0f} GB/s algorithmic")
+    return out
+
+
 def angle_backward_leg(ctx, stream, final, tht, pht, bt, reps=5):
     """dE/dtheta, dE/dphi and the per-term cotangents of the final 124-qubit
     Hamiltonian (in-place store) in one call, timed with HIP events on the
@@ -505,6 +573,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the 50-step joint optimisation")
+    ap.add_argument("--no-extended", action="store_true",
+                    help="skip the chain continued to ~3e8 terms (12-GB-class footprint)")
     ap.add_argument("--no-qcc", action="store_true")
     ap.add_argument("--no-sortless", action="store_true")
     ap.add_argument("--no-poly", action="store_true")
@@ -521,7 +591,7 @@ def main():
     args = ap.parse_args()
     if args.only is not None:
         for leg in ("cpu_baseline", "dis", "chain", "batch", "autograd", "c5", "qcc", "sortless",
-                    "poly"):
+                    "poly", "extended"):
             setattr(args, "no_" + leg, True)
         if args.only in ("chain", "angle-backward"):
             args.no_chain = False
@@ -558,7 +628,7 @@ def main():
     log(f"device copy {copy_gbps:.0f} GB/s (read + write)")
 
     wl = None
-    if not (args.no_chain and args.no_autograd):
+    if not (args.no_chain and args.no_autograd and args.no_extended):
         t = time.perf_counter()
         wl = workload_chain()
         log(f"124-qubit workload: {len(wl[2])} terms generated in {time.perf_counter() - t:.1f}s")
@@ -827,6 +897,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_c5:
         result["c5_optimisation"] = c5_leg(ctx, wl)
+    wl_ext = wl if not args.no_extended else None
     del wl
 
     if not args.no_dis:
@@ -972,6 +1043,9 @@ def main():
         log(f"iQCC iteration {result['qcc_iteration']['iteration_ms']:.1f} ms "
             f"({result['qcc_iteration']['n_candidates']} candidates)")
         torch.cuda.empty_cache()
+
+    if wl_ext is not None:
+        result["extended_chain"] = extended_chain_leg(ctx, stream, wl_ext)
 
     ctx.close()
     print(json.dumps(result), flush=True)
