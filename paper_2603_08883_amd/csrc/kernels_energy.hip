@@ -339,18 +339,7 @@ void launch_energy_table(int W, int nq, const StoreDev& st, int grid, const doub
 // 2^-61 per added value.
 // acc layout per workgroup: [3 * nq] with sigma order X, Z, Y.
 // ---------------------------------------------------------------------------
-#ifndef IQCC_BWD_GROT
-#define IQCC_BWD_GROT 1
-#endif
-#ifndef IQCC_BWD_BLOCK
-#define IQCC_BWD_BLOCK 512
-#endif
-#ifndef IQCC_BWD_COPIES
-#define IQCC_BWD_COPIES 1
-#endif
-constexpr int kBwdBlock = IQCC_BWD_BLOCK;
-// copies of the integer tables; lane l adds into copy l % kBwdCopies
-constexpr int kBwdCopies = IQCC_BWD_COPIES;
+constexpr int kBwdBlock = 512;
 constexpr int kBwdGroup = 256;   // most buckets per group of one flat range
 // LDS tables of the backward hold each 3-qubit group's 64 entries at a stride
 // of 65, so that equal codes of different groups fall in different banks.
@@ -359,7 +348,7 @@ constexpr int kBwdStride = kLutEntries + 1;
 size_t energy_bwd_lds_bytes(int W) {
   // energy table, the two integer tables (the per-qubit factors of the
   // epilogue reuse the first), bucket-group scan
-  return (size_t)(1 + 2 * kBwdCopies) * W * kGroupsPerWord * kBwdStride * 8 + (size_t)(2 * kBwdGroup + 1) * 8;
+  return (size_t)3 * W * kGroupsPerWord * kBwdStride * 8 + (size_t)(2 * kBwdGroup + 1) * 8;
 }
 
 // Workgroups per CU that the LDS of one CU holds (160 KiB), at most 2048
@@ -423,10 +412,10 @@ __device__ __forceinline__ void bwd_term(const double* lut, unsigned long long* 
 #pragma unroll
   for (int h = 2 * W - 1; h >= 0; --h) { ho[h] *= suf; suf *= hp[h]; }
   // each half word: prefix and suffix over its groups.  A term visits its
-  // half words starting at one picked from its own key bits, so that the
-  // lanes of a wave add into different half words' tables at a time (fewer
-  // lanes on one LDS address); the values do not depend on where the term
-  // sits in the store.
+  // half words, and the groups of each, starting at ones picked from its own
+  // key bits, so that the lanes of a wave add into different groups' tables
+  // at a time (fewer lanes on one LDS address or bank); the values do not
+  // depend on where the term sits in the store.
   const uint32_t mix = ((uint32_t)kx[0] ^ (uint32_t)(kz[0] >> 29) ^ (uint32_t)(kx[W - 1] >> 35)) * 0x9E3779B1u;
   const int rot = (int)__umulhi(mix, 2u * W);
 #pragma unroll 1
@@ -442,8 +431,6 @@ __device__ __forceinline__ void bwd_term(const double* lut, unsigned long long* 
     }
     const uint32_t xh = (uint32_t)(xw >> (32 * (h & 1)));
     const uint32_t zh = (uint32_t)(zw >> (32 * (h & 1)));
-#if IQCC_BWD_GROT
-    // groups visited from one picked from the term's key bits as well
     const int rg = (int)__umulhi(mix * 0x85EBCA6Bu, (uint32_t)kGroupsPerHalf);
     const uint64_t xr = ((uint64_t)xh | ((uint64_t)xh << 33)) >> (3 * rg);
     const uint64_t zr = ((uint64_t)zh | ((uint64_t)zh << 33)) >> (3 * rg);
@@ -459,18 +446,6 @@ __device__ __forceinline__ void bwd_term(const double* lut, unsigned long long* 
       idx[g] = (rg < kGroupsPerHalf - g ? base_lo : base_hi) + g * kBwdStride + (int)code[g];
       L[g] = lut[idx[g]];
     }
-#else
-    const double* lh = lut + h * NH;
-    double L[kGroupsPerHalf];
-    uint32_t code[kGroupsPerHalf];
-    int idx[kGroupsPerHalf];
-#pragma unroll
-    for (int g = 0; g < kGroupsPerHalf; ++g) {
-      code[g] = __builtin_amdgcn_ubfe(xh, 3 * g, 3) | (__builtin_amdgcn_ubfe(zh, 3 * g, 3) << 3);
-      idx[g] = h * NH + g * kBwdStride + (int)code[g];
-      L[g] = lh[g * kBwdStride + code[g]];
-    }
-#endif
     double sf[kGroupsPerHalf];
     sf[kGroupsPerHalf - 1] = 1.0;
 #pragma unroll
@@ -496,7 +471,7 @@ __global__ __launch_bounds__(kBwdBlock, 4) void k_energy_bwd(StoreDev st, int nq
   unsigned long long* thi = (unsigned long long*)(lut + NE);           // [NE] sums of round(v 2^20)
   unsigned long long* tlo = thi + NE;                                  // [NE] sums of the remainders
   double* fac = (double*)thi;   // epilogue: per qubit, factor of I, X, Z, Y (4 * 64W <= NE)
-  int64_t* s_pre = (int64_t*)(thi + 2 * kBwdCopies * NE);              // [kBwdGroup + 1] group scan
+  int64_t* s_pre = (int64_t*)(tlo + NE);                               // [kBwdGroup + 1] group scan
   int64_t* s_off = s_pre + kBwdGroup + 1;                              // [kBwdGroup] first rows
   __shared__ double s_cmax[kBwdBlock / 64];
   __shared__ long long s_cnt[kBwdBlock / 64];
@@ -507,12 +482,10 @@ __global__ __launch_bounds__(kBwdBlock, 4) void k_energy_bwd(StoreDev st, int nq
   for (int i = threadIdx.x; i < NE; i += kBwdBlock) {
     const int k = i % kBwdStride;
     lut[i] = k < kLutEntries ? lut_g[i / kBwdStride * kLutEntries + k] : 0.0;
-#pragma unroll
-    for (int k = 0; k < kBwdCopies; ++k) thi[2 * k * NE + i] = tlo[2 * k * NE + i] = 0ull;
+    thi[i] = tlo[i] = 0ull;
   }
   for (int q = threadIdx.x; q < nq; q += kBwdBlock)
     if (!(fabs(theta[q]) <= DBL_MAX && fabs(phi[q]) <= DBL_MAX)) s_bad = 1;
-  const int my_copy = (int)(threadIdx.x % kBwdCopies) * 2 * NE;
   const double scale = dE ? *dE : 1.0;
   bool ok = true;   // every coefficient finite and below 2^31 in magnitude
   double cmax = 0.0;
@@ -578,7 +551,7 @@ __global__ __launch_bounds__(kBwdBlock, 4) void k_energy_bwd(StoreDev st, int nq
         ++nmine;
         ok = ok && fabs(cc) < 0x1p31;
         cmax = fmax(cmax, fabs(cc));
-        bwd_term<W>(lut, thi + my_copy, tlo + my_copy, cx, cz, cc, lam ? lam + crow : nullptr, scale);
+        bwd_term<W>(lut, thi, tlo, cx, cz, cc, lam ? lam + crow : nullptr, scale);
       }
 #pragma unroll
       for (int w = 0; w < W; ++w) { cx[w] = nx[w]; cz[w] = nz[w]; }
@@ -607,12 +580,8 @@ __global__ __launch_bounds__(kBwdBlock, 4) void k_energy_bwd(StoreDev st, int nq
   const bool in_range = s_bad == 0 && nwg < (1ll << 23) && cm * (double)nwg < 0x1p42;
   // the sums as doubles, over the energy table (no longer needed), then the
   // per-qubit factors over the first integer table
-  for (int i = threadIdx.x; i < NE; i += kBwdBlock) {
-    unsigned long long a = thi[i], b = tlo[i];
-#pragma unroll
-    for (int k = 1; k < kBwdCopies; ++k) { a += thi[2 * k * NE + i]; b += tlo[2 * k * NE + i]; }
-    lut[i] = (double)(long long)a * 0x1p-20 + (double)(long long)b * 0x1p-60;
-  }
+  for (int i = threadIdx.x; i < NE; i += kBwdBlock)
+    lut[i] = (double)(long long)thi[i] * 0x1p-20 + (double)(long long)tlo[i] * 0x1p-60;
   __syncthreads();
   for (int q = threadIdx.x; q < 64 * W; q += kBwdBlock) {
     double st_ = 0, ct = 1, sp = 0, cp = 1;
