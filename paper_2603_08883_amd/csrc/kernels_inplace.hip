@@ -143,10 +143,11 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
+// Sum over the wave, returned as a wave-uniform (scalar) value.
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 struct Geo {
@@ -251,8 +252,10 @@ __device__ __forceinline__ void issue_slices(const StoreDev& st, const Item& I, 
   }
 }
 
+// Per-wavefront tallies of a step, kept in scalar registers: each is bounded
+// by the store's rows (below 2^31) or by the number of work items.
 struct WaveCounts {
-  int64_t anti = 0, fresh = 0, delta = 0, reloc = 0, freed = 0;
+  int anti = 0, fresh = 0, delta = 0, reloc = 0, freed = 0;
 };
 
 // Rows for the entries with `has` set, placed in their slot `d` in stash
@@ -612,7 +615,7 @@ __device__ bool relocate_item(const StoreDev& st, const Entangler& P, const Inpl
   while ((int64_t)R * (g.cap / 4) < nanti && R < (1u << 20)) R <<= 1;
   for (;;) {
     double e_try = 0.0;
-    int64_t fresh_try = 0;
+    int fresh_try = 0;
     if (lane < I.nslots) g.s_ctr[lane] = 0;
     wave_sync();
     bool ok = true;
@@ -739,13 +742,13 @@ __device__ void process_item(const StoreDev& st, const Entangler& P, const Inpla
   if (lane < I.nslots) st.cnt[I.b] = I.cnt + nn - nh;
   wc.delta += wave_sum(nn - nh);
   wc.fresh += wave_sum(nn);
-  wc.freed += freed;
+  wc.freed += __builtin_amdgcn_readfirstlane(freed);
 }
 
 template <int W, bool ENERGY>
 __global__ __launch_bounds__(kIPB) void k_dress_inplace(StoreDev st, Entangler P, InplaceConfig cfg) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: segment pointers stay scalar
   const int lane = threadIdx.x & 63;
   const size_t lut_bytes = ENERGY ? (size_t)W * kGroupsPerWord * kLutEntries * 8 : 0;
   double* lut = (double*)smem;
