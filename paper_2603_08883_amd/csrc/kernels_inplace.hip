@@ -51,7 +51,12 @@ enum : uint8_t { kFComm = 1, kFHole = 2, kFNew = 4 };
 // per-slot counters of the item.
 constexpr int kIPSlotArrays = 4;
 
-__host__ __device__ inline int ip_tsize(int cap) { return (3 * cap / 2 + 7) & ~7; }
+// Join table entries: 11/8 of the stash.  At most one member of each {K, K^P}
+// pair is inserted, so the table is seldom more than ~40 % full and always has
+// an empty entry (probes end); it has at least `cap` entries because it later
+// lists the freed rows.  (With the energy table at W = 2 this size keeps the
+// stash at 200 entries; a fuller table lengthens the slowest probe of the wave.)
+__host__ __device__ inline int ip_tsize(int cap) { return (11 * cap / 8 + 7) & ~7; }
 
 __host__ __device__ inline size_t seg_bytes(int W, int cap) {
   size_t o = (size_t)W * cap * 16 + (size_t)cap * 8       // keys, coefficient
@@ -376,7 +381,11 @@ __device__ __forceinline__ void entry_key(const Seg<W>& g, int i, uint64_t* kx, 
 }
 
 // Pair each stashed anticommuting K with K^P: the members whose pivot bit is
-// 0 go into the table, the others look up K^P.
+// 0 go into the table, the others look up K^P.  A table entry holds the
+// stash index in its low 16 bits and the low 16 bits of the key's hash above
+// them (the slot comes from the high bits), so a probe that meets another key
+// is mostly rejected without reading its words (-1 marks an empty entry; the
+// stash holds at most 512 entries).
 template <int W>
 __device__ void item_join(const Entangler& P, const Seg<W>& g, int n) {
   const int lane = threadIdx.x & 63;
@@ -388,8 +397,10 @@ __device__ void item_join(const Entangler& P, const Seg<W>& g, int n) {
     uint64_t kx[W], kz[W];
     entry_key<W>(g, i, kx, kz);
     if (pivot_of<W>(P, kx, kz)) continue;
-    uint32_t h = table_slot(table_hash<W>(kx, kz), g.tsize);
-    while (atomicCAS(&g.tab[h], -1, i) != -1) h = (h + 1 == (uint32_t)g.tsize) ? 0 : h + 1;
+    const uint32_t hk = table_hash<W>(kx, kz);
+    const int32_t e = (int32_t)((hk << 16) | (uint32_t)i);
+    uint32_t h = table_slot(hk, g.tsize);
+    while (atomicCAS(&g.tab[h], -1, e) != -1) h = (h + 1 == (uint32_t)g.tsize) ? 0 : h + 1;
   }
   wave_sync();
   for (int i = lane; i < n; i += 64) {
@@ -402,17 +413,22 @@ __device__ void item_join(const Entangler& P, const Seg<W>& g, int n) {
       kz[w] ^= P.pz[w];
     }
     if (pivot_of<W>(P, kx, kz)) continue;   // the pivot bit of K is 0: K is in the table
-    uint32_t h = table_slot(table_hash<W>(kx, kz), g.tsize);
+    const uint32_t hk = table_hash<W>(kx, kz);
+    const uint32_t fp = hk << 16;
+    uint32_t h = table_slot(hk, g.tsize);
     for (;;) {
-      const int j = g.tab[h];
-      if (j < 0) break;
-      bool eq = true;
+      const int32_t e = g.tab[h];
+      if (e == -1) break;
+      if (((uint32_t)e & 0xFFFF0000u) == fp) {
+        const int j = e & 0xFFFF;
+        bool eq = true;
 #pragma unroll
-      for (int w = 0; w < W; ++w) eq = eq && g.ax[w * g.cap + j] == kx[w] && g.az[w * g.cap + j] == kz[w];
-      if (eq) {
-        g.partner[i] = (int16_t)j;
-        g.partner[j] = (int16_t)i;
-        break;
+        for (int w = 0; w < W; ++w) eq = eq && g.ax[w * g.cap + j] == kx[w] && g.az[w * g.cap + j] == kz[w];
+        if (eq) {
+          g.partner[i] = (int16_t)j;
+          g.partner[j] = (int16_t)i;
+          break;
+        }
       }
       h = (h + 1 == (uint32_t)g.tsize) ? 0 : h + 1;
     }
