@@ -161,7 +161,11 @@ int iqcc_store_shape(const iqcc_store *store, int *n_qubits, int *n_words);
  * qubits >= n_qubits zero; this is not checked unless the IQCC_DEBUG_VALIDATE
  * environment variable is set, which adds a synchronising host-side check of
  * both (IQCC_ERR_INVALID_ARG, store unchanged, on a duplicate key or a set
- * padding bit).  Chooses the bucket count from "load_bucket_terms". */
+ * padding bit).  Chooses the bucket count from "load_bucket_terms".  Each
+ * bucket receives its terms in ascending key order, so loading the same terms
+ * (in any input order) gives the same rows, and every later step and sum
+ * over the store repeats bit for bit.  Uses library working memory of about
+ * 8 bytes per row (the context's scratch, grown on demand). */
 int iqcc_store_load(iqcc_ctx *ctx, iqcc_store *store, const uint64_t *x, const uint64_t *z,
                     const double *c, int64_t n, int64_t ld, void *stream);
 

@@ -543,7 +543,7 @@ int iqcc_store_load(iqcc_ctx* ctx, iqcc_store* st, const uint64_t* x, const uint
     int64_t R = 0;
     inplace_geometry(ctx, st, m, R);
     const int64_t Bi = 1ll << m;
-    rc = ensure_scratch(ctx, 2 * Bi + Bi / 1024 + 16);
+    rc = ensure_scratch(ctx, 3 * Bi + Bi / 1024 + 16 + n);
     if (rc) return rc;
     launch_store_load_regions(st->W, st->d, x, z, c, n, ld, m, R, ctx->scratch, s);
     LAUNCH_CHECK(ctx);
@@ -551,7 +551,7 @@ int iqcc_store_load(iqcc_ctx* ctx, iqcc_store* st, const uint64_t* x, const uint
     st->region_m = m;
     return IQCC_OK;
   }
-  rc = ensure_scratch(ctx, B + B / 1024 + 16);
+  rc = ensure_scratch(ctx, B + B / 1024 + 16 + n);
   if (rc) return rc;
   launch_store_load(st->W, st->d, x, z, c, n, ld, m, ctx->scratch, s);
   LAUNCH_CHECK(ctx);

@@ -547,6 +547,8 @@ __device__ __forceinline__ void pair_buckets(int64_t pi, uint32_t f, int thi, ui
 void launch_build_lut(int W, int nq, const double* theta, const double* phi, double* lut,
                       hipStream_t s);
 void launch_zero_counters(StoreDev out, hipStream_t s);
+// Load of flat rows into packed buckets, each bucket's rows in ascending key
+// order (the same rows whatever the input order).  scratch: B + B/1024 + 16 + n.
 int launch_store_load(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
                       int64_t n, int64_t ld, int m, int64_t* scratch, hipStream_t s);
 void launch_store_export(int W, StoreDev st, int m, uint64_t* x, uint64_t* z, double* c, int64_t ld,
@@ -595,9 +597,10 @@ int inplace_waves_per_block();
 void launch_dress_inplace(int W, const StoreDev& st, const Entangler& P, const InplaceConfig& cfg, int grid,
                           const double* energy_in, double* energy_out, hipStream_t s);
 // Bucket regions: bucket b gets max(R, 2 cnt_b rounded up to 16) rows; the
-// pool starts after the last region.  Load of flat rows (as launch_store_load)
-// and copy of a store (deterministic: each destination bucket takes its rows
-// in source order).  Both set err = 1 when the regions do not fit the arena.
+// pool starts after the last region.  Load of flat rows (as launch_store_load;
+// scratch 3 B + B/1024 + 16 + n) and copy of a store (deterministic: each
+// destination bucket takes its rows in source order).  Both set err = 1 when
+// the regions do not fit the arena.
 int launch_store_load_regions(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
                               int64_t n, int64_t ld, int m, int64_t R, int64_t* scratch, hipStream_t s);
 // same_m: the source has the same bucket count m (its current m is known on

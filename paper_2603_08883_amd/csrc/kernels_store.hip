@@ -118,10 +118,14 @@ __global__ void k_load_hist(const uint64_t* __restrict__ x, const uint64_t* __re
   }
 }
 
+// Load, second pass: the input index of every term into its bucket's slot
+// list (lists packed at poff); the order inside a list follows the atomics
+// and is undone by the third pass.  err (optional): skip when it is set.
 template <int W>
-__global__ void k_load_scatter(const uint64_t* __restrict__ x, const uint64_t* __restrict__ z,
-                               const double* __restrict__ c, int64_t n, int64_t ld,
-                               uint32_t mask, const int64_t* off, int64_t* fill, StoreDev st) {
+__global__ void k_load_slots(const uint64_t* __restrict__ x, const uint64_t* __restrict__ z, int64_t n,
+                             int64_t ld, uint32_t mask, const int64_t* poff, int64_t* fill, int64_t* slots,
+                             const int* err) {
+  if (err && *err) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     uint64_t kx[W], kz[W];
@@ -130,14 +134,122 @@ __global__ void k_load_scatter(const uint64_t* __restrict__ x, const uint64_t* _
       kx[w] = x[w * ld + i];
       kz[w] = z[w * ld + i];
     }
-    uint32_t b = bucket_hash<W>(kx, kz) & mask;
-    int64_t pos = off[b] + (int64_t)atomicAdd((unsigned long long*)&fill[b], 1ull);
+    const uint32_t b = bucket_hash<W>(kx, kz) & mask;
+    slots[poff[b] + (int64_t)atomicAdd((unsigned long long*)&fill[b], 1ull)] = i;
+  }
+}
+
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int t) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, t);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), t);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// -1, 0 or +1 as a is below, equal to or above b; `ord` carries the verdict of
+// the more significant words.
+__device__ __forceinline__ int cmp_next(int ord, uint64_t a, uint64_t b) {
+  return ord ? ord : (a < b ? -1 : (a > b ? 1 : 0));
+}
+
+// Load, third pass: one wavefront per bucket writes the bucket's terms in
+// ascending key order (x words, then z words, most significant first; ties,
+// which a valid input does not have, by input index), so a loaded store's
+// rows depend only on the terms, not on the order of the second pass's
+// atomics or of the input.  A term's row is off_b plus the number of the
+// bucket's terms that precede it; candidates are broadcast from lane
+// registers 64 at a time, O(cnt^2 / 64) steps per bucket.  Terms are read
+// from the input and written to the store, so no row is overwritten early.
+template <int W>
+__global__ void k_load_place(const uint64_t* __restrict__ x, const uint64_t* __restrict__ z,
+                             const double* __restrict__ c, int64_t ld, int64_t B, const int64_t* poff,
+                             const int64_t* slots, StoreDev st, int guarded) {
+  if (guarded && *st.err) return;   // the regions do not fit the arena: write nothing
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const int nw = (int)(gridDim.x * (blockDim.x >> 6));
+  for (int64_t b = wid; b < B; b += nw) {
+    const int64_t cnt = st.cnt[b], base = poff[b], out = st.off[b];
+    for (int64_t j0 = 0; j0 < cnt; j0 += 64) {
+      const bool has = j0 + lane < cnt;
+      int64_t ij = 0;
+      uint64_t jx[W], jz[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      st.x[w * st.cap + pos] = kx[w];
-      st.z[w * st.cap + pos] = kz[w];
+      for (int w = 0; w < W; ++w) jx[w] = jz[w] = 0;
+      if (has) {
+        ij = slots[base + j0 + lane];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          jx[w] = x[w * ld + ij];
+          jz[w] = z[w * ld + ij];
+        }
+      }
+      int64_t rank = 0;
+      for (int64_t k0 = 0; k0 < cnt; k0 += 64) {
+        int64_t ik = 0;
+        uint64_t kx[W], kz[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) kx[w] = kz[w] = 0;
+        if (k0 + lane < cnt) {
+          ik = slots[base + k0 + lane];
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            kx[w] = x[w * ld + ik];
+            kz[w] = z[w * ld + ik];
+          }
+        }
+        const int kn = (int)(cnt - k0 < 64 ? cnt - k0 : 64);
+        for (int t = 0; t < kn; ++t) {
+          int ord = 0;
+#pragma unroll
+          for (int w = W - 1; w >= 0; --w) ord = cmp_next(ord, lane_u64(kx[w], t), jx[w]);
+#pragma unroll
+          for (int w = W - 1; w >= 0; --w) ord = cmp_next(ord, lane_u64(kz[w], t), jz[w]);
+          ord = cmp_next(ord, lane_u64((uint64_t)ik, t), (uint64_t)ij);
+          rank += ord < 0;
+        }
+      }
+      if (has) {
+        const int64_t row = out + rank;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          st.x[w * st.cap + row] = jx[w];
+          st.z[w * st.cap + row] = jz[w];
+        }
+        st.c[row] = c[ij];
+      }
     }
-    st.c[pos] = c[i];
+  }
+}
+
+// The second and third passes of a load (the bucket counts, their packed
+// offsets poff and the rows' offsets st.off are in place).
+static void load_place_rows(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
+                            int64_t n, int64_t ld, uint32_t mask, int64_t B, const int64_t* poff,
+                            int64_t* fill, int64_t* slots, bool guarded, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  const int* err = guarded ? st.err : nullptr;
+  int64_t pb = (B + kWaves - 1) / kWaves;
+  if (pb > 8192) pb = 8192;
+  const int g = guarded ? 1 : 0;
+  switch (W) {
+    case 1:
+      hipLaunchKernelGGL(k_load_slots<1>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, poff, fill, slots, err);
+      hipLaunchKernelGGL(k_load_place<1>, dim3(pb), dim3(kBlock), 0, s, x, z, c, ld, B, poff, slots, st, g);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_load_slots<2>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, poff, fill, slots, err);
+      hipLaunchKernelGGL(k_load_place<2>, dim3(pb), dim3(kBlock), 0, s, x, z, c, ld, B, poff, slots, st, g);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_load_slots<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, poff, fill, slots, err);
+      hipLaunchKernelGGL(k_load_place<3>, dim3(pb), dim3(kBlock), 0, s, x, z, c, ld, B, poff, slots, st, g);
+      break;
+    default:
+      hipLaunchKernelGGL(k_load_slots<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, n, ld, mask, poff, fill, slots, err);
+      hipLaunchKernelGGL(k_load_place<4>, dim3(pb), dim3(kBlock), 0, s, x, z, c, ld, B, poff, slots, st, g);
+      break;
   }
 }
 
@@ -159,12 +271,14 @@ __global__ void k_load_finish(StoreDev st, int m, int64_t n) {
   }
 }
 
+// scratch: B + ceil(B/1024) + 16 + n int64 (fill, scan, slot lists).
 int launch_store_load(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
                       int64_t n, int64_t ld, int m, int64_t* scratch, hipStream_t s) {
   const int64_t B = 1ll << m;
   const uint32_t mask = (uint32_t)(B - 1);
-  int64_t* fill = scratch;                 // B
-  int64_t* scan_tmp = scratch + B;         // ceil(B/1024)+1
+  int64_t* fill = scratch;                       // B
+  int64_t* scan_tmp = scratch + B;               // ceil(B/1024)+1
+  int64_t* slots = scratch + B + B / 1024 + 16;  // n
   fill_i64(st.cnt, B, 0, s);
   fill_i64(fill, B, 0, s);
   int64_t blocks = (n + kBlock - 1) / kBlock;
@@ -179,14 +293,8 @@ int launch_store_load(int W, StoreDev st, const uint64_t* x, const uint64_t* z, 
     }
   }
   launch_scan_i64(st.cnt, st.off, B, scan_tmp, s);
-  if (n > 0) {
-    switch (W) {
-      case 1: hipLaunchKernelGGL(k_load_scatter<1>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
-      case 2: hipLaunchKernelGGL(k_load_scatter<2>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
-      case 3: hipLaunchKernelGGL(k_load_scatter<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
-      default: hipLaunchKernelGGL(k_load_scatter<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, st.off, fill, st); break;
-    }
-  }
+  // packed rows: the slot lists and the rows share their offsets
+  load_place_rows(W, st, x, z, c, n, ld, mask, B, st.off, fill, slots, false, s);
   {
     int64_t lb = (B + kBlock - 1) / kBlock;
     if (lb > 4096) lb = 4096;
@@ -236,30 +344,6 @@ __global__ void k_regions_finish(StoreDev st, const int64_t* reg, int64_t B, int
   }
 }
 
-template <int W>
-__global__ void k_load_scatter_guarded(const uint64_t* __restrict__ x, const uint64_t* __restrict__ z,
-                                       const double* __restrict__ c, int64_t n, int64_t ld, uint32_t mask,
-                                       int64_t* fill, StoreDev st) {
-  if (*st.err) return;   // the regions do not fit the arena: write nothing
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t kx[W], kz[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      kx[w] = x[w * ld + i];
-      kz[w] = z[w * ld + i];
-    }
-    const uint32_t b = bucket_hash<W>(kx, kz) & mask;
-    const int64_t pos = st.off[b] + (int64_t)atomicAdd((unsigned long long*)&fill[b], 1ull);
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      st.x[w * st.cap + pos] = kx[w];
-      st.z[w * st.cap + pos] = kz[w];
-    }
-    st.c[pos] = c[i];
-  }
-}
-
 static void regions_from_counts(StoreDev st, int64_t B, int m, int64_t R, int64_t n, const StoreDev& src,
                                 int64_t* reg, int64_t* scan_tmp, hipStream_t s) {
   int64_t lb = (B + kBlock - 1) / kBlock;
@@ -270,13 +354,17 @@ static void regions_from_counts(StoreDev st, int64_t B, int m, int64_t R, int64_
   hipLaunchKernelGGL(k_regions_finish, dim3(1), dim3(64), 0, s, st, reg, B, m, R, n, src);
 }
 
+// scratch: 3 B + ceil(B/1024) + 16 + n int64 (fill, region sizes, scan,
+// packed slot offsets, slot lists).
 int launch_store_load_regions(int W, StoreDev st, const uint64_t* x, const uint64_t* z, const double* c,
                               int64_t n, int64_t ld, int m, int64_t R, int64_t* scratch, hipStream_t s) {
   const int64_t B = 1ll << m;
   const uint32_t mask = (uint32_t)(B - 1);
-  int64_t* fill = scratch;              // B
-  int64_t* reg = scratch + B;           // B
-  int64_t* scan_tmp = scratch + 2 * B;  // ceil(B/1024)+1
+  int64_t* fill = scratch;                           // B
+  int64_t* reg = scratch + B;                        // B
+  int64_t* scan_tmp = scratch + 2 * B;               // ceil(B/1024)+1
+  int64_t* poff = scratch + 2 * B + B / 1024 + 16;   // B
+  int64_t* slots = poff + B;                         // n
   fill_i64(st.cnt, B, 0, s);
   fill_i64(fill, B, 0, s);
   int64_t blocks = (n + kBlock - 1) / kBlock;
@@ -291,14 +379,8 @@ int launch_store_load_regions(int W, StoreDev st, const uint64_t* x, const uint6
     }
   }
   regions_from_counts(st, B, m, R, n, st, reg, scan_tmp, s);
-  if (n > 0) {
-    switch (W) {
-      case 1: hipLaunchKernelGGL(k_load_scatter_guarded<1>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, fill, st); break;
-      case 2: hipLaunchKernelGGL(k_load_scatter_guarded<2>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, fill, st); break;
-      case 3: hipLaunchKernelGGL(k_load_scatter_guarded<3>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, fill, st); break;
-      default: hipLaunchKernelGGL(k_load_scatter_guarded<4>, dim3(blocks), dim3(kBlock), 0, s, x, z, c, n, ld, mask, fill, st); break;
-    }
-  }
+  launch_scan_i64(st.cnt, poff, B, scan_tmp, s);
+  load_place_rows(W, st, x, z, c, n, ld, mask, B, poff, fill, slots, true, s);
   return 0;
 }
 

@@ -196,6 +196,50 @@ def test_inplace_same_rows_every_run(ctx):
     h0.close()
 
 
+def test_load_rows_independent_of_input_order(ctx):
+    """A load writes each bucket's terms in ascending key order: the same terms
+    in two input orders give identical rows, for packed stores (buckets of up
+    to ~256 terms, and a few buckets of thousands when the bucket count is
+    held down) and in-place stores (a few terms per bucket); and chains from
+    two separately loaded stores agree bit for bit."""
+    nq = 124
+    x, z, c = I.hamiltonian_banded(nq, 2, band=6, decay=3.0)
+    perm = np.random.default_rng(5).permutation(len(c))
+    cases = [(0, len(c), {}), (0, len(c), {"load_bucket_terms": 4096}), (INPLACE, 64 * len(c), {})]
+    for flags, max_terms, params in cases:
+        describe(0, "load order", flags=flags, max_terms=max_terms, **params)
+        rows = []
+        with _Params(ctx, **params):
+            for order in (slice(None), perm):
+                s = iqcc.Store(ctx, nq, max_terms, flags).load_numpy(x[order], z[order], c[order])
+                assert s.count() == len(c)
+                gx, gz, gc = s.to_numpy()
+                rows.append((gx, gz, gc.view(np.uint64)))
+                s.close()
+        for a, b in zip(*rows):
+            assert np.array_equal(a, b)
+        # the same multiset as the input
+        key_in = np.concatenate([x, z, c.view(np.uint64)[:, None]], axis=1)
+        key_out = np.concatenate([rows[0][0], rows[0][1], rows[0][2][:, None]], axis=1)
+        assert np.array_equal(np.unique(key_in, axis=0), np.unique(key_out, axis=0))
+    # chains from two loads (input in two orders) give the same energy bits
+    steps = 6
+    cx, cz = I.dis_candidates(x, nq, steps, 8, np.random.default_rng(63))
+    taus = I.taus(steps, np.random.default_rng(64))
+    th, ph, tht, pht = _angles(nq, 18)
+    out = []
+    for order in (slice(None), perm):
+        describe(1, "chain after load", nq=nq, steps=steps)
+        s = iqcc.Store(ctx, nq, 64 * len(c), INPLACE).load_numpy(x[order], z[order], c[order])
+        e = torch.zeros(steps, dtype=torch.float64, device="cuda")
+        for j in range(steps):
+            iqcc.iqcc_dress_inplace(ctx.handle, s.handle, cx[j], cz[j], taus[j], 1e-8, tht, pht,
+                                    e[j - 1:j] if j else None, e[j:j + 1])
+        out.append(e.cpu().numpy().view(np.uint64))
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
 def test_store_copy_rebuckets(ctx):
     """Copies from an ordinary store into in-place stores with fewer, about
     as many and more buckets keep the terms, and the copy dresses like the
