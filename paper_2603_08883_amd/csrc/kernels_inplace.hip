@@ -560,48 +560,86 @@ __device__ void emit_inplace(const StoreDev& st, const Entangler& P, double C, d
 // the slot's new count move, in order, into the freed rows below it that no
 // new key took.  A moved row is either an anticommuting term of the stash
 // (its new coefficient is recomputed from the stash) or a commuting term that
-// this step has not written (read from the store).
+// this step has not written (read from the store).  The windows [fin, cnt) of
+// all such slots are walked together, 64 rows per pass (one lane per row,
+// slot-major, so the lanes of one slot are consecutive); a row's destination
+// is the slot's freed row number nn + (live rows of its window below it).
+// Reads are at rows >= fin and writes below fin, so no row is read after it
+// is overwritten.
 template <int W>
 __device__ void refill(const StoreDev& st, const Entangler& P, double C, double S, const Seg<W>& g,
                        const Item& I, int n) {
   const int lane = threadIdx.x & 63;
-  for (int s = 0; s < I.nslots; ++s) {
-    const int nh = g.s_nhole[s], nn = g.s_nnew[s];
+  // lane s: the length of slot s's window and the slot's stash range
+  // (the stash is slot-major: aslot is non-decreasing)
+  int len = 0, e0 = 0, e1 = 0;
+  if (lane < I.nslots) {
+    const int nh = g.s_nhole[lane], nn = g.s_nnew[lane];
+    len = nh > nn ? nh - nn : 0;
+    if (len) {
+      int lo = 0, hi = n;
+      while (lo < hi) { const int m = (lo + hi) >> 1; if (g.aslot[m] < lane) lo = m + 1; else hi = m; }
+      e0 = lo;
+      hi = n;
+      while (lo < hi) { const int m = (lo + hi) >> 1; if (g.aslot[m] <= lane) lo = m + 1; else hi = m; }
+      e1 = lo;
+    }
+    g.s_ctr[lane] = 0;
+  }
+  const int incl = wave_incl_scan(len);
+  const int pre = incl - len;
+  const int total = __shfl(incl, 63, 64);
+  wave_sync();
+  for (int f0 = 0; f0 < total; f0 += 64) {
+    const int f = f0 + lane;
+    const bool act = f < total;
+    // the slot of f: the largest s < nslots with pre_s <= f
+    int s = 0;
+#pragma unroll
+    for (int step = kIPSlots / 2; step; step >>= 1) {
+      const int cand = s + step;
+      const int pc = __shfl(pre, cand < kIPSlots ? cand : kIPSlots - 1, 64);
+      if (cand < I.nslots && pc <= f) s = cand;
+    }
+    const int ps = __shfl(pre, s, 64);
     const int cnt = __shfl(I.cnt, s, 64);
     const int off = __shfl(I.off, s, 64);
-    if (nh <= nn) continue;
-    const int fin = cnt - (nh - nn);
+    const int se0 = __shfl(e0, s, 64), se1 = __shfl(e1, s, 64);
+    const int nh = g.s_nhole[s], nn = g.s_nnew[s];
     const int32_t* H = g.tab + g.s_hfirst[s];
-    // the slot's stash entries: aslot is non-decreasing
-    int lo = 0, hi = n;
-    while (lo < hi) { const int m = (lo + hi) >> 1; if (g.aslot[m] < s) lo = m + 1; else hi = m; }
-    const int e0 = lo;
-    hi = n;
-    while (lo < hi) { const int m = (lo + hi) >> 1; if (g.aslot[m] <= s) lo = m + 1; else hi = m; }
-    const int e1 = lo;
-    int moved = 0;
-    for (int b = fin; b < cnt; b += 64) {
-      const int r = b + lane;
-      const bool lv = r < cnt && !sorted_contains(H, nh, r);
-      const uint64_t mm = __ballot(lv);
-      if (lv) {
-        const int dst = H[nn + moved + (int)lanes_below(mm)];
-        int a0 = e0, a1 = e1;   // stash entry with row r (rows ascend within the slot)
-        while (a0 < a1) { const int m = (a0 + a1) >> 1; if (g.arel[m] < r) a0 = m + 1; else a1 = m; }
-        uint64_t kx[W], kz[W];
-        double c;
-        if (a0 < e1 && g.arel[a0] == r) {
-          entry_key<W>(g, a0, kx, kz);
-          double a, vn;
-          bool paired;
-          entry_values<W>(P, C, S, g, a0, kx, kz, a, c, vn, paired);
-        } else {
-          load_key<W>(st, (int64_t)off + r, kx, kz, c);
-        }
-        store_key<W>(st, (int64_t)off + dst, kx, kz, c);
+    const int r = cnt - (nh - nn) + (f - ps);
+    const bool lv = act && !sorted_contains(H, nh, r);
+    // rank among the live rows of the slot: its count so far plus the live
+    // lanes between the start of its run of equal slots and this lane
+    const int d = act ? s : -1;
+    const uint64_t hm = __ballot(lv);
+    const int dprev = __shfl_up(d, 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || d != dprev);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const int start = 63 - __clzll(heads & upto);
+    const uint64_t run_below = ((1ull << lane) - 1) & ~((1ull << start) - 1);
+    const int before = __popcll(hm & run_below);
+    const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1);
+    const int base = act ? g.s_ctr[s] : 0;
+    if (lv) {
+      const int dst = H[nn + base + before];
+      int a0 = se0, a1 = se1;   // stash entry with row r (rows ascend within the slot)
+      while (a0 < a1) { const int m = (a0 + a1) >> 1; if (g.arel[m] < r) a0 = m + 1; else a1 = m; }
+      uint64_t kx[W], kz[W];
+      double c;
+      if (a0 < se1 && g.arel[a0] == r) {
+        entry_key<W>(g, a0, kx, kz);
+        double a, vn;
+        bool paired;
+        entry_values<W>(P, C, S, g, a0, kx, kz, a, c, vn, paired);
+      } else {
+        load_key<W>(st, (int64_t)off + r, kx, kz, c);
       }
-      moved += (int)__popcll(mm);
+      store_key<W>(st, (int64_t)off + dst, kx, kz, c);
     }
+    wave_sync();
+    if (tail && act) g.s_ctr[s] = base + before + (lv ? 1 : 0);
+    wave_sync();
   }
 }
 
