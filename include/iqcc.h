@@ -71,7 +71,9 @@ const char *iqcc_last_error(const iqcc_ctx *ctx);
 const char *iqcc_version(void);
 
 /* Tuning knobs (the autotuner and tests set them).  Names:
- *   "load_bucket_terms"  target mean bucket size when a store is loaded (>= 1)
+ *   "load_bucket_terms"  target mean bucket size when a store is loaded
+ *                        (1 .. 16384; a load ranks each bucket's terms, at a
+ *                        cost that grows with the square of the bucket size)
  *   "split_bucket_terms" a dressing step doubles the bucket count when the
  *                        mean input bucket exceeds this many terms (>= 1)
  *   "anti_cap"           LDS capacity, in anticommuting terms, of one bucket
@@ -93,7 +95,7 @@ const char *iqcc_version(void);
  *                        batched DIS launch; 0 = about 8 workgroups per CU
  *                        in total (0 .. 4096)
  *   "inplace_bucket_terms" mean bucket size of an IQCC_STORE_INPLACE store
- *                        when it holds max_terms terms (1 .. 65536)
+ *                        when it holds max_terms terms (1 .. 16384)
  *   "inplace_item_terms" input terms per work item of iqcc_dress_inplace
  *                        while buckets are small; 0 = 1.5 x the stash
  *   "inplace_cap"        anticommuting terms a wavefront of iqcc_dress_inplace

@@ -431,7 +431,7 @@ int iqcc_ctx_destroy(iqcc_ctx* ctx) {
 int iqcc_set_param(iqcc_ctx* ctx, const char* name, int64_t v) {
   if (!ctx || !name) return IQCC_ERR_INVALID_ARG;
   struct { const char* n; int64_t* p; int64_t lo, hi; } tab[] = {
-      {"load_bucket_terms", &ctx->load_bucket_terms, 1, 1 << 20},
+      {"load_bucket_terms", &ctx->load_bucket_terms, 1, 1 << 14},
       {"split_bucket_terms", &ctx->split_bucket_terms, 1, 1 << 20},
       {"anti_cap", &ctx->anti_cap, 16, 8192},
       {"grid_per_cu", &ctx->grid_per_cu, 1, 16},
@@ -442,7 +442,7 @@ int iqcc_set_param(iqcc_ctx* ctx, const char* name, int64_t v) {
       {"fuse_energy", &ctx->fuse_energy, 0, 1},
       {"dis_tile", &ctx->dis_tile, 1, 256},
       {"dis_bucket_ranges", &ctx->dis_bucket_ranges, 0, 4096},
-      {"inplace_bucket_terms", &ctx->inplace_bucket_terms, 1, 1 << 16},
+      {"inplace_bucket_terms", &ctx->inplace_bucket_terms, 1, 1 << 14},
       {"inplace_item_terms", &ctx->inplace_item_terms, 0, 1 << 16},
       {"inplace_cap", &ctx->inplace_cap, 0, 512},
       {"inplace_region_rows", &ctx->inplace_region_rows, 0, 1 << 24},

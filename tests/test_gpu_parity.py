@@ -170,7 +170,7 @@ def test_chain_split_every_step(ctx):
     cx, cz = I.dis_candidates(x, nq, 4, 8, np.random.default_rng(8))
     th, ph = I.qmf_angles(nq, np.random.default_rng(9))
     _chain_compare(ctx, nq, x, z, c, list(zip(cx, cz)), [0.1, 0.2, -0.1, 0.05], 0.0, th, ph, 4 * 10**6,
-                   params={"load_bucket_terms": 100000, "split_bucket_terms": 1})
+                   params={"load_bucket_terms": 16384, "split_bucket_terms": 1})
 
 
 def test_edge_cases(ctx):
