@@ -901,10 +901,26 @@ __global__ __launch_bounds__(kBlock) void k_inplace_end(StoreDev st, const int64
   __syncthreads();
   unsigned long long mine[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
   double e = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kBlock) {
+  // four strided partials per round, their loads issued together; the
+  // energy adds stay in increasing partial order
+  constexpr int kU = 4;
+  for (int i0 = threadIdx.x; i0 < nparts; i0 += kU * kBlock) {
+    int64_t cv[kU][5];
+    double ev[kU];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) mine[k] += (unsigned long long)counts[5 * i + k];
-    if (energy_out) e += e_partial[i];
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kBlock;
+      const bool ok = i < nparts;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) cv[u][k] = ok ? counts[5 * i + k] : 0;
+      ev[u] = (ok && energy_out) ? e_partial[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) mine[k] += (unsigned long long)cv[u][k];
+      if (i0 + u * kBlock < nparts && energy_out) e += ev[u];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k)
