@@ -4,7 +4,7 @@
 //
 //  1. Partition H by the key bits the entangler flips (the x bits under P's x
 //     part and the z bits under P's z part): within a partition those bits are
-//     equal, so K -> K ^ P preserves order.  The partition is stable (a radix
+//     equal, so K -> K ^ P preserves order.  The partition is stable (a binary
 //     sort of the small label only), so every partition stays sorted.
 //  2. Local dressing: rotate the anticommuting terms in place (cos tau) and
 //     write their images K ^ P (+-sin tau, sign from the product phase); the
@@ -16,8 +16,6 @@
 //     combined (one IEEE addition), then |c| < eps is dropped.
 //  4. Rebuild the global order by a deterministic multiway merge: pairs of
 //     sorted runs are merged by rank, log2(#partitions) rounds.
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include <vector>
 
 #include "iqcc_internal.h"
@@ -87,6 +85,25 @@ __global__ void k_sl_bounds(const uint32_t* label, int64_t n, int64_t npart, int
     const int64_t prev = i == 0 ? -1 : (int64_t)label[i - 1];
     const int64_t cur = i == n ? npart : (int64_t)label[i];
     for (int64_t l = prev + 1; l <= cur; ++l) start[l] = i;
+  }
+}
+
+// Stable partition by the label, one label bit per pass (least significant
+// first): flag = bit b, then every element moves to (zeros before it) or
+// (all zeros + ones before it), which keeps the order within each side.
+__global__ void k_sl_bitflag(const uint32_t* label, int64_t n, int b, int64_t* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    flag[i] = (int64_t)((label[i] >> b) & 1u);
+}
+
+__global__ void k_sl_split(const uint32_t* label, const uint32_t* idx, int64_t n, const int64_t* flag,
+                           const int64_t* ones_before, uint32_t* label_out, uint32_t* idx_out) {
+  const int64_t zeros = n - (ones_before[n - 1] + flag[n - 1]);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = ones_before[i];
+    const int64_t dst = flag[i] ? zeros + o : i - o;
+    label_out[dst] = label[i];
+    idx_out[dst] = idx[i];
   }
 }
 
@@ -255,7 +272,7 @@ namespace {
 struct DevMem {
   std::vector<void*> p;
   ~DevMem() {
-    for (void* q : p) hipFree(q);
+    for (void* q : p) (void)hipFree(q);
   }
   template <class T>
   T* get(size_t count, hipError_t& e) {
@@ -293,21 +310,32 @@ hipError_t sortless_w(const Flat& h, int64_t n, const PauliKey& P, int nbits, do
   uint32_t* perm = mem.get<uint32_t>(n, e);
   int64_t* start = mem.get<int64_t>(npart + 1, e);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sl_labels<W>, dim3(grid_for(n)), dim3(kBlock), 0, s, h, n, P, label, idx);
-  size_t tmp_bytes = 0;
-  e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, label, label_s, idx, perm, (size_t)n, 0u,
-                                (unsigned)(nbits > 0 ? nbits : 1), s);
-  void* tmp = mem.get<unsigned char>(tmp_bytes, e);
-  if (e != hipSuccess) return e;
-  e = rocprim::radix_sort_pairs(tmp, tmp_bytes, label, label_s, idx, perm, (size_t)n, 0u,
-                                (unsigned)(nbits > 0 ? nbits : 1), s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sl_bounds, dim3(grid_for(n + 1)), dim3(kBlock), 0, s, label_s, n, npart, start);
-  // 2. rotate in place (partition order) and write the images
-  Flat g = mem.flat(W, n, e);
   int64_t* flag = mem.get<int64_t>(n, e);
   int64_t* pos = mem.get<int64_t>(n, e);
   int64_t* sc = mem.get<int64_t>((n + 1023) / 1024 + 2, e);
+  if (e != hipSuccess) return e;
+  // nbits stable binary splits between the buffers (label, idx) and
+  // (label_s, perm); the labels start in the one that makes the last split
+  // land in (label_s, perm)
+  const int passes = nbits > 0 ? nbits : 1;
+  uint32_t* cur_l = (passes & 1) ? label : label_s;
+  uint32_t* cur_i = (passes & 1) ? idx : perm;
+  uint32_t* oth_l = (passes & 1) ? label_s : label;
+  uint32_t* oth_i = (passes & 1) ? perm : idx;
+  hipLaunchKernelGGL(k_sl_labels<W>, dim3(grid_for(n)), dim3(kBlock), 0, s, h, n, P, cur_l, cur_i);
+  if (n > 0) {
+    for (int b = 0; b < passes; ++b) {
+      hipLaunchKernelGGL(k_sl_bitflag, dim3(grid_for(n)), dim3(kBlock), 0, s, cur_l, n, b, flag);
+      launch_scan_i64(flag, pos, n, sc, s);
+      hipLaunchKernelGGL(k_sl_split, dim3(grid_for(n)), dim3(kBlock), 0, s, cur_l, cur_i, n, flag, pos, oth_l,
+                         oth_i);
+      uint32_t* t = cur_l; cur_l = oth_l; oth_l = t;
+      t = cur_i; cur_i = oth_i; oth_i = t;
+    }
+  }
+  hipLaunchKernelGGL(k_sl_bounds, dim3(grid_for(n + 1)), dim3(kBlock), 0, s, label_s, n, npart, start);
+  // 2. rotate in place (partition order) and write the images
+  Flat g = mem.flat(W, n, e);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sl_gather<W>, dim3(grid_for(n)), dim3(kBlock), 0, s, h, perm, n, P, C, g, flag);
   launch_scan_i64(flag, pos, n, sc, s);
