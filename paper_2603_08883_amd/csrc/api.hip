@@ -1198,7 +1198,7 @@ int iqcc_dis_gradients(iqcc_ctx* ctx, const iqcc_store* h, const double* theta, 
     launch_dis(h->W, h->d, ctx->lut, cx, cz, n_cand, ld_cand, 0, (int)ctx->dis_tile, 0,
                ctx->partial, (int)gt, g, s, theta, phi, h->nq, ctx->partial + n_part);
   } else {
-    const int grid = (int)(ctx->n_cu * 4);
+    const int grid = (int)(ctx->n_cu * dis_one_blocks_per_cu(h->W));
     rc = ensure_partial(ctx, grid + 1);   // per-workgroup sums and a finish counter
     if (rc) return rc;
     launch_dis(h->W, h->d, ctx->lut, cx, cz, n_cand, ld_cand, 1, 1, grid, ctx->partial, 0, g, s,

@@ -700,6 +700,7 @@ void launch_backward_finalize(int nq, int grid, const double* acc, const double*
                               const double* phi, const double* dE, double* dtheta, double* dphi,
                               hipStream_t s);
 
+int dis_one_blocks_per_cu(int W);
 void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx,
                 const uint64_t* cz, int64_t n_cand, int64_t ld_cand, int mode, int tile,
                 int grid, double* partial /*[grid_terms][n_cand]*/, int grid_terms,

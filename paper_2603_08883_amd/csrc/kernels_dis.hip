@@ -346,6 +346,11 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
     s_off[threadIdx.x] = off;
     if (threadIdx.x == 0) s_pre[kBlock] = (int64_t)total;
     __syncthreads();
+    // the group's rows are one range when every bucket starts where the one
+    // before it ends (a loaded store); then row = base + i, the row the
+    // search below would find (thread 0 holds the group's first bucket)
+    const int64_t base = s_off[0];
+    const bool contig = __syncthreads_and(!mine || off - (int64_t)ex == base) != 0;
     const int64_t n = (int64_t)total;
     for (int64_t i0 = 0; i0 < n; i0 += kBlock * R) {
       uint64_t kx[R][W], kz[R][W];
@@ -357,11 +362,14 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
 #pragma unroll
         for (int w = 0; w < W; ++w) kx[r][w] = kz[r][w] = 0;
         if (i < n) {
-          int lo = 0;   // the last bucket of the group whose first row is <= i
+          int64_t row = base + i;
+          if (!contig) {
+            int lo = 0;   // the last bucket of the group whose first row is <= i
 #pragma unroll
-          for (int step = kBlock / 2; step; step >>= 1)
-            if (s_pre[lo + step] <= i) lo += step;
-          const int64_t row = s_off[lo] + (i - s_pre[lo]);
+            for (int step = kBlock / 2; step; step >>= 1)
+              if (s_pre[lo + step] <= i) lo += step;
+            row = s_off[lo] + (i - s_pre[lo]);
+          }
 #pragma unroll
           for (int w = 0; w < W; ++w) {
             kx[r][w] = __builtin_nontemporal_load(&st.x[w * st.cap + row]);
@@ -412,6 +420,21 @@ __global__ __launch_bounds__(kBlock) void k_dis_one(StoreDev st, const double* l
 }
 
 __global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
+
+// Workgroups of k_dis_one that one CU holds at once (its LDS bounds it): the
+// plain launch uses exactly that many per CU, so every workgroup is resident
+// and takes one bucket group.
+int dis_one_blocks_per_cu(int W) {
+  int nb = 0;
+  hipError_t e;
+  switch (W) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_dis_one<1>, kBlock, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_dis_one<2>, kBlock, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_dis_one<3>, kBlock, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_dis_one<4>, kBlock, 0); break;
+  }
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
 
 void launch_dis(int W, const StoreDev& st, const double* lut, const uint64_t* cx,
                 const uint64_t* cz, int64_t n_cand, int64_t ld_cand, int mode, int tile,

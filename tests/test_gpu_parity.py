@@ -365,6 +365,35 @@ def test_dis_gradients_match_oracle(ctx, mode):
     assert np.abs(ref).max() > 1e-6
 
 
+@pytest.mark.parametrize("layout", ["dressed", "inplace"])
+@pytest.mark.parametrize("mode", [iqcc.IQCC_DIS_BATCHED, iqcc.IQCC_DIS_PLAIN])
+def test_dis_gradients_on_dressed_stores(ctx, mode, layout):
+    """DIS screening of a store whose buckets do not sit back to back (rows
+    reserved by an out-of-place step, or bucket regions with free rows after
+    the live ones), against the oracle's gradients of the dressed terms."""
+    nq = 40
+    x, z, c = I.hamiltonian_dense(nq, 1)
+    th, ph, tht, pht = _angles(nq, 23)
+    px, pz = I.dis_candidates(x, nq, 1, 8, np.random.default_rng(24))
+    cx, cz = I.dis_candidates(x, nq, 120, 12, np.random.default_rng(25))
+    tau, eps = 0.21, 1e-8
+    describe(0, "dis on dressed store", layout=layout, mode=mode)
+    if layout == "dressed":
+        s0 = iqcc.Store(ctx, nq, 2 * len(c)).load_numpy(x, z, c)
+        s = iqcc.Store(ctx, nq, 4 * len(c))
+        iqcc.iqcc_dress(ctx.handle, s0.handle, px[0], pz[0], tau, eps, s.handle)
+    else:
+        s = iqcc.Store(ctx, nq, 8 * len(c), iqcc.IQCC_STORE_INPLACE).load_numpy(x, z, c)
+        iqcc.iqcc_dress_inplace(ctx.handle, s.handle, px[0], pz[0], tau, eps)
+    hx, hz, hc = O.dress(nq, x, z, c, px[0], pz[0], tau, eps)
+    assert s.count() == len(hc)
+    g = iqcc.iqcc_dis_gradients(ctx.handle, s.handle, tht, pht, iqcc.to_device_words(cx),
+                                iqcc.to_device_words(cz), mode).cpu().numpy()
+    ref = O.dis_gradients(nq, hx, hz, hc, th, ph, cx, cz)
+    assert np.abs(g - ref).max() <= E_TOL
+    assert np.abs(ref).max() > 1e-6
+
+
 @pytest.mark.parametrize("nq,angles", [(40, "z-eigen"), (40, "mixed"), (124, "random"), (124, "mixed"),
                                        (150, "mixed"), (256, "random")])
 def test_dis_gradients_special_angles(ctx, nq, angles):
