@@ -25,7 +25,9 @@ BATCH_SPACE = {"batch_anti_cap": [512, 1024], "grid_per_cu": [1, 2, 4],
                "batch_split_bucket_terms": [384, 768], "batch_unit_pairs": [4, 8, 32]}
 CHAIN_SPACE = {"anti_cap": [512, 1024], "grid_per_cu": [1, 2, 4],
                "split_bucket_terms": [256, 384, 768]}
-INPLACE_SPACE = {"inplace_item_terms": [0, 192, 384], "inplace_cap": [0, 256]}
+# the stash size (inplace_cap) is not searched: the knob can only lower it
+# below what the LDS holds, and a smaller stash only relocates more items
+INPLACE_SPACE = {"inplace_item_terms": [0, 128, 192, 256, 384]}
 DIS_SPACE = {"dis_tile": [64, 128, 256], "dis_bucket_ranges": [0, 512, 1024]}
 
 
