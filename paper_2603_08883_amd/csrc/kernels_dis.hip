@@ -273,7 +273,7 @@ __global__ void k_dis_reduce(const double* partial, int rows, int64_t n_cand, do
 // not issued for lanes whose term commutes.  The last workgroup to finish
 // sums the per-workgroup partials in a fixed order and writes g[a], so a
 // candidate costs one launch.
-constexpr int kDisOneR = 4;
+constexpr int kDisOneR = 8;
 constexpr int kDisRing = 128;   // ring entries per wavefront (< 64 left + 64 added)
 
 template <int W>
